@@ -1,0 +1,198 @@
+#!/usr/bin/env python3
+"""Benchmark: DG element-stage updates/s on the single-basin workload.
+
+Workload (synthetic, seeded): 1,002,528-triangle jittered basin over
+200 km x 200 km (708 x 708 quads cut along the shorter diagonal), -3000 m
+ocean rising through a tanh shelf to +20 m land with 32 Gaussian bumps and
+a dry land strip, ocean boundary at x = 0, parametric rain (peak 50 mm/h,
+r_m 30 km, r_e 100 km, moving east at 5 m/s), p = 1, LLF flux, slope
+limiter on, Manning 0.025, thin layer H0 = 0.05 m, SSP-RK2 at CFL 0.3.
+
+One step = rain evaluation + 2 x (stage kernel + limiter/positive-depth
+kernel) + the FP64 dt/budget reduction.  value = elements x stages x steps /
+wall time of the timed steps (inputs resident in HBM), reported for the FP32
+path (FP32 state and fluxes; FP64 wet/dry tests, dt and budgets); the FP64
+path is reported beside it.  The dominant kernel's roofline uses the
+algorithmic bytes of :func:`algorithmic_bytes` and its mean duration from
+HIP events recorded by the library on its stream around every launch.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import subprocess
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "DG element-stage updates/s (FP64 vs FP32-batched); p50/p99 scenario latency"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(kernel, E, rs, p, a_nonzero, last, limiter):
+    """Bytes one launch must move from/to HBM (each array streamed once;
+    neighbour gathers are cache traffic and not counted).
+
+    stage: own state 3 Np rs, w^n 3 Np rs when the stage blends it, edge
+           vectors 6 rs, vertex bathymetry 3 rs, friction rs, rain rs,
+           neighbour ids 12, edge codes 1, flag 1; writes the new state
+           3 Np rs and one flag byte; the last stage without limiter also
+           reads d_in (rs).
+    post:  reads the unlimited state 3 Np rs, bathymetry 3 rs, neighbour
+           ids 12, limiter weights 6 rs and code 1, wet byte 1; writes the
+           state 3 Np rs and a flag; the last stage reads edge vectors and
+           d_in (7 rs) for the volume and dt partials.
+    """
+    Np = 3 if p == 1 else 6
+    st = 3 * Np * rs
+    if kernel == "stage":
+        b = st + (st if a_nonzero else 0) + 11 * rs + 14 + st + 1
+        if last and not limiter:
+            b += rs
+    else:
+        b = st + 3 * rs + 12 + 6 * rs + 1 + 1 + st + 1 + (7 * rs if last else 0)
+    return E * b
+
+
+def run_precision(sc, precision, steps, warmup):
+    from paper_2307_14302_amd import Solver
+    import torch
+
+    t0 = time.perf_counter()
+    s = Solver.from_scenario(sc, precision=precision)
+    log(f"[{precision}] setup {time.perf_counter() - t0:.1f}s  E={s.n_tri}")
+    s.step(warmup)
+    s.sync()
+    s.profiling(True)
+    torch.cuda.synchronize()
+    s.sync()
+    t0 = time.perf_counter()
+    s.step(steps)
+    s.sync()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    m = s.mass()
+    stats = {k: s.kernel_stats(k) for k in ("stage", "post", "rain", "reduce")}
+    s.profiling(False)
+    E = s.n_tri
+    stages = int(sc.params.get("rk_stages", 2))
+    rate = E * stages * steps / el
+    log(f"[{precision}] {steps} steps in {el:.3f}s -> {rate:.4e} element-stage/s; t={m['t']:.2f}s dt={m['dt_last']:.4f} "
+        f"dry={m['n_dry']} kernels " + ", ".join(f"{k}:{n}x{(ms / max(n, 1)) * 1e3:.1f}us" for k, (n, ms) in stats.items()))
+    s.close()
+    return dict(rate=rate, elapsed=el, stats=stats, mass=m, E=E, stages=stages)
+
+
+def roofline(res, precision, p, limiter):
+    rs = 4 if precision == "fp32" else 8
+    stats = res["stats"]
+    dom = max(("stage", "post"), key=lambda k: stats[k][1])
+    n, ms = stats[dom]
+    if n == 0:
+        return None
+    # SSP(2,2): stage 0 does not blend w^n, stage 1 does and is the last
+    per_launch = [algorithmic_bytes(dom, res["E"], rs, p, a, last, limiter)
+                  for a, last in ((False, False), (True, True))]
+    byts = sum(per_launch) / len(per_launch)
+    avg_s = ms / n * 1e-3
+    ach = byts / avg_s / 1e9
+    return {"kernel": dom, "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None, "bytes_per_launch": int(byts),
+            "avg_us": round(avg_s * 1e6, 2), "launches": n}
+
+
+def cpu_baseline(timeout=600):
+    """The FP64 oracle on one host core: 2 SSP-RK2 steps of the full mesh."""
+    code = r"""
+import json, os, sys, time
+sys.path.insert(0, %r)
+import meshgen
+from oracle.solver import from_scenario
+sc = meshgen.basin(708)
+s = from_scenario(sc)
+t0 = time.perf_counter()
+s.step(2)
+el = time.perf_counter() - t0
+print(json.dumps({"E": s.E, "elapsed": el}))
+""" % ROOT
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    try:
+        out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=timeout)
+        r = json.loads(out.stdout.strip().splitlines()[-1])
+    except Exception as e:  # report, never fail the bench on the baseline leg
+        return {"value": None, "unit": "element-stage updates/s", "cores": 1, "kind": "oracle", "error": str(e)[:200]}
+    cpu_model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            cpu_model = next(l.split(":", 1)[1].strip() for l in f if l.startswith("model name"))
+    except Exception:
+        pass
+    return {"value": round(r["E"] * 2 * 2 / r["elapsed"], 1), "unit": "element-stage updates/s", "cores": 1,
+            "kind": "oracle", "sample": f"2 SSP-RK2 steps of the full {r['E']}-triangle basin, FP64 NumPy oracle, "
+            f"1 thread ({r['elapsed']:.1f}s)", "host_cpus": os.cpu_count(), "cpu_model": cpu_model}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--precision", choices=["both", "fp32", "fp64"], default="both")
+    ap.add_argument("--N", type=int, default=708, help="quads per side (708 -> 1,002,528 triangles)")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--calib-copy", action="store_true", help="also run a 1 GiB device copy (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (see the design notes on sharding); "
+              "run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import meshgen
+    torch.cuda.set_device(0)
+    t0 = time.perf_counter()
+    sc = meshgen.basin(args.N)
+    log(f"workload generated in {time.perf_counter() - t0:.1f}s: {sc.mesh.n_tri} triangles")
+    prm = sc.params
+    res = {}
+    for prec in (["fp32", "fp64"] if args.precision == "both" else [args.precision]):
+        res[prec] = run_precision(sc, prec, args.steps, args.warmup)
+    if args.calib_copy:
+        a = torch.empty(256 * 1024 * 1024, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log("calibration copy: 3 x 1 GiB read + 1 GiB written")
+    main_prec = "fp32" if "fp32" in res else "fp64"
+    r = res[main_prec]
+    out = {
+        "metric": METRIC, "value": round(r["rate"], 1), "unit": "element-stage updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(r["elapsed"] / args.steps * 1e3, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32" if main_prec == "fp32" else "f64", "data": "synthetic",
+        "config": {"workload": f"single basin, {r['E']} triangles (jittered {args.N}x{args.N} grid over 200 km), "
+                               f"p=1, LLF, limiter on, parametric moving rain, wet/dry front, SSP-RK2 CFL 0.3",
+                   "n_tri": r["E"], "p": prm["p"], "rk_stages": r["stages"], "precision": main_prec,
+                   "parallelism": "single GPU"},
+        "roofline": roofline(r, main_prec, prm["p"], prm["limiter"]),
+    }
+    if "fp64" in res and main_prec != "fp64":
+        f = res["fp64"]
+        out["fp64"] = {"value": round(f["rate"], 1), "ms_per_step": round(f["elapsed"] / args.steps * 1e3, 4),
+                       "dtype": "f64", "roofline": roofline(f, "fp64", prm["p"], prm["limiter"]),
+                       "fp32_over_fp64": round(r["rate"] / f["rate"], 3)}
+    if not args.no_cpu:
+        log("timing the oracle on one host core ...")
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,243 @@
+/*
+ * dgswe.h -- C ABI of the MI355X (gfx950) discontinuous Galerkin solver for
+ * the rain-augmented shallow water equations.
+ *
+ * Model (Wichitrnithed et al., "A Discontinuous Galerkin Finite Element Model
+ * for Compound Flood Simulations"):
+ *   Sec. 2.1, Eq. SWE      d(zeta)/dt + div(H u) = R, momentum with bed slope
+ *                          g zeta grad(hb) and bottom friction tau_b H u;
+ *                          boundary partition ocean (specified elevation),
+ *                          land (zero normal flow), river (Eq. river_bc:
+ *                          specified normal flux in m^2/s).
+ *   Sec. 2.2, Eq. elem_weak_form / Eq. dubiner / Eq. RKSSP
+ *                          element weak form in an orthogonal Dubiner modal
+ *                          basis (diagonal mass), SSP Runge-Kutta in time.
+ *   Sec. 2.3               Roe or local Lax-Friedrichs flux, optional slope
+ *                          limiter; Eq. rain: nodal rain averaged per element
+ *                          and added in every element.
+ *   Sec. 2.4               positive-depth operator (depth part, discharge
+ *                          part) after every stage; wet/dry element flags.
+ *   Sec. 2.5, Sec. 3.3     parametric storm rain and gridded rain lattices.
+ *
+ * Units are SI throughout: metres, seconds, m/s for rain, m^2/s for
+ * discharge.  Bathymetry hb is positive downward, the free surface zeta
+ * positive upward, the water depth is H = zeta + hb.
+ *
+ * Conventions shared by every call
+ *   - Every function returns DGSWE_OK (0) or a negative DGSWE_E* code; the
+ *     message of the last failure on the calling thread is returned by
+ *     dgswe_last_error().  A failed call leaves the object as it was, except
+ *     where stated.
+ *   - Host arrays passed in are copied; the caller keeps ownership.  Host
+ *     arrays passed out must be allocated by the caller with the documented
+ *     size.  Device memory is owned by the context (or batch) and released by
+ *     the matching destroy call.
+ *   - dgswe_step / dgswe_batch_step enqueue work on the context's HIP stream
+ *     and return without waiting; errors raised on the device (a non-finite
+ *     volume) are latched and reported by dgswe_sync and every later call.
+ *     Every read_* call and dgswe_mass_totals synchronise the stream.
+ *   - A context is not thread-safe; distinct contexts may be used from
+ *     distinct threads.
+ */
+#ifndef DGSWE_H
+#define DGSWE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------ codes ---- */
+#define DGSWE_OK          0
+#define DGSWE_EINVAL     -1   /* bad argument, bad mesh, NaN input          */
+#define DGSWE_ENOMEM     -2   /* device or host allocation failed           */
+#define DGSWE_EHIP       -3   /* a HIP runtime call failed                  */
+#define DGSWE_ESTATE     -4   /* call out of order (e.g. step before mesh)  */
+#define DGSWE_ENONFINITE -5   /* latched: the volume became NaN/Inf         */
+#define DGSWE_EBUDGET    -6   /* batch admission would exceed the budget    */
+
+#define DGSWE_FP64 0          /* state, fluxes and reductions in FP64       */
+#define DGSWE_FP32 1          /* state and fluxes in FP32; wet/dry tests,
+                                 dt and mass/rain/boundary volumes in FP64  */
+
+#define DGSWE_ROE 0           /* Roe flux (Sec. 3 default)                  */
+#define DGSWE_LLF 1           /* local Lax-Friedrichs (Sec. 3.3)            */
+
+#define DGSWE_MANNING   0     /* tau_b = g n^2 |u| / H^(4/3)               */
+#define DGSWE_QUADRATIC 1     /* tau_b = C_f |u| / H                        */
+
+#define DGSWE_LAND    0       /* zero normal flow: mirrored normal discharge */
+#define DGSWE_OCEAN   1       /* specified elevation (tide of its slot)      */
+#define DGSWE_RIVER   2       /* specified normal flux (series of its slot)  */
+#define DGSWE_OUTFLOW 3       /* transmissive: ghost = interior state        */
+
+#define DGSWE_MODAL  0        /* per element, per variable, per mode         */
+#define DGSWE_VERTEX 1        /* per element, per variable, per vertex       */
+
+#define DGSWE_MAX_SLOTS  16   /* forcing slots for ocean and river series    */
+
+/* Solver settings (Sec. 2.3, Sec. 3).  p = 1 with rk_stages = 2 is the
+ * paper's set-up; p = 2 needs rk_stages = 3 for linear stability;
+ * rk_stages = 5 selects the optimal five-stage second-order SSP scheme. */
+typedef struct dgswe_params {
+  int32_t p;            /* polynomial degree: 1 or 2                          */
+  int32_t precision;    /* DGSWE_FP64 | DGSWE_FP32                            */
+  int32_t flux;         /* DGSWE_ROE | DGSWE_LLF                              */
+  int32_t rk_stages;    /* 2, 3 or 5                                          */
+  int32_t limiter;      /* 0 = off, 1 = slope limiter on                      */
+  int32_t friction;     /* DGSWE_MANNING | DGSWE_QUADRATIC                    */
+  double  cfl;          /* dt = cfl * min_e d_e / lambda_e  (if dt_fixed <= 0) */
+  double  dt_fixed;     /* > 0: fixed time step                               */
+  double  dt_max;       /* upper bound of the CFL step                        */
+  double  H0;           /* thin-layer depth of the positive-depth operator    */
+  double  g;            /* gravity                                            */
+} dgswe_params;
+
+/* Time and mass bookkeeping (FP64 on the device). */
+typedef struct dgswe_mass {
+  double  t;            /* simulated time                                     */
+  double  dt_last;      /* step just taken                                    */
+  double  dt_next;      /* step that the next dgswe_step will take            */
+  double  volume;       /* sum over elements of area * mean depth             */
+  double  rain_in;      /* cumulative rain volume                             */
+  double  bnd_in;       /* cumulative volume entering through the boundary    */
+  double  bnd_out;      /* cumulative volume leaving through the boundary     */
+  int64_t steps;        /* time steps taken                                   */
+  int64_t n_dry;        /* elements flagged dry now                           */
+} dgswe_mass;
+
+typedef struct dgswe_ctx dgswe_ctx;
+typedef struct dgswe_batch dgswe_batch;
+
+/* Fill *out with the defaults: p = 1, FP64, Roe, 2 stages, no limiter,
+ * Manning, cfl 0.3, no fixed dt, dt_max 1e30, H0 1e-3, g 9.81. */
+int dgswe_default_params(dgswe_params* out);
+
+/* Create a solver context on the current HIP device.  hip_stream is a
+ * hipStream_t to enqueue on (for example torch.cuda.current_stream()), or
+ * NULL for a stream owned by the context.  EINVAL for unsupported settings. */
+int dgswe_create(const dgswe_params* params, void* hip_stream, dgswe_ctx** out);
+int dgswe_destroy(dgswe_ctx* ctx);
+
+/* Upload the mesh (Sec. 2.1 domain, Sec. 2.3 element-local operator).
+ *   xy[2*n_nodes]            node coordinates (x0, y0, x1, y1, ...), m
+ *   hb[n_nodes]              bathymetry, positive downward, m
+ *   fric[n_nodes]            Manning n or quadratic C_f (element value =
+ *                            mean of its three nodes)
+ *   tri[3*n_tri]             0-based node ids; clockwise triangles are
+ *                            reoriented (counted in dgswe_info)
+ *   bedge_nodes[2*n_bedges]  node pairs of typed boundary edges
+ *   bedge_type[n_bedges]     DGSWE_LAND/OCEAN/RIVER/OUTFLOW
+ *   bedge_slot[n_bedges]     forcing slot (< DGSWE_MAX_SLOTS)
+ * Boundary edges not listed are LAND.  EINVAL for node ids out of range,
+ * zero-area triangles, edges shared by more than two triangles, listed
+ * edges that are not on the boundary, bad types or slots, non-finite
+ * coordinates.  Elements are reordered along a Hilbert curve internally;
+ * every array passed in or out uses the caller's element order.
+ * Allowed once per context; n_tri = 0 is allowed (empty mesh). */
+int dgswe_upload_mesh(dgswe_ctx* ctx, int64_t n_nodes, const double* xy, const double* hb,
+                      const double* fric, int64_t n_tri, const int32_t* tri, int64_t n_bedges,
+                      const int32_t* bedge_nodes, const int32_t* bedge_type,
+                      const int32_t* bedge_slot);
+
+/* Reuse the mesh already uploaded to src (read-only device arrays are
+ * shared and kept alive while any context uses them).  Both contexts must
+ * have the same precision, p and limiter setting. */
+int dgswe_share_mesh(dgswe_ctx* dst, const dgswe_ctx* src);
+
+/* Initial state from nodal values (zeta, qx, qy)[n_nodes]: each element
+ * takes the linear interpolant of its vertices; the limiter (if on) and the
+ * positive-depth operator are applied once (Sec. 2.4); t = 0 and the
+ * budgets restart.  EINVAL on non-finite input. */
+int dgswe_set_initial_nodal(dgswe_ctx* ctx, const double* zeta, const double* qx, const double* qy);
+
+/* Set the state directly.  layout DGSWE_MODAL: w[n_tri][3][Np] with
+ * variables (zeta, qx, qy) and Dubiner modes ordered (0,0),(1,0),(0,1),
+ * (2,0),(1,1),(0,2) (Np = 3 for p = 1, 6 for p = 2).  The state is used as
+ * given (no limiter or positive-depth pass); flags and dt are derived from
+ * it.  The budgets restart at time t.  EINVAL on non-finite input. */
+int dgswe_set_state(dgswe_ctx* ctx, int layout, const double* w, double t);
+
+/* Rain (Sec. 2.3 Eq. rain; Sec. 2.5; Sec. 3.3).  Each replaces the previous
+ * rain source.  Nodal rain r[n_nodes] (m/s) is held until replaced.
+ * Parametric rain: rec[7*n_rec] rows (t, xc, yc, peak, T0, r_m, r_e) with
+ * increasing t; parameters are interpolated linearly in time (held outside
+ * the record span) and each node gets T0 + (peak - T0) r / r_m inside r_m
+ * and peak exp(-(r - r_m)/r_e) outside, r its distance to (xc, yc).
+ * Gridded rain: vals[n_rec][ny][nx] (m/s) on the lattice x0 + i dx,
+ * y0 + j dy at times t_rec[n_rec]; bilinear in space (0 outside the
+ * lattice), linear in time (held outside).  Rain is evaluated at the start
+ * of each step and used for all its stages. */
+int dgswe_set_rain_nodal(dgswe_ctx* ctx, const double* r);
+int dgswe_set_rain_parametric(dgswe_ctx* ctx, int32_t n_rec, const double* rec);
+int dgswe_set_rain_gridded(dgswe_ctx* ctx, double x0, double y0, double dx, double dy, int32_t nx,
+                           int32_t ny, int32_t n_rec, const double* t_rec, const float* vals);
+int dgswe_clear_rain(dgswe_ctx* ctx);
+
+/* Ocean elevation of a slot (Sec. 2.1): mean + sum_k a_k sin(2 pi t/T_k +
+ * phase_k), amp_period_phase[3*n_const].  River normal flux of a slot
+ * (Eq. river_bc), outward positive, m^2/s, linear in time between samples
+ * t[n], q[n] and held outside.  Both are evaluated at every stage time. */
+int dgswe_set_ocean_tide(dgswe_ctx* ctx, int32_t slot, double mean, int32_t n_const,
+                         const double* amp_period_phase);
+int dgswe_set_river_flux(dgswe_ctx* ctx, int32_t slot, int32_t n, const double* t, const double* q);
+
+/* Advance n_steps time steps (asynchronous; see the conventions above). */
+int dgswe_step(dgswe_ctx* ctx, int64_t n_steps);
+/* Wait for queued work; returns the latched device error if any. */
+int dgswe_sync(dgswe_ctx* ctx);
+
+/* Read the state as FP64 in the caller's element order:
+ * DGSWE_MODAL out[n_tri*3*Np], DGSWE_VERTEX out[n_tri*3*3]. */
+int dgswe_read_state(dgswe_ctx* ctx, int layout, double* out);
+/* Wet/dry flags (1 = dry) out[n_tri], caller's element order. */
+int dgswe_read_flags(dgswe_ctx* ctx, uint8_t* out);
+int dgswe_mass_totals(dgswe_ctx* ctx, dgswe_mass* out);
+
+/* Mesh and bookkeeping sizes: any pointer may be NULL. */
+int dgswe_info(const dgswe_ctx* ctx, int64_t* n_tri, int64_t* n_nodes, int64_t* n_edges,
+               int64_t* n_flipped);
+/* Device bytes a context of this size needs (state, mesh, rain, scratch). */
+int64_t dgswe_footprint_bytes(const dgswe_params* params, int64_t n_tri, int64_t n_nodes);
+
+/* Per-kernel timing with HIP events recorded on the context's stream
+ * around every launch of the named kernel ("stage", "post", "rain",
+ * "reduce").  Off by default; turning it on resets the counters. */
+int dgswe_set_profiling(dgswe_ctx* ctx, int on);
+int dgswe_kernel_stats(dgswe_ctx* ctx, const char* kernel, int64_t* launches, double* total_ms);
+
+/* ---------------------------------------------------------------- batches
+ * A batch advances many contexts (ensemble members or serving requests)
+ * together: each stage is one launch over the element tiles of every active
+ * member with the same (precision, p, flux, limiter, stages).  Members keep
+ * their own dt, forcing and budgets; each member's result is bitwise the
+ * same as when it runs alone.  The batch references (does not own) its
+ * member contexts; a member must stay alive until it is retired. */
+/* budget_bytes: admission limit on the summed dgswe_footprint_bytes of the
+ * members (<= 0: no limit).  The params fix the precision of the batch. */
+int dgswe_batch_create(const dgswe_params* params, void* hip_stream, int64_t budget_bytes,
+                       dgswe_batch** out);
+int dgswe_batch_destroy(dgswe_batch* b);
+/* Add an initialised member that should run n_steps more steps.  *slot
+ * receives its slot id.  EBUDGET if the footprint does not fit, EINVAL if
+ * its precision differs from the batch. */
+int dgswe_batch_add(dgswe_batch* b, dgswe_ctx* member, int64_t n_steps, int32_t* slot);
+/* Advance every active member by up to max_steps steps (asynchronous). */
+int dgswe_batch_step(dgswe_batch* b, int64_t max_steps);
+/* Synchronise, then report members that reached their step count:
+ * done_slots[cap] receives up to cap slot ids, *n_done their number. */
+int dgswe_batch_poll(dgswe_batch* b, int32_t* done_slots, int32_t cap, int32_t* n_done);
+/* Remove a member (done or not); its context stays valid. */
+int dgswe_batch_retire(dgswe_batch* b, int32_t slot);
+/* Number of members, summed footprint. Either pointer may be NULL. */
+int dgswe_batch_info(const dgswe_batch* b, int32_t* n_members, int64_t* footprint);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* dgswe_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DGSWE_H */

@@ -1,0 +1,1168 @@
+// C ABI of the DG solver: contexts, state I/O, forcing, stepping, batches.
+// See include/dgswe.h for the contract of every call.
+#include "dgswe.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <limits>
+#include <map>
+#include <memory>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "device_common.h"
+#include "internal.h"
+#include "mesh.h"
+
+using namespace dg;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIPCHK(x)                                                                              \
+  do {                                                                                         \
+    hipError_t e_ = (x);                                                                       \
+    if (e_ != hipSuccess) return fail(DGSWE_EHIP, std::string(#x) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+  DevBuf& operator=(DevBuf&& o) noexcept {
+    if (this != &o) {
+      release();
+      p = o.p;
+      bytes = o.bytes;
+      o.p = nullptr;
+      o.bytes = 0;
+    }
+    return *this;
+  }
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  hipError_t alloc(size_t n) {
+    release();
+    if (n == 0) return hipSuccess;
+    hipError_t e = hipMalloc(&p, n);
+    if (e == hipSuccess) bytes = n;
+    return e;
+  }
+  template <typename T> T* as() const { return static_cast<T*>(p); }
+};
+
+template <typename T>
+hipError_t upload(DevBuf& b, const std::vector<T>& v) {
+  hipError_t e = b.alloc(v.size() * sizeof(T));
+  if (e != hipSuccess || v.empty()) return e;
+  return hipMemcpy(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
+}
+
+template <typename R>
+std::vector<R> cast(const std::vector<double>& v) {
+  return std::vector<R>(v.begin(), v.end());
+}
+
+// Shu-Osher coefficients (a_i, b_i, g_i, c_i): stage i computes
+// w(i) = a_i w^n + b_i (w(i-1) + g_i dt L(w(i-1), t^n + c_i dt)).
+struct RKTable {
+  int n = 0;
+  double a[MAX_STAGES], b[MAX_STAGES], g[MAX_STAGES], c[MAX_STAGES], w[MAX_STAGES];
+};
+
+bool make_rk(int stages, RKTable& T) {
+  T.n = stages;
+  if (stages == 2) {  // SSP(2,2)
+    const double t[2][4] = {{0, 1, 1, 0}, {0.5, 0.5, 1, 1}};
+    for (int i = 0; i < 2; ++i) { T.a[i] = t[i][0]; T.b[i] = t[i][1]; T.g[i] = t[i][2]; T.c[i] = t[i][3]; }
+  } else if (stages == 3) {  // SSP(3,3)
+    const double t[3][4] = {{0, 1, 1, 0}, {0.75, 0.25, 1, 1}, {1.0 / 3.0, 2.0 / 3.0, 1, 0.5}};
+    for (int i = 0; i < 3; ++i) { T.a[i] = t[i][0]; T.b[i] = t[i][1]; T.g[i] = t[i][2]; T.c[i] = t[i][3]; }
+  } else if (stages == 5) {  // SSP(5,2): four forward-Euler stages of dt/4, then the 1/5 - 4/5 blend
+    for (int i = 0; i < 5; ++i) { T.a[i] = 0; T.b[i] = 1; T.g[i] = 0.25; T.c[i] = 0.25 * i; }
+    T.a[4] = 0.2;
+    T.b[4] = 0.8;
+  } else {
+    return false;
+  }
+  // weight of each stage's L in w^{n+1}: e_i = b_i (e_{i-1} + g_i delta_i)
+  double e[MAX_STAGES] = {0, 0, 0, 0, 0};
+  for (int i = 0; i < stages; ++i) {
+    for (int j = 0; j < i; ++j) e[j] *= T.b[i];
+    e[i] = T.b[i] * T.g[i];
+  }
+  for (int i = 0; i < stages; ++i) T.w[i] = e[i];
+  return true;
+}
+
+struct MeshDev {
+  HostMesh host;
+  int real_size = 8, p = 1, limiter = 0;
+  DevBuf ev, hbv, fric, din, lima, nbr, nk, tri, limc, nxy;
+  size_t device_bytes() const {
+    return ev.bytes + hbv.bytes + fric.bytes + din.bytes + lima.bytes + nbr.bytes + nk.bytes + tri.bytes +
+           limc.bytes + nxy.bytes;
+  }
+};
+
+// value of Dubiner mode m at reference vertex k
+inline double dg_vertex_basis(int k, int m) { return phi_(m, vr_(k), vs_(k)); }
+
+enum KName { K_STAGE = 0, K_POST, K_RAIN, K_REDUCE, K_N };
+const char* kname[K_N] = {"stage", "post", "rain", "reduce"};
+
+struct Pending {
+  int k;
+  hipEvent_t a, b;
+};
+
+}  // namespace
+
+struct dgswe_ctx {
+  dgswe_params prm{};
+  int rs = 8;                       // bytes per Real
+  RKTable rk;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::shared_ptr<MeshDev> mesh;
+  int n_tiles = 0;
+  DevBuf W[3], Wt, F[3], fullwet, R, part, sc, memb, tiles, ids, rnode;
+  DevBuf storm, gt, gvals, tide_c, riv_tq;
+  Forcing fo{};
+  std::vector<double> tide_rows[MAX_SLOTS];
+  double tide_mean[MAX_SLOTS] = {0};
+  std::vector<double> riv_rows[MAX_SLOTS];
+  bool have_state = false;
+  bool in_batch = false;
+  hipStream_t batch_stream = nullptr;   // stream of the batch this context belongs to
+  // profiling
+  bool prof = false;
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> free_events;
+  int64_t k_launches[K_N] = {0, 0, 0, 0};
+  double k_ms[K_N] = {0, 0, 0, 0};
+  // graph of one step
+  hipGraphExec_t graph = nullptr;
+  bool graph_dirty = true;
+
+  ~dgswe_ctx() {
+    if (graph) (void)hipGraphExecDestroy(graph);
+    if (stream) (void)hipStreamSynchronize(stream);
+    for (auto& p : pending) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
+    for (auto e : free_events) (void)hipEventDestroy(e);
+    if (own_stream && stream) (void)hipStreamDestroy(stream);
+  }
+  int E() const { return mesh ? int(mesh->host.E) : 0; }
+  int NP() const { return prm.p == 1 ? 3 : 6; }
+};
+
+struct dgswe_batch {
+  dgswe_params prm{};
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  int64_t budget = 0;
+  struct Slot {
+    dgswe_ctx* ctx = nullptr;
+    int64_t target = 0;
+    bool live = false;
+  };
+  std::vector<Slot> slots;
+  bool dirty = true;
+  struct Group {
+    int p, flux, limiter;
+    RKTable rk;
+    std::vector<int> members;       // indices into the member array
+    int n_tiles = 0;
+    DevBuf tiles, ids;
+    bool has_rain = false;
+  };
+  std::vector<Group> groups;
+  DevBuf memb;
+  ~dgswe_batch() {
+    if (stream) (void)hipStreamSynchronize(stream);
+    if (own_stream && stream) (void)hipStreamDestroy(stream);
+  }
+};
+
+namespace {
+
+// ------------------------------------------------------------ helpers
+template <typename Real>
+Member<Real> member_struct(const dgswe_ctx* c) {
+  Member<Real> m{};
+  const MeshDev* md = c->mesh.get();
+  m.E = c->E();
+  m.n_nodes = md ? int(md->host.n_nodes) : 0;
+  m.n_tiles = c->n_tiles;
+  m.friction = c->prm.friction;
+  m.H0 = c->prm.H0;
+  m.g = c->prm.g;
+  m.cfl = c->prm.cfl;
+  m.dt_fixed = c->prm.dt_fixed;
+  m.dt_max = c->prm.dt_max;
+  if (md) {
+    m.ev = md->ev.as<Real>();
+    m.hbv = md->hbv.as<Real>();
+    m.fric = md->fric.as<Real>();
+    m.nbr = md->nbr.as<int>();
+    m.nk = md->nk.as<uint8_t>();
+    m.din = md->din.as<Real>();
+    m.tri = md->tri.as<int>();
+    m.nxy = md->nxy.as<double>();
+    m.lima = md->lima.as<Real>();
+    m.limc = md->limc.as<uint8_t>();
+  }
+  for (int i = 0; i < 3; ++i) {
+    m.W[i] = c->W[i].as<Real>();
+    m.F[i] = c->F[i].as<uint8_t>();
+  }
+  m.Wt = c->Wt.as<Real>();
+  m.fullwet = c->fullwet.as<uint8_t>();
+  m.R = c->R.as<Real>();
+  m.part = c->part.as<double>();
+  m.sc = c->sc.as<Scalars>();
+  m.fo = c->fo;
+  return m;
+}
+
+int push_member(dgswe_ctx* c) {
+  if (c->stream) HIPCHK(hipStreamSynchronize(c->stream));
+  if (c->rs == 8) {
+    Member<double> m = member_struct<double>(c);
+    HIPCHK(hipMemcpy(c->memb.p, &m, sizeof m, hipMemcpyHostToDevice));
+  } else {
+    Member<float> m = member_struct<float>(c);
+    HIPCHK(hipMemcpy(c->memb.p, &m, sizeof m, hipMemcpyHostToDevice));
+  }
+  c->graph_dirty = true;
+  return DGSWE_OK;
+}
+
+hipEvent_t get_event(dgswe_ctx* c) {
+  if (!c->free_events.empty()) {
+    hipEvent_t e = c->free_events.back();
+    c->free_events.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  (void)hipEventCreate(&e);
+  return e;
+}
+
+void harvest(dgswe_ctx* c) {
+  for (auto& p : c->pending) {
+    (void)hipEventSynchronize(p.b);
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+      c->k_ms[p.k] += ms;
+      c->k_launches[p.k] += 1;
+    }
+    c->free_events.push_back(p.a);
+    c->free_events.push_back(p.b);
+  }
+  c->pending.clear();
+}
+
+struct ProfScope {
+  dgswe_ctx* c;
+  int k;
+  hipEvent_t a = nullptr;
+  ProfScope(dgswe_ctx* c_, int k_) : c(c_), k(k_) {
+    if (c && c->prof) {
+      a = get_event(c);
+      (void)hipEventRecord(a, c->stream);
+    }
+  }
+  ~ProfScope() {
+    if (c && c->prof) {
+      hipEvent_t b = get_event(c);
+      (void)hipEventRecord(b, c->stream);
+      c->pending.push_back({k, a, b});
+      if (c->pending.size() > 4096) harvest(c);
+    }
+  }
+};
+
+RKInfo rk_info(const RKTable& T) {
+  RKInfo r{};
+  r.n = T.n;
+  for (int i = 0; i < MAX_STAGES; ++i) {
+    r.w[i] = i < T.n ? T.w[i] : 0.0;
+    r.c[i] = i < T.n ? T.c[i] : 0.0;
+  }
+  return r;
+}
+
+// Buffers of stage i: in/out state and flag buffers (the last stage writes
+// buffer 0 in place; intermediate stages alternate between 1 and 2).
+StageArgs stage_args(const RKTable& T, int i) {
+  StageArgs a{};
+  a.stage = i;
+  a.last = (i == T.n - 1);
+  a.in_buf = (i == 0) ? 0 : 1 + ((i - 1) % 2);
+  a.out_buf = a.last ? 0 : 1 + (i % 2);
+  a.fin = a.in_buf;
+  a.fout = a.out_buf;
+  a.a = T.a[i];
+  a.b = T.b[i];
+  a.gam = T.g[i];
+  return a;
+}
+
+// One time step of a set of members sharing (precision, p, flux, limiter,
+// stages): rain, stages (+ post when limiting), reduce.
+template <typename Real>
+int enqueue_step_group(const Member<Real>* d_m, const Tile* d_t, int n_tiles, const int* d_ids, int n_members,
+                       int p, int flux, int limiter, const RKTable& T, bool rain, hipStream_t s, dgswe_ctx* prof) {
+  if (rain) {
+    ProfScope ps(prof, K_RAIN);
+    HIPCHK(launch_rain<Real>(d_m, d_t, n_tiles, 0, nullptr, s));
+  }
+  for (int i = 0; i < T.n; ++i) {
+    StageArgs a = stage_args(T, i);
+    if (limiter) {
+      StageArgs sa = a;
+      sa.out_buf = -1;
+      {
+        ProfScope ps(prof, K_STAGE);
+        HIPCHK(launch_stage<Real>(p, flux, 1, d_m, d_t, n_tiles, sa, s));
+      }
+      ProfScope ps(prof, K_POST);
+      HIPCHK(launch_post<Real>(p, 1, d_m, d_t, n_tiles, a, 0, s));
+    } else {
+      ProfScope ps(prof, K_STAGE);
+      HIPCHK(launch_stage<Real>(p, flux, 0, d_m, d_t, n_tiles, a, s));
+    }
+  }
+  ProfScope ps(prof, K_REDUCE);
+  HIPCHK(launch_reduce<Real>(d_m, d_ids, n_members, 0, rk_info(T), s));
+  return DGSWE_OK;
+}
+
+int ctx_enqueue_step(dgswe_ctx* c) {
+  const bool rain = c->fo.rain_kind != RAIN_CONST;
+  if (c->rs == 8)
+    return enqueue_step_group<double>(c->memb.as<Member<double>>(), c->tiles.as<Tile>(), c->n_tiles, c->ids.as<int>(),
+                                      1, c->prm.p, c->prm.flux, c->prm.limiter, c->rk, rain, c->stream, c);
+  return enqueue_step_group<float>(c->memb.as<Member<float>>(), c->tiles.as<Tile>(), c->n_tiles, c->ids.as<int>(), 1,
+                                   c->prm.p, c->prm.flux, c->prm.limiter, c->rk, rain, c->stream, c);
+}
+
+int ctx_reduce_init(dgswe_ctx* c) {
+  if (c->rs == 8)
+    HIPCHK(launch_reduce<double>(c->memb.as<Member<double>>(), c->ids.as<int>(), 1, 1, rk_info(c->rk), c->stream));
+  else
+    HIPCHK(launch_reduce<float>(c->memb.as<Member<float>>(), c->ids.as<int>(), 1, 1, rk_info(c->rk), c->stream));
+  return DGSWE_OK;
+}
+
+int check_ctx(const dgswe_ctx* c, bool need_mesh = true, bool need_state = false) {
+  if (!c) return fail(DGSWE_EINVAL, "null context");
+  if (need_mesh && !c->mesh) return fail(DGSWE_ESTATE, "no mesh uploaded");
+  if (need_state && !c->have_state) return fail(DGSWE_ESTATE, "no state set");
+  return DGSWE_OK;
+}
+
+int read_scalars(dgswe_ctx* c, Scalars& s) {
+  if (c->batch_stream) HIPCHK(hipStreamSynchronize(c->batch_stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  HIPCHK(hipMemcpy(&s, c->sc.p, sizeof s, hipMemcpyDeviceToHost));
+  return DGSWE_OK;
+}
+
+int write_scalars(dgswe_ctx* c, const Scalars& s) {
+  HIPCHK(hipStreamSynchronize(c->stream));
+  HIPCHK(hipMemcpy(c->sc.p, &s, sizeof s, hipMemcpyHostToDevice));
+  return DGSWE_OK;
+}
+
+int refresh_forcing(dgswe_ctx* c) {
+  int rc = push_member(c);
+  if (rc) return rc;
+  if (!c->have_state) return DGSWE_OK;
+  rc = ctx_reduce_init(c);
+  if (rc) return rc;
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return DGSWE_OK;
+}
+
+int upload_boundary_forcing(dgswe_ctx* c) {
+  std::vector<double> tc, rq;
+  c->fo.ocean_mask = 0;
+  c->fo.river_mask = 0;
+  for (int s = 0; s < MAX_SLOTS; ++s) {
+    c->fo.tide_mean[s] = c->tide_mean[s];
+    c->fo.tide_off[s] = int(tc.size() / 3);
+    c->fo.tide_cnt[s] = int(c->tide_rows[s].size() / 3);
+    tc.insert(tc.end(), c->tide_rows[s].begin(), c->tide_rows[s].end());
+    c->fo.riv_off[s] = int(rq.size() / 2);
+    c->fo.riv_cnt[s] = int(c->riv_rows[s].size() / 2);
+    rq.insert(rq.end(), c->riv_rows[s].begin(), c->riv_rows[s].end());
+  }
+  for (int s = 0; s < MAX_SLOTS; ++s) {
+    if (c->tide_mean[s] != 0.0 || !c->tide_rows[s].empty()) c->fo.ocean_mask |= 1u << s;
+    if (!c->riv_rows[s].empty()) c->fo.river_mask |= 1u << s;
+  }
+  if (c->stream) HIPCHK(hipStreamSynchronize(c->stream));
+  if (tc.empty()) tc.push_back(0.0);
+  if (rq.empty()) rq.push_back(0.0);
+  HIPCHK(upload(c->tide_c, tc));
+  HIPCHK(upload(c->riv_tq, rq));
+  c->fo.tide_c = c->tide_c.as<double>();
+  c->fo.riv_tq = c->riv_tq.as<double>();
+  return refresh_forcing(c);
+}
+
+int alloc_state(dgswe_ctx* c) {
+  const int64_t E = c->E();
+  const size_t st = size_t(3) * c->NP() * E * c->rs;
+  for (int i = 0; i < 3; ++i) {
+    HIPCHK(c->W[i].alloc(st));
+    HIPCHK(c->F[i].alloc(size_t(E)));
+    if (E) HIPCHK(hipMemset(c->F[i].p, 0, size_t(E)));
+  }
+  if (c->prm.limiter) {
+    HIPCHK(c->Wt.alloc(st));
+    HIPCHK(c->fullwet.alloc(size_t(E)));
+  } else {
+    // the initial positive-depth pass stages its input in Wt
+    HIPCHK(c->Wt.alloc(st));
+    c->fullwet.release();
+  }
+  HIPCHK(c->R.alloc(size_t(E) * c->rs));
+  if (E) HIPCHK(hipMemset(c->R.p, 0, size_t(E) * c->rs));
+  c->n_tiles = int((E + TILE - 1) / TILE);
+  const size_t pb = size_t(NPART) * std::max(c->n_tiles, 1) * sizeof(double);
+  HIPCHK(c->part.alloc(pb));
+  HIPCHK(hipMemset(c->part.p, 0, pb));
+  std::vector<Tile> tl(c->n_tiles);
+  for (int t = 0; t < c->n_tiles; ++t) tl[t] = {0, t};
+  if (tl.empty()) tl.push_back({0, 0});
+  HIPCHK(upload(c->tiles, tl));
+  return push_member(c);
+}
+
+template <typename R>
+int upload_mesh_arrays(MeshDev& md) {
+  const HostMesh& h = md.host;
+  HIPCHK(upload(md.ev, cast<R>(h.ev)));
+  HIPCHK(upload(md.hbv, cast<R>(h.hbv)));
+  HIPCHK(upload(md.fric, cast<R>(h.fric)));
+  HIPCHK(upload(md.din, cast<R>(h.din)));
+  HIPCHK(upload(md.nbr, h.nbr));
+  HIPCHK(upload(md.nk, h.nk));
+  HIPCHK(upload(md.tri, h.tri));
+  HIPCHK(upload(md.nxy, h.xy));
+  if (md.limiter) {
+    HIPCHK(upload(md.lima, cast<R>(h.lima)));
+    HIPCHK(upload(md.limc, h.limc));
+  }
+  return DGSWE_OK;
+}
+
+// modal coefficients of the linear interpolant of vertex values (n0, n1, n2)
+inline void modal_from_vertex(double n0, double n1, double n2, double* w) {
+  w[0] = (n0 + n1 + n2) / 3.0;
+  w[1] = (n1 - n0) / 2.0;
+  w[2] = (2.0 * n2 - n0 - n1) / 6.0;
+}
+
+int upload_state(dgswe_ctx* c, const std::vector<double>& wint /* [3*NP][E] internal order */, DevBuf& dst) {
+  HIPCHK(hipStreamSynchronize(c->stream));
+  if (c->rs == 8) {
+    if (!wint.empty()) HIPCHK(hipMemcpy(dst.p, wint.data(), wint.size() * 8, hipMemcpyHostToDevice));
+  } else {
+    std::vector<float> f(wint.begin(), wint.end());
+    if (!f.empty()) HIPCHK(hipMemcpy(dst.p, f.data(), f.size() * 4, hipMemcpyHostToDevice));
+  }
+  return DGSWE_OK;
+}
+
+int reset_scalars(dgswe_ctx* c, double t) {
+  Scalars s{};
+  s.t = t;
+  s.active = 1;
+  s.target = std::numeric_limits<long long>::max();
+  return write_scalars(c, s);
+}
+
+int post_initial(dgswe_ctx* c, int init) {
+  StageArgs a{};
+  const int p = c->prm.p;
+  if (c->rs == 8) {
+    auto* m = c->memb.as<Member<double>>();
+    if (init == 1 && c->prm.limiter) HIPCHK(launch_classify<double>(p, m, c->tiles.as<Tile>(), c->n_tiles, c->stream));
+    HIPCHK(launch_post<double>(p, init == 1 ? c->prm.limiter : 0, m, c->tiles.as<Tile>(), c->n_tiles, a, init, c->stream));
+  } else {
+    auto* m = c->memb.as<Member<float>>();
+    if (init == 1 && c->prm.limiter) HIPCHK(launch_classify<float>(p, m, c->tiles.as<Tile>(), c->n_tiles, c->stream));
+    HIPCHK(launch_post<float>(p, init == 1 ? c->prm.limiter : 0, m, c->tiles.as<Tile>(), c->n_tiles, a, init, c->stream));
+  }
+  int rc = ctx_reduce_init(c);
+  if (rc) return rc;
+  HIPCHK(hipStreamSynchronize(c->stream));
+  c->have_state = true;
+  c->graph_dirty = true;
+  return DGSWE_OK;
+}
+
+int64_t footprint(const dgswe_params* p, int64_t E, int64_t n_nodes) {
+  const int64_t rs = p->precision == DGSWE_FP32 ? 4 : 8;
+  const int64_t NP = p->p == 2 ? 6 : 3;
+  const int64_t tiles = (E + TILE - 1) / TILE;
+  int64_t b = 4 * 3 * NP * E * rs;                   // W0..W2 + Wt
+  b += 3 * E + (p->limiter ? E : 0);                 // flags, fully-wet bytes
+  b += E * rs;                                       // element rain
+  b += (6 + 3 + 1 + 1) * E * rs;                     // edge vectors, hb, friction, d_in
+  b += 3 * E * 4 + E + 3 * E * 4;                    // neighbours, codes, node ids
+  if (p->limiter) b += 6 * E * rs + E;               // limiter stencil
+  b += 2 * n_nodes * 8;                              // node coordinates
+  b += NPART * std::max<int64_t>(tiles, 1) * 8 + 4096;
+  return b;
+}
+
+}  // namespace
+
+// ======================================================================= API
+extern "C" {
+
+const char* dgswe_last_error(void) { return g_err.c_str(); }
+
+int dgswe_default_params(dgswe_params* out) {
+  if (!out) return fail(DGSWE_EINVAL, "null params");
+  *out = dgswe_params{};
+  out->p = 1;
+  out->precision = DGSWE_FP64;
+  out->flux = DGSWE_ROE;
+  out->rk_stages = 2;
+  out->limiter = 0;
+  out->friction = DGSWE_MANNING;
+  out->cfl = 0.3;
+  out->dt_fixed = 0.0;
+  out->dt_max = 1e30;
+  out->H0 = 1e-3;
+  out->g = 9.81;
+  return DGSWE_OK;
+}
+
+static int check_params(const dgswe_params* p) {
+  if (!p) return fail(DGSWE_EINVAL, "null params");
+  if (p->p != 1 && p->p != 2) return fail(DGSWE_EINVAL, "p must be 1 or 2");
+  if (p->precision != DGSWE_FP32 && p->precision != DGSWE_FP64) return fail(DGSWE_EINVAL, "bad precision");
+  if (p->flux != DGSWE_ROE && p->flux != DGSWE_LLF) return fail(DGSWE_EINVAL, "bad flux");
+  if (p->rk_stages != 2 && p->rk_stages != 3 && p->rk_stages != 5) return fail(DGSWE_EINVAL, "rk_stages must be 2, 3 or 5");
+  if (p->friction != DGSWE_MANNING && p->friction != DGSWE_QUADRATIC) return fail(DGSWE_EINVAL, "bad friction law");
+  if (!(p->H0 > 0.0) || !(p->g > 0.0) || !std::isfinite(p->H0) || !std::isfinite(p->g))
+    return fail(DGSWE_EINVAL, "H0 and g must be positive");
+  if (!(p->dt_fixed > 0.0) && !(p->cfl > 0.0 && p->dt_max > 0.0)) return fail(DGSWE_EINVAL, "need dt_fixed > 0 or cfl, dt_max > 0");
+  return DGSWE_OK;
+}
+
+int dgswe_create(const dgswe_params* params, void* hip_stream, dgswe_ctx** out) {
+  if (!out) return fail(DGSWE_EINVAL, "null output pointer");
+  *out = nullptr;
+  int rc = check_params(params);
+  if (rc) return rc;
+  auto c = std::make_unique<dgswe_ctx>();
+  c->prm = *params;
+  c->rs = params->precision == DGSWE_FP32 ? 4 : 8;
+  make_rk(params->rk_stages, c->rk);
+  if (hip_stream) {
+    c->stream = static_cast<hipStream_t>(hip_stream);
+  } else {
+    HIPCHK(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+    c->own_stream = true;
+  }
+  HIPCHK(c->sc.alloc(sizeof(Scalars)));
+  HIPCHK(c->memb.alloc(std::max(sizeof(Member<double>), sizeof(Member<float>))));
+  std::vector<int> ids{0};
+  HIPCHK(upload(c->ids, ids));
+  rc = reset_scalars(c.get(), 0.0);
+  if (rc) return rc;
+  c->fo.rain_kind = RAIN_CONST;
+  rc = upload_boundary_forcing(c.get());
+  if (rc) return rc;
+  *out = c.release();
+  return DGSWE_OK;
+}
+
+int dgswe_destroy(dgswe_ctx* c) {
+  if (!c) return DGSWE_OK;
+  if (c->in_batch) return fail(DGSWE_ESTATE, "context is a member of a batch; retire it first");
+  delete c;
+  return DGSWE_OK;
+}
+
+int dgswe_upload_mesh(dgswe_ctx* c, int64_t n_nodes, const double* xy, const double* hb, const double* fric,
+                      int64_t n_tri, const int32_t* tri, int64_t n_bedges, const int32_t* bedge_nodes,
+                      const int32_t* bedge_type, const int32_t* bedge_slot) {
+  int rc = check_ctx(c, false);
+  if (rc) return rc;
+  if (c->mesh) return fail(DGSWE_ESTATE, "mesh already uploaded");
+  if (n_bedges > 0 && !bedge_nodes) return fail(DGSWE_EINVAL, "null boundary edge array");
+  auto md = std::make_shared<MeshDev>();
+  std::string err;
+  if (build_mesh(n_nodes, xy, hb, fric, n_tri, tri, n_bedges, bedge_nodes, bedge_type, bedge_slot, md->host, err))
+    return fail(DGSWE_EINVAL, err);
+  md->real_size = c->rs;
+  md->p = c->prm.p;
+  md->limiter = c->prm.limiter;
+  rc = c->rs == 8 ? upload_mesh_arrays<double>(*md) : upload_mesh_arrays<float>(*md);
+  if (rc) return rc;
+  c->mesh = md;
+  return alloc_state(c);
+}
+
+int dgswe_share_mesh(dgswe_ctx* dst, const dgswe_ctx* src) {
+  int rc = check_ctx(dst, false);
+  if (rc) return rc;
+  rc = check_ctx(src, true);
+  if (rc) return rc;
+  if (dst->mesh) return fail(DGSWE_ESTATE, "mesh already uploaded");
+  if (dst->rs != src->rs || dst->prm.p != src->prm.p || dst->prm.limiter != src->prm.limiter)
+    return fail(DGSWE_EINVAL, "precision, p and limiter must match to share a mesh");
+  dst->mesh = src->mesh;
+  return alloc_state(dst);
+}
+
+int dgswe_set_initial_nodal(dgswe_ctx* c, const double* zeta, const double* qx, const double* qy) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (c->in_batch) return fail(DGSWE_ESTATE, "context is a member of a batch");
+  const HostMesh& h = c->mesh->host;
+  const int64_t E = h.E, NP = c->NP();
+  if (E > 0 && (!zeta || !qx || !qy)) return fail(DGSWE_EINVAL, "null state array");
+  for (int64_t n = 0; n < h.n_nodes; ++n)
+    if (!std::isfinite(zeta[n]) || !std::isfinite(qx[n]) || !std::isfinite(qy[n]))
+      return fail(DGSWE_EINVAL, "non-finite initial value at node " + std::to_string(n));
+  std::vector<double> w(size_t(3) * NP * E, 0.0);
+  const double* src[3] = {zeta, qx, qy};
+  for (int64_t i = 0; i < E; ++i) {
+    const int n0 = h.tri[i], n1 = h.tri[E + i], n2 = h.tri[2 * E + i];
+    for (int v = 0; v < 3; ++v) {
+      double m[3];
+      modal_from_vertex(src[v][n0], src[v][n1], src[v][n2], m);
+      for (int k = 0; k < 3; ++k) w[(v * NP + k) * E + i] = m[k];
+    }
+  }
+  rc = reset_scalars(c, 0.0);
+  if (rc) return rc;
+  rc = upload_state(c, w, c->Wt);
+  if (rc) return rc;
+  return post_initial(c, 1);
+}
+
+int dgswe_set_state(dgswe_ctx* c, int layout, const double* w, double t) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (c->in_batch) return fail(DGSWE_ESTATE, "context is a member of a batch");
+  if (layout != DGSWE_MODAL) return fail(DGSWE_EINVAL, "set_state takes DGSWE_MODAL");
+  if (!std::isfinite(t)) return fail(DGSWE_EINVAL, "non-finite time");
+  const HostMesh& h = c->mesh->host;
+  const int64_t E = h.E, NP = c->NP();
+  if (E > 0 && !w) return fail(DGSWE_EINVAL, "null state array");
+  std::vector<double> wi(size_t(3) * NP * E);
+  for (int64_t i = 0; i < E; ++i) {
+    const int64_t e = h.perm[i];
+    for (int v = 0; v < 3; ++v)
+      for (int m = 0; m < NP; ++m) {
+        const double x = w[(e * 3 + v) * NP + m];
+        if (!std::isfinite(x)) return fail(DGSWE_EINVAL, "non-finite state value");
+        wi[(v * NP + m) * E + i] = x;
+      }
+  }
+  rc = reset_scalars(c, t);
+  if (rc) return rc;
+  rc = upload_state(c, wi, c->W[0]);
+  if (rc) return rc;
+  return post_initial(c, 2);
+}
+
+int dgswe_set_rain_nodal(dgswe_ctx* c, const double* r) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  const HostMesh& h = c->mesh->host;
+  if (h.n_nodes > 0 && !r) return fail(DGSWE_EINVAL, "null rain array");
+  std::vector<double> v(r, r + h.n_nodes);
+  for (double x : v)
+    if (!std::isfinite(x)) return fail(DGSWE_EINVAL, "non-finite rain rate");
+  HIPCHK(hipStreamSynchronize(c->stream));
+  if (v.empty()) v.push_back(0.0);
+  HIPCHK(upload(c->rnode, v));
+  c->fo.rain_kind = RAIN_CONST;
+  rc = push_member(c);
+  if (rc) return rc;
+  if (c->rs == 8)
+    HIPCHK(launch_rain<double>(c->memb.as<Member<double>>(), c->tiles.as<Tile>(), c->n_tiles, 1, c->rnode.as<double>(), c->stream));
+  else
+    HIPCHK(launch_rain<float>(c->memb.as<Member<float>>(), c->tiles.as<Tile>(), c->n_tiles, 1, c->rnode.as<double>(), c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return refresh_forcing(c);
+}
+
+int dgswe_clear_rain(dgswe_ctx* c) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  HIPCHK(hipStreamSynchronize(c->stream));
+  if (c->R.bytes) HIPCHK(hipMemset(c->R.p, 0, c->R.bytes));
+  HIPCHK(hipMemset(c->part.as<double>() + size_t(P_RAIN) * std::max(c->n_tiles, 1), 0,
+                   sizeof(double) * std::max(c->n_tiles, 1)));
+  c->fo.rain_kind = RAIN_CONST;
+  return refresh_forcing(c);
+}
+
+int dgswe_set_rain_parametric(dgswe_ctx* c, int32_t n_rec, const double* rec) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (n_rec < 1 || !rec) return fail(DGSWE_EINVAL, "need at least one storm record");
+  for (int i = 0; i < 7 * n_rec; ++i)
+    if (!std::isfinite(rec[i])) return fail(DGSWE_EINVAL, "non-finite storm record");
+  for (int i = 0; i < n_rec; ++i) {
+    if (!(rec[7 * i + 5] > 0.0) || !(rec[7 * i + 6] > 0.0)) return fail(DGSWE_EINVAL, "r_m and r_e must be positive");
+    if (i > 0 && !(rec[7 * i] > rec[7 * (i - 1)])) return fail(DGSWE_EINVAL, "storm record times must increase");
+  }
+  HIPCHK(hipStreamSynchronize(c->stream));
+  HIPCHK(upload(c->storm, std::vector<double>(rec, rec + 7 * n_rec)));
+  c->fo.rain_kind = RAIN_PARAM;
+  c->fo.n_storm = n_rec;
+  c->fo.storm = c->storm.as<double>();
+  return refresh_forcing(c);
+}
+
+int dgswe_set_rain_gridded(dgswe_ctx* c, double x0, double y0, double dx, double dy, int32_t nx, int32_t ny,
+                           int32_t n_rec, const double* t_rec, const float* vals) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (nx < 2 || ny < 2 || n_rec < 1 || !t_rec || !vals) return fail(DGSWE_EINVAL, "lattice needs nx, ny >= 2 and a record");
+  if (!(dx > 0.0) || !(dy > 0.0) || !std::isfinite(x0) || !std::isfinite(y0)) return fail(DGSWE_EINVAL, "bad lattice geometry");
+  for (int i = 1; i < n_rec; ++i)
+    if (!(t_rec[i] > t_rec[i - 1])) return fail(DGSWE_EINVAL, "record times must increase");
+  const size_t nv = size_t(n_rec) * nx * ny;
+  for (size_t i = 0; i < nv; ++i)
+    if (!std::isfinite(vals[i])) return fail(DGSWE_EINVAL, "non-finite rain value");
+  HIPCHK(hipStreamSynchronize(c->stream));
+  HIPCHK(upload(c->gt, std::vector<double>(t_rec, t_rec + n_rec)));
+  HIPCHK(upload(c->gvals, std::vector<float>(vals, vals + nv)));
+  c->fo.rain_kind = RAIN_GRID;
+  c->fo.gnx = nx;
+  c->fo.gny = ny;
+  c->fo.gnrec = n_rec;
+  c->fo.gx0 = x0;
+  c->fo.gy0 = y0;
+  c->fo.gdx = dx;
+  c->fo.gdy = dy;
+  c->fo.gt = c->gt.as<double>();
+  c->fo.gvals = c->gvals.as<float>();
+  return refresh_forcing(c);
+}
+
+int dgswe_set_ocean_tide(dgswe_ctx* c, int32_t slot, double mean, int32_t n_const, const double* apt) {
+  int rc = check_ctx(c, false);
+  if (rc) return rc;
+  if (slot < 0 || slot >= MAX_SLOTS) return fail(DGSWE_EINVAL, "slot out of range");
+  if (n_const < 0 || (n_const > 0 && !apt)) return fail(DGSWE_EINVAL, "bad constituent array");
+  if (!std::isfinite(mean)) return fail(DGSWE_EINVAL, "non-finite mean level");
+  for (int i = 0; i < 3 * n_const; ++i)
+    if (!std::isfinite(apt[i])) return fail(DGSWE_EINVAL, "non-finite constituent");
+  for (int i = 0; i < n_const; ++i)
+    if (apt[3 * i + 1] == 0.0) return fail(DGSWE_EINVAL, "zero tidal period");
+  c->tide_mean[slot] = mean;
+  c->tide_rows[slot].assign(apt, apt + 3 * n_const);
+  return upload_boundary_forcing(c);
+}
+
+int dgswe_set_river_flux(dgswe_ctx* c, int32_t slot, int32_t n, const double* t, const double* q) {
+  int rc = check_ctx(c, false);
+  if (rc) return rc;
+  if (slot < 0 || slot >= MAX_SLOTS) return fail(DGSWE_EINVAL, "slot out of range");
+  if (n < 1 || !t || !q) return fail(DGSWE_EINVAL, "need at least one river sample");
+  std::vector<double> rows;
+  for (int i = 0; i < n; ++i) {
+    if (!std::isfinite(t[i]) || !std::isfinite(q[i])) return fail(DGSWE_EINVAL, "non-finite river sample");
+    if (i > 0 && !(t[i] > t[i - 1])) return fail(DGSWE_EINVAL, "river sample times must increase");
+    rows.push_back(t[i]);
+    rows.push_back(q[i]);
+  }
+  c->riv_rows[slot] = rows;
+  return upload_boundary_forcing(c);
+}
+
+static int build_graph(dgswe_ctx* c) {
+  if (c->graph) {
+    (void)hipGraphExecDestroy(c->graph);
+    c->graph = nullptr;
+  }
+  hipGraph_t g = nullptr;
+  HIPCHK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+  const bool prof = c->prof;
+  c->prof = false;
+  int rc = ctx_enqueue_step(c);
+  c->prof = prof;
+  hipError_t e = hipStreamEndCapture(c->stream, &g);
+  if (rc) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess) return fail(DGSWE_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+  e = hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) return fail(DGSWE_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+  c->graph_dirty = false;
+  return DGSWE_OK;
+}
+
+int dgswe_step(dgswe_ctx* c, int64_t n) {
+  int rc = check_ctx(c, true, true);
+  if (rc) return rc;
+  if (c->in_batch) return fail(DGSWE_ESTATE, "context is a member of a batch");
+  if (n < 0) return fail(DGSWE_EINVAL, "negative step count");
+  const bool use_graph = !c->prof && n >= 2;
+  if (use_graph && c->graph_dirty) {
+    rc = build_graph(c);
+    if (rc) return rc;
+  }
+  for (int64_t i = 0; i < n; ++i) {
+    if (use_graph) {
+      HIPCHK(hipGraphLaunch(c->graph, c->stream));
+    } else {
+      rc = ctx_enqueue_step(c);
+      if (rc) return rc;
+    }
+  }
+  return DGSWE_OK;
+}
+
+int dgswe_sync(dgswe_ctx* c) {
+  int rc = check_ctx(c, false);
+  if (rc) return rc;
+  Scalars s;
+  rc = read_scalars(c, s);
+  if (rc) return rc;
+  if (s.error) return fail(DGSWE_ENONFINITE, "the volume or the time step became non-finite");
+  return DGSWE_OK;
+}
+
+int dgswe_read_state(dgswe_ctx* c, int layout, double* out) {
+  int rc = check_ctx(c, true, true);
+  if (rc) return rc;
+  if (layout != DGSWE_MODAL && layout != DGSWE_VERTEX) return fail(DGSWE_EINVAL, "bad layout");
+  const HostMesh& h = c->mesh->host;
+  const int64_t E = h.E, NP = c->NP();
+  if (E > 0 && !out) return fail(DGSWE_EINVAL, "null output array");
+  if (c->batch_stream) HIPCHK(hipStreamSynchronize(c->batch_stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  std::vector<double> w(size_t(3) * NP * E);
+  if (c->rs == 8) {
+    if (E) HIPCHK(hipMemcpy(w.data(), c->W[0].p, w.size() * 8, hipMemcpyDeviceToHost));
+  } else {
+    std::vector<float> f(w.size());
+    if (E) HIPCHK(hipMemcpy(f.data(), c->W[0].p, f.size() * 4, hipMemcpyDeviceToHost));
+    std::copy(f.begin(), f.end(), w.begin());
+  }
+  for (int64_t i = 0; i < E; ++i) {
+    const int64_t e = h.perm[i];
+    for (int v = 0; v < 3; ++v) {
+      if (layout == DGSWE_MODAL) {
+        for (int m = 0; m < NP; ++m) out[(e * 3 + v) * NP + m] = w[(v * NP + m) * E + i];
+      } else {
+        for (int k = 0; k < 3; ++k) {
+          double s = 0.0;
+          for (int m = 0; m < NP; ++m)
+            s += dg_vertex_basis(k, m) * w[(v * NP + m) * E + i];
+          out[(e * 3 + v) * 3 + k] = s;
+        }
+      }
+    }
+  }
+  return DGSWE_OK;
+}
+
+int dgswe_read_flags(dgswe_ctx* c, uint8_t* out) {
+  int rc = check_ctx(c, true, true);
+  if (rc) return rc;
+  const HostMesh& h = c->mesh->host;
+  if (h.E > 0 && !out) return fail(DGSWE_EINVAL, "null output array");
+  if (c->batch_stream) HIPCHK(hipStreamSynchronize(c->batch_stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  std::vector<uint8_t> f(h.E);
+  if (h.E) HIPCHK(hipMemcpy(f.data(), c->F[0].p, h.E, hipMemcpyDeviceToHost));
+  for (int64_t i = 0; i < h.E; ++i) out[h.perm[i]] = f[i] & 1;
+  return DGSWE_OK;
+}
+
+int dgswe_mass_totals(dgswe_ctx* c, dgswe_mass* out) {
+  int rc = check_ctx(c, false);
+  if (rc) return rc;
+  if (!out) return fail(DGSWE_EINVAL, "null output");
+  if (c->prof) harvest(c);
+  Scalars s;
+  rc = read_scalars(c, s);
+  if (rc) return rc;
+  out->t = s.t;
+  out->dt_last = s.dt_last;
+  out->dt_next = s.dt;
+  out->volume = s.volume;
+  out->rain_in = s.rain_in;
+  out->bnd_in = s.bnd_in;
+  out->bnd_out = s.bnd_out;
+  out->steps = s.steps;
+  out->n_dry = s.n_dry;
+  if (s.error) return fail(DGSWE_ENONFINITE, "the volume or the time step became non-finite");
+  return DGSWE_OK;
+}
+
+int dgswe_info(const dgswe_ctx* c, int64_t* n_tri, int64_t* n_nodes, int64_t* n_edges, int64_t* n_flipped) {
+  int rc = check_ctx(c, true);
+  if (rc) return rc;
+  const HostMesh& h = c->mesh->host;
+  if (n_tri) *n_tri = h.E;
+  if (n_nodes) *n_nodes = h.n_nodes;
+  if (n_edges) *n_edges = h.n_edges;
+  if (n_flipped) *n_flipped = h.n_flipped;
+  return DGSWE_OK;
+}
+
+int64_t dgswe_footprint_bytes(const dgswe_params* p, int64_t n_tri, int64_t n_nodes) {
+  if (check_params(p)) return DGSWE_EINVAL;
+  if (n_tri < 0 || n_nodes < 0) return fail(DGSWE_EINVAL, "negative size");
+  return footprint(p, n_tri, n_nodes);
+}
+
+int dgswe_set_profiling(dgswe_ctx* c, int on) {
+  int rc = check_ctx(c, false);
+  if (rc) return rc;
+  if (c->stream) HIPCHK(hipStreamSynchronize(c->stream));
+  harvest(c);
+  for (int k = 0; k < K_N; ++k) { c->k_launches[k] = 0; c->k_ms[k] = 0.0; }
+  c->prof = on != 0;
+  return DGSWE_OK;
+}
+
+int dgswe_kernel_stats(dgswe_ctx* c, const char* kernel, int64_t* launches, double* total_ms) {
+  int rc = check_ctx(c, false);
+  if (rc) return rc;
+  if (!kernel) return fail(DGSWE_EINVAL, "null kernel name");
+  harvest(c);
+  for (int k = 0; k < K_N; ++k)
+    if (std::strcmp(kernel, kname[k]) == 0) {
+      if (launches) *launches = c->k_launches[k];
+      if (total_ms) *total_ms = c->k_ms[k];
+      return DGSWE_OK;
+    }
+  return fail(DGSWE_EINVAL, std::string("unknown kernel name ") + kernel);
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ batches
+namespace {
+
+template <typename Real>
+int batch_rebuild_t(dgswe_batch* b) {
+  std::vector<Member<Real>> ms;
+  std::map<std::tuple<int, int, int, int>, int> gi;
+  b->groups.clear();
+  for (size_t i = 0; i < b->slots.size(); ++i) {
+    const auto& sl = b->slots[i];
+    if (!sl.live) continue;
+    const int idx = int(ms.size());
+    ms.push_back(member_struct<Real>(sl.ctx));
+    const dgswe_params& p = sl.ctx->prm;
+    auto key = std::make_tuple(p.p, p.flux, p.limiter, p.rk_stages);
+    auto it = gi.find(key);
+    if (it == gi.end()) {
+      dgswe_batch::Group g;
+      g.p = p.p;
+      g.flux = p.flux;
+      g.limiter = p.limiter;
+      make_rk(p.rk_stages, g.rk);
+      b->groups.push_back(std::move(g));
+      it = gi.emplace(key, int(b->groups.size()) - 1).first;
+    }
+    b->groups[it->second].members.push_back(idx);
+    if (sl.ctx->fo.rain_kind != RAIN_CONST) b->groups[it->second].has_rain = true;
+  }
+  if (ms.empty()) ms.push_back(Member<Real>{});
+  HIPCHK(upload(b->memb, ms));
+  for (auto& g : b->groups) {
+    std::vector<Tile> tl;
+    for (int m : g.members) {
+      const int nt = ms[m].n_tiles;
+      for (int t = 0; t < nt; ++t) tl.push_back({m, t});
+    }
+    g.n_tiles = int(tl.size());
+    if (tl.empty()) tl.push_back({0, 0});
+    HIPCHK(upload(g.tiles, tl));
+    HIPCHK(upload(g.ids, g.members));
+  }
+  b->dirty = false;
+  return DGSWE_OK;
+}
+
+int batch_rebuild(dgswe_batch* b) {
+  HIPCHK(hipStreamSynchronize(b->stream));
+  return b->prm.precision == DGSWE_FP32 ? batch_rebuild_t<float>(b) : batch_rebuild_t<double>(b);
+}
+
+int64_t batch_footprint(const dgswe_batch* b) {
+  int64_t f = 0;
+  for (const auto& sl : b->slots)
+    if (sl.live) f += footprint(&sl.ctx->prm, sl.ctx->E(), sl.ctx->mesh ? sl.ctx->mesh->host.n_nodes : 0);
+  return f;
+}
+
+}  // namespace
+
+extern "C" {
+
+int dgswe_batch_create(const dgswe_params* params, void* hip_stream, int64_t budget_bytes, dgswe_batch** out) {
+  if (!out) return fail(DGSWE_EINVAL, "null output pointer");
+  *out = nullptr;
+  int rc = check_params(params);
+  if (rc) return rc;
+  auto b = std::make_unique<dgswe_batch>();
+  b->prm = *params;
+  b->budget = budget_bytes;
+  if (hip_stream) {
+    b->stream = static_cast<hipStream_t>(hip_stream);
+  } else {
+    HIPCHK(hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking));
+    b->own_stream = true;
+  }
+  *out = b.release();
+  return DGSWE_OK;
+}
+
+int dgswe_batch_destroy(dgswe_batch* b) {
+  if (!b) return DGSWE_OK;
+  (void)hipStreamSynchronize(b->stream);
+  for (auto& sl : b->slots)
+    if (sl.live) {
+      sl.ctx->in_batch = false;
+      sl.ctx->batch_stream = nullptr;
+    }
+  delete b;
+  return DGSWE_OK;
+}
+
+int dgswe_batch_add(dgswe_batch* b, dgswe_ctx* c, int64_t n_steps, int32_t* slot) {
+  if (!b) return fail(DGSWE_EINVAL, "null batch");
+  int rc = check_ctx(c, true, true);
+  if (rc) return rc;
+  if (c->in_batch) return fail(DGSWE_ESTATE, "context already belongs to a batch");
+  if (n_steps < 0) return fail(DGSWE_EINVAL, "negative step count");
+  if (c->prm.precision != b->prm.precision) return fail(DGSWE_EINVAL, "member precision differs from the batch");
+  const int64_t need = footprint(&c->prm, c->E(), c->mesh->host.n_nodes);
+  if (b->budget > 0 && batch_footprint(b) + need > b->budget)
+    return fail(DGSWE_EBUDGET, "member footprint exceeds the remaining batch budget");
+  Scalars s;
+  rc = read_scalars(c, s);
+  if (rc) return rc;
+  if (s.error) return fail(DGSWE_ENONFINITE, "member has a latched error");
+  s.target = s.steps + n_steps;
+  s.active = n_steps > 0 ? 1 : 0;
+  rc = write_scalars(c, s);
+  if (rc) return rc;
+  int id = -1;
+  for (size_t i = 0; i < b->slots.size(); ++i)
+    if (!b->slots[i].live) { id = int(i); break; }
+  if (id < 0) {
+    id = int(b->slots.size());
+    b->slots.push_back({});
+  }
+  b->slots[id] = {c, s.target, true};
+  c->in_batch = true;
+  c->batch_stream = b->stream;
+  b->dirty = true;
+  if (slot) *slot = id;
+  return DGSWE_OK;
+}
+
+int dgswe_batch_step(dgswe_batch* b, int64_t max_steps) {
+  if (!b) return fail(DGSWE_EINVAL, "null batch");
+  if (max_steps < 0) return fail(DGSWE_EINVAL, "negative step count");
+  if (b->dirty) {
+    int rc = batch_rebuild(b);
+    if (rc) return rc;
+  }
+  for (int64_t i = 0; i < max_steps; ++i) {
+    for (auto& g : b->groups) {
+      int rc;
+      if (b->prm.precision == DGSWE_FP32)
+        rc = enqueue_step_group<float>(b->memb.as<Member<float>>(), g.tiles.as<Tile>(), g.n_tiles, g.ids.as<int>(),
+                                       int(g.members.size()), g.p, g.flux, g.limiter, g.rk, g.has_rain, b->stream,
+                                       nullptr);
+      else
+        rc = enqueue_step_group<double>(b->memb.as<Member<double>>(), g.tiles.as<Tile>(), g.n_tiles, g.ids.as<int>(),
+                                        int(g.members.size()), g.p, g.flux, g.limiter, g.rk, g.has_rain, b->stream,
+                                        nullptr);
+      if (rc) return rc;
+    }
+  }
+  return DGSWE_OK;
+}
+
+int dgswe_batch_poll(dgswe_batch* b, int32_t* done_slots, int32_t cap, int32_t* n_done) {
+  if (!b || !n_done) return fail(DGSWE_EINVAL, "null argument");
+  HIPCHK(hipStreamSynchronize(b->stream));
+  int32_t n = 0;
+  for (size_t i = 0; i < b->slots.size(); ++i) {
+    const auto& sl = b->slots[i];
+    if (!sl.live) continue;
+    Scalars s;
+    HIPCHK(hipMemcpy(&s, sl.ctx->sc.p, sizeof s, hipMemcpyDeviceToHost));
+    if (!s.active) {
+      if (done_slots && n < cap) done_slots[n] = int32_t(i);
+      ++n;
+    }
+  }
+  *n_done = n;
+  return DGSWE_OK;
+}
+
+int dgswe_batch_retire(dgswe_batch* b, int32_t slot) {
+  if (!b) return fail(DGSWE_EINVAL, "null batch");
+  if (slot < 0 || size_t(slot) >= b->slots.size() || !b->slots[slot].live) return fail(DGSWE_EINVAL, "no such slot");
+  HIPCHK(hipStreamSynchronize(b->stream));
+  dgswe_ctx* c = b->slots[slot].ctx;
+  b->slots[slot] = {};
+  c->in_batch = false;
+  c->batch_stream = nullptr;
+  Scalars s;
+  int rc = read_scalars(c, s);
+  if (rc) return rc;
+  s.target = std::numeric_limits<long long>::max();
+  s.active = s.error ? 0 : 1;
+  rc = write_scalars(c, s);
+  if (rc) return rc;
+  b->dirty = true;
+  return DGSWE_OK;
+}
+
+int dgswe_batch_info(const dgswe_batch* b, int32_t* n_members, int64_t* fp) {
+  if (!b) return fail(DGSWE_EINVAL, "null batch");
+  int32_t n = 0;
+  for (const auto& sl : b->slots) n += sl.live ? 1 : 0;
+  if (n_members) *n_members = n;
+  if (fp) *fp = batch_footprint(b);
+  return DGSWE_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,204 @@
+// Device-side building blocks shared by the HIP kernels of the DG solver:
+// Dubiner basis tables, quadrature rules, numerical fluxes and friction.
+//
+// Reference triangle v0 = (-1,-1), v1 = (1,-1), v2 = (-1,1); local edge k
+// runs v_k -> v_{k+1}.  Dubiner modes (Sec. 2.2, Eq. dubiner) in the order
+// (0,0),(1,0),(0,1),(2,0),(1,1),(0,2), written as explicit polynomials with
+// x = r + (1+s)/2 and b = (1-s)/2 (the collapsed Legendre factor
+// P_i(a) b^i is a polynomial in x and b):
+//   phi00 = 1                  phi10 = x              phi01 = (1 + 3s)/2
+//   phi20 = (3x^2 - b^2)/2     phi11 = x (5s + 3)/2   phi02 = (5s^2 + 2s - 1)/2
+// Diagonal mass int phi^2 = 2/((2i+1)(i+j+1)) = 2, 1/3, 1, 2/15, 2/9, 2/3.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define DG_DEV __device__ __forceinline__
+#define DG_HD __host__ __device__ constexpr
+
+namespace dg {
+
+// ------------------------------------------------------------------ basis
+DG_HD double phi_(int m, double r, double s) {
+  const double x = r + 0.5 * (1.0 + s), b = 0.5 * (1.0 - s);
+  switch (m) {
+    case 0: return 1.0;
+    case 1: return x;
+    case 2: return 0.5 * (1.0 + 3.0 * s);
+    case 3: return 0.5 * (3.0 * x * x - b * b);
+    case 4: return 0.5 * x * (5.0 * s + 3.0);
+    default: return 0.5 * (5.0 * s * s + 2.0 * s - 1.0);
+  }
+}
+DG_HD double dphi_dr_(int m, double r, double s) {
+  const double x = r + 0.5 * (1.0 + s);
+  switch (m) {
+    case 0: return 0.0;
+    case 1: return 1.0;
+    case 2: return 0.0;
+    case 3: return 3.0 * x;
+    case 4: return 0.5 * (5.0 * s + 3.0);
+    default: return 0.0;
+  }
+}
+DG_HD double dphi_ds_(int m, double r, double s) {
+  const double x = r + 0.5 * (1.0 + s), b = 0.5 * (1.0 - s);
+  switch (m) {
+    case 0: return 0.0;
+    case 1: return 0.5;
+    case 2: return 1.5;
+    case 3: return 0.5 * (3.0 * x + b);
+    case 4: return 0.25 * (5.0 * s + 3.0) + 2.5 * x;
+    default: return 5.0 * s + 1.0;
+  }
+}
+DG_HD double mass_(int m) {
+  return m == 0 ? 2.0 : m == 1 ? 1.0 / 3.0 : m == 2 ? 1.0 : m == 3 ? 2.0 / 15.0 : m == 4 ? 2.0 / 9.0 : 2.0 / 3.0;
+}
+DG_HD double vr_(int i) { return i == 1 ? 1.0 : -1.0; }
+DG_HD double vs_(int i) { return i == 2 ? 1.0 : -1.0; }
+
+// Gauss-Legendre nodes/weights on [-1,1] (p+1 points, ascending).
+DG_HD double gl_t(int P, int g) {
+  return P == 1 ? (g == 0 ? -0.57735026918962576451 : 0.57735026918962576451)
+                : (g == 0 ? -0.77459666924148337704 : g == 1 ? 0.0 : 0.77459666924148337704);
+}
+DG_HD double gl_w(int P, int g) {
+  return P == 1 ? 1.0 : (g == 1 ? 8.0 / 9.0 : 5.0 / 9.0);
+}
+
+template <int P> struct Tab;
+
+// p = 1: 3-point interior area rule (barycentric 2/3, 1/6, 1/6; weight 2/3)
+template <> struct Tab<1> {
+  static constexpr int NP = 3, NQ = 3, NG = 2;
+  DG_HD static double qr(int q) { return q == 1 ? 1.0 / 3.0 : -2.0 / 3.0; }
+  DG_HD static double qs(int q) { return q == 2 ? 1.0 / 3.0 : -2.0 / 3.0; }
+  DG_HD static double qw(int) { return 2.0 / 3.0; }
+};
+// p = 2: collapsed 3 x 3 Gauss-Legendre (b outer, a inner)
+template <> struct Tab<2> {
+  static constexpr int NP = 6, NQ = 9, NG = 3;
+  DG_HD static double qa(int q) { return gl_t(2, q % 3); }
+  DG_HD static double qb(int q) { return gl_t(2, q / 3); }
+  DG_HD static double qr(int q) { return 0.5 * (1.0 + qa(q)) * (1.0 - qb(q)) - 1.0; }
+  DG_HD static double qs(int q) { return qb(q); }
+  DG_HD static double qw(int q) { return gl_w(2, q % 3) * gl_w(2, q / 3) * 0.5 * (1.0 - qb(q)); }
+};
+
+// barycentric weights of a reference point
+DG_HD double lam_(int i, double r, double s) {
+  return i == 0 ? -0.5 * (r + s) : i == 1 ? 0.5 * (1.0 + r) : 0.5 * (1.0 + s);
+}
+// reference point on local edge k at parameter t
+DG_HD double er_(int k, double t) { return 0.5 * (1.0 - t) * vr_(k) + 0.5 * (1.0 + t) * vr_((k + 1) % 3); }
+DG_HD double es_(int k, double t) { return 0.5 * (1.0 - t) * vs_(k) + 0.5 * (1.0 + t) * vs_((k + 1) % 3); }
+// edge-midpoint reference coordinates
+DG_HD double mr_(int k) { return 0.5 * (vr_(k) + vr_((k + 1) % 3)); }
+DG_HD double ms_(int k) { return 0.5 * (vs_(k) + vs_((k + 1) % 3)); }
+
+// 1D Lagrange weights at parameter t for edge nodes at t = -1, (0,) +1.
+DG_HD double lag_(int P, int j, double t) {
+  if (P == 1) return j == 0 ? 0.5 * (1.0 - t) : 0.5 * (1.0 + t);
+  return j == 0 ? 0.5 * t * (t - 1.0) : j == 1 ? 1.0 - t * t : 0.5 * t * (t + 1.0);
+}
+
+// ------------------------------------------------------------- arithmetic
+template <typename R> DG_DEV R rcp(R x);
+template <> DG_DEV double rcp<double>(double x) { return 1.0 / x; }
+template <> DG_DEV float rcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+template <typename R> DG_DEV R dsqrt(R x);
+template <> DG_DEV double dsqrt<double>(double x) { return __builtin_sqrt(x); }
+template <> DG_DEV float dsqrt<float>(float x) { return __builtin_amdgcn_sqrtf(x); }
+// H^(4/3) = H * cbrt(H)
+template <typename R> DG_DEV R pow43(R x);
+template <> DG_DEV double pow43<double>(double x) { return x * cbrt(x); }
+template <> DG_DEV float pow43<float>(float x) {
+  return __builtin_amdgcn_exp2f(1.3333333333333333f * __builtin_amdgcn_logf(x));
+}
+template <typename R> DG_DEV R dmax(R a, R b) { return a > b ? a : b; }
+template <typename R> DG_DEV R dmin(R a, R b) { return a < b ? a : b; }
+template <typename R> DG_DEV R dabs(R a) { return a < R(0) ? -a : a; }
+
+// -------------------------------------------------------------- fluxes
+// State w = (zeta, qx, qy); H = zeta + hb; velocities q / max(H, H0);
+// pressure g/2 (H^2 - hb^2) = g/2 zeta (zeta + 2 hb) (Eq. SWE).
+template <typename R> struct W3 { R z, x, y; };
+
+template <typename R>
+DG_DEV void flux_normal(const W3<R>& w, R hb, R nx, R ny, R g, R H0, R& f0, R& f1, R& f2) {
+  const R Hs = dmax(w.z + hb, H0);
+  const R qn = w.x * nx + w.y * ny;
+  const R un = qn * rcp(Hs);
+  const R P = R(0.5) * g * w.z * (w.z + R(2) * hb);
+  f0 = qn;
+  f1 = w.x * un + P * nx;
+  f2 = w.y * un + P * ny;
+}
+
+// Local Lax-Friedrichs: (F(a)+F(b))/2 - lam/2 (b - a), lam the larger of
+// |u.n| + sqrt(g H) on the two sides.
+template <typename R>
+DG_DEV void flux_llf(const W3<R>& a, const W3<R>& b, R hb, R nx, R ny, R g, R H0, R* F) {
+  R fa0, fa1, fa2, fb0, fb1, fb2;
+  flux_normal(a, hb, nx, ny, g, H0, fa0, fa1, fa2);
+  flux_normal(b, hb, nx, ny, g, H0, fb0, fb1, fb2);
+  const R Ha = a.z + hb, Hb = b.z + hb;
+  const R ua = (a.x * nx + a.y * ny) * rcp(dmax(Ha, H0));
+  const R ub = (b.x * nx + b.y * ny) * rcp(dmax(Hb, H0));
+  const R la = dabs(ua) + dsqrt(g * dmax(Ha, R(0)));
+  const R lb = dabs(ub) + dsqrt(g * dmax(Hb, R(0)));
+  const R lam = dmax(la, lb);
+  F[0] = R(0.5) * (fa0 + fb0) - R(0.5) * lam * (b.z - a.z);
+  F[1] = R(0.5) * (fa1 + fb1) - R(0.5) * lam * (b.x - a.x);
+  F[2] = R(0.5) * (fa2 + fb2) - R(0.5) * lam * (b.y - a.y);
+}
+
+// Roe: linearisation about the Roe average in the frame (n, t):
+// waves u~n - c~, u~n, u~n + c~ with c~ = sqrt(g (Ha + Hb)/2); right
+// eigenvectors (1, u~n - c~, u~t), (0, 0, 1), (1, u~n + c~, u~t); with a
+// continuous bed the depth jump equals the elevation jump.  No entropy fix.
+template <typename R>
+DG_DEV void flux_roe(const W3<R>& a, const W3<R>& b, R hb, R nx, R ny, R g, R H0, R* F) {
+  R fa0, fa1, fa2, fb0, fb1, fb2;
+  flux_normal(a, hb, nx, ny, g, H0, fa0, fa1, fa2);
+  flux_normal(b, hb, nx, ny, g, H0, fb0, fb1, fb2);
+  const R Ha = dmax(a.z + hb, H0), Hb = dmax(b.z + hb, H0);
+  const R qna = a.x * nx + a.y * ny, qta = -a.x * ny + a.y * nx;
+  const R qnb = b.x * nx + b.y * ny, qtb = -b.x * ny + b.y * nx;
+  const R sa = dsqrt(Ha), sb = dsqrt(Hb);
+  const R isum = rcp(sa + sb);
+  const R un = (sa * (qna * rcp(Ha)) + sb * (qnb * rcp(Hb))) * isum;
+  const R ut = (sa * (qta * rcp(Ha)) + sb * (qtb * rcp(Hb))) * isum;
+  const R c = dsqrt(R(0.5) * g * (Ha + Hb));
+  const R i2c = rcp(R(2) * c);
+  const R dH = b.z - a.z, dqn = qnb - qna, dqt = qtb - qta;
+  const R a1 = ((un + c) * dH - dqn) * i2c;
+  const R a3 = (dqn - (un - c) * dH) * i2c;
+  const R a2 = dqt - ut * dH;
+  const R l1 = dabs(un - c) * a1, l2 = dabs(un) * a2, l3 = dabs(un + c) * a3;
+  const R d0 = l1 + l3;
+  const R dn = l1 * (un - c) + l3 * (un + c);
+  const R dt = (l1 + l3) * ut + l2;
+  F[0] = R(0.5) * (fa0 + fb0) - R(0.5) * d0;
+  F[1] = R(0.5) * (fa1 + fb1) - R(0.5) * (dn * nx - dt * ny);
+  F[2] = R(0.5) * (fa2 + fb2) - R(0.5) * (dn * ny + dt * nx);
+}
+
+template <int FLUX, typename R>
+DG_DEV void num_flux(const W3<R>& a, const W3<R>& b, R hb, R nx, R ny, R g, R H0, R* F) {
+  if (FLUX == 0) flux_roe(a, b, hb, nx, ny, g, H0, F);
+  else flux_llf(a, b, hb, nx, ny, g, H0, F);
+}
+
+// Land boundary: the state against its mirror image (normal discharge
+// reversed): zero mass flux, hydrostatic pressure.
+template <int FLUX, typename R>
+DG_DEV void wall_flux(const W3<R>& a, R hb, R nx, R ny, R g, R H0, R* F) {
+  const R qn = a.x * nx + a.y * ny;
+  W3<R> m{a.z, a.x - R(2) * qn * nx, a.y - R(2) * qn * ny};
+  num_flux<FLUX>(a, m, hb, nx, ny, g, H0, F);
+}
+
+}  // namespace dg

@@ -1,0 +1,113 @@
+// Internal data layout of the DG solver (device structs and launchers).
+//
+// Element-major structure of arrays: every per-element quantity is an array
+// of length E in Hilbert-curve element order, so that the 64 lanes of a
+// wavefront read consecutive addresses and the neighbours they gather sit in
+// nearby cache lines.  The state of one buffer is 3 * Np arrays
+// W[(var * Np + mode) * E + e] for var in (zeta, qx, qy).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dg {
+
+constexpr int TILE = 256;          // elements per workgroup (4 wavefronts)
+constexpr int MAX_STAGES = 5;
+constexpr int MAX_SLOTS = 16;
+// per-tile FP64 partial sums: boundary out/in flux per stage, volume,
+// min(d/lambda), rain volume, dry count
+enum PartKind { P_OUT0 = 0, P_IN0 = MAX_STAGES, P_VOL = 2 * MAX_STAGES, P_MINR, P_RAIN, P_NDRY, NPART };
+enum RainKind { RAIN_CONST = 0, RAIN_PARAM = 1, RAIN_GRID = 2 };
+
+// Device-resident time/budget/forcing scalars of one member.  Written only
+// by the reduce kernel (the last launch of a step) and by the host between
+// steps, read by every other kernel.
+struct Scalars {
+  double t, dt, dt_last;
+  double volume, rain_in, bnd_in, bnd_out;
+  long long steps, n_dry, target;
+  int active, error;
+  double tide[MAX_STAGES][MAX_SLOTS];   // ocean level at each stage time
+  double river[MAX_STAGES][MAX_SLOTS];  // river normal flux at each stage time
+  double storm[6];                      // xc, yc, peak, T0, r_m, r_e at t^n
+  int gk0, gk1;                         // rain-lattice records around t^n
+  double gth;                           // weight of record gk1
+};
+
+struct Forcing {
+  int rain_kind;
+  int n_storm;                // records of (t, xc, yc, peak, T0, rm, re)
+  const double* storm;
+  int gnx, gny, gnrec;
+  double gx0, gy0, gdx, gdy;
+  const double* gt;           // [gnrec]
+  const float* gvals;         // [gnrec][gny][gnx]
+  unsigned ocean_mask, river_mask;
+  double tide_mean[MAX_SLOTS];
+  int tide_off[MAX_SLOTS], tide_cnt[MAX_SLOTS];   // triples in tide_c
+  int riv_off[MAX_SLOTS], riv_cnt[MAX_SLOTS];     // (t, q) pairs in riv_tq
+  const double* tide_c;
+  const double* riv_tq;
+};
+
+template <typename Real>
+struct Member {
+  int E, n_nodes, n_tiles, friction;
+  double H0, g, cfl, dt_fixed, dt_max;
+  // static mesh data (read-only, shareable between members)
+  const Real* ev;             // [6][E] edge vectors v1-v0, v2-v1, v0-v2 (x, y)
+  const Real* hbv;            // [3][E] bathymetry at the vertices
+  const Real* fric;           // [E]    element friction coefficient
+  const int* nbr;             // [3][E] neighbour id, or -1 - (type | slot << 2)
+  const uint8_t* nk;          // [E]    neighbours' local edge ids, 2 bits each
+  const Real* din;            // [E]    inscribed-circle diameter
+  const int* tri;             // [3][E] node ids
+  const double* nxy;          // [2][n_nodes] node coordinates
+  const Real* lima;           // [6][E] limiter weights (alpha_j, alpha_k) per midpoint
+  const uint8_t* limc;        // [E]    bit0: limitable; bit 1+i: second neighbour of midpoint i is i+2
+  // dynamic
+  Real* W[3];                 // state buffers
+  Real* Wt;                   // unlimited stage output (limiter on)
+  uint8_t* F[3];              // dry flags of the state in W[i] (bit 0)
+  uint8_t* fullwet;           // [E] every vertex depth > H0 (limiter on)
+  Real* R;                    // [E] element rain rate
+  double* part;               // [NPART][n_tiles]
+  Scalars* sc;
+  Forcing fo;
+};
+
+struct StageArgs {
+  int stage;                  // 0-based stage index
+  int last;                   // 1 on the last stage of a step
+  int in_buf, out_buf;        // state buffer indices (out_buf = -1: Wt)
+  int fin, fout;              // flag buffer indices
+  double a, b, gam;           // w_out = a w^n + b (w_in + gam dt L(w_in))
+};
+
+struct Tile { int member, tile; };
+
+struct RKInfo {
+  int n;
+  double w[MAX_STAGES];       // weight of each stage's boundary flux in w^{n+1}
+  double c[MAX_STAGES];       // stage times t^n + c_i dt
+};
+
+// launchers (kernels.hip)
+template <typename Real>
+hipError_t launch_stage(int P, int flux, int limiter, const Member<Real>* d_members, const Tile* d_tiles,
+                        int n_tiles, StageArgs a, hipStream_t s);
+template <typename Real>
+hipError_t launch_post(int P, int use_lim, const Member<Real>* d_members, const Tile* d_tiles, int n_tiles,
+                       StageArgs a, int init, hipStream_t s);
+template <typename Real>
+hipError_t launch_classify(int P, const Member<Real>* d_members, const Tile* d_tiles, int n_tiles,
+                           hipStream_t s);
+template <typename Real>
+hipError_t launch_rain(const Member<Real>* d_members, const Tile* d_tiles, int n_tiles, int nodal,
+                       const double* d_rnode, hipStream_t s);
+template <typename Real>
+hipError_t launch_reduce(const Member<Real>* d_members, const int* d_member_ids, int n_members, int init,
+                         const RKInfo& rk, hipStream_t s);
+
+}  // namespace dg
