@@ -37,6 +37,8 @@ class LoopSolver:
         self.hbn = [float(v) for v in hb]
         self.p, self.kind, self.fric_kind = p, flux, friction
         self.use_lim, self.H0, self.g = limiter, float(H0), float(g)
+        self.H_dry = self.H0 * (1.0 + 1e-3)
+        self.F_eps = 1e-3 * self.H0 * math.sqrt(self.g * self.H0)
         self.tides, self.rivers = dict(tides or {}), dict(rivers or {})
         self.T = basis.Tables(p)
         self.tri = []
@@ -176,10 +178,10 @@ class LoopSolver:
             return self._wall(a, hb, nx, ny)
         if not dry_me:          # me wet, neighbour dry
             F = _flux(self.kind, a, [b[0], 0.0, 0.0], hb, nx, ny, g, H0)
-            return F if F[0] > 0 else self._wall(a, hb, nx, ny)
+            return F if F[0] > self.F_eps else self._wall(a, hb, nx, ny)
         # me dry, neighbour wet: seen from the neighbour's side
         F = _flux(self.kind, b, [a[0], 0.0, 0.0], hb, -nx, -ny, g, H0)
-        return [-x for x in F] if F[0] > 0 else self._wall(a, hb, nx, ny)
+        return [-x for x in F] if F[0] > self.F_eps else self._wall(a, hb, nx, ny)
 
     # ------------------------------------------------------------------- post
     def post(self, w):
@@ -196,7 +198,7 @@ class LoopSolver:
                 for i in range(3):
                     Hv = sum(w[e][0][m] * T.phi_v[i][m] for m in range(T.np)) + hbv[i]
                     Hm = sum(w[e][0][m] * T.phi_m[i][m] for m in range(T.np)) + 0.5 * (hbv[i] + hbv[(i + 1) % 3])
-                    if Hv <= H0 or Hm <= H0:
+                    if Hv <= self.H_dry or Hm <= self.H_dry:
                         trunc = True
                 if trunc:
                     for v in range(3):
@@ -220,7 +222,7 @@ class LoopSolver:
                 z = [Hn[i] - hbv[i] for i in range(3)]
                 for m in range(3):
                     w[e][0][m] = sum(T.V1inv[m][i] * z[i] for i in range(3))
-            d = [Hn[i] <= H0 for i in range(3)]
+            d = [Hn[i] <= self.H_dry for i in range(3)]
             nd = sum(d)
             if nd:
                 for v in (1, 2):
@@ -240,7 +242,7 @@ class LoopSolver:
         full = []
         for e in range(self.E):
             hbv = [self.hbn[i] for i in self.tri[e]]
-            full.append(all(sum(w[e][0][m] * T.phi_v[i][m] for m in range(T.np)) + hbv[i] > H0 for i in range(3)))
+            full.append(all(sum(w[e][0][m] * T.phi_v[i][m] for m in range(T.np)) + hbv[i] > self.H_dry for i in range(3)))
         cen = [tuple(sum(P[i][d] for i in range(3)) / 3.0 for d in range(2)) for P, _, _, _ in self.geo]
         out = [[list(r) for r in we] for we in w]
         pinv = np.linalg.pinv(T.phi_m[:, 1:3])

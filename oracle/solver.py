@@ -51,6 +51,13 @@ Readings of silent or garbled points (also listed in the design notes):
     decided per Gauss point; boundary edges ignore the flags;
   * the limiter acts only where the element and its three neighbours have
     every vertex depth > H0 (no limiting across a wet/dry front);
+  * decision margins: the positive-depth operator itself puts vertices at
+    exactly H0, and at a front the mass flux between two such traces is pure
+    round-off, so the tests that follow it are ties.  Every "is this vertex
+    dry / wet" test uses H0 (1 + 1e-3), and a wet-dry edge exchanges water
+    only when the mass flux into the dry element exceeds
+    1e-3 H0 sqrt(g H0); both margins are far below anything physical and
+    above the round-off of FP64 and FP32 arithmetic;
   * p = 2 wet/dry: if any vertex or edge-midpoint depth is <= H0 the element
     is truncated to its linear part before the p = 1 operator;
   * p = 0 (only used to pin the scheme against a finite-volume code): no
@@ -124,6 +131,11 @@ class OracleSolver:
         self.use_limiter = bool(limiter)
         self.cfl, self.dt_fixed, self.dt_max = float(cfl), float(dt_fixed), float(dt_max)
         self.H0, self.g = float(H0), float(g)
+        # decision margins (see the module docstring): a vertex is dry when
+        # H <= H0 (1 + 1e-3); a wet-dry edge exchanges water only when its
+        # mass flux into the dry element exceeds 1e-3 H0 sqrt(g H0)
+        self.H_dry = self.H0 * (1.0 + 1e-3)
+        self.F_eps = 1e-3 * self.H0 * np.sqrt(self.g * self.H0)
         self.hbv = self.hb_nodes[self.tri]                                  # (E, 3)
         fr = np.asarray(fric, dtype=np.float64)[self.tri]
         self.fric_e = (fr[:, 0] + fr[:, 1] + fr[:, 2]) / 3.0
@@ -319,7 +331,7 @@ class OracleSolver:
             a = wl[:, m]
             b = np.stack([wr[0, m], np.zeros_like(wr[0, m]), np.zeros_like(wr[0, m])])
             Fm = physics.numerical_flux(kind, a, b, hb[m], nx[m], ny[m], g, H0)
-            into = Fm[0] > 0.0
+            into = Fm[0] > self.F_eps
             fL[:, m] = np.where(into, Fm, self._wall_flux(a, hb[m], nx[m], ny[m]))
             fR[:, m] = np.where(into, -Fm, self._wall_flux(wr[:, m], hb[m], -nx[m], -ny[m]))
         if np.any(mixRw):
@@ -327,7 +339,7 @@ class OracleSolver:
             b = wr[:, m]
             a = np.stack([wl[0, m], np.zeros_like(wl[0, m]), np.zeros_like(wl[0, m])])
             Fm = physics.numerical_flux(kind, a, b, hb[m], nx[m], ny[m], g, H0)
-            into = Fm[0] < 0.0
+            into = Fm[0] < -self.F_eps
             fL[:, m] = np.where(into, Fm, self._wall_flux(wl[:, m], hb[m], nx[m], ny[m]))
             fR[:, m] = np.where(into, -Fm, self._wall_flux(b, hb[m], -nx[m], -ny[m]))
         return fL, fR
@@ -347,7 +359,7 @@ class OracleSolver:
         if self.p == 0:
             return w[:, 0, 0] + self.hbar <= self.H0
         Hv = np.einsum("em,im->ei", w[:, 0, :], self.T.phi_v) + self.hbv
-        return np.all(Hv <= self.H0, axis=1)
+        return np.all(Hv <= self.H_dry, axis=1)
 
     def post(self, w):
         """Limiter (optional) -> depth operator -> discharge operator -> flags."""
@@ -357,19 +369,19 @@ class OracleSolver:
             return w, w[:, 0, 0] + self.hbar <= H0
         if self.use_limiter:
             Hv0 = np.einsum("em,im->ei", w[:, 0, :], T.phi_v) + self.hbv
-            full = np.all(Hv0 > H0, axis=1)
+            full = np.all(Hv0 > self.H_dry, axis=1)
             nb = self.G["nbr"]
             stencil_wet = full & np.all(np.where(nb >= 0, full[np.maximum(nb, 0)], False), axis=1)
             w = limmod.apply(w, self.G, self.stencil, T, stencil_wet)
         if self.p >= 2:
             Hv = np.einsum("em,im->ei", w[:, 0, :], T.phi_v) + self.hbv
             Hm = np.einsum("em,im->ei", w[:, 0, :], T.phi_m) + self.hb_m
-            trunc = np.any(Hv <= H0, axis=1) | np.any(Hm <= H0, axis=1)
+            trunc = np.any(Hv <= self.H_dry, axis=1) | np.any(Hm <= self.H_dry, axis=1)
             w[trunc, :, 3:] = 0.0
         vals = np.einsum("evm,im->evi", w, T.phi_v)                    # vertex values
         Hv = vals[:, 0] + self.hbv
         Hn, dchg = wetdry.depth_operator(Hv, H0)
-        dry = Hn <= H0
+        dry = Hn <= self.H_dry
         zn = Hn - self.hbv
         if np.any(dchg):
             w[dchg, 0, :3] = zn[dchg] @ T.V1inv.T
@@ -385,7 +397,7 @@ class OracleSolver:
             return self.dt_fixed
         vals = np.einsum("evm,im->evi", w, self.T.phi_v)
         Hv = vals[:, 0] + self.hbv
-        wet = Hv > self.H0
+        wet = Hv > self.H_dry
         Hs = np.where(wet, Hv, 1.0)
         lam = np.sqrt(vals[:, 1] ** 2 + vals[:, 2] ** 2) / Hs + np.sqrt(self.g * Hs)
         lam = np.where(wet, lam, 0.0).max(axis=1)

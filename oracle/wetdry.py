@@ -14,7 +14,10 @@ depth part
      H0), and give the largest what keeps the sum.
 A vertex is dry when its new depth is <= H0 (the paper says "less than";
 with a strict test case 3 would never leave a dry vertex and the partial
-discharge redistribution described next could not occur).
+discharge redistribution described next could not occur).  The solver
+applies this test with a margin of 1e-3 H0 (the depth part puts vertices at
+exactly H0, so later tests on them would otherwise be ties decided by
+round-off); the functions here take the dry mask from the caller.
 
 discharge part
   the discharge of dry vertices is removed and spread evenly over the wet
