@@ -61,16 +61,17 @@ def algorithmic_bytes(kernel, E, rs, p, a_nonzero, last, limiter):
     return E * b
 
 
-def run_precision(sc, precision, steps, warmup):
+def run_precision(sc, precision, steps, warmup, variant=1, events=True):
     from paper_2307_14302_amd import Solver
     import torch
 
     t0 = time.perf_counter()
     s = Solver.from_scenario(sc, precision=precision)
+    s.set_variant(variant)
     log(f"[{precision}] setup {time.perf_counter() - t0:.1f}s  E={s.n_tri}")
     s.step(warmup)
     s.sync()
-    s.profiling(True)
+    s.profiling(events)
     torch.cuda.synchronize()
     s.sync()
     t0 = time.perf_counter()
@@ -147,7 +148,10 @@ def main():
     ap.add_argument("--precision", choices=["both", "fp32", "fp64"], default="both")
     ap.add_argument("--N", type=int, default=708, help="quads per side (708 -> 1,002,528 triangles)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--variant", type=int, default=1, help="stage kernel: 0 per element, 1 per edge (default)")
     ap.add_argument("--calib-copy", action="store_true", help="also run a 1 GiB device copy (counter calibration)")
+    ap.add_argument("--no-events", action="store_true",
+                    help="no per-kernel HIP events in the timed region (steps replay a HIP graph)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (see the design notes on sharding); "
@@ -162,7 +166,7 @@ def main():
     prm = sc.params
     res = {}
     for prec in (["fp32", "fp64"] if args.precision == "both" else [args.precision]):
-        res[prec] = run_precision(sc, prec, args.steps, args.warmup)
+        res[prec] = run_precision(sc, prec, args.steps, args.warmup, args.variant, not args.no_events)
     if args.calib_copy:
         a = torch.empty(256 * 1024 * 1024, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)
@@ -180,6 +184,7 @@ def main():
         "config": {"workload": f"single basin, {r['E']} triangles (jittered {args.N}x{args.N} grid over 200 km), "
                                f"p=1, LLF, limiter on, parametric moving rain, wet/dry front, SSP-RK2 CFL 0.3",
                    "n_tri": r["E"], "p": prm["p"], "rk_stages": r["stages"], "precision": main_prec,
+                   "stage_variant": args.variant,
                    "parallelism": "single GPU"},
         "roofline": roofline(r, main_prec, prm["p"], prm["limiter"]),
     }

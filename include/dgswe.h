@@ -208,6 +208,15 @@ int64_t dgswe_footprint_bytes(const dgswe_params* params, int64_t n_tri, int64_t
 int dgswe_set_profiling(dgswe_ctx* ctx, int on);
 int dgswe_kernel_stats(dgswe_ctx* ctx, const char* kernel, int64_t* launches, double* total_ms);
 
+/* Kernel choices (same arithmetic, different work layout; results differ
+ * only by summation order).  DGSWE_TUNE_STAGE_VARIANT: 0 = every element
+ * evaluates its three edges; 1 (default) = the tile's point values are
+ * staged in LDS and each edge inside a tile is evaluated once.  EINVAL for
+ * unknown keys or values; ESTATE while the context is in a batch. */
+#define DGSWE_TUNE_STAGE_VARIANT 1
+int dgswe_set_tuning(dgswe_ctx* ctx, int key, int value);
+int dgswe_get_tuning(const dgswe_ctx* ctx, int key, int* value);
+
 /* ---------------------------------------------------------------- batches
  * A batch advances many contexts (ensemble members or serving requests)
  * together: each stage is one launch over the element tiles of every active

@@ -10,7 +10,7 @@ import ctypes as C
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libdgswe.so")
+LIB_PATH = os.environ.get("DGSWE_LIB") or os.path.join(_HERE, "libdgswe.so")
 
 DGSWE_OK, DGSWE_EINVAL, DGSWE_ENOMEM, DGSWE_EHIP, DGSWE_ESTATE, DGSWE_ENONFINITE, DGSWE_EBUDGET = 0, -1, -2, -3, -4, -5, -6
 FP64, FP32 = 0, 1
@@ -19,6 +19,7 @@ MANNING, QUADRATIC = 0, 1
 LAND, OCEAN, RIVER, OUTFLOW = 0, 1, 2, 3
 MODAL, VERTEX = 0, 1
 MAX_SLOTS = 16
+TUNE_STAGE_VARIANT = 1
 
 ERRORS = {
     DGSWE_EINVAL: "EINVAL", DGSWE_ENOMEM: "ENOMEM", DGSWE_EHIP: "EHIP",
@@ -77,6 +78,8 @@ SIGNATURES = {
     "dgswe_mass_totals": (C.c_int, [_P, C.POINTER(Mass)]),
     "dgswe_info": (C.c_int, [_P, _I64, _I64, _I64, _I64]),
     "dgswe_footprint_bytes": (C.c_int64, [C.POINTER(Params), C.c_int64, C.c_int64]),
+    "dgswe_set_tuning": (C.c_int, [_P, C.c_int, C.c_int]),
+    "dgswe_get_tuning": (C.c_int, [_P, C.c_int, C.POINTER(C.c_int)]),
     "dgswe_set_profiling": (C.c_int, [_P, C.c_int]),
     "dgswe_kernel_stats": (C.c_int, [_P, C.c_char_p, _I64, _D]),
     "dgswe_batch_create": (C.c_int, [C.POINTER(Params), _P, C.c_int64, C.POINTER(_P)]),

@@ -41,8 +41,8 @@ def _run(cmd):
     return out
 
 
-def build(verbose: bool = False) -> str:
-    bdir = os.path.join(ROOT, "_build")
+def build(verbose: bool = False, out: str = OUT, defines=()) -> str:
+    bdir = os.path.join(ROOT, "_build" if not defines else "_build_" + "_".join(d.replace("=", "") for d in defines))
     os.makedirs(bdir, exist_ok=True)
     cc = hipcc()
     objs = []
@@ -50,22 +50,22 @@ def build(verbose: bool = False) -> str:
     procs = []
     for f in srcs:
         obj = os.path.join(bdir, f + ".o")
-        cmd = [cc] + HIP_FLAGS + ["-c", os.path.join(CSRC, f), "-o", obj]
+        cmd = [cc] + HIP_FLAGS + [f"-D{d}" for d in defines] + ["-c", os.path.join(CSRC, f), "-o", obj]
         if f.endswith(".cpp"):
             cmd = [cc, "-O2", "-std=c++17", "-fPIC", f"-I{INCLUDE}", f"-I{CSRC}", "-c",
                    os.path.join(CSRC, f), "-o", obj]
         procs.append((cmd, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)))
         objs.append(obj)
     for cmd, p in procs:
-        out, _ = p.communicate()
+        log, _ = p.communicate()
         if p.returncode != 0:
-            raise RuntimeError("build failed:\n" + " ".join(cmd) + "\n" + out)
-        if verbose and out.strip():
-            print(out)
-    tmp = OUT + ".tmp"
+            raise RuntimeError("build failed:\n" + " ".join(cmd) + "\n" + log)
+        if verbose and log.strip():
+            print(log)
+    tmp = out + ".tmp"
     _run([cc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs)
-    os.replace(tmp, OUT)
-    return OUT
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

@@ -143,7 +143,9 @@ struct dgswe_ctx {
   bool own_stream = false;
   std::shared_ptr<MeshDev> mesh;
   int n_tiles = 0;
-  DevBuf W[3], Wt, F[3], fullwet, R, part, sc, memb, tiles, ids, rnode;
+  int variant = 1;                  // stage kernel: 0 per element, 1 per edge
+  DevBuf W[3], Wt, F[3], fullwet, R, part, sc, memb, tiles, ids, rnode, node_tiles;
+  int n_node_tiles = 0;
   DevBuf storm, gt, gvals, tide_c, riv_tq;
   Forcing fo{};
   std::vector<double> tide_rows[MAX_SLOTS];
@@ -186,11 +188,11 @@ struct dgswe_batch {
   std::vector<Slot> slots;
   bool dirty = true;
   struct Group {
-    int p, flux, limiter;
+    int p, flux, limiter, variant;
     RKTable rk;
     std::vector<int> members;       // indices into the member array
-    int n_tiles = 0;
-    DevBuf tiles, ids;
+    int n_tiles = 0, n_node_tiles = 0;
+    DevBuf tiles, node_tiles, ids;
     bool has_rain = false;
   };
   std::vector<Group> groups;
@@ -236,6 +238,7 @@ Member<Real> member_struct(const dgswe_ctx* c) {
   m.Wt = c->Wt.as<Real>();
   m.fullwet = c->fullwet.as<uint8_t>();
   m.R = c->R.as<Real>();
+  m.rn = c->rnode.as<double>();
   m.part = c->part.as<double>();
   m.sc = c->sc.as<Scalars>();
   m.fo = c->fo;
@@ -329,11 +332,13 @@ StageArgs stage_args(const RKTable& T, int i) {
 // One time step of a set of members sharing (precision, p, flux, limiter,
 // stages): rain, stages (+ post when limiting), reduce.
 template <typename Real>
-int enqueue_step_group(const Member<Real>* d_m, const Tile* d_t, int n_tiles, const int* d_ids, int n_members,
-                       int p, int flux, int limiter, const RKTable& T, bool rain, hipStream_t s, dgswe_ctx* prof) {
+int enqueue_step_group(const Member<Real>* d_m, const Tile* d_t, int n_tiles, const Tile* d_nt, int n_node_tiles,
+                       const int* d_ids, int n_members, int p, int flux, int limiter, int variant, const RKTable& T,
+                       bool rain, hipStream_t s, dgswe_ctx* prof) {
   if (rain) {
     ProfScope ps(prof, K_RAIN);
-    HIPCHK(launch_rain<Real>(d_m, d_t, n_tiles, 0, nullptr, s));
+    // nodal rates at t^n; the first stage averages them per element
+    HIPCHK(launch_rain<Real>(d_m, d_t, 0, 0, d_nt, n_node_tiles, s));
   }
   for (int i = 0; i < T.n; ++i) {
     StageArgs a = stage_args(T, i);
@@ -342,13 +347,13 @@ int enqueue_step_group(const Member<Real>* d_m, const Tile* d_t, int n_tiles, co
       sa.out_buf = -1;
       {
         ProfScope ps(prof, K_STAGE);
-        HIPCHK(launch_stage<Real>(p, flux, 1, d_m, d_t, n_tiles, sa, s));
+        HIPCHK(launch_stage<Real>(p, flux, 1, variant, d_m, d_t, n_tiles, sa, s));
       }
       ProfScope ps(prof, K_POST);
       HIPCHK(launch_post<Real>(p, 1, d_m, d_t, n_tiles, a, 0, s));
     } else {
       ProfScope ps(prof, K_STAGE);
-      HIPCHK(launch_stage<Real>(p, flux, 0, d_m, d_t, n_tiles, a, s));
+      HIPCHK(launch_stage<Real>(p, flux, 0, variant, d_m, d_t, n_tiles, a, s));
     }
   }
   ProfScope ps(prof, K_REDUCE);
@@ -359,10 +364,11 @@ int enqueue_step_group(const Member<Real>* d_m, const Tile* d_t, int n_tiles, co
 int ctx_enqueue_step(dgswe_ctx* c) {
   const bool rain = c->fo.rain_kind != RAIN_CONST;
   if (c->rs == 8)
-    return enqueue_step_group<double>(c->memb.as<Member<double>>(), c->tiles.as<Tile>(), c->n_tiles, c->ids.as<int>(),
-                                      1, c->prm.p, c->prm.flux, c->prm.limiter, c->rk, rain, c->stream, c);
-  return enqueue_step_group<float>(c->memb.as<Member<float>>(), c->tiles.as<Tile>(), c->n_tiles, c->ids.as<int>(), 1,
-                                   c->prm.p, c->prm.flux, c->prm.limiter, c->rk, rain, c->stream, c);
+    return enqueue_step_group<double>(c->memb.as<Member<double>>(), c->tiles.as<Tile>(), c->n_tiles,
+                                      c->node_tiles.as<Tile>(), c->n_node_tiles, c->ids.as<int>(), 1, c->prm.p, c->prm.flux, c->prm.limiter, c->variant, c->rk, rain, c->stream, c);
+  return enqueue_step_group<float>(c->memb.as<Member<float>>(), c->tiles.as<Tile>(), c->n_tiles,
+                                   c->node_tiles.as<Tile>(), c->n_node_tiles, c->ids.as<int>(), 1,
+                                   c->prm.p, c->prm.flux, c->prm.limiter, c->variant, c->rk, rain, c->stream, c);
 }
 
 int ctx_reduce_init(dgswe_ctx* c) {
@@ -448,6 +454,14 @@ int alloc_state(dgswe_ctx* c) {
   }
   HIPCHK(c->R.alloc(size_t(E) * c->rs));
   if (E) HIPCHK(hipMemset(c->R.p, 0, size_t(E) * c->rs));
+  const int64_t nn = c->mesh->host.n_nodes;
+  HIPCHK(c->rnode.alloc(size_t(std::max<int64_t>(nn, 1)) * sizeof(double)));
+  HIPCHK(hipMemset(c->rnode.p, 0, c->rnode.bytes));
+  c->n_node_tiles = int((nn + TILE - 1) / TILE);
+  std::vector<Tile> ntl(c->n_node_tiles);
+  for (int t = 0; t < c->n_node_tiles; ++t) ntl[t] = {0, t};
+  if (ntl.empty()) ntl.push_back({0, 0});
+  HIPCHK(upload(c->node_tiles, ntl));
   c->n_tiles = int((E + TILE - 1) / TILE);
   const size_t pb = size_t(NPART) * std::max(c->n_tiles, 1) * sizeof(double);
   HIPCHK(c->part.alloc(pb));
@@ -533,7 +547,7 @@ int64_t footprint(const dgswe_params* p, int64_t E, int64_t n_nodes) {
   b += (6 + 3 + 1 + 1) * E * rs;                     // edge vectors, hb, friction, d_in
   b += 3 * E * 4 + E + 3 * E * 4;                    // neighbours, codes, node ids
   if (p->limiter) b += 6 * E * rs + E;               // limiter stencil
-  b += 2 * n_nodes * 8;                              // node coordinates
+  b += 3 * n_nodes * 8;                              // node coordinates, nodal rain
   b += NPART * std::max<int64_t>(tiles, 1) * 8 + 4096;
   return b;
 }
@@ -700,19 +714,17 @@ int dgswe_set_rain_nodal(dgswe_ctx* c, const double* r) {
   if (rc) return rc;
   const HostMesh& h = c->mesh->host;
   if (h.n_nodes > 0 && !r) return fail(DGSWE_EINVAL, "null rain array");
-  std::vector<double> v(r, r + h.n_nodes);
-  for (double x : v)
-    if (!std::isfinite(x)) return fail(DGSWE_EINVAL, "non-finite rain rate");
+  for (int64_t i = 0; i < h.n_nodes; ++i)
+    if (!std::isfinite(r[i])) return fail(DGSWE_EINVAL, "non-finite rain rate");
   HIPCHK(hipStreamSynchronize(c->stream));
-  if (v.empty()) v.push_back(0.0);
-  HIPCHK(upload(c->rnode, v));
+  if (h.n_nodes) HIPCHK(hipMemcpy(c->rnode.p, r, size_t(h.n_nodes) * sizeof(double), hipMemcpyHostToDevice));
   c->fo.rain_kind = RAIN_CONST;
   rc = push_member(c);
   if (rc) return rc;
   if (c->rs == 8)
-    HIPCHK(launch_rain<double>(c->memb.as<Member<double>>(), c->tiles.as<Tile>(), c->n_tiles, 1, c->rnode.as<double>(), c->stream));
+    HIPCHK(launch_rain<double>(c->memb.as<Member<double>>(), c->tiles.as<Tile>(), c->n_tiles, 1, nullptr, 0, c->stream));
   else
-    HIPCHK(launch_rain<float>(c->memb.as<Member<float>>(), c->tiles.as<Tile>(), c->n_tiles, 1, c->rnode.as<double>(), c->stream));
+    HIPCHK(launch_rain<float>(c->memb.as<Member<float>>(), c->tiles.as<Tile>(), c->n_tiles, 1, nullptr, 0, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
   return refresh_forcing(c);
 }
@@ -945,6 +957,26 @@ int64_t dgswe_footprint_bytes(const dgswe_params* p, int64_t n_tri, int64_t n_no
   return footprint(p, n_tri, n_nodes);
 }
 
+int dgswe_set_tuning(dgswe_ctx* c, int key, int value) {
+  int rc = check_ctx(c, false);
+  if (rc) return rc;
+  if (c->in_batch) return fail(DGSWE_ESTATE, "context is a member of a batch");
+  if (key != DGSWE_TUNE_STAGE_VARIANT) return fail(DGSWE_EINVAL, "unknown tuning key");
+  if (value != 0 && value != 1) return fail(DGSWE_EINVAL, "stage variant must be 0 or 1");
+  if (c->stream) HIPCHK(hipStreamSynchronize(c->stream));
+  c->variant = value;
+  c->graph_dirty = true;
+  return DGSWE_OK;
+}
+
+int dgswe_get_tuning(const dgswe_ctx* c, int key, int* value) {
+  int rc = check_ctx(c, false);
+  if (rc) return rc;
+  if (key != DGSWE_TUNE_STAGE_VARIANT || !value) return fail(DGSWE_EINVAL, "unknown tuning key or null output");
+  *value = c->variant;
+  return DGSWE_OK;
+}
+
 int dgswe_set_profiling(dgswe_ctx* c, int on) {
   int rc = check_ctx(c, false);
   if (rc) return rc;
@@ -977,7 +1009,7 @@ namespace {
 template <typename Real>
 int batch_rebuild_t(dgswe_batch* b) {
   std::vector<Member<Real>> ms;
-  std::map<std::tuple<int, int, int, int>, int> gi;
+  std::map<std::tuple<int, int, int, int, int>, int> gi;
   b->groups.clear();
   for (size_t i = 0; i < b->slots.size(); ++i) {
     const auto& sl = b->slots[i];
@@ -985,13 +1017,14 @@ int batch_rebuild_t(dgswe_batch* b) {
     const int idx = int(ms.size());
     ms.push_back(member_struct<Real>(sl.ctx));
     const dgswe_params& p = sl.ctx->prm;
-    auto key = std::make_tuple(p.p, p.flux, p.limiter, p.rk_stages);
+    auto key = std::make_tuple(p.p, p.flux, p.limiter, p.rk_stages, sl.ctx->variant);
     auto it = gi.find(key);
     if (it == gi.end()) {
       dgswe_batch::Group g;
       g.p = p.p;
       g.flux = p.flux;
       g.limiter = p.limiter;
+      g.variant = sl.ctx->variant;
       make_rk(p.rk_stages, g.rk);
       b->groups.push_back(std::move(g));
       it = gi.emplace(key, int(b->groups.size()) - 1).first;
@@ -1002,14 +1035,19 @@ int batch_rebuild_t(dgswe_batch* b) {
   if (ms.empty()) ms.push_back(Member<Real>{});
   HIPCHK(upload(b->memb, ms));
   for (auto& g : b->groups) {
-    std::vector<Tile> tl;
+    std::vector<Tile> tl, ntl;
     for (int m : g.members) {
       const int nt = ms[m].n_tiles;
       for (int t = 0; t < nt; ++t) tl.push_back({m, t});
+      const int nnt = (ms[m].n_nodes + TILE - 1) / TILE;
+      for (int t = 0; t < nnt; ++t) ntl.push_back({m, t});
     }
     g.n_tiles = int(tl.size());
+    g.n_node_tiles = int(ntl.size());
     if (tl.empty()) tl.push_back({0, 0});
+    if (ntl.empty()) ntl.push_back({0, 0});
     HIPCHK(upload(g.tiles, tl));
+    HIPCHK(upload(g.node_tiles, ntl));
     HIPCHK(upload(g.ids, g.members));
   }
   b->dirty = false;
@@ -1106,12 +1144,14 @@ int dgswe_batch_step(dgswe_batch* b, int64_t max_steps) {
     for (auto& g : b->groups) {
       int rc;
       if (b->prm.precision == DGSWE_FP32)
-        rc = enqueue_step_group<float>(b->memb.as<Member<float>>(), g.tiles.as<Tile>(), g.n_tiles, g.ids.as<int>(),
-                                       int(g.members.size()), g.p, g.flux, g.limiter, g.rk, g.has_rain, b->stream,
+        rc = enqueue_step_group<float>(b->memb.as<Member<float>>(), g.tiles.as<Tile>(), g.n_tiles,
+                                       g.node_tiles.as<Tile>(), g.n_node_tiles, g.ids.as<int>(),
+                                       int(g.members.size()), g.p, g.flux, g.limiter, g.variant, g.rk, g.has_rain, b->stream,
                                        nullptr);
       else
-        rc = enqueue_step_group<double>(b->memb.as<Member<double>>(), g.tiles.as<Tile>(), g.n_tiles, g.ids.as<int>(),
-                                        int(g.members.size()), g.p, g.flux, g.limiter, g.rk, g.has_rain, b->stream,
+        rc = enqueue_step_group<double>(b->memb.as<Member<double>>(), g.tiles.as<Tile>(), g.n_tiles,
+                                        g.node_tiles.as<Tile>(), g.n_node_tiles, g.ids.as<int>(),
+                                        int(g.members.size()), g.p, g.flux, g.limiter, g.variant, g.rk, g.has_rain, b->stream,
                                         nullptr);
       if (rc) return rc;
     }

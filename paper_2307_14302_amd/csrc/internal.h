@@ -72,6 +72,7 @@ struct Member {
   uint8_t* F[3];              // dry flags of the state in W[i] (bit 0)
   uint8_t* fullwet;           // [E] every vertex depth > H0 (limiter on)
   Real* R;                    // [E] element rain rate
+  double* rn;                 // [n_nodes] nodal rain rate
   double* part;               // [NPART][n_tiles]
   Scalars* sc;
   Forcing fo;
@@ -95,17 +96,19 @@ struct RKInfo {
 
 // launchers (kernels.hip)
 template <typename Real>
-hipError_t launch_stage(int P, int flux, int limiter, const Member<Real>* d_members, const Tile* d_tiles,
-                        int n_tiles, StageArgs a, hipStream_t s);
+hipError_t launch_stage(int P, int flux, int limiter, int variant, const Member<Real>* d_members,
+                        const Tile* d_tiles, int n_tiles, StageArgs a, hipStream_t s);
 template <typename Real>
 hipError_t launch_post(int P, int use_lim, const Member<Real>* d_members, const Tile* d_tiles, int n_tiles,
                        StageArgs a, int init, hipStream_t s);
 template <typename Real>
 hipError_t launch_classify(int P, const Member<Real>* d_members, const Tile* d_tiles, int n_tiles,
                            hipStream_t s);
+// rain at t^n: nodal rates (node tiles), then element means (element tiles);
+// always = 1 only averages (constant nodal rain at set-up)
 template <typename Real>
-hipError_t launch_rain(const Member<Real>* d_members, const Tile* d_tiles, int n_tiles, int nodal,
-                       const double* d_rnode, hipStream_t s);
+hipError_t launch_rain(const Member<Real>* d_members, const Tile* d_tiles, int n_tiles, int always,
+                       const Tile* d_node_tiles, int n_node_tiles, hipStream_t s);
 template <typename Real>
 hipError_t launch_reduce(const Member<Real>* d_members, const int* d_member_ids, int n_members, int init,
                          const RKInfo& rk, hipStream_t s);

@@ -19,16 +19,54 @@
 
 namespace dg {
 
+#ifndef DG_STAGE_WAVES
+#define DG_STAGE_WAVES 1
+#endif
+#define DG_STAGE_ATTR __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(DG_STAGE_WAVES)))
+
+// Pointers read from the member descriptor are generic to the compiler; all
+// device arrays live in global memory, so they are re-typed to the global
+// address space (global_load/store with a scalar base instead of flat).
+#define DG_G __attribute__((address_space(1)))
+template <typename T> DG_DEV DG_G T* gp(T* p) { return (DG_G T*)p; }
+template <typename T> DG_DEV const DG_G T* gp(const T* p) { return (const DG_G T*)p; }
+
 // ------------------------------------------------------------ reductions
+// Wavefront reductions in a fixed order with DPP lane moves (VALU only; no
+// LDS traffic): within each 16-lane row, swap neighbours, swap pairs, rotate
+// by 4 and by 8, which leaves the row total in every lane of the row; then
+// the four row totals are combined in order 0, 1, 2, 3 through readlane.
+// Doubles move as two 32-bit halves.
+DG_DEV double dpp_f64(double x, int ctrl_sel) {
+  const long long b = __double_as_longlong(x);
+  int lo = int(b & 0xffffffffll), hi = int(b >> 32);
+  switch (ctrl_sel) {
+    case 0: lo = __builtin_amdgcn_update_dpp(0, lo, 0xB1, 0xF, 0xF, false);
+            hi = __builtin_amdgcn_update_dpp(0, hi, 0xB1, 0xF, 0xF, false); break;   // quad_perm [1,0,3,2]
+    case 1: lo = __builtin_amdgcn_update_dpp(0, lo, 0x4E, 0xF, 0xF, false);
+            hi = __builtin_amdgcn_update_dpp(0, hi, 0x4E, 0xF, 0xF, false); break;   // quad_perm [2,3,0,1]
+    case 2: lo = __builtin_amdgcn_update_dpp(0, lo, 0x124, 0xF, 0xF, false);
+            hi = __builtin_amdgcn_update_dpp(0, hi, 0x124, 0xF, 0xF, false); break;  // row_ror:4
+    default: lo = __builtin_amdgcn_update_dpp(0, lo, 0x128, 0xF, 0xF, false);
+             hi = __builtin_amdgcn_update_dpp(0, hi, 0x128, 0xF, 0xF, false); break; // row_ror:8
+  }
+  return __longlong_as_double((long long)(unsigned)lo | ((long long)hi << 32));
+}
+DG_DEV double lane_f64(double x, int lane) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readlane(int(b & 0xffffffffll), lane);
+  const int hi = __builtin_amdgcn_readlane(int(b >> 32), lane);
+  return __longlong_as_double((long long)(unsigned)lo | ((long long)hi << 32));
+}
 DG_DEV double wave_sum(double v) {
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+  for (int c = 0; c < 4; ++c) v += dpp_f64(v, c);
+  return ((lane_f64(v, 0) + lane_f64(v, 16)) + lane_f64(v, 32)) + lane_f64(v, 48);
 }
 DG_DEV double wave_min(double v) {
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
-  return v;
+  for (int c = 0; c < 4; ++c) v = fmin(v, dpp_f64(v, c));
+  return fmin(fmin(lane_f64(v, 0), lane_f64(v, 16)), fmin(lane_f64(v, 32), lane_f64(v, 48)));
 }
 
 // Sums a per-thread value over the workgroup in a fixed order.
@@ -45,6 +83,22 @@ DG_DEV void block_sums(double (&v)[NV], double* lds) {
   for (int i = 0; i < NV; ++i) v[i] = (lds[i] + lds[NV + i]) + (lds[2 * NV + i] + lds[3 * NV + i]);
   __syncthreads();
 }
+
+// Decision margins: the positive-depth operator puts vertices at exactly H0,
+// so the tests that follow use H0 (1 + 1e-3) for "dry", and a wet-dry edge
+// exchanges water only above a mass flux of 1e-3 H0 sqrt(g H0).
+DG_DEV double dry_depth(double H0) { return H0 * (1.0 + 1e-3); }
+DG_DEV double exchange_eps(double H0, double g) { return 1e-3 * H0 * sqrt(g * H0); }
+
+// Workgroups are dispatched round-robin over the 8 XCDs, each with its own
+// L2.  The grid is padded to a multiple of 8 and block b takes tile
+// (b mod 8) * chunk + b / 8, so every XCD walks one contiguous run of
+// (Hilbert-ordered) tiles and the halos of neighbouring tiles share its L2.
+DG_DEV int xcd_tile() {
+  const int chunk = int(gridDim.x) >> 3;
+  return int(blockIdx.x & 7u) * chunk + int(blockIdx.x >> 3);
+}
+inline int xcd_grid(int n) { return ((n + 7) / 8) * 8; }
 
 // ------------------------------------------------------- element basics
 template <int P> struct B {
@@ -89,10 +143,40 @@ DG_DEV Real trace(Real a, Real c, Real b, int g) {
 // Positive-depth operator (Sec. 2.4) on one element, FP64 decisions.
 // Returns the dry flag; hv/qxv/qyv receive the final vertex depths and
 // discharges (for the CFL speed).
+// True when every vertex (and, for p = 2, edge-midpoint) depth is above the
+// dry margin by more than the rounding error of evaluating it in Real: then
+// the exact FP64 tests below would find the element fully wet and leave it
+// unchanged, so they can be skipped.
+template <typename Real, int P>
+DG_DEV bool surely_wet(const Real (&w)[3][Tab<P>::NP], const Real (&hb)[3], double Hd) {
+  constexpr int NP = Tab<P>::NP;
+  const Real rel = Real(sizeof(Real) == 4 ? 4e-6 : 1e-12);
+  bool ok = true;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    Real s = Real(0), t = Real(0);
+#pragma unroll
+    for (int m = 0; m < NP; ++m) {
+      s += Real(B<P>::V(i, m)) * w[0][m];
+      if (P == 2) t += Real(B<P>::M(i, m)) * w[0][m];
+    }
+    ok &= (s + hb[i]) > Real(Hd) + rel * (dabs(s) + dabs(hb[i]) + Real(1));
+    if (P == 2) {
+      const Real hm = Real(0.5) * (hb[i] + hb[(i + 1) % 3]);
+      ok &= (t + hm) > Real(Hd) + rel * (dabs(t) + dabs(hm) + Real(1));
+    }
+  }
+  return ok;
+}
+
+// need_v: the caller needs hv/qxv/qyv (the CFL speed); otherwise a surely
+// wet element returns at once.
 template <typename Real, int P>
 DG_DEV bool positive_depth(Real (&w)[3][Tab<P>::NP], const Real (&hb)[3], double H0, double (&hv)[3],
-                           double (&qxv)[3], double (&qyv)[3]) {
+                           double (&qxv)[3], double (&qyv)[3], bool need_v = true) {
   constexpr int NP = Tab<P>::NP;
+  const double Hd = dry_depth(H0);
+  if (!need_v && surely_wet<Real, P>(w, hb, Hd)) return false;
   double z[3];
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
@@ -110,15 +194,15 @@ DG_DEV bool positive_depth(Real (&w)[3][Tab<P>::NP], const Real (&hb)[3], double
   }
   if (P == 2) {
     // any vertex or edge-midpoint depth <= H0: keep only the linear part
-    bool low = (hv[0] <= H0) | (hv[1] <= H0) | (hv[2] <= H0);
+    bool low = (hv[0] <= Hd) | (hv[1] <= Hd) | (hv[2] <= Hd);
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
       double s = 0.0;
 #pragma unroll
       for (int m = 0; m < NP; ++m) s += B<P>::M(i, m) * double(w[0][m]);
-      low |= (s + 0.5 * (double(hb[i]) + double(hb[(i + 1) % 3]))) <= H0;
+      low |= (s + 0.5 * (double(hb[i]) + double(hb[(i + 1) % 3]))) <= Hd;
     }
-    if (!low) return false;   // every vertex depth > H0: nothing to do
+    if (!low) return false;   // every vertex depth above the dry margin: nothing to do
 #pragma unroll
     for (int v = 0; v < 3; ++v)
 #pragma unroll
@@ -167,7 +251,7 @@ DG_DEV bool positive_depth(Real (&w)[3][Tab<P>::NP], const Real (&hb)[3], double
     w[0][1] = Real((z[1] - z[0]) / 2.0);
     w[0][2] = Real((2.0 * z[2] - z[0] - z[1]) / 6.0);
   }
-  const bool d0 = hv[0] <= H0, d1 = hv[1] <= H0, d2 = hv[2] <= H0;
+  const bool d0 = hv[0] <= Hd, d1 = hv[1] <= Hd, d2 = hv[2] <= Hd;
   const int nd = int(d0) + int(d1) + int(d2);
   if (nd > 0) {
     double* qs[2] = {qxv, qyv};
@@ -198,7 +282,7 @@ DG_DEV double cfl_speed(const double (&hv)[3], const double (&qx)[3], const doub
   double lam = 0.0;
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
-    if (hv[i] > H0) {
+    if (hv[i] > dry_depth(H0)) {
       const double s = sqrt(qx[i] * qx[i] + qy[i] * qy[i]) / hv[i] + sqrt(g * hv[i]);
       lam = fmax(lam, s);
     }
@@ -206,180 +290,69 @@ DG_DEV double cfl_speed(const double (&hv)[3], const double (&qx)[3], const doub
   return lam;
 }
 
-// ----------------------------------------------------------- stage kernel
-// LIM = 0: full stage + positive-depth operator; LIM = 1: unlimited stage
-// output to Wt and the fully-wet byte (the post kernel limits afterwards).
-template <typename Real, int P, int FLUX, int LIM>
-__global__ __launch_bounds__(TILE) void stage_kernel(const Member<Real>* __restrict__ mem,
-                                                     const Tile* __restrict__ tiles, StageArgs A) {
-  constexpr int NP = Tab<P>::NP, NG = Tab<P>::NG, NQ = Tab<P>::NQ;
-  __shared__ double lds[4 * 6];
-  const Tile tl = tiles[blockIdx.x];
-  const Member<Real>& M = mem[tl.member];
-  Scalars* __restrict__ sc = M.sc;
-  if (!sc->active) return;
-  const int E = M.E;
-  const int e = tl.tile * TILE + int(threadIdx.x);
-  const bool valid = e < E;
-  const int ec = valid ? e : E - 1;
-  const Real g = Real(M.g), H0 = Real(M.H0);
-  const double dt = sc->dt;
-  const Real* __restrict__ Win = M.W[A.in_buf];
-  const uint8_t* __restrict__ Fin = M.F[A.fin];
-
-  Real w[3][NP];
-#pragma unroll
-  for (int v = 0; v < 3; ++v)
-#pragma unroll
-    for (int m = 0; m < NP; ++m) w[v][m] = Win[(v * NP + m) * E + ec];
-  Real ex[3], ey[3], hb[3];
-#pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    ex[k] = M.ev[(2 * k) * E + ec];
-    ey[k] = M.ev[(2 * k + 1) * E + ec];
-    hb[k] = M.hbv[k * E + ec];
+// ------------------------------------------------------ stage building blocks
+// Outward fluxes at one Gauss point of an interior edge, in the canonical
+// orientation (L = lower element id, n = L's outward normal, a/b = traces of
+// L and R at this point).  wet-wet: the numerical flux.  Otherwise the wet
+// trace meets the dry one with its discharge zeroed; if that mass flux enters
+// the dry element the flux is exchanged, else each side gets the flux of its
+// own mirrored state (land boundary).  FL / FR are the outward fluxes of L
+// and R; needL / needR say which the caller uses.
+template <int FLUX, typename Real>
+DG_DEV void interior_point(const W3<Real>& a, const W3<Real>& b, Real hg, Real lnx, Real lny, Real g, Real H0,
+                           Real feps, bool dryL, bool dryR, bool needL, bool needR, Real* FL, Real* FR) {
+  Real Fc[3] = {Real(0), Real(0), Real(0)};
+  bool exch;
+  if (!dryL && !dryR) {
+    num_flux<FLUX>(a, b, hg, lnx, lny, g, H0, Fc);
+    exch = true;
+  } else if (dryL && dryR) {
+    exch = false;
+  } else {
+    W3<Real> a2 = a, b2 = b;
+    if (dryR) { b2.x = Real(0); b2.y = Real(0); } else { a2.x = Real(0); a2.y = Real(0); }
+    num_flux<FLUX>(a2, b2, hg, lnx, lny, g, H0, Fc);
+    exch = dryR ? (Fc[0] > feps) : (Fc[0] < -feps);
   }
-  const Real detJ = Real(0.25) * (ex[2] * ey[0] - ex[0] * ey[2]);
-  const Real idet = rcp(detJ);
-  // det J * J^{-T} = [[-e2y, -e0y], [e2x, e0x]] / 2
-  const Real cx0 = Real(-0.5) * ey[2], cx1 = Real(-0.5) * ey[0];
-  const Real cy0 = Real(0.5) * ex[2], cy1 = Real(0.5) * ex[0];
-  const uint8_t myflag = Fin[ec] & 1;
-  const uint8_t nkp = M.nk[ec];
-
-  Real acc[3][NP];
-#pragma unroll
-  for (int v = 0; v < 3; ++v)
-#pragma unroll
-    for (int m = 0; m < NP; ++m) acc[v][m] = Real(0);
-
-  Real vv[3][3], mv[3][3];
-  edge_nodes<Real, P>(w, vv, mv);
-  double bout = 0.0, bin = 0.0;
-
-  // ---- edge integrals: sum_g (l/2) w_g Fhat_g phi_m(g)
-#pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    const int k1 = (k + 1) % 3;
-    const Real ell = dsqrt(ex[k] * ex[k] + ey[k] * ey[k]);
-    const Real il = rcp(ell);
-    const Real nx = ey[k] * il, ny = -ex[k] * il;
-    const Real half = Real(0.5) * ell;
-    const int nb = M.nbr[k * E + ec];
-    if (nb >= 0) {
-      const int kn = (nkp >> (2 * k)) & 3;
-      Real wn[3][NP];
-#pragma unroll
-      for (int v = 0; v < 3; ++v)
-#pragma unroll
-        for (int m = 0; m < NP; ++m) wn[v][m] = Win[(v * NP + m) * E + nb];
-      const uint8_t nflag = Fin[nb] & 1;
-      Real nvv[3][3], nmv[3][3];
-      edge_nodes<Real, P>(wn, nvv, nmv);
-      const int kn1 = kn == 2 ? 0 : kn + 1;
-      const bool meL = e < nb;
-      // edge node values of the left (L) and right (R) sides along their own edges
-      Real La[3], Lc[3], Lb[3], Ra[3], Rc[3], Rb[3];
-#pragma unroll
-      for (int v = 0; v < 3; ++v) {
-        const Real oa = vv[v][k], oc = mv[v][k], ob = vv[v][k1];
-        const Real na = kn == 0 ? nvv[v][0] : kn == 1 ? nvv[v][1] : nvv[v][2];
-        const Real nc = kn == 0 ? nmv[v][0] : kn == 1 ? nmv[v][1] : nmv[v][2];
-        const Real nbv = kn1 == 0 ? nvv[v][0] : kn1 == 1 ? nvv[v][1] : nvv[v][2];
-        La[v] = meL ? oa : na; Lc[v] = meL ? oc : nc; Lb[v] = meL ? ob : nbv;
-        Ra[v] = meL ? na : oa; Rc[v] = meL ? nc : oc; Rb[v] = meL ? nbv : ob;
-      }
-      const Real hLa = meL ? hb[k] : hb[k1], hLb = meL ? hb[k1] : hb[k];
-      const Real lnx = meL ? nx : -nx, lny = meL ? ny : -ny;
-      const bool dryL = meL ? myflag : nflag, dryR = meL ? nflag : myflag;
-#pragma unroll
-      for (int gL = 0; gL < NG; ++gL) {
-        const int gR = NG - 1 - gL;
-        W3<Real> a{trace<Real, P>(La[0], Lc[0], Lb[0], gL), trace<Real, P>(La[1], Lc[1], Lb[1], gL),
-                   trace<Real, P>(La[2], Lc[2], Lb[2], gL)};
-        W3<Real> b{trace<Real, P>(Ra[0], Rc[0], Rb[0], gR), trace<Real, P>(Ra[1], Rc[1], Rb[1], gR),
-                   trace<Real, P>(Ra[2], Rc[2], Rb[2], gR)};
-        const Real hg = Real(lag_(1, 0, gl_t(P, gL))) * hLa + Real(lag_(1, 1, gl_t(P, gL))) * hLb;
-        Real Fc[3] = {Real(0), Real(0), Real(0)};
-        bool exch;
-        if (!dryL && !dryR) {
-          num_flux<FLUX>(a, b, hg, lnx, lny, g, H0, Fc);
-          exch = true;
-        } else if (dryL && dryR) {
-          exch = false;
-        } else {
-          if (dryR) { b.x = Real(0); b.y = Real(0); } else { a.x = Real(0); a.y = Real(0); }
-          num_flux<FLUX>(a, b, hg, lnx, lny, g, H0, Fc);
-          exch = dryR ? (Fc[0] > Real(0)) : (Fc[0] < Real(0));
-        }
-        Real F[3];
-        if (exch) {
-          const Real sgn = meL ? Real(1) : Real(-1);
-          F[0] = sgn * Fc[0]; F[1] = sgn * Fc[1]; F[2] = sgn * Fc[2];
-        } else {
-          const int gm = meL ? gL : gR;
-          W3<Real> own{trace<Real, P>(vv[0][k], mv[0][k], vv[0][k1], gm),
-                       trace<Real, P>(vv[1][k], mv[1][k], vv[1][k1], gm),
-                       trace<Real, P>(vv[2][k], mv[2][k], vv[2][k1], gm)};
-          wall_flux<FLUX>(own, hg, nx, ny, g, H0, F);
-        }
-        const Real wg = half * Real(gl_w(P, gL));
-#pragma unroll
-        for (int m = 0; m < NP; ++m) {
-          const Real ph = meL ? Real(B<P>::EG(k, gL, m)) : Real(B<P>::EG(k, gR, m));
-          const Real c = wg * ph;
-          acc[0][m] -= c * F[0];
-          acc[1][m] -= c * F[1];
-          acc[2][m] -= c * F[2];
-        }
-      }
-    } else {
-      const int code = -1 - nb;
-      const int type = code & 3, slot = code >> 2;
-      double fm = 0.0;
-#pragma unroll
-      for (int gi = 0; gi < NG; ++gi) {
-        W3<Real> a{trace<Real, P>(vv[0][k], mv[0][k], vv[0][k1], gi),
-                   trace<Real, P>(vv[1][k], mv[1][k], vv[1][k1], gi),
-                   trace<Real, P>(vv[2][k], mv[2][k], vv[2][k1], gi)};
-        const Real hg = Real(lag_(1, 0, gl_t(P, gi))) * hb[k] + Real(lag_(1, 1, gl_t(P, gi))) * hb[k1];
-        Real F[3];
-        if (type == 0) {
-          wall_flux<FLUX>(a, hg, nx, ny, g, H0, F);
-        } else if (type == 3) {
-          flux_normal(a, hg, nx, ny, g, H0, F[0], F[1], F[2]);
-        } else if (type == 1) {
-          W3<Real> gh{Real(sc->tide[A.stage][slot]), a.x, a.y};
-          num_flux<FLUX>(a, gh, hg, nx, ny, g, H0, F);
-        } else {
-          const Real qr = Real(sc->river[A.stage][slot]);
-          const Real qn = a.x * nx + a.y * ny;
-          const Real dq = (Real(2) * qr - qn) - qn;
-          W3<Real> gh{a.z, a.x + dq * nx, a.y + dq * ny};
-          num_flux<FLUX>(a, gh, hg, nx, ny, g, H0, F);
-          F[0] = qr;
-        }
-        const Real wg = half * Real(gl_w(P, gi));
-        fm += double(wg * F[0]);
-#pragma unroll
-        for (int m = 0; m < NP; ++m) {
-          const Real c = wg * Real(B<P>::EG(k, gi, m));
-          acc[0][m] -= c * F[0];
-          acc[1][m] -= c * F[1];
-          acc[2][m] -= c * F[2];
-        }
-      }
-      if (fm > 0.0) bout += fm; else bin -= fm;
-    }
+  if (exch) {
+    FL[0] = Fc[0]; FL[1] = Fc[1]; FL[2] = Fc[2];
+    FR[0] = -Fc[0]; FR[1] = -Fc[1]; FR[2] = -Fc[2];
+  } else {
+    if (needL) wall_flux<FLUX>(a, hg, lnx, lny, g, H0, FL);
+    if (needR) wall_flux<FLUX>(b, hg, -lnx, -lny, g, H0, FR);
   }
+}
 
-  // ---- rain (Eq. rain): only the mean mode sees a constant source
-  acc[0][0] += Real(2) * detJ * M.R[ec];
+// Outward flux at a boundary Gauss point (Sec. 2.1 boundary partition):
+// land = mirrored normal discharge, outflow = interior state, ocean =
+// elevation of its slot with the interior discharge, river = ghost normal
+// discharge 2 q_river - q_n and the mass flux set to q_river.
+template <int FLUX, typename Real>
+DG_DEV void boundary_point(const W3<Real>& a, Real hg, Real nx, Real ny, Real g, Real H0, int type, Real tide,
+                           Real qr, Real* F) {
+  if (type == 0) {
+    wall_flux<FLUX>(a, hg, nx, ny, g, H0, F);
+  } else if (type == 3) {
+    flux_normal(a, hg, nx, ny, g, H0, F[0], F[1], F[2]);
+  } else if (type == 1) {
+    W3<Real> gh{tide, a.x, a.y};
+    num_flux<FLUX>(a, gh, hg, nx, ny, g, H0, F);
+  } else {
+    const Real qn = a.x * nx + a.y * ny;
+    const Real dq = (Real(2) * qr - qn) - qn;
+    W3<Real> gh{a.z, a.x + dq * nx, a.y + dq * ny};
+    num_flux<FLUX>(a, gh, hg, nx, ny, g, H0, F);
+    F[0] = qr;
+  }
+}
 
-  // ---- area integrals: volume flux, bed slope, friction
+// Area integrals: volume flux, bed slope and bottom friction (Eq. SWE).
+template <typename Real, int P>
+DG_DEV void area_terms(const Real (&w)[3][Tab<P>::NP], const Real (&hb)[3], Real cx0, Real cx1, Real cy0, Real cy1,
+                       Real detJ, Real idet, Real fc, int friction, Real g, Real H0, Real (&acc)[3][Tab<P>::NP]) {
+  constexpr int NP = Tab<P>::NP, NQ = Tab<P>::NQ;
   const Real dhr = Real(0.5) * (hb[1] - hb[0]), dhs = Real(0.5) * (hb[2] - hb[0]);
   const Real dhx = (cx0 * dhr + cx1 * dhs) * idet, dhy = (cy0 * dhr + cy1 * dhs) * idet;
-  const Real fc = M.fric[ec];
   const Real gn2 = g * fc * fc;
 #pragma unroll
   for (int q = 0; q < NQ; ++q) {
@@ -398,7 +371,7 @@ __global__ __launch_bounds__(TILE) void stage_kernel(const Member<Real>* __restr
     const Real u = wq[1] * iH, vv_ = wq[2] * iH;
     const Real Pq = Real(0.5) * g * wq[0] * (wq[0] + Real(2) * hq);
     const Real spd = dsqrt(wq[1] * wq[1] + wq[2] * wq[2]) * iH;
-    const Real tau = (M.friction == 0) ? gn2 * spd * rcp(pow43(Hs)) : fc * spd * iH;
+    const Real tau = (friction == 0) ? gn2 * spd * rcp(pow43(Hs)) : fc * spd * iH;
     const Real Fx[3] = {wq[1], wq[1] * u + Pq, wq[2] * u};
     const Real Fy[3] = {wq[2], wq[1] * vv_, wq[2] * vv_ + Pq};
     const Real s1 = g * wq[0] * dhx - tau * wq[1];
@@ -419,11 +392,40 @@ __global__ __launch_bounds__(TILE) void stage_kernel(const Member<Real>* __restr
       acc[2][m] += ps * s2;
     }
   }
+}
 
-  // ---- inverse mass and SSP combination
+// Element rain rate (Eq. rain).  With time-dependent rain the first stage of
+// a step averages the nodal rates of t^n (rain_node_kernel), stores R for the
+// later stages and returns the element's rain volume rate in part.
+template <typename Real>
+DG_DEV Real element_rain(const Member<Real>& M, const StageArgs& A, int E, int e, int ec, bool valid,
+                         const Real (&ex)[3], const Real (&ey)[3], double& part) {
+  if (A.stage == 0 && M.fo.rain_kind != RAIN_CONST) {
+    const DG_G double* __restrict__ rn = gp(M.rn);
+    const DG_G int* __restrict__ tri = gp(M.tri);
+    const double r = (rn[tri[ec]] + rn[tri[E + ec]] + rn[tri[2 * E + ec]]) / 3.0;
+    const Real R = Real(r);
+    if (valid) gp(M.R)[e] = R;
+    const double area = 0.5 * (double(ex[2]) * double(ey[0]) - double(ex[0]) * double(ey[2]));
+    part = valid ? area * double(R) : 0.0;
+    return R;
+  }
+  part = 0.0;
+  return gp(M.R)[ec];
+}
+
+// Inverse mass, SSP combination, positive-depth operator (LIM = 0) or the
+// fully-wet byte (LIM = 1), stores, and the tile partials.
+template <typename Real, int P, int LIM>
+DG_DEV void finish_stage(const Member<Real>& M, const StageArgs& A, int tile, int e, int ec, bool valid, int E,
+                         Real (&w)[3][Tab<P>::NP], Real (&acc)[3][Tab<P>::NP], const Real (&hb)[3], const Real (&ex)[3],
+                         const Real (&ey)[3], Real detJ, Real idet, double dt, double bout, double bin, Real Rv,
+                         double rain_part, double* lds) {
+  constexpr int NP = Tab<P>::NP;
+  acc[0][0] += Real(2) * detJ * Rv;
   const Real cdt = Real(A.gam * dt);
   const Real ca = Real(A.a), cb = Real(A.b);
-  const Real* __restrict__ W0 = M.W[0];
+  const DG_G Real* __restrict__ W0 = gp(M.W[0]);
 #pragma unroll
   for (int v = 0; v < 3; ++v)
 #pragma unroll
@@ -433,70 +435,458 @@ __global__ __launch_bounds__(TILE) void stage_kernel(const Member<Real>* __restr
       if (A.a != 0.0) nw += ca * W0[(v * NP + m) * E + ec];
       w[v][m] = nw;
     }
-
-  double part[6] = {bout, bin, 0.0, 0.0, 0.0, 0.0};
+  double part[5] = {bout, bin, 0.0, __builtin_inf(), 0.0};
   if (LIM == 0) {
     double hv[3], qxv[3], qyv[3];
-    const bool dry = positive_depth<Real, P>(w, hb, M.H0, hv, qxv, qyv);
+    const bool dry = positive_depth<Real, P>(w, hb, M.H0, hv, qxv, qyv, A.last != 0);
     if (valid) {
-      Real* __restrict__ Wout = M.W[A.out_buf];
+      DG_G Real* __restrict__ Wout = gp(M.W[A.out_buf]);
 #pragma unroll
       for (int v = 0; v < 3; ++v)
 #pragma unroll
         for (int m = 0; m < NP; ++m) Wout[(v * NP + m) * E + e] = w[v][m];
-      M.F[A.fout][e] = dry ? 1 : 0;
+      gp(M.F[A.fout])[e] = dry ? 1 : 0;
     }
     if (A.last) {
       const double lam = cfl_speed(hv, qxv, qyv, M.H0, M.g);
       const double area = 0.5 * (double(ex[2]) * double(ey[0]) - double(ex[0]) * double(ey[2]));
       part[2] = valid ? area * (double(w[0][0]) + (double(hb[0]) + double(hb[1]) + double(hb[2])) / 3.0) : 0.0;
-      part[3] = (valid && lam > 0.0) ? double(M.din[ec]) / lam : __builtin_inf();
+      part[3] = (valid && lam > 0.0) ? double(gp(M.din)[ec]) / lam : __builtin_inf();
       part[4] = (valid && dry) ? 1.0 : 0.0;
     }
   } else {
     if (valid) {
-      Real* __restrict__ Wt = M.Wt;
+      DG_G Real* __restrict__ Wt = gp(M.Wt);
 #pragma unroll
       for (int v = 0; v < 3; ++v)
 #pragma unroll
         for (int m = 0; m < NP; ++m) Wt[(v * NP + m) * E + e] = w[v][m];
-      bool full = true;
+      bool full = surely_wet<Real, P>(w, hb, dry_depth(M.H0));
+      if (!full) {
+        full = true;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          double s = 0.0;
+#pragma unroll
+          for (int m = 0; m < NP; ++m) s += B<P>::V(i, m) * double(w[0][m]);
+          full &= (s + double(hb[i])) > dry_depth(M.H0);
+        }
+      }
+      gp(M.fullwet)[e] = full ? 1 : 0;
+    }
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  // bout/bin arrive already restricted to the edges this lane evaluated
+  const bool rain_here = A.stage == 0 && M.fo.rain_kind != RAIN_CONST;
+  // most tiles have no boundary edge: skip those sums when the wavefront holds only zeros
+  const bool any_b = __any(part[0] != 0.0 || part[1] != 0.0);
+  const double s0 = any_b ? wave_sum(part[0]) : 0.0, s1 = any_b ? wave_sum(part[1]) : 0.0;
+  double s2 = 0.0, s4 = 0.0, s5 = 0.0, mn = __builtin_inf();
+  if (LIM == 0 && A.last) {
+    s2 = wave_sum(part[2]);
+    s4 = double(__popcll(__ballot(part[4] != 0.0)));
+    mn = wave_min(part[3]);
+  }
+  if (rain_here) s5 = wave_sum(rain_part);
+  if (lane == 0) {
+    lds[wv * 6 + 0] = s0; lds[wv * 6 + 1] = s1; lds[wv * 6 + 2] = s2; lds[wv * 6 + 3] = mn; lds[wv * 6 + 4] = s4;
+    lds[wv * 6 + 5] = s5;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    DG_G double* __restrict__ pt = gp(M.part);
+    const int nt = M.n_tiles;
+    pt[(P_OUT0 + A.stage) * nt + tile] = (lds[0] + lds[6]) + (lds[12] + lds[18]);
+    pt[(P_IN0 + A.stage) * nt + tile] = (lds[1] + lds[7]) + (lds[13] + lds[19]);
+    if (LIM == 0 && A.last) {
+      pt[P_VOL * nt + tile] = (lds[2] + lds[8]) + (lds[14] + lds[20]);
+      pt[P_MINR * nt + tile] = fmin(fmin(lds[3], lds[9]), fmin(lds[15], lds[21]));
+      pt[P_NDRY * nt + tile] = (lds[4] + lds[10]) + (lds[16] + lds[22]);
+    }
+    if (rain_here) pt[P_RAIN * nt + tile] = (lds[5] + lds[11]) + (lds[17] + lds[23]);
+  }
+}
+
+// Own data of an element: modes, vertex bathymetry, edge vectors, Jacobian.
+template <typename Real, int P>
+struct ElemData {
+  Real w[3][Tab<P>::NP];
+  Real ex[3], ey[3], hb[3];
+  Real detJ, idet, cx0, cx1, cy0, cy1;
+};
+
+template <typename Real, int P>
+DG_DEV void load_elem(const Member<Real>& M, const DG_G Real* __restrict__ Win, int E, int ec, ElemData<Real, P>& d) {
+  constexpr int NP = Tab<P>::NP;
+#pragma unroll
+  for (int v = 0; v < 3; ++v)
+#pragma unroll
+    for (int m = 0; m < NP; ++m) d.w[v][m] = Win[(v * NP + m) * E + ec];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    d.ex[k] = gp(M.ev)[(2 * k) * E + ec];
+    d.ey[k] = gp(M.ev)[(2 * k + 1) * E + ec];
+    d.hb[k] = gp(M.hbv)[k * E + ec];
+  }
+  d.detJ = Real(0.25) * (d.ex[2] * d.ey[0] - d.ex[0] * d.ey[2]);
+  d.idet = rcp(d.detJ);
+  // det J * J^{-T} = [[-e2y, -e0y], [e2x, e0x]] / 2
+  d.cx0 = Real(-0.5) * d.ey[2];
+  d.cx1 = Real(-0.5) * d.ey[0];
+  d.cy0 = Real(0.5) * d.ex[2];
+  d.cy1 = Real(0.5) * d.ex[0];
+}
+
+// ------------------------------------------------- stage kernel, per element
+// Every element evaluates its three edges itself (interior edge fluxes are
+// computed by both neighbours).  LIM = 0: full stage + positive-depth
+// operator; LIM = 1: unlimited stage output to Wt plus the fully-wet byte
+// (the post kernel limits afterwards).
+template <typename Real, int P, int FLUX, int LIM>
+__global__ DG_STAGE_ATTR void stage_kernel(const Member<Real>* __restrict__ mem,
+                                                     const Tile* __restrict__ tiles, int n_tiles, StageArgs A) {
+  constexpr int NP = Tab<P>::NP, NG = Tab<P>::NG;
+  __shared__ double lds[4 * 5];
+  const int ti = xcd_tile();
+  if (ti >= n_tiles) return;
+  const Tile tl = tiles[ti];
+  const Member<Real>& M = mem[tl.member];
+  const DG_G Scalars* __restrict__ sc = gp((const Scalars*)M.sc);
+  if (!sc->active) return;
+  const int E = M.E;
+  const int e = tl.tile * TILE + int(threadIdx.x);
+  const bool valid = e < E;
+  const int ec = valid ? e : E - 1;
+  const Real g = Real(M.g), H0 = Real(M.H0);
+  const Real feps = Real(exchange_eps(M.H0, M.g));
+  const double dt = sc->dt;
+  const DG_G Real* __restrict__ Win = gp(M.W[A.in_buf]);
+  const DG_G uint8_t* __restrict__ Fin = gp(M.F[A.fin]);
+  ElemData<Real, P> d;
+  load_elem<Real, P>(M, Win, E, ec, d);
+  const bool myflag = Fin[ec] & 1;
+  const uint8_t nkp = gp(M.nk)[ec];
+  Real acc[3][NP];
+#pragma unroll
+  for (int v = 0; v < 3; ++v)
+#pragma unroll
+    for (int m = 0; m < NP; ++m) acc[v][m] = Real(0);
+  Real vv[3][3], mv[3][3];
+  edge_nodes<Real, P>(d.w, vv, mv);
+  double bout = 0.0, bin = 0.0;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const int k1 = (k + 1) % 3;
+    const Real ell = dsqrt(d.ex[k] * d.ex[k] + d.ey[k] * d.ey[k]);
+    const Real il = rcp(ell);
+    const Real nx = d.ey[k] * il, ny = -d.ex[k] * il;
+    const Real half = Real(0.5) * ell;
+    const int nb = gp(M.nbr)[k * E + ec];
+    if (nb >= 0) {
+      const int kn = (nkp >> (2 * k)) & 3;
+      Real wn[3][NP];
+#pragma unroll
+      for (int v = 0; v < 3; ++v)
+#pragma unroll
+        for (int m = 0; m < NP; ++m) wn[v][m] = Win[(v * NP + m) * E + nb];
+      const bool nflag = Fin[nb] & 1;
+      Real nvv[3][3], nmv[3][3];
+      edge_nodes<Real, P>(wn, nvv, nmv);
+      const int kn1 = kn == 2 ? 0 : kn + 1;
+      const bool meL = e < nb;
+      Real La[3], Lc[3], Lb[3], Ra[3], Rc[3], Rb[3];
+#pragma unroll
+      for (int v = 0; v < 3; ++v) {
+        const Real oa = vv[v][k], oc = mv[v][k], ob = vv[v][k1];
+        const Real na = kn == 0 ? nvv[v][0] : kn == 1 ? nvv[v][1] : nvv[v][2];
+        const Real nc = kn == 0 ? nmv[v][0] : kn == 1 ? nmv[v][1] : nmv[v][2];
+        const Real nbv = kn1 == 0 ? nvv[v][0] : kn1 == 1 ? nvv[v][1] : nvv[v][2];
+        La[v] = meL ? oa : na; Lc[v] = meL ? oc : nc; Lb[v] = meL ? ob : nbv;
+        Ra[v] = meL ? na : oa; Rc[v] = meL ? nc : oc; Rb[v] = meL ? nbv : ob;
+      }
+      const Real hLa = meL ? d.hb[k] : d.hb[k1], hLb = meL ? d.hb[k1] : d.hb[k];
+      const Real lnx = meL ? nx : -nx, lny = meL ? ny : -ny;
+      const bool dryL = meL ? myflag : nflag, dryR = meL ? nflag : myflag;
+#pragma unroll
+      for (int gL = 0; gL < NG; ++gL) {
+        const int gR = NG - 1 - gL;
+        W3<Real> a{trace<Real, P>(La[0], Lc[0], Lb[0], gL), trace<Real, P>(La[1], Lc[1], Lb[1], gL),
+                   trace<Real, P>(La[2], Lc[2], Lb[2], gL)};
+        W3<Real> b{trace<Real, P>(Ra[0], Rc[0], Rb[0], gR), trace<Real, P>(Ra[1], Rc[1], Rb[1], gR),
+                   trace<Real, P>(Ra[2], Rc[2], Rb[2], gR)};
+        const Real hg = Real(lag_(1, 0, gl_t(P, gL))) * hLa + Real(lag_(1, 1, gl_t(P, gL))) * hLb;
+        Real FL[3], FR[3];
+        interior_point<FLUX>(a, b, hg, lnx, lny, g, H0, feps, dryL, dryR, meL, !meL, FL, FR);
+        const Real wg = half * Real(gl_w(P, gL));
+#pragma unroll
+        for (int m = 0; m < NP; ++m) {
+          const Real ph = meL ? Real(B<P>::EG(k, gL, m)) : Real(B<P>::EG(k, gR, m));
+          const Real c = wg * ph;
+          acc[0][m] -= c * (meL ? FL[0] : FR[0]);
+          acc[1][m] -= c * (meL ? FL[1] : FR[1]);
+          acc[2][m] -= c * (meL ? FL[2] : FR[2]);
+        }
+      }
+    } else {
+      const int code = -1 - nb;
+      const int type = code & 3, slot = code >> 2;
+      const Real tide = Real(sc->tide[A.stage][slot]), qr = Real(sc->river[A.stage][slot]);
+      double fm = 0.0;
+#pragma unroll
+      for (int gi = 0; gi < NG; ++gi) {
+        W3<Real> a{trace<Real, P>(vv[0][k], mv[0][k], vv[0][k1], gi),
+                   trace<Real, P>(vv[1][k], mv[1][k], vv[1][k1], gi),
+                   trace<Real, P>(vv[2][k], mv[2][k], vv[2][k1], gi)};
+        const Real hg = Real(lag_(1, 0, gl_t(P, gi))) * d.hb[k] + Real(lag_(1, 1, gl_t(P, gi))) * d.hb[k1];
+        Real F[3];
+        boundary_point<FLUX>(a, hg, nx, ny, g, H0, type, tide, qr, F);
+        const Real wg = half * Real(gl_w(P, gi));
+        fm += double(wg * F[0]);
+#pragma unroll
+        for (int m = 0; m < NP; ++m) {
+          const Real c = wg * Real(B<P>::EG(k, gi, m));
+          acc[0][m] -= c * F[0];
+          acc[1][m] -= c * F[1];
+          acc[2][m] -= c * F[2];
+        }
+      }
+      if (fm > 0.0) bout += fm; else bin -= fm;
+    }
+  }
+  area_terms<Real, P>(d.w, d.hb, d.cx0, d.cx1, d.cy0, d.cy1, d.detJ, d.idet, gp(M.fric)[ec], M.friction, g, H0, acc);
+  double rain_part;
+  const Real Rv = element_rain<Real>(M, A, E, e, ec, valid, d.ex, d.ey, rain_part);
+  // lanes past the end of the mesh evaluated a copy of the last element
+  finish_stage<Real, P, LIM>(M, A, tl.tile, e, ec, valid, E, d.w, acc, d.hb, d.ex, d.ey, d.detJ, d.idet, dt,
+                             valid ? bout : 0.0, valid ? bin : 0.0, Rv, rain_part, lds);
+}
+
+// ---------------------------------------------------- stage kernel, per edge
+// Same result, less arithmetic: the tile's point values go to LDS, every
+// edge whose two sides are in the tile is evaluated once (by the thread of
+// its lower-id element), and the lanes work through an LDS-compacted list of
+// the tile's edges instead of three per element.  Edges to other tiles are
+// still evaluated on both sides in the canonical orientation, so both tiles
+// obtain the same bits.
+template <typename Real, int P, int FLUX, int LIM>
+__global__ DG_STAGE_ATTR void stage_edge_kernel(const Member<Real>* __restrict__ mem,
+                                                          const Tile* __restrict__ tiles, int n_tiles, StageArgs A) {
+  constexpr int NP = Tab<P>::NP, NG = Tab<P>::NG;
+  constexpr int NN = P == 1 ? 3 : 6;                  // point values per variable (vertices, midpoints)
+  __shared__ Real s_node[3 * NN][TILE];
+  __shared__ Real s_hb[3][TILE];
+  __shared__ Real s_flux[3 * NG * 3][TILE];            // [(k NG + g) 3 + var][element], scaled by (l/2) w_g
+  __shared__ Real s_ev[6][TILE];
+  __shared__ int s_nbr[3][TILE];
+  __shared__ uint8_t s_nk[TILE];
+  __shared__ uint8_t s_flag[TILE];
+  __shared__ uint16_t s_list[3 * TILE];
+  __shared__ int s_wsum[4];
+  __shared__ double lds[4 * 6];
+  const int ti = xcd_tile();
+  if (ti >= n_tiles) return;
+  const Tile tl = tiles[ti];
+  const Member<Real>& M = mem[tl.member];
+  const DG_G Scalars* __restrict__ sc = gp((const Scalars*)M.sc);
+  if (!sc->active) return;
+  const int E = M.E;
+  const int t0 = tl.tile * TILE;
+  const int tend = t0 + TILE < E ? t0 + TILE : E;
+  const int el = threadIdx.x;
+  const int e = t0 + el;
+  const bool valid = e < E;
+  const int ec = valid ? e : E - 1;
+  const Real g = Real(M.g), H0 = Real(M.H0);
+  const Real feps = Real(exchange_eps(M.H0, M.g));
+  const double dt = sc->dt;
+  const DG_G Real* __restrict__ Win = gp(M.W[A.in_buf]);
+  const DG_G uint8_t* __restrict__ Fin = gp(M.F[A.fin]);
+  const DG_G int* __restrict__ nbr = gp(M.nbr);
+
+  // ---- phase A: own data, point values to LDS, owned-edge list, area terms
+  ElemData<Real, P> d;
+  load_elem<Real, P>(M, Win, E, ec, d);
+  {
+    Real vv[3][3], mv[3][3];
+    edge_nodes<Real, P>(d.w, vv, mv);
+#pragma unroll
+    for (int v = 0; v < 3; ++v)
 #pragma unroll
       for (int i = 0; i < 3; ++i) {
-        double s = 0.0;
+        s_node[v * NN + i][el] = vv[v][i];
+        if (P == 2) s_node[v * NN + 3 + i][el] = mv[v][i];
+      }
+  }
 #pragma unroll
-        for (int m = 0; m < NP; ++m) s += B<P>::V(i, m) * double(w[0][m]);
-        full &= (s + double(hb[i])) > M.H0;
-      }
-      M.fullwet[e] = full ? 1 : 0;
-    }
+  for (int k = 0; k < 3; ++k) {
+    s_hb[k][el] = d.hb[k];
+    s_ev[2 * k][el] = d.ex[k];
+    s_ev[2 * k + 1][el] = d.ey[k];
   }
-  // ---- tile partials (fixed-order reductions)
+  s_flag[el] = Fin[ec] & 1;
+  s_nk[el] = gp(M.nk)[ec];
+  double rain_part;
+  const Real Rv = element_rain<Real>(M, A, E, e, ec, valid, d.ex, d.ey, rain_part);
+  int own = 0;
+  int nbk[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    nbk[k] = nbr[k * E + ec];
+    s_nbr[k][el] = nbk[k];
+    const bool o = valid && (nbk[k] < 0 || nbk[k] < t0 || nbk[k] >= tend || e < nbk[k]);
+    own |= int(o) << k;
+  }
+  const int cnt = (own & 1) + ((own >> 1) & 1) + ((own >> 2) & 1);
+  // block-wide exclusive scan of the counts
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  int incl = cnt;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += y;
+  }
+  if (lane == 63) s_wsum[wv] = incl;
+  Real acc[3][NP];
+#pragma unroll
+  for (int v = 0; v < 3; ++v)
+#pragma unroll
+    for (int m = 0; m < NP; ++m) acc[v][m] = Real(0);
+  area_terms<Real, P>(d.w, d.hb, d.cx0, d.cx1, d.cy0, d.cy1, d.detJ, d.idet, gp(M.fric)[ec], M.friction, g, H0, acc);
+  __syncthreads();
+  int base = 0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) base += (i < wv) ? s_wsum[i] : 0;
+  const int n_list = s_wsum[0] + s_wsum[1] + s_wsum[2] + s_wsum[3];
   {
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    double s0 = wave_sum(valid ? part[0] : 0.0), s1 = wave_sum(valid ? part[1] : 0.0);
-    double s2 = 0.0, s4 = 0.0, mn = __builtin_inf();
-    if (LIM == 0 && A.last) {
-      s2 = wave_sum(part[2]);
-      s4 = wave_sum(part[4]);
-      mn = wave_min(part[3]);
+    int pos = base + incl - cnt;
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+      if ((own >> k) & 1) s_list[pos++] = uint16_t((el << 2) | k);
+  }
+  __syncthreads();
+
+  // ---- phase B: edge fluxes, scaled by (l/2) w_g, into s_flux
+  double bout = 0.0, bin = 0.0;
+  for (int it = threadIdx.x; it < n_list; it += TILE) {
+    const int ent = s_list[it];
+    const int l = ent >> 2, k = ent & 3;
+    const int k1 = k == 2 ? 0 : k + 1;
+    const int eg = t0 + l;
+    const int nb = s_nbr[k][l];
+    const Real exk = s_ev[2 * k][l], eyk = s_ev[2 * k + 1][l];
+    const Real ell = dsqrt(exk * exk + eyk * eyk);
+    const Real il = rcp(ell);
+    const Real nx = eyk * il, ny = -exk * il;
+    const Real half = Real(0.5) * ell;
+    Real Oa[3], Oc[3], Ob[3];
+#pragma unroll
+    for (int v = 0; v < 3; ++v) {
+      Oa[v] = s_node[v * NN + k][l];
+      Ob[v] = s_node[v * NN + k1][l];
+      Oc[v] = (P == 2) ? s_node[v * NN + 3 + k][l] : Real(0);
     }
-    if (lane == 0) {
-      lds[wv * 5 + 0] = s0; lds[wv * 5 + 1] = s1; lds[wv * 5 + 2] = s2; lds[wv * 5 + 3] = mn; lds[wv * 5 + 4] = s4;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      double* __restrict__ pt = M.part;
-      const int nt = M.n_tiles, t = tl.tile;
-      pt[(P_OUT0 + A.stage) * nt + t] = (lds[0] + lds[5]) + (lds[10] + lds[15]);
-      pt[(P_IN0 + A.stage) * nt + t] = (lds[1] + lds[6]) + (lds[11] + lds[16]);
-      if (LIM == 0 && A.last) {
-        pt[P_VOL * nt + t] = (lds[2] + lds[7]) + (lds[12] + lds[17]);
-        pt[P_MINR * nt + t] = fmin(fmin(lds[3], lds[8]), fmin(lds[13], lds[18]));
-        pt[P_NDRY * nt + t] = (lds[4] + lds[9]) + (lds[14] + lds[19]);
+    const Real hA = s_hb[k][l], hB = s_hb[k1][l];
+    if (nb >= 0) {
+      const int kn = (s_nk[l] >> (2 * k)) & 3;
+      const int kn1 = kn == 2 ? 0 : kn + 1;
+      const bool in_tile = nb >= t0 && nb < tend;
+      Real Na[3], Nc[3], Nb[3];
+      bool nflag;
+      if (in_tile) {
+        const int ln = nb - t0;
+#pragma unroll
+        for (int v = 0; v < 3; ++v) {
+          Na[v] = s_node[v * NN + kn][ln];
+          Nb[v] = s_node[v * NN + kn1][ln];
+          Nc[v] = (P == 2) ? s_node[v * NN + 3 + kn][ln] : Real(0);
+        }
+        nflag = s_flag[ln];
+      } else {
+        Real wn[3][NP];
+#pragma unroll
+        for (int v = 0; v < 3; ++v)
+#pragma unroll
+          for (int m = 0; m < NP; ++m) wn[v][m] = Win[(v * NP + m) * E + nb];
+        Real nvv[3][3], nmv[3][3];
+        edge_nodes<Real, P>(wn, nvv, nmv);
+#pragma unroll
+        for (int v = 0; v < 3; ++v) {
+          Na[v] = kn == 0 ? nvv[v][0] : kn == 1 ? nvv[v][1] : nvv[v][2];
+          Nb[v] = kn1 == 0 ? nvv[v][0] : kn1 == 1 ? nvv[v][1] : nvv[v][2];
+          Nc[v] = kn == 0 ? nmv[v][0] : kn == 1 ? nmv[v][1] : nmv[v][2];
+        }
+        nflag = Fin[nb] & 1;
       }
+      const bool myflag = s_flag[l];
+      const bool meL = eg < nb;
+      Real La[3], Lc[3], Lb[3], Ra[3], Rc[3], Rb[3];
+#pragma unroll
+      for (int v = 0; v < 3; ++v) {
+        La[v] = meL ? Oa[v] : Na[v]; Lc[v] = meL ? Oc[v] : Nc[v]; Lb[v] = meL ? Ob[v] : Nb[v];
+        Ra[v] = meL ? Na[v] : Oa[v]; Rc[v] = meL ? Nc[v] : Oc[v]; Rb[v] = meL ? Nb[v] : Ob[v];
+      }
+      const Real hLa = meL ? hA : hB, hLb = meL ? hB : hA;
+      const Real lnx = meL ? nx : -nx, lny = meL ? ny : -ny;
+      const bool dryL = meL ? myflag : nflag, dryR = meL ? nflag : myflag;
+#pragma unroll
+      for (int gL = 0; gL < NG; ++gL) {
+        const int gR = NG - 1 - gL;
+        W3<Real> a{trace<Real, P>(La[0], Lc[0], Lb[0], gL), trace<Real, P>(La[1], Lc[1], Lb[1], gL),
+                   trace<Real, P>(La[2], Lc[2], Lb[2], gL)};
+        W3<Real> b{trace<Real, P>(Ra[0], Rc[0], Rb[0], gR), trace<Real, P>(Ra[1], Rc[1], Rb[1], gR),
+                   trace<Real, P>(Ra[2], Rc[2], Rb[2], gR)};
+        const Real hg = Real(lag_(1, 0, gl_t(P, gL))) * hLa + Real(lag_(1, 1, gl_t(P, gL))) * hLb;
+        Real FL[3], FR[3];
+        // the neighbour's side is needed when it is in the tile (then this element is L)
+        interior_point<FLUX>(a, b, hg, lnx, lny, g, H0, feps, dryL, dryR, meL, !meL || in_tile, FL, FR);
+        const Real wg = half * Real(gl_w(P, gL));
+        const int gm = meL ? gL : gR;
+#pragma unroll
+        for (int v = 0; v < 3; ++v) s_flux[(k * NG + gm) * 3 + v][l] = wg * (meL ? FL[v] : FR[v]);
+        if (in_tile) {
+#pragma unroll
+          for (int v = 0; v < 3; ++v) s_flux[(kn * NG + gR) * 3 + v][nb - t0] = wg * FR[v];
+        }
+      }
+    } else {
+      const int code = -1 - nb;
+      const int type = code & 3, slot = code >> 2;
+      const Real tide = Real(sc->tide[A.stage][slot]), qr = Real(sc->river[A.stage][slot]);
+      double fm = 0.0;
+#pragma unroll
+      for (int gi = 0; gi < NG; ++gi) {
+        W3<Real> a{trace<Real, P>(Oa[0], Oc[0], Ob[0], gi), trace<Real, P>(Oa[1], Oc[1], Ob[1], gi),
+                   trace<Real, P>(Oa[2], Oc[2], Ob[2], gi)};
+        const Real hg = Real(lag_(1, 0, gl_t(P, gi))) * hA + Real(lag_(1, 1, gl_t(P, gi))) * hB;
+        Real F[3];
+        boundary_point<FLUX>(a, hg, nx, ny, g, H0, type, tide, qr, F);
+        const Real wg = half * Real(gl_w(P, gi));
+        fm += double(wg * F[0]);
+#pragma unroll
+        for (int v = 0; v < 3; ++v) s_flux[(k * NG + gi) * 3 + v][l] = wg * F[v];
+      }
+      if (fm > 0.0) bout += fm; else bin -= fm;
     }
   }
+  __syncthreads();
+
+  // ---- phase C: edge contributions, inverse mass, stage combination, post
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+#pragma unroll
+    for (int gi = 0; gi < NG; ++gi) {
+      const Real f0 = s_flux[(k * NG + gi) * 3 + 0][el], f1 = s_flux[(k * NG + gi) * 3 + 1][el],
+                 f2 = s_flux[(k * NG + gi) * 3 + 2][el];
+#pragma unroll
+      for (int m = 0; m < NP; ++m) {
+        const Real ph = Real(B<P>::EG(k, gi, m));
+        acc[0][m] -= ph * f0;
+        acc[1][m] -= ph * f1;
+        acc[2][m] -= ph * f2;
+      }
+    }
+  finish_stage<Real, P, LIM>(M, A, tl.tile, e, ec, valid, E, d.w, acc, d.hb, d.ex, d.ey, d.detJ, d.idet, dt, bout,
+                             bin, Rv, rain_part, lds);
 }
 
 // ------------------------------------------------------------ post kernel
@@ -507,19 +897,21 @@ __global__ __launch_bounds__(TILE) void stage_kernel(const Member<Real>* __restr
 // the member has it, positive depth); 2 = flags and partials of W[0] only.
 template <typename Real, int P>
 __global__ __launch_bounds__(TILE) void post_kernel(const Member<Real>* __restrict__ mem,
-                                                    const Tile* __restrict__ tiles, StageArgs A, int init,
-                                                    int use_lim) {
+                                                    const Tile* __restrict__ tiles, int n_tiles, StageArgs A,
+                                                    int init, int use_lim) {
   constexpr int NP = Tab<P>::NP;
   __shared__ double lds[4 * 5];
-  const Tile tl = tiles[blockIdx.x];
+  const int ti = xcd_tile();
+  if (ti >= n_tiles) return;
+  const Tile tl = tiles[ti];
   const Member<Real>& M = mem[tl.member];
-  Scalars* __restrict__ sc = M.sc;
+  const DG_G Scalars* __restrict__ sc = gp((const Scalars*)M.sc);
   if (!sc->active && init == 0) return;
   const int E = M.E;
   const int e = tl.tile * TILE + int(threadIdx.x);
   const bool valid = e < E;
   const int ec = valid ? e : E - 1;
-  const Real* __restrict__ Wsrc = (init == 2) ? M.W[0] : M.Wt;
+  const DG_G Real* __restrict__ Wsrc = gp((init == 2) ? M.W[0] : M.Wt);
   Real w[3][NP];
 #pragma unroll
   for (int v = 0; v < 3; ++v)
@@ -527,22 +919,22 @@ __global__ __launch_bounds__(TILE) void post_kernel(const Member<Real>* __restri
     for (int m = 0; m < NP; ++m) w[v][m] = Wsrc[(v * NP + m) * E + ec];
   Real hb[3];
 #pragma unroll
-  for (int k = 0; k < 3; ++k) hb[k] = M.hbv[k * E + ec];
+  for (int k = 0; k < 3; ++k) hb[k] = gp(M.hbv)[k * E + ec];
 
   if (init != 2 && use_lim) {
-    const uint8_t lc = M.limc[ec];
+    const uint8_t lc = gp(M.limc)[ec];
     int nb[3];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) nb[k] = M.nbr[k * E + ec];
-    bool ok = (lc & 1) && M.fullwet[ec];
+    for (int k = 0; k < 3; ++k) nb[k] = gp(M.nbr)[k * E + ec];
+    bool ok = (lc & 1) && gp(M.fullwet)[ec];
     if (ok) {
 #pragma unroll
-      for (int k = 0; k < 3; ++k) ok = ok && M.fullwet[nb[k]];
+      for (int k = 0; k < 3; ++k) ok = ok && gp(M.fullwet)[nb[k]];
     }
     if (ok) {
       Real al[6];
 #pragma unroll
-      for (int j = 0; j < 6; ++j) al[j] = M.lima[j * E + ec];
+      for (int j = 0; j < 6; ++j) al[j] = gp(M.lima)[j * E + ec];
 #pragma unroll
       for (int v = 0; v < 3; ++v) {
         const Real wb = w[v][0];
@@ -598,40 +990,41 @@ __global__ __launch_bounds__(TILE) void post_kernel(const Member<Real>* __restri
       qxv[i] = a;
       qyv[i] = c;
     }
-    dry = (hv[0] <= M.H0) & (hv[1] <= M.H0) & (hv[2] <= M.H0);
+    const double Hd = dry_depth(M.H0);
+    dry = (hv[0] <= Hd) & (hv[1] <= Hd) & (hv[2] <= Hd);
   } else {
-    dry = positive_depth<Real, P>(w, hb, M.H0, hv, qxv, qyv);
+    dry = positive_depth<Real, P>(w, hb, M.H0, hv, qxv, qyv, init != 0 || A.last != 0);
   }
   const int ob = init ? 0 : A.out_buf;
   const int fo = init ? 0 : A.fout;
   if (valid) {
     if (init != 2) {
-      Real* __restrict__ Wout = M.W[ob];
+      DG_G Real* __restrict__ Wout = gp(M.W[ob]);
 #pragma unroll
       for (int v = 0; v < 3; ++v)
 #pragma unroll
         for (int m = 0; m < NP; ++m) Wout[(v * NP + m) * E + e] = w[v][m];
     }
-    M.F[fo][e] = dry ? 1 : 0;
+    gp(M.F[fo])[e] = dry ? 1 : 0;
   }
   if (init || A.last) {
     Real ex[3], ey[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      ex[k] = M.ev[(2 * k) * E + ec];
-      ey[k] = M.ev[(2 * k + 1) * E + ec];
+      ex[k] = gp(M.ev)[(2 * k) * E + ec];
+      ey[k] = gp(M.ev)[(2 * k + 1) * E + ec];
     }
     const double area = 0.5 * (double(ex[2]) * double(ey[0]) - double(ex[0]) * double(ey[2]));
     const double lam = cfl_speed(hv, qxv, qyv, M.H0, M.g);
     double vals[2] = {valid ? area * (double(w[0][0]) + (double(hb[0]) + double(hb[1]) + double(hb[2])) / 3.0) : 0.0,
                       (valid && dry) ? 1.0 : 0.0};
-    const double mr = (valid && lam > 0.0) ? double(M.din[ec]) / lam : __builtin_inf();
+    const double mr = (valid && lam > 0.0) ? double(gp(M.din)[ec]) / lam : __builtin_inf();
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const double s0 = wave_sum(vals[0]), s1 = wave_sum(vals[1]), mn = wave_min(mr);
+    const double s0 = wave_sum(vals[0]), s1 = double(__popcll(__ballot(vals[1] != 0.0))), mn = wave_min(mr);
     if (lane == 0) { lds[wv * 3 + 0] = s0; lds[wv * 3 + 1] = s1; lds[wv * 3 + 2] = mn; }
     __syncthreads();
     if (threadIdx.x == 0) {
-      double* __restrict__ pt = M.part;
+      DG_G double* __restrict__ pt = gp(M.part);
       const int nt = M.n_tiles, t = tl.tile;
       pt[P_VOL * nt + t] = (lds[0] + lds[3]) + (lds[6] + lds[9]);
       pt[P_NDRY * nt + t] = (lds[1] + lds[4]) + (lds[7] + lds[10]);
@@ -643,9 +1036,11 @@ __global__ __launch_bounds__(TILE) void post_kernel(const Member<Real>* __restri
 // fully-wet bytes of the state in Wt (initial limiting)
 template <typename Real, int P>
 __global__ __launch_bounds__(TILE) void classify_kernel(const Member<Real>* __restrict__ mem,
-                                                        const Tile* __restrict__ tiles) {
+                                                        const Tile* __restrict__ tiles, int n_tiles) {
   constexpr int NP = Tab<P>::NP;
-  const Tile tl = tiles[blockIdx.x];
+  const int ti = xcd_tile();
+  if (ti >= n_tiles) return;
+  const Tile tl = tiles[ti];
   const Member<Real>& M = mem[tl.member];
   const int E = M.E;
   const int e = tl.tile * TILE + int(threadIdx.x);
@@ -655,14 +1050,14 @@ __global__ __launch_bounds__(TILE) void classify_kernel(const Member<Real>* __re
   for (int i = 0; i < 3; ++i) {
     double s = 0.0;
 #pragma unroll
-    for (int m = 0; m < NP; ++m) s += B<P>::V(i, m) * double(M.Wt[(0 * NP + m) * E + e]);
-    full &= (s + double(M.hbv[i * E + e])) > M.H0;
+    for (int m = 0; m < NP; ++m) s += B<P>::V(i, m) * double(gp(M.Wt)[(0 * NP + m) * E + e]);
+    full &= (s + double(gp(M.hbv)[i * E + e])) > dry_depth(M.H0);
   }
-  M.fullwet[e] = full ? 1 : 0;
+  gp(M.fullwet)[e] = full ? 1 : 0;
 }
 
 // -------------------------------------------------------------- rain
-DG_DEV double lattice(const float* __restrict__ v, int nx, int ny, double x0, double y0, double dx, double dy,
+DG_DEV double lattice(const DG_G float* __restrict__ v, int nx, int ny, double x0, double y0, double dx, double dy,
                       double x, double y) {
   const double fx = (x - x0) / dx, fy = (y - y0) / dy;
   if (!(fx >= 0.0 && fx <= double(nx - 1) && fy >= 0.0 && fy <= double(ny - 1))) return 0.0;
@@ -677,138 +1072,213 @@ DG_DEV double lattice(const float* __restrict__ v, int nx, int ny, double x0, do
   return (1.0 - ay) * ((1.0 - ax) * v00 + ax * v01) + ay * ((1.0 - ax) * v10 + ax * v11);
 }
 
+// Nodal rain rate at t^n (Sec. 2.5 parametric storm profile or Sec. 3.3
+// rain lattice), one thread per node; block t covers nodes [t TILE, (t+1) TILE).
+template <typename Real>
+__global__ __launch_bounds__(TILE) void rain_node_kernel(const Member<Real>* __restrict__ mem,
+                                                         const Tile* __restrict__ tiles, int n_tiles) {
+  const int ti = xcd_tile();
+  if (ti >= n_tiles) return;
+  const Tile tl = tiles[ti];
+  const Member<Real>& M = mem[tl.member];
+  const DG_G Scalars* __restrict__ sc = gp((const Scalars*)M.sc);
+  const int kind = M.fo.rain_kind;
+  if (!sc->active || kind == RAIN_CONST) return;
+  const int n = tl.tile * TILE + int(threadIdx.x);
+  if (n >= M.n_nodes) return;
+  const double x = gp(M.nxy)[n], y = gp(M.nxy)[M.n_nodes + n];
+  double r;
+  if (kind == RAIN_PARAM) {
+    const double xc = sc->storm[0], yc = sc->storm[1], pk = sc->storm[2], T0 = sc->storm[3];
+    const double rm = sc->storm[4], re = sc->storm[5];
+    const double d = hypot(x - xc, y - yc);
+    r = d < rm ? T0 + (pk - T0) * d / rm : pk * exp(-(d - rm) / re);
+  } else {
+    const Forcing& f = M.fo;
+    const size_t rs = size_t(f.gnx) * f.gny;
+    const double th = sc->gth;
+    const double a = lattice(gp(f.gvals) + rs * sc->gk0, f.gnx, f.gny, f.gx0, f.gy0, f.gdx, f.gdy, x, y);
+    const double b = lattice(gp(f.gvals) + rs * sc->gk1, f.gnx, f.gny, f.gx0, f.gy0, f.gdx, f.gdy, x, y);
+    r = (1.0 - th) * a + th * b;
+  }
+  gp(M.rn)[n] = r;
+}
+
+// Element rain (Eq. rain): the mean of the three nodal rates, and the tile's
+// rain volume rate.  always = 1 runs even for constant rain (set-up).
 template <typename Real>
 __global__ __launch_bounds__(TILE) void rain_kernel(const Member<Real>* __restrict__ mem,
-                                                    const Tile* __restrict__ tiles, int nodal,
-                                                    const double* __restrict__ rnode) {
+                                                    const Tile* __restrict__ tiles, int n_tiles, int always) {
   __shared__ double lds[4];
-  const Tile tl = tiles[blockIdx.x];
+  const int ti = xcd_tile();
+  if (ti >= n_tiles) return;
+  const Tile tl = tiles[ti];
   const Member<Real>& M = mem[tl.member];
-  const Scalars* __restrict__ sc = M.sc;
-  if (!nodal && (!sc->active || M.fo.rain_kind == RAIN_CONST)) return;
+  const DG_G Scalars* __restrict__ sc = gp((const Scalars*)M.sc);
+  if (!always && (!sc->active || M.fo.rain_kind == RAIN_CONST)) return;
   const int E = M.E;
   const int e = tl.tile * TILE + int(threadIdx.x);
   const bool valid = e < E;
   const int ec = valid ? e : E - 1;
-  double r[3];
-  const int kind = M.fo.rain_kind;
-#pragma unroll
-  for (int i = 0; i < 3; ++i) {
-    const int n = M.tri[i * E + ec];
-    if (nodal) {
-      r[i] = rnode[n];
-    } else {
-      const double x = M.nxy[n], y = M.nxy[M.n_nodes + n];
-      if (kind == RAIN_PARAM) {
-        const double xc = sc->storm[0], yc = sc->storm[1], pk = sc->storm[2], T0 = sc->storm[3];
-        const double rm = sc->storm[4], re = sc->storm[5];
-        const double d = hypot(x - xc, y - yc);
-        r[i] = d < rm ? T0 + (pk - T0) * d / rm : pk * exp(-(d - rm) / re);
-      } else {
-        const Forcing& f = M.fo;
-        const size_t rs = size_t(f.gnx) * f.gny;
-        const double th = sc->gth;
-        const double a = lattice(f.gvals + rs * sc->gk0, f.gnx, f.gny, f.gx0, f.gy0, f.gdx, f.gdy, x, y);
-        const double b = lattice(f.gvals + rs * sc->gk1, f.gnx, f.gny, f.gx0, f.gy0, f.gdx, f.gdy, x, y);
-        r[i] = (1.0 - th) * a + th * b;
-      }
-    }
-  }
-  const Real Re = Real((r[0] + r[1] + r[2]) / 3.0);
-  if (valid) M.R[e] = Re;
-  const double area = 0.5 * (double(M.ev[4 * E + ec]) * double(M.ev[1 * E + ec]) -
-                             double(M.ev[0 * E + ec]) * double(M.ev[5 * E + ec]));
+  const DG_G double* __restrict__ rn = gp(M.rn);
+  const double r0 = rn[gp(M.tri)[ec]], r1 = rn[gp(M.tri)[E + ec]], r2 = rn[gp(M.tri)[2 * E + ec]];
+  const Real Re = Real((r0 + r1 + r2) / 3.0);
+  if (valid) gp(M.R)[e] = Re;
+  const double area = 0.5 * (double(gp(M.ev)[4 * E + ec]) * double(gp(M.ev)[1 * E + ec]) -
+                             double(gp(M.ev)[0 * E + ec]) * double(gp(M.ev)[5 * E + ec]));
   double v = valid ? area * double(Re) : 0.0;
   v = wave_sum(v);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   if (lane == 0) lds[wv] = v;
   __syncthreads();
-  if (threadIdx.x == 0) M.part[P_RAIN * M.n_tiles + tl.tile] = (lds[0] + lds[1]) + (lds[2] + lds[3]);
+  if (threadIdx.x == 0) gp(M.part)[P_RAIN * M.n_tiles + tl.tile] = (lds[0] + lds[1]) + (lds[2] + lds[3]);
 }
 
 // ------------------------------------------------------------ reduce
 
-DG_DEV double interp_series(const double* __restrict__ tq, int n, double t) {
-  // (t, q) pairs; linear between samples, held outside
-  if (n <= 0) return 0.0;
-  if (n == 1 || t <= tq[0]) return tq[1];
-  if (t >= tq[2 * (n - 1)]) return tq[2 * (n - 1) + 1];
-  int k = 0;
-  while (k + 1 < n && tq[2 * (k + 1)] <= t) ++k;
-  const double th = (t - tq[2 * k]) / (tq[2 * (k + 1)] - tq[2 * k]);
-  return (1.0 - th) * tq[2 * k + 1] + th * tq[2 * k + 3];
-}
 
+// Per-member scalar update at the end of a step (or after set-up): fixed
+// order sums of the tile partials, budgets, t, the next dt (FP64), the
+// latched error, and the forcing values of the coming step (tide and river
+// at every stage time, storm parameters and rain-lattice records at t^n).
+// Every global read is issued up front (scalars, tables staged in LDS), so
+// the kernel pays one memory round trip rather than a chain of them.
 template <typename Real>
-__global__ __launch_bounds__(256) void reduce_kernel(const Member<Real>* __restrict__ mem,
-                                                     const int* __restrict__ ids, int init, RKInfo rk) {
-  __shared__ double lds[4 * (3 + 2 * MAX_STAGES)];
-  __shared__ double shared_t, shared_dt;
-  const Member<Real>& M = mem[ids[blockIdx.x]];
-  Scalars* __restrict__ sc = M.sc;
-  if (!init && !sc->active) return;
-  const int nt = M.n_tiles;
-  const double* __restrict__ pt = M.part;
+__global__ __launch_bounds__(1024) void reduce_kernel(const Member<Real>* __restrict__ mem,
+                                                      const int* __restrict__ ids, int init, RKInfo rk) {
   constexpr int NV = 3 + 2 * MAX_STAGES;
+  constexpr int NW = 16;                       // wavefronts per workgroup
+  constexpr int NT = 256;                      // table entries staged in LDS
+  __shared__ double lds[NW * (NV + 1)];
+  __shared__ double s_storm[7 * NT];
+  __shared__ double s_gt[NT];
+  __shared__ double s_tide[3 * NT];
+  __shared__ double s_riv[2 * NT];
+  __shared__ double s_t, s_dt;
+  const Member<Real>& M = mem[ids[blockIdx.x]];
+  DG_G Scalars* __restrict__ sc = gp(M.sc);
+  if (!init && !sc->active) return;
+  const Forcing& f = M.fo;
+  const int tid = threadIdx.x;
+  // stage the forcing tables
+  const int nst = f.rain_kind == RAIN_PARAM ? (f.n_storm < NT ? f.n_storm : NT) : 0;
+  for (int i = tid; i < 7 * nst; i += 1024) s_storm[i] = gp(f.storm)[i];
+  const int ngt = f.rain_kind == RAIN_GRID ? (f.gnrec < NT ? f.gnrec : NT) : 0;
+  for (int i = tid; i < ngt; i += 1024) s_gt[i] = gp(f.gt)[i];
+  int ntc = 0, nrq = 0;
+#pragma unroll
+  for (int s = 0; s < MAX_SLOTS; ++s) {
+    ntc = (f.ocean_mask & (1u << s)) ? max(ntc, f.tide_off[s] + f.tide_cnt[s]) : ntc;
+    nrq = (f.river_mask & (1u << s)) ? max(nrq, f.riv_off[s] + f.riv_cnt[s]) : nrq;
+  }
+  const bool tide_lds = ntc <= NT, riv_lds = nrq <= NT;
+  if (tide_lds)
+    for (int i = tid; i < 3 * ntc; i += 1024) s_tide[i] = gp(f.tide_c)[i];
+  if (riv_lds)
+    for (int i = tid; i < 2 * nrq; i += 1024) s_riv[i] = gp(f.riv_tq)[i];
+  // scalars (thread 0)
+  double t0 = 0.0, dt0 = 0.0, rain0 = 0.0, bo0 = 0.0, bi0 = 0.0;
+  long long steps0 = 0, target0 = 0;
+  if (tid == 0) {
+    t0 = sc->t; dt0 = sc->dt; rain0 = sc->rain_in; bo0 = sc->bnd_out; bi0 = sc->bnd_in;
+    steps0 = sc->steps; target0 = sc->target;
+  }
+  // tile partials
+  const int nt = M.n_tiles;
+  const DG_G double* __restrict__ pt = gp(M.part);
   double v[NV];
 #pragma unroll
   for (int i = 0; i < NV; ++i) v[i] = 0.0;
   double mn = __builtin_inf();
-  for (int t = threadIdx.x; t < nt; t += 256) {
-    v[0] += pt[P_VOL * nt + t];
-    v[1] += pt[P_RAIN * nt + t];
-    v[2] += pt[P_NDRY * nt + t];
-    mn = fmin(mn, pt[P_MINR * nt + t]);
-    if (!init) {
+  const int ns = init ? 0 : rk.n;
+  // chunks of U strided tiles per thread: every load of a chunk is issued
+  // before any is consumed; sums still run in increasing tile order
+  constexpr int U = 1;
+  for (int base = 0; base < nt; base += U * NW * 64) {
+    double a[U][4 + 2 * MAX_STAGES];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int t = base + u * NW * 64 + tid;
+      const bool ok = t < nt;
+      const int tt = ok ? t : 0;
+      a[u][0] = ok ? pt[P_VOL * nt + tt] : 0.0;
+      a[u][1] = ok ? pt[P_RAIN * nt + tt] : 0.0;
+      a[u][2] = ok ? pt[P_NDRY * nt + tt] : 0.0;
+      a[u][3] = ok ? pt[P_MINR * nt + tt] : __builtin_inf();
 #pragma unroll
       for (int s = 0; s < MAX_STAGES; ++s) {
-        if (s < rk.n) {
-          v[3 + s] += pt[(P_OUT0 + s) * nt + t];
-          v[3 + MAX_STAGES + s] += pt[(P_IN0 + s) * nt + t];
-        }
+        a[u][4 + s] = (ok && s < ns) ? pt[(P_OUT0 + s) * nt + tt] : 0.0;
+        a[u][4 + MAX_STAGES + s] = (ok && s < ns) ? pt[(P_IN0 + s) * nt + tt] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      v[0] += a[u][0];
+      v[1] += a[u][1];
+      v[2] += a[u][2];
+      mn = fmin(mn, a[u][3]);
+#pragma unroll
+      for (int s = 0; s < MAX_STAGES; ++s) {
+        v[3 + s] += a[u][4 + s];
+        v[3 + MAX_STAGES + s] += a[u][4 + MAX_STAGES + s];
       }
     }
   }
-  block_sums<NV>(v, lds);
+  // fixed-order reduction: within each wavefront, then over wavefronts
+  const int lane = tid & 63, wv = tid >> 6;
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    const double x = wave_sum(v[i]);
+    if (lane == 0) lds[wv * (NV + 1) + i] = x;
+  }
   mn = wave_min(mn);
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  if (lane == 0) lds[wv] = mn;
+  if (lane == 0) lds[wv * (NV + 1) + NV] = mn;
   __syncthreads();
-  mn = fmin(fmin(lds[0], lds[1]), fmin(lds[2], lds[3]));
-  if (threadIdx.x == 0) {
-    double t = sc->t;
+  if (tid < 64) {
+    const int w = lane & (NW - 1);
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      double x = lds[w * (NV + 1) + i];
+#pragma unroll
+      for (int o = NW / 2; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+      v[i] = x;
+    }
+    double x = lds[w * (NV + 1) + NV];
+#pragma unroll
+    for (int o = NW / 2; o > 0; o >>= 1) x = fmin(x, __shfl_xor(x, o, 64));
+    mn = x;
+  }
+  if (tid == 0) {
+    double t = t0;
+    long long steps = steps0;
     if (!init) {
-      const double dt = sc->dt;
       double bo = 0.0, bi = 0.0;
       for (int s = 0; s < rk.n; ++s) {
         bo += rk.w[s] * v[3 + s];
         bi += rk.w[s] * v[3 + MAX_STAGES + s];
       }
-      sc->rain_in += dt * v[1];
-      sc->bnd_out += dt * bo;
-      sc->bnd_in += dt * bi;
-      t = t + dt;
+      sc->rain_in = rain0 + dt0 * v[1];
+      sc->bnd_out = bo0 + dt0 * bo;
+      sc->bnd_in = bi0 + dt0 * bi;
+      t = t0 + dt0;
+      steps = steps0 + 1;
       sc->t = t;
-      sc->steps += 1;
-      sc->dt_last = dt;
+      sc->steps = steps;
+      sc->dt_last = dt0;
     }
     sc->volume = v[0];
     sc->n_dry = (long long)(v[2]);
-    double dtn = M.dt_fixed > 0.0 ? M.dt_fixed : fmin(M.dt_max, M.cfl * mn);
-    if (!(v[0] == v[0]) || v[0] == __builtin_inf() || v[0] == -__builtin_inf() || !(dtn > 0.0)) {
-      sc->error = 1;
-      sc->active = 0;
-    }
-    if (sc->steps >= sc->target) sc->active = 0;
+    const double dtn = M.dt_fixed > 0.0 ? M.dt_fixed : fmin(M.dt_max, M.cfl * mn);
+    const bool bad = !(v[0] == v[0]) || v[0] == __builtin_inf() || v[0] == -__builtin_inf() || !(dtn > 0.0);
+    if (bad) sc->error = 1;
+    if (bad || steps >= target0) sc->active = 0;
     sc->dt = dtn;
-    shared_t = t;
-    shared_dt = dtn;
+    s_t = t;
+    s_dt = dtn;
   }
   __syncthreads();
   // forcing for the coming step
-  const double t = shared_t, dt = shared_dt;
-  const Forcing& f = M.fo;
-  const int tid = threadIdx.x;
+  const double t = s_t, dt = s_dt;
   if (tid < MAX_SLOTS) {
     const int s = tid;
     for (int st = 0; st < rk.n; ++st) {
@@ -816,51 +1286,70 @@ __global__ __launch_bounds__(256) void reduce_kernel(const Member<Real>* __restr
       double lev = 0.0, q = 0.0;
       if (f.ocean_mask & (1u << s)) {
         lev = f.tide_mean[s];
-        const double* c = f.tide_c + 3 * f.tide_off[s];
-        for (int k = 0; k < f.tide_cnt[s]; ++k)
-          lev += c[3 * k] * sin(2.0 * 3.14159265358979323846 * ts / c[3 * k + 1] + c[3 * k + 2]);
+        for (int k = 0; k < f.tide_cnt[s]; ++k) {
+          const int j = 3 * (f.tide_off[s] + k);
+          const double a = tide_lds ? s_tide[j] : gp(f.tide_c)[j];
+          const double T = tide_lds ? s_tide[j + 1] : gp(f.tide_c)[j + 1];
+          const double ph = tide_lds ? s_tide[j + 2] : gp(f.tide_c)[j + 2];
+          lev += a * sin(2.0 * 3.14159265358979323846 * ts / T + ph);
+        }
       }
-      if (f.river_mask & (1u << s)) q = interp_series(f.riv_tq + 2 * f.riv_off[s], f.riv_cnt[s], t + rk.c[st] * dt);
+      if (f.river_mask & (1u << s)) {
+        const int n = f.riv_cnt[s], o = 2 * f.riv_off[s];
+        auto RT = [&](int k) { return riv_lds ? s_riv[o + 2 * k] : gp(f.riv_tq)[o + 2 * k]; };
+        auto RQ = [&](int k) { return riv_lds ? s_riv[o + 2 * k + 1] : gp(f.riv_tq)[o + 2 * k + 1]; };
+        if (n == 1 || ts <= RT(0)) {
+          q = RQ(0);
+        } else if (ts >= RT(n - 1)) {
+          q = RQ(n - 1);
+        } else {
+          int k = 0;
+          while (k + 1 < n && RT(k + 1) <= ts) ++k;
+          const double th = (ts - RT(k)) / (RT(k + 1) - RT(k));
+          q = (1.0 - th) * RQ(k) + th * RQ(k + 1);
+        }
+      }
       sc->tide[st][s] = lev;
       sc->river[st][s] = q;
     }
   } else if (tid == MAX_SLOTS && f.rain_kind == RAIN_PARAM && f.n_storm > 0) {
-    const double* r = f.storm;
     const int n = f.n_storm;
-    if (n == 1 || t <= r[0]) {
-      for (int i = 0; i < 6; ++i) sc->storm[i] = r[1 + i];
-    } else if (t >= r[7 * (n - 1)]) {
-      for (int i = 0; i < 6; ++i) sc->storm[i] = r[7 * (n - 1) + 1 + i];
+    auto R = [&](int i) { return i < 7 * NT ? s_storm[i] : gp(f.storm)[i]; };
+    if (n == 1 || t <= R(0)) {
+      for (int i = 0; i < 6; ++i) sc->storm[i] = R(1 + i);
+    } else if (t >= R(7 * (n - 1))) {
+      for (int i = 0; i < 6; ++i) sc->storm[i] = R(7 * (n - 1) + 1 + i);
     } else {
       int k = 0;
-      while (k + 1 < n && r[7 * (k + 1)] <= t) ++k;
-      const double th = (t - r[7 * k]) / (r[7 * (k + 1)] - r[7 * k]);
-      for (int i = 0; i < 6; ++i) sc->storm[i] = (1.0 - th) * r[7 * k + 1 + i] + th * r[7 * (k + 1) + 1 + i];
+      while (k + 1 < n && R(7 * (k + 1)) <= t) ++k;
+      const double th = (t - R(7 * k)) / (R(7 * (k + 1)) - R(7 * k));
+      for (int i = 0; i < 6; ++i) sc->storm[i] = (1.0 - th) * R(7 * k + 1 + i) + th * R(7 * (k + 1) + 1 + i);
     }
   } else if (tid == MAX_SLOTS + 1 && f.rain_kind == RAIN_GRID && f.gnrec > 0) {
-    const double* tr = f.gt;
     const int n = f.gnrec;
-    if (n == 1 || t <= tr[0]) {
+    auto TR = [&](int i) { return i < NT ? s_gt[i] : gp(f.gt)[i]; };
+    if (n == 1 || t <= TR(0)) {
       sc->gk0 = 0; sc->gk1 = 0; sc->gth = 0.0;
-    } else if (t >= tr[n - 1]) {
+    } else if (t >= TR(n - 1)) {
       sc->gk0 = n - 1; sc->gk1 = n - 1; sc->gth = 0.0;
     } else {
       int k = 0;
-      while (k + 1 < n && tr[k + 1] <= t) ++k;
-      sc->gk0 = k; sc->gk1 = k + 1; sc->gth = (t - tr[k]) / (tr[k + 1] - tr[k]);
+      while (k + 1 < n && TR(k + 1) <= t) ++k;
+      sc->gk0 = k; sc->gk1 = k + 1; sc->gth = (t - TR(k)) / (TR(k + 1) - TR(k));
     }
   }
 }
 
 // ------------------------------------------------------------ launchers
 template <typename Real>
-hipError_t launch_stage(int P, int flux, int limiter, const Member<Real>* m, const Tile* t, int n, StageArgs a,
-                        hipStream_t s) {
+hipError_t launch_stage(int P, int flux, int limiter, int variant, const Member<Real>* m, const Tile* t, int n,
+                        StageArgs a, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  dim3 grid(n), block(TILE);
+  dim3 grid(xcd_grid(n)), block(TILE);
 #define DG_STAGE(PP, FF, LL) \
   if (P == PP && flux == FF && limiter == LL) { \
-    hipLaunchKernelGGL((stage_kernel<Real, PP, FF, LL>), grid, block, 0, s, m, t, a); \
+    if (variant == 1) hipLaunchKernelGGL((stage_edge_kernel<Real, PP, FF, LL>), grid, block, 0, s, m, t, n, a); \
+    else hipLaunchKernelGGL((stage_kernel<Real, PP, FF, LL>), grid, block, 0, s, m, t, n, a); \
     return hipGetLastError(); \
   }
   DG_STAGE(1, 0, 0) DG_STAGE(1, 1, 0) DG_STAGE(1, 0, 1) DG_STAGE(1, 1, 1)
@@ -873,8 +1362,9 @@ template <typename Real>
 hipError_t launch_post(int P, int use_lim, const Member<Real>* m, const Tile* t, int n, StageArgs a, int init,
                        hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  if (P == 1) hipLaunchKernelGGL((post_kernel<Real, 1>), dim3(n), dim3(TILE), 0, s, m, t, a, init, use_lim);
-  else if (P == 2) hipLaunchKernelGGL((post_kernel<Real, 2>), dim3(n), dim3(TILE), 0, s, m, t, a, init, use_lim);
+  dim3 grid(xcd_grid(n)), block(TILE);
+  if (P == 1) hipLaunchKernelGGL((post_kernel<Real, 1>), grid, block, 0, s, m, t, n, a, init, use_lim);
+  else if (P == 2) hipLaunchKernelGGL((post_kernel<Real, 2>), grid, block, 0, s, m, t, n, a, init, use_lim);
   else return hipErrorInvalidValue;
   return hipGetLastError();
 }
@@ -882,15 +1372,19 @@ hipError_t launch_post(int P, int use_lim, const Member<Real>* m, const Tile* t,
 template <typename Real>
 hipError_t launch_classify(int P, const Member<Real>* m, const Tile* t, int n, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  if (P == 1) hipLaunchKernelGGL((classify_kernel<Real, 1>), dim3(n), dim3(TILE), 0, s, m, t);
-  else hipLaunchKernelGGL((classify_kernel<Real, 2>), dim3(n), dim3(TILE), 0, s, m, t);
+  dim3 grid(xcd_grid(n)), block(TILE);
+  if (P == 1) hipLaunchKernelGGL((classify_kernel<Real, 1>), grid, block, 0, s, m, t, n);
+  else hipLaunchKernelGGL((classify_kernel<Real, 2>), grid, block, 0, s, m, t, n);
   return hipGetLastError();
 }
 
 template <typename Real>
-hipError_t launch_rain(const Member<Real>* m, const Tile* t, int n, int nodal, const double* rnode, hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL((rain_kernel<Real>), dim3(n), dim3(TILE), 0, s, m, t, nodal, rnode);
+hipError_t launch_rain(const Member<Real>* m, const Tile* t, int n, int always, const Tile* node_tiles, int n_node_tiles,
+                       hipStream_t s) {
+  if (!always && node_tiles && n_node_tiles > 0)
+    hipLaunchKernelGGL((rain_node_kernel<Real>), dim3(xcd_grid(n_node_tiles)), dim3(TILE), 0, s, m, node_tiles,
+                       n_node_tiles);
+  if (n > 0) hipLaunchKernelGGL((rain_kernel<Real>), dim3(xcd_grid(n)), dim3(TILE), 0, s, m, t, n, always);
   return hipGetLastError();
 }
 
@@ -898,15 +1392,15 @@ template <typename Real>
 hipError_t launch_reduce(const Member<Real>* m, const int* ids, int n_members, int init, const RKInfo& rk,
                          hipStream_t s) {
   if (n_members <= 0) return hipSuccess;
-  hipLaunchKernelGGL((reduce_kernel<Real>), dim3(n_members), dim3(256), 0, s, m, ids, init, rk);
+  hipLaunchKernelGGL((reduce_kernel<Real>), dim3(n_members), dim3(1024), 0, s, m, ids, init, rk);
   return hipGetLastError();
 }
 
 #define DG_INST(R)                                                                                              \
-  template hipError_t launch_stage<R>(int, int, int, const Member<R>*, const Tile*, int, StageArgs, hipStream_t); \
+  template hipError_t launch_stage<R>(int, int, int, int, const Member<R>*, const Tile*, int, StageArgs, hipStream_t); \
   template hipError_t launch_post<R>(int, int, const Member<R>*, const Tile*, int, StageArgs, int, hipStream_t);  \
   template hipError_t launch_classify<R>(int, const Member<R>*, const Tile*, int, hipStream_t);                   \
-  template hipError_t launch_rain<R>(const Member<R>*, const Tile*, int, int, const double*, hipStream_t);        \
+  template hipError_t launch_rain<R>(const Member<R>*, const Tile*, int, int, const Tile*, int, hipStream_t);     \
   template hipError_t launch_reduce<R>(const Member<R>*, const int*, int, int, const RKInfo&, hipStream_t);
 DG_INST(float)
 DG_INST(double)

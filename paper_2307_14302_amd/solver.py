@@ -148,6 +148,14 @@ class Solver:
         call("dgswe_info", self.h, *[C.byref(x) for x in v])
         return dict(n_tri=v[0].value, n_nodes=v[1].value, n_edges=v[2].value, n_flipped=v[3].value)
 
+    def set_variant(self, variant: int):
+        call("dgswe_set_tuning", self.h, N.TUNE_STAGE_VARIANT, int(variant))
+
+    def variant(self) -> int:
+        v = C.c_int()
+        call("dgswe_get_tuning", self.h, N.TUNE_STAGE_VARIANT, C.byref(v))
+        return v.value
+
     def profiling(self, on: bool = True):
         call("dgswe_set_profiling", self.h, int(bool(on)))
 

@@ -1,0 +1,271 @@
+"""GPU behaviour beyond single-run parity: the bathtub experiment printed in
+the paper, checkpoint/resume, batches (alone vs mixed, admission, polling),
+failure paths, edge cases, the five-stage scheme, rain switching, mesh
+sharing and a one-step parity check on the full 1,002,528-triangle basin."""
+import os
+
+import numpy as np
+import pytest
+
+import meshgen
+from oracle.solver import from_scenario
+from tests.parity import rel_l2
+
+pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+@pytest.fixture(scope="module")
+def dg():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2307_14302_amd as pkg
+    return pkg
+
+
+def golden():
+    vals = {}
+    for line in open(os.path.join(HERE, "golden", "bathtub.txt")):
+        line = line.split("#")[0].strip()
+        if line:
+            k, v = line.split("=")
+            vals[k.strip()] = float(v)
+    return vals
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_bathtub_72h_matches_paper(dg, precision):
+    """All 72 h of the experiment.  The elevation is the paper's to the
+    digits it prints, and over the rain period (as in the oracle's test) the
+    FP64 velocity stays within the paper's printed 0.35e-13 m/s.  At rest the
+    balanced pressure and bed-slope terms leave a round-off residual that is
+    the same every step while the surface is flat, so the momentum grows
+    linearly in time; over the full 72 h it is held to 1e-12 m/s in FP64
+    (about 1.4e-13 of the gravity wave speed of 7 m/s) and 1e-3 m/s in FP32."""
+    gv = golden()
+    sc = meshgen.bathtub()
+    s = dg.Solver.from_scenario(sc, precision=precision)
+    n_rain = int(gv["rain_hours"] * 3600 / gv["dt_s"])
+    n_dry = int(gv["dry_hours"] * 3600 / gv["dt_s"])
+    vel = []                      # |q| / H with H >= 4 m, every 2 h
+    for _ in range(n_rain // 1440):
+        s.step(1440)
+        v = s.state("vertex")
+        vel.append(np.abs(v[:, 1:]).max() / 4.0)
+    s.set_rain({"kind": "none"})
+    for _ in range(n_dry // 1440):
+        s.step(1440)
+        v = s.state("vertex")
+        vel.append(np.abs(v[:, 1:]).max() / 4.0)
+    print(precision, "largest velocity every 2 h:", " ".join(f"{x:.2e}" for x in vel), flush=True)
+    vmax = max(vel)
+    m = s.mass()
+    assert m["steps"] == n_rain + n_dry and abs(m["t"] - 259200.0) < 1e-6
+    zeta = v[:, 0]
+    exact = gv["rain_rate_m_per_s"] * gv["rain_hours"] * 3600
+    if precision == "fp64":
+        assert round(float(zeta.mean()), 4) == gv["final_elevation_m"]
+        assert np.abs(zeta - exact).max() < 1e-10
+        assert max(vel[:12]) <= gv["max_velocity_m_per_s"], vel[:12]
+        assert vmax <= 1e-12, vmax
+    else:
+        # FP32 state: 17,280 rain increments of 3.5e-5 m onto ~0.6 m
+        assert np.abs(zeta - exact).max() < 5e-4
+        assert vmax <= 1e-3, vmax
+    s.close()
+
+
+def test_checkpoint_resume_is_bitwise(dg):
+    sc = meshgen.small_mixed(seed=21, nx=24, ny=12, flux="llf", limiter=True, rain_kind="parametric")
+    a = dg.Solver.from_scenario(sc)
+    a.step(60)
+    w = a.state("modal")
+    t = a.mass()["t"]
+    a.step(40)
+    b = dg.Solver.from_scenario(sc)
+    b.set_state(w, t)
+    b.step(40)
+    assert np.array_equal(a.state(), b.state())
+    assert a.mass()["t"] == b.mass()["t"]
+    a.close(); b.close()
+
+
+def _member(dg, sc, precision="fp32", **over):
+    return dg.Solver.from_scenario(sc, precision=precision, **over)
+
+
+def test_batch_members_match_alone_bitwise(dg):
+    scs = [meshgen.small_mixed(seed=31, nx=30, ny=14, rain_kind="gridded"),
+           meshgen.basin_window(50, seed=meshgen.seed_for(3, 1)),
+           meshgen.small_mixed(seed=32, nx=18, ny=9, p=2, flux="llf", limiter=True, rain_kind="parametric"),
+           meshgen.basin_window(36, seed=meshgen.seed_for(3, 2))]
+    steps = [40, 25, 30, 40]
+    alone = []
+    for sc, n in zip(scs, steps):
+        s = _member(dg, sc)
+        s.step(n)
+        alone.append((s.state(), s.mass()))
+        s.close()
+    members = [_member(dg, sc) for sc in scs]
+    b = dg.Batch({"precision": "fp32"})
+    slots = [b.add(m, n) for m, n in zip(members, steps)]
+    done = []
+    for _ in range(50):
+        b.step(1)
+        done = b.poll()
+        if len(done) == len(slots):
+            break
+    assert sorted(done) == sorted(slots)
+    for m, (w, mass) in zip(members, alone):
+        assert np.array_equal(m.state(), w)
+        assert m.mass() == mass
+    for sl in slots:
+        b.retire(sl)
+    # retired members can run on their own again
+    members[0].step(1)
+    assert members[0].mass()["steps"] == steps[0] + 1
+    b.close()
+    for m in members:
+        m.close()
+
+
+def test_batch_admission_budget(dg):
+    from paper_2307_14302_amd import _native as N
+    sc = meshgen.basin_window(40)
+    a, bm = _member(dg, sc), _member(dg, sc)
+    fp = a.footprint()
+    b = dg.Batch({"precision": "fp32"}, budget_bytes=int(1.5 * fp))
+    b.add(a, 10)
+    with pytest.raises(N.DgsweError) as ei:
+        b.add(bm, 10)
+    assert ei.value.code == N.DGSWE_EBUDGET
+    n, f = b.info()
+    assert n == 1 and f == fp
+    with pytest.raises(N.DgsweError):
+        b.add(_member(dg, sc, precision="fp64"), 5)          # precision differs
+    b.close()
+    a.close(); bm.close()
+
+
+def test_invalid_inputs_are_rejected(dg):
+    from paper_2307_14302_amd import _native as N
+    sc = meshgen.small_mixed(seed=3, nx=8, ny=4)
+    m = sc.mesh
+    s = dg.Solver(dict(sc.params))
+    bad = m.tri.copy(); bad[0, 1] = 10 ** 6
+    with pytest.raises(N.DgsweError, match="out of range"):
+        s.upload_mesh(m.xy, m.hb, m.fric, bad)
+    deg = m.tri.copy(); deg[0] = [0, 1, 1]
+    with pytest.raises(N.DgsweError, match="zero area"):
+        s.upload_mesh(m.xy, m.hb, m.fric, deg)
+    tri3 = np.vstack([m.tri, m.tri[:1]])
+    with pytest.raises(N.DgsweError, match="more than two"):
+        s.upload_mesh(m.xy, m.hb, m.fric, tri3)
+    with pytest.raises(N.DgsweError, match="not on the mesh boundary"):
+        s.upload_mesh(m.xy, m.hb, m.fric, m.tri, np.array([[0, m.n_nodes - 1]]), np.array([1]), np.array([0]))
+    with pytest.raises(N.DgsweError, match="no mesh"):
+        s.step(1)
+    s.upload_mesh(m.xy, m.hb, m.fric, m.tri, m.bedges, m.btype, m.bslot)
+    with pytest.raises(N.DgsweError, match="no state"):
+        s.step(1)
+    z = sc.zeta0.copy(); z[3] = np.nan
+    with pytest.raises(N.DgsweError, match="non-finite"):
+        s.set_initial_nodal(z, sc.qx0, sc.qy0)
+    with pytest.raises(N.DgsweError):
+        s.set_tide(99, 0.0, [])
+    with pytest.raises(N.DgsweError):
+        s.set_river(1, [0.0, 0.0], [1.0, 2.0])
+    s.close()
+
+
+def test_nonfinite_volume_is_latched(dg):
+    from paper_2307_14302_amd import _native as N
+    sc = meshgen.small_mixed(seed=3, nx=8, ny=4)
+    s = dg.Solver.from_scenario(sc)
+    w = s.state()
+    w[:, 0, 0] = 1e308          # the volume overflows to inf on the next reduction
+    s.set_state(w, 0.0)
+    with pytest.raises(N.DgsweError) as ei:
+        s.mass()
+    assert ei.value.code == N.DGSWE_ENONFINITE
+    s.close()
+
+
+def test_empty_mesh_and_tiny_meshes(dg):
+    s = dg.Solver({"dt_fixed": 2.0})
+    s.upload_mesh(np.zeros((0, 2)), np.zeros(0), np.zeros(0), np.zeros((0, 3), dtype=np.int32))
+    s.set_initial_nodal(np.zeros(0), np.zeros(0), np.zeros(0))
+    s.step(5)
+    m = s.mass()
+    assert m["steps"] == 5 and m["t"] == 10.0 and m["volume"] == 0.0
+    s.close()
+    # one triangle, all land walls
+    xy = np.array([[0.0, 0.0], [10.0, 0.0], [0.0, 10.0]])
+    s = dg.Solver({"dt_fixed": 0.1})
+    s.upload_mesh(xy, np.full(3, 2.0), np.full(3, 0.02), np.array([[0, 1, 2]]))
+    s.set_initial_nodal(np.array([0.1, 0.0, -0.1]), np.zeros(3), np.zeros(3))
+    V0 = s.mass()["volume"]
+    s.step(20)
+    assert abs(s.mass()["volume"] - V0) < 1e-12 * V0
+    s.close()
+
+
+def test_five_stage_scheme_parity(dg):
+    sc = meshgen.small_mixed(seed=5, nx=20, ny=10, flux="llf", limiter=True, rain_kind="gridded")
+    sc.params.update(rk_stages=5, cfl=0.5)
+    gpu = dg.Solver.from_scenario(sc)
+    orc = from_scenario(sc)
+    gpu.step(30)
+    orc.step(30)
+    assert rel_l2(gpu.state(), orc.w, orc).max() < 1e-10
+    mg, mo = gpu.mass(), orc.mass_totals()
+    for k in ("t", "volume", "rain_in", "bnd_in", "bnd_out"):
+        assert abs(mg[k] - mo[k]) <= 1e-10 * max(1.0, abs(mo[k])), k
+    gpu.close()
+
+
+def test_rain_switching_and_mesh_sharing(dg):
+    sc = meshgen.small_mixed(seed=8, nx=20, ny=10, rain_kind="nodal")
+    gpu = dg.Solver.from_scenario(sc)
+    twin = dg.Solver.from_scenario(sc, mesh_from=gpu)
+    orc = from_scenario(sc)
+    for s in (gpu, twin):
+        s.step(10)
+    orc.step(10)
+    park = meshgen.small_mixed(seed=8, nx=20, ny=10, rain_kind="parametric").rain
+    for s in (gpu, twin):
+        s.set_rain(park)
+    orc.rain = park
+    for s in (gpu, twin):
+        s.step(10)
+    orc.step(10)
+    assert rel_l2(gpu.state(), orc.w, orc).max() < 1e-10
+    assert np.array_equal(gpu.state(), twin.state())
+    info = gpu.info()
+    assert info["n_tri"] == sc.mesh.n_tri and info["n_flipped"] == 0
+    twin.close(); gpu.close()
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-11), ("fp32", 2e-5)])
+def test_full_size_basin_one_step(dg, precision, tol):
+    """The benchmark workload at full size (1,002,528 triangles): 20 GPU
+    steps, then one more step on the GPU and in the oracle from the same
+    state; every element is compared."""
+    sc = meshgen.basin(708)
+    gpu = dg.Solver.from_scenario(sc, precision=precision)
+    gpu.step(20)
+    w = gpu.state()
+    m0 = gpu.mass()
+    orc = from_scenario(sc)
+    orc.set_state(w, m0["t"], post=False)
+    assert abs(orc.dt - m0["dt_next"]) <= 1e-6 * m0["dt_next"]
+    orc.dt = m0["dt_next"]
+    gpu.step(1)
+    orc.step(1)
+    err = rel_l2(gpu.state(), orc.w, orc)
+    print(precision, "full-size one-step rel L2", err, flush=True)
+    assert err.max() < tol, err
+    m1 = gpu.mass()
+    assert abs((m1["rain_in"] - m0["rain_in"]) - orc.rain_in) <= 1e-9 * orc.rain_in
+    assert np.array_equal(gpu.flags().astype(bool), orc.flags) or precision == "fp32"
+    gpu.close()
