@@ -19,5 +19,5 @@ from .generators import (  # noqa: F401
     LAND, OCEAN, RIVER, OUTFLOW,
     Mesh, Scenario,
     rect_grid, channel_c1, bathtub, basin, basin_window, small_mixed, lake_at_rest,
-    parametric_track, gridded_field, seed_for,
+    parametric_track, gridded_field, seed_for, dam_break, inclined_plane,
 )

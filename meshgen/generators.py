@@ -358,3 +358,46 @@ def lake_at_rest(seed: int = 3, nx: int = 16, ny: int = 10, level: float = 0.7,
     return Scenario("lake_at_rest", mesh, zeta0, np.zeros_like(hb), np.zeros_like(hb),
                     default_params(p=p, flux=flux, friction="manning", limiter=False),
                     tides={0: (level, np.zeros((0, 3)))})
+
+
+# ---------------------------------------------------------------------------
+# textbook checks: dam breaks on a strip, rain on an inclined plane
+# ---------------------------------------------------------------------------
+def dam_break(nx: int = 200, *, h_left: float = 2.0, h_right: float = 1.0, L: float = 200.0,
+              W: float = 2.0, H0: float = 1e-3, limiter: bool = True) -> Scenario:
+    """Quasi-1D strip x in (-L/2, L/2), nx x 1 quads, flat bed at the datum
+    (hb = 0), walls all round, fluid at rest with depth h_left for x < 0 and
+    h_right for x > 0 (h_right = 0 is a dry bed).  No friction, no rain.
+    The nodal zeta0 puts the nodes on x = 0 on the right; a piecewise
+    constant start (element means h_left / h_right, the dam on the quad
+    boundary at x = 0 for even nx) is set from the element centroids."""
+    xy, tri, sides = rect_grid(nx, 1, L, W, x0=-L / 2)
+    be, bt, bs = _bnd(sides, {})
+    hb = np.zeros(len(xy))
+    mesh = Mesh(xy, tri, hb, np.zeros(len(hb)), be, bt, bs)
+    # node values are set so that each element holds one side's depth: the
+    # dam sits on the quad boundary at x = 0 (nx even)
+    zeta0 = np.where(xy[:, 0] < 0.0, h_left, h_right).astype(np.float64)
+    sc = Scenario("dam_break", mesh, zeta0, np.zeros(len(hb)), np.zeros(len(hb)),
+                  default_params(flux="roe", friction="manning", limiter=limiter, cfl=0.3, H0=H0),
+                  n_steps=0)
+    return sc
+
+
+def inclined_plane(nx: int = 96, *, L: float = 24.0, W: float = 0.196, slope: float = 0.015,
+                   rain: float = 8.33e-4, manning: float = 0.009, H0: float = 1e-4) -> Scenario:
+    """Rain on an initially dry plane (Sec. 3.2, condition (A)): a 24 m flume
+    of width 0.196 m at sin(theta) = 0.015, uniform rain 0.0833 cm/s,
+    Manning n = 0.009.  The bed falls toward x = L (hb = slope * x, positive
+    downward); walls on the sides and the upper end, free outflow at x = L;
+    dry start (zeta = -hb).  A dry plane has no wave speed, so the step is
+    capped at 0.02 s (the paper ran at a fixed 0.001 s)."""
+    xy, tri, sides = rect_grid(nx, 1, L, W)
+    hb = slope * xy[:, 0]
+    be, bt, bs = _bnd(sides, {"right": (OUTFLOW, 0)})
+    mesh = Mesh(xy, tri, hb, np.full(len(hb), manning), be, bt, bs)
+    z = np.zeros(len(hb))
+    return Scenario("inclined_plane", mesh, -hb, z.copy(), z.copy(),
+                    default_params(flux="roe", friction="manning", limiter=False, cfl=0.3, H0=H0,
+                                   dt_max=0.02),
+                    rain={"kind": "nodal", "r": np.full(len(hb), rain)}, n_steps=0)
