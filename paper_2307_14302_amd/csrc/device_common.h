@@ -126,6 +126,22 @@ template <typename R> DG_DEV R dabs(R a) { return a < R(0) ? -a : a; }
 // pressure g/2 (H^2 - hb^2) = g/2 zeta (zeta + 2 hb) (Eq. SWE).
 template <typename R> struct W3 { R z, x, y; };
 
+// Inverse depth and gravity-wave speed of one side: ih = 1 / max(H, H0),
+// c = sqrt(g max(H, 0)).  FP32 takes both from one reciprocal square root
+// (sqrt(x) = x / sqrt(x), 1/x = (1/sqrt(x))^2; below H0 the clamped inverse
+// is the constant 1/H0); FP64 divides and takes the square root.
+template <typename R>
+DG_DEV void depth_inv_speed(R H, R g, R H0, R& ih, R& c) {
+  if constexpr (sizeof(R) == 4) {
+    const float r = __builtin_amdgcn_rsqf(dmax(H, 1e-30f));
+    ih = H >= H0 ? r * r : __builtin_amdgcn_rcpf(H0);
+    c = __builtin_amdgcn_sqrtf(g) * (dmax(H, 0.0f) * r);
+  } else {
+    ih = R(1) / dmax(H, H0);
+    c = dsqrt(g * dmax(H, R(0)));
+  }
+}
+
 template <typename R>
 DG_DEV void flux_normal(const W3<R>& w, R hb, R nx, R ny, R g, R H0, R& f0, R& f1, R& f2) {
   const R Hs = dmax(w.z + hb, H0);
@@ -141,38 +157,51 @@ DG_DEV void flux_normal(const W3<R>& w, R hb, R nx, R ny, R g, R H0, R& f0, R& f
 // |u.n| + sqrt(g H) on the two sides.
 template <typename R>
 DG_DEV void flux_llf(const W3<R>& a, const W3<R>& b, R hb, R nx, R ny, R g, R H0, R* F) {
-  R fa0, fa1, fa2, fb0, fb1, fb2;
-  flux_normal(a, hb, nx, ny, g, H0, fa0, fa1, fa2);
-  flux_normal(b, hb, nx, ny, g, H0, fb0, fb1, fb2);
-  const R Ha = a.z + hb, Hb = b.z + hb;
-  const R ua = (a.x * nx + a.y * ny) * rcp(dmax(Ha, H0));
-  const R ub = (b.x * nx + b.y * ny) * rcp(dmax(Hb, H0));
-  const R la = dabs(ua) + dsqrt(g * dmax(Ha, R(0)));
-  const R lb = dabs(ub) + dsqrt(g * dmax(Hb, R(0)));
-  const R lam = dmax(la, lb);
-  F[0] = R(0.5) * (fa0 + fb0) - R(0.5) * lam * (b.z - a.z);
-  F[1] = R(0.5) * (fa1 + fb1) - R(0.5) * lam * (b.x - a.x);
-  F[2] = R(0.5) * (fa2 + fb2) - R(0.5) * lam * (b.y - a.y);
+  R ia, ib, ca, cb;
+  depth_inv_speed(a.z + hb, g, H0, ia, ca);
+  depth_inv_speed(b.z + hb, g, H0, ib, cb);
+  const R qna = a.x * nx + a.y * ny, qnb = b.x * nx + b.y * ny;
+  const R ua = qna * ia, ub = qnb * ib;
+  const R Pa = R(0.5) * g * a.z * (a.z + R(2) * hb), Pb = R(0.5) * g * b.z * (b.z + R(2) * hb);
+  const R lam = dmax(dabs(ua) + ca, dabs(ub) + cb);
+  F[0] = R(0.5) * (qna + qnb) - R(0.5) * lam * (b.z - a.z);
+  F[1] = R(0.5) * ((a.x * ua + Pa * nx) + (b.x * ub + Pb * nx)) - R(0.5) * lam * (b.x - a.x);
+  F[2] = R(0.5) * ((a.y * ua + Pa * ny) + (b.y * ub + Pb * ny)) - R(0.5) * lam * (b.y - a.y);
 }
 
 // Roe: linearisation about the Roe average in the frame (n, t):
 // waves u~n - c~, u~n, u~n + c~ with c~ = sqrt(g (Ha + Hb)/2); right
 // eigenvectors (1, u~n - c~, u~t), (0, 0, 1), (1, u~n + c~, u~t); with a
 // continuous bed the depth jump equals the elevation jump.  No entropy fix.
+// The Roe average of a velocity is (q_a/sqrt(Ha) + q_b/sqrt(Hb)) / (sqrt(Ha)
+// + sqrt(Hb)).
 template <typename R>
 DG_DEV void flux_roe(const W3<R>& a, const W3<R>& b, R hb, R nx, R ny, R g, R H0, R* F) {
-  R fa0, fa1, fa2, fb0, fb1, fb2;
-  flux_normal(a, hb, nx, ny, g, H0, fa0, fa1, fa2);
-  flux_normal(b, hb, nx, ny, g, H0, fb0, fb1, fb2);
   const R Ha = dmax(a.z + hb, H0), Hb = dmax(b.z + hb, H0);
   const R qna = a.x * nx + a.y * ny, qta = -a.x * ny + a.y * nx;
   const R qnb = b.x * nx + b.y * ny, qtb = -b.x * ny + b.y * nx;
-  const R sa = dsqrt(Ha), sb = dsqrt(Hb);
+  R sa, sb, ia, ib, ra, rb, c, i2c;
+  if constexpr (sizeof(R) == 4) {
+    ra = __builtin_amdgcn_rsqf(Ha);
+    rb = __builtin_amdgcn_rsqf(Hb);
+    sa = Ha * ra; sb = Hb * rb;
+    ia = ra * ra; ib = rb * rb;
+    const R c2 = R(0.5) * g * (Ha + Hb);
+    const R rc = __builtin_amdgcn_rsqf(c2);
+    c = c2 * rc;
+    i2c = R(0.5) * rc;
+  } else {
+    sa = dsqrt(Ha); sb = dsqrt(Hb);
+    ia = R(1) / Ha; ib = R(1) / Hb;
+    ra = sa * ia; rb = sb * ib;
+    c = dsqrt(R(0.5) * g * (Ha + Hb));
+    i2c = R(1) / (R(2) * c);
+  }
   const R isum = rcp(sa + sb);
-  const R un = (sa * (qna * rcp(Ha)) + sb * (qnb * rcp(Hb))) * isum;
-  const R ut = (sa * (qta * rcp(Ha)) + sb * (qtb * rcp(Hb))) * isum;
-  const R c = dsqrt(R(0.5) * g * (Ha + Hb));
-  const R i2c = rcp(R(2) * c);
+  const R un = (qna * ra + qnb * rb) * isum;
+  const R ut = (qta * ra + qtb * rb) * isum;
+  const R Pa = R(0.5) * g * a.z * (a.z + R(2) * hb), Pb = R(0.5) * g * b.z * (b.z + R(2) * hb);
+  const R ua = qna * ia, ub = qnb * ib;
   const R dH = b.z - a.z, dqn = qnb - qna, dqt = qtb - qta;
   const R a1 = ((un + c) * dH - dqn) * i2c;
   const R a3 = (dqn - (un - c) * dH) * i2c;
@@ -181,9 +210,9 @@ DG_DEV void flux_roe(const W3<R>& a, const W3<R>& b, R hb, R nx, R ny, R g, R H0
   const R d0 = l1 + l3;
   const R dn = l1 * (un - c) + l3 * (un + c);
   const R dt = (l1 + l3) * ut + l2;
-  F[0] = R(0.5) * (fa0 + fb0) - R(0.5) * d0;
-  F[1] = R(0.5) * (fa1 + fb1) - R(0.5) * (dn * nx - dt * ny);
-  F[2] = R(0.5) * (fa2 + fb2) - R(0.5) * (dn * ny + dt * nx);
+  F[0] = R(0.5) * (qna + qnb) - R(0.5) * d0;
+  F[1] = R(0.5) * ((a.x * ua + Pa * nx) + (b.x * ub + Pb * nx)) - R(0.5) * (dn * nx - dt * ny);
+  F[2] = R(0.5) * ((a.y * ua + Pa * ny) + (b.y * ub + Pb * ny)) - R(0.5) * (dn * ny + dt * nx);
 }
 
 template <int FLUX, typename R>

@@ -346,6 +346,21 @@ DG_DEV void boundary_point(const W3<Real>& a, Real hg, Real nx, Real ny, Real g,
   }
 }
 
+// Length of an edge vector and its inverse (FP32: one reciprocal square
+// root).  Both neighbours of an edge hold the same vector up to sign, so they
+// obtain the same bits.
+template <typename Real>
+DG_DEV void edge_length(Real ex, Real ey, Real& ell, Real& il) {
+  const Real l2 = ex * ex + ey * ey;
+  if constexpr (sizeof(Real) == 4) {
+    il = __builtin_amdgcn_rsqf(l2);
+    ell = l2 * il;
+  } else {
+    ell = dsqrt(l2);
+    il = Real(1) / ell;
+  }
+}
+
 // Area integrals: volume flux, bed slope and bottom friction (Eq. SWE).
 template <typename Real, int P>
 DG_DEV void area_terms(const Real (&w)[3][Tab<P>::NP], const Real (&hb)[3], Real cx0, Real cx1, Real cy0, Real cy1,
@@ -367,11 +382,19 @@ DG_DEV void area_terms(const Real (&w)[3][Tab<P>::NP], const Real (&hb)[3], Real
     const double qr = Tab<P>::qr(q), qs = Tab<P>::qs(q);
     const Real hq = Real(lam_(0, qr, qs)) * hb[0] + Real(lam_(1, qr, qs)) * hb[1] + Real(lam_(2, qr, qs)) * hb[2];
     const Real Hs = dmax(wq[0] + hq, H0);
-    const Real iH = rcp(Hs);
+    Real iH, Hm43;   // 1/H and (Manning) H^(-4/3)
+    if constexpr (sizeof(Real) == 4) {
+      const float r = __builtin_amdgcn_rsqf(Hs);
+      iH = r * r;
+      Hm43 = friction == 0 ? __builtin_amdgcn_exp2f(-1.3333333333333333f * __builtin_amdgcn_logf(Hs)) : 0.0f;
+    } else {
+      iH = Real(1) / Hs;
+      Hm43 = friction == 0 ? Real(1) / pow43(Hs) : Real(0);
+    }
     const Real u = wq[1] * iH, vv_ = wq[2] * iH;
     const Real Pq = Real(0.5) * g * wq[0] * (wq[0] + Real(2) * hq);
     const Real spd = dsqrt(wq[1] * wq[1] + wq[2] * wq[2]) * iH;
-    const Real tau = (friction == 0) ? gn2 * spd * rcp(pow43(Hs)) : fc * spd * iH;
+    const Real tau = (friction == 0) ? gn2 * spd * Hm43 : fc * spd * iH;
     const Real Fx[3] = {wq[1], wq[1] * u + Pq, wq[2] * u};
     const Real Fy[3] = {wq[2], wq[1] * vv_, wq[2] * vv_ + Pq};
     const Real s1 = g * wq[0] * dhx - tau * wq[1];
@@ -577,8 +600,8 @@ __global__ DG_STAGE_ATTR void stage_kernel(const Member<Real>* __restrict__ mem,
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     const int k1 = (k + 1) % 3;
-    const Real ell = dsqrt(d.ex[k] * d.ex[k] + d.ey[k] * d.ey[k]);
-    const Real il = rcp(ell);
+    Real ell, il;
+    edge_length<Real>(d.ex[k], d.ey[k], ell, il);
     const Real nx = d.ey[k] * il, ny = -d.ex[k] * il;
     const Real half = Real(0.5) * ell;
     const int nb = gp(M.nbr)[k * E + ec];
@@ -677,12 +700,11 @@ __global__ DG_STAGE_ATTR void stage_edge_kernel(const Member<Real>* __restrict__
   __shared__ Real s_hb[3][TILE];
   __shared__ Real s_flux[3 * NG * 3][TILE];            // [(k NG + g) 3 + var][element], scaled by (l/2) w_g
   __shared__ Real s_ev[6][TILE];
-  __shared__ int s_nbr[3][TILE];
-  __shared__ uint8_t s_nk[TILE];
   __shared__ uint8_t s_flag[TILE];
-  __shared__ uint16_t s_list[3 * TILE];
+  // edge list; after phase B the same memory holds the block's partial sums
+  __shared__ double s_lbuf[3 * TILE / 2];
+  uint32_t* s_list = reinterpret_cast<uint32_t*>(s_lbuf);
   __shared__ int s_wsum[4];
-  __shared__ double lds[4 * 6];
   const int ti = xcd_tile();
   if (ti >= n_tiles) return;
   const Tile tl = tiles[ti];
@@ -724,22 +746,28 @@ __global__ DG_STAGE_ATTR void stage_edge_kernel(const Member<Real>* __restrict__
     s_ev[2 * k + 1][el] = d.ey[k];
   }
   s_flag[el] = Fin[ec] & 1;
-  s_nk[el] = gp(M.nk)[ec];
+  const int nkp = gp(M.nk)[ec];
   double rain_part;
   const Real Rv = element_rain<Real>(M, A, E, e, ec, valid, d.ex, d.ey, rain_part);
-  int own = 0;
-  int nbk[3];
+  // The edges this element evaluates, in three classes listed one after the
+  // other so that a wavefront mostly runs one code path: (0) interior edges
+  // inside the tile, owned by the lower id; (1) edges to other tiles;
+  // (2) boundary edges.  Entry: l | k << 8 | kn << 10 | ln << 12.
+  uint32_t ent[3];
+  int cls[3];
+  int packed = 0;                                    // 10-bit count per class
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    nbk[k] = nbr[k * E + ec];
-    s_nbr[k][el] = nbk[k];
-    const bool o = valid && (nbk[k] < 0 || nbk[k] < t0 || nbk[k] >= tend || e < nbk[k]);
-    own |= int(o) << k;
+    const int nb = nbr[k * E + ec];
+    const int kn = (nkp >> (2 * k)) & 3;
+    const bool inside = nb >= t0 && nb < tend;
+    cls[k] = !valid ? 3 : nb < 0 ? 2 : !inside ? 1 : (e < nb ? 0 : 3);
+    ent[k] = uint32_t(el) | uint32_t(k) << 8 | uint32_t(kn) << 10 | uint32_t(inside ? nb - t0 : 0) << 12;
+    packed += cls[k] < 3 ? 1 << (10 * cls[k]) : 0;
   }
-  const int cnt = (own & 1) + ((own >> 1) & 1) + ((own >> 2) & 1);
-  // block-wide exclusive scan of the counts
+  // block-wide exclusive scan of the packed counts
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  int incl = cnt;
+  int incl = packed;
 #pragma unroll
   for (int o = 1; o < 64; o <<= 1) {
     const int y = __shfl_up(incl, o, 64);
@@ -756,26 +784,36 @@ __global__ DG_STAGE_ATTR void stage_edge_kernel(const Member<Real>* __restrict__
   int base = 0;
 #pragma unroll
   for (int i = 0; i < 4; ++i) base += (i < wv) ? s_wsum[i] : 0;
-  const int n_list = s_wsum[0] + s_wsum[1] + s_wsum[2] + s_wsum[3];
+  const int tot = s_wsum[0] + s_wsum[1] + s_wsum[2] + s_wsum[3];
+  const int n0 = tot & 1023, n1 = (tot >> 10) & 1023, n2 = tot >> 20;
+  const int n_list = n0 + n1 + n2;
   {
-    int pos = base + incl - cnt;
+    const int ex_ = base + incl - packed;
+    int pos[3] = {ex_ & 1023, n0 + ((ex_ >> 10) & 1023), n0 + n1 + (ex_ >> 20)};
 #pragma unroll
-    for (int k = 0; k < 3; ++k)
-      if ((own >> k) & 1) s_list[pos++] = uint16_t((el << 2) | k);
+    for (int k = 0; k < 3; ++k) {
+      const int c = cls[k];
+      if (c < 3) {
+        const int at = c == 0 ? pos[0]++ : c == 1 ? pos[1]++ : pos[2]++;
+        s_list[at] = ent[k];
+      }
+    }
   }
   __syncthreads();
 
   // ---- phase B: edge fluxes, scaled by (l/2) w_g, into s_flux
   double bout = 0.0, bin = 0.0;
   for (int it = threadIdx.x; it < n_list; it += TILE) {
-    const int ent = s_list[it];
-    const int l = ent >> 2, k = ent & 3;
+    const uint32_t ent = s_list[it];
+    const int l = ent & 255, k = (ent >> 8) & 3, kn = (ent >> 10) & 3;
     const int k1 = k == 2 ? 0 : k + 1;
     const int eg = t0 + l;
-    const int nb = s_nbr[k][l];
+    const bool in_tile = it < n0;
+    // class 0: the neighbour's id is in the entry; otherwise re-read (cached)
+    const int nb = in_tile ? t0 + int(ent >> 12) : nbr[k * E + eg];
     const Real exk = s_ev[2 * k][l], eyk = s_ev[2 * k + 1][l];
-    const Real ell = dsqrt(exk * exk + eyk * eyk);
-    const Real il = rcp(ell);
+    Real ell, il;
+    edge_length<Real>(exk, eyk, ell, il);
     const Real nx = eyk * il, ny = -exk * il;
     const Real half = Real(0.5) * ell;
     Real Oa[3], Oc[3], Ob[3];
@@ -787,9 +825,7 @@ __global__ DG_STAGE_ATTR void stage_edge_kernel(const Member<Real>* __restrict__
     }
     const Real hA = s_hb[k][l], hB = s_hb[k1][l];
     if (nb >= 0) {
-      const int kn = (s_nk[l] >> (2 * k)) & 3;
       const int kn1 = kn == 2 ? 0 : kn + 1;
-      const bool in_tile = nb >= t0 && nb < tend;
       Real Na[3], Nc[3], Nb[3];
       bool nflag;
       if (in_tile) {
@@ -886,7 +922,7 @@ __global__ DG_STAGE_ATTR void stage_edge_kernel(const Member<Real>* __restrict__
       }
     }
   finish_stage<Real, P, LIM>(M, A, tl.tile, e, ec, valid, E, d.w, acc, d.hb, d.ex, d.ey, d.detJ, d.idet, dt, bout,
-                             bin, Rv, rain_part, lds);
+                             bin, Rv, rain_part, s_lbuf);
 }
 
 // ------------------------------------------------------------ post kernel
