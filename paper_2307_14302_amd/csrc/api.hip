@@ -191,7 +191,7 @@ struct dgswe_batch {
     int p, flux, limiter, variant;
     RKTable rk;
     std::vector<int> members;       // indices into the member array
-    int n_tiles = 0, n_node_tiles = 0;
+    int n_tiles = 0, n_node_tiles = 0, max_chunks = 1;
     DevBuf tiles, node_tiles, ids;
     bool has_rain = false;
   };
@@ -240,6 +240,8 @@ Member<Real> member_struct(const dgswe_ctx* c) {
   m.R = c->R.as<Real>();
   m.rn = c->rnode.as<double>();
   m.part = c->part.as<double>();
+  m.red = m.part ? m.part + size_t(NPART) * std::max(c->n_tiles, 1) : nullptr;
+  m.red_count = m.red ? reinterpret_cast<unsigned*>(m.red + size_t(NRED) * red_chunks(c->n_tiles)) : nullptr;
   m.sc = c->sc.as<Scalars>();
   m.fo = c->fo;
   return m;
@@ -333,8 +335,8 @@ StageArgs stage_args(const RKTable& T, int i) {
 // stages): rain, stages (+ post when limiting), reduce.
 template <typename Real>
 int enqueue_step_group(const Member<Real>* d_m, const Tile* d_t, int n_tiles, const Tile* d_nt, int n_node_tiles,
-                       const int* d_ids, int n_members, int p, int flux, int limiter, int variant, const RKTable& T,
-                       bool rain, hipStream_t s, dgswe_ctx* prof) {
+                       const int* d_ids, int n_members, int max_chunks, int p, int flux, int limiter, int variant,
+                       const RKTable& T, bool rain, hipStream_t s, dgswe_ctx* prof) {
   if (rain) {
     ProfScope ps(prof, K_RAIN);
     // nodal rates at t^n; the first stage averages them per element
@@ -357,7 +359,7 @@ int enqueue_step_group(const Member<Real>* d_m, const Tile* d_t, int n_tiles, co
     }
   }
   ProfScope ps(prof, K_REDUCE);
-  HIPCHK(launch_reduce<Real>(d_m, d_ids, n_members, 0, rk_info(T), s));
+  HIPCHK(launch_reduce<Real>(d_m, d_ids, n_members, max_chunks, 0, rk_info(T), s));
   return DGSWE_OK;
 }
 
@@ -365,17 +367,20 @@ int ctx_enqueue_step(dgswe_ctx* c) {
   const bool rain = c->fo.rain_kind != RAIN_CONST;
   if (c->rs == 8)
     return enqueue_step_group<double>(c->memb.as<Member<double>>(), c->tiles.as<Tile>(), c->n_tiles,
-                                      c->node_tiles.as<Tile>(), c->n_node_tiles, c->ids.as<int>(), 1, c->prm.p, c->prm.flux, c->prm.limiter, c->variant, c->rk, rain, c->stream, c);
+                                      c->node_tiles.as<Tile>(), c->n_node_tiles, c->ids.as<int>(), 1, red_chunks(c->n_tiles),
+                                      c->prm.p, c->prm.flux, c->prm.limiter, c->variant, c->rk, rain, c->stream, c);
   return enqueue_step_group<float>(c->memb.as<Member<float>>(), c->tiles.as<Tile>(), c->n_tiles,
-                                   c->node_tiles.as<Tile>(), c->n_node_tiles, c->ids.as<int>(), 1,
+                                   c->node_tiles.as<Tile>(), c->n_node_tiles, c->ids.as<int>(), 1, red_chunks(c->n_tiles),
                                    c->prm.p, c->prm.flux, c->prm.limiter, c->variant, c->rk, rain, c->stream, c);
 }
 
 int ctx_reduce_init(dgswe_ctx* c) {
   if (c->rs == 8)
-    HIPCHK(launch_reduce<double>(c->memb.as<Member<double>>(), c->ids.as<int>(), 1, 1, rk_info(c->rk), c->stream));
+    HIPCHK(launch_reduce<double>(c->memb.as<Member<double>>(), c->ids.as<int>(), 1, red_chunks(c->n_tiles), 1,
+                                 rk_info(c->rk), c->stream));
   else
-    HIPCHK(launch_reduce<float>(c->memb.as<Member<float>>(), c->ids.as<int>(), 1, 1, rk_info(c->rk), c->stream));
+    HIPCHK(launch_reduce<float>(c->memb.as<Member<float>>(), c->ids.as<int>(), 1, red_chunks(c->n_tiles), 1,
+                                rk_info(c->rk), c->stream));
   return DGSWE_OK;
 }
 
@@ -463,7 +468,9 @@ int alloc_state(dgswe_ctx* c) {
   if (ntl.empty()) ntl.push_back({0, 0});
   HIPCHK(upload(c->node_tiles, ntl));
   c->n_tiles = int((E + TILE - 1) / TILE);
-  const size_t pb = size_t(NPART) * std::max(c->n_tiles, 1) * sizeof(double);
+  // tile partials, then the reduction's chunk records, then its counter
+  const size_t pb = (size_t(NPART) * std::max(c->n_tiles, 1) + size_t(NRED) * red_chunks(c->n_tiles) + 1) *
+                    sizeof(double);
   HIPCHK(c->part.alloc(pb));
   HIPCHK(hipMemset(c->part.p, 0, pb));
   std::vector<Tile> tl(c->n_tiles);
@@ -548,7 +555,7 @@ int64_t footprint(const dgswe_params* p, int64_t E, int64_t n_nodes) {
   b += 3 * E * 4 + E + 3 * E * 4;                    // neighbours, codes, node ids
   if (p->limiter) b += 6 * E * rs + E;               // limiter stencil
   b += 3 * n_nodes * 8;                              // node coordinates, nodal rain
-  b += NPART * std::max<int64_t>(tiles, 1) * 8 + 4096;
+  b += (NPART * std::max<int64_t>(tiles, 1) + NRED * int64_t(red_chunks(int(tiles))) + 1) * 8 + 4096;
   return b;
 }
 
@@ -1036,8 +1043,10 @@ int batch_rebuild_t(dgswe_batch* b) {
   HIPCHK(upload(b->memb, ms));
   for (auto& g : b->groups) {
     std::vector<Tile> tl, ntl;
+    g.max_chunks = 1;
     for (int m : g.members) {
       const int nt = ms[m].n_tiles;
+      g.max_chunks = std::max(g.max_chunks, red_chunks(nt));
       for (int t = 0; t < nt; ++t) tl.push_back({m, t});
       const int nnt = (ms[m].n_nodes + TILE - 1) / TILE;
       for (int t = 0; t < nnt; ++t) ntl.push_back({m, t});
@@ -1146,12 +1155,12 @@ int dgswe_batch_step(dgswe_batch* b, int64_t max_steps) {
       if (b->prm.precision == DGSWE_FP32)
         rc = enqueue_step_group<float>(b->memb.as<Member<float>>(), g.tiles.as<Tile>(), g.n_tiles,
                                        g.node_tiles.as<Tile>(), g.n_node_tiles, g.ids.as<int>(),
-                                       int(g.members.size()), g.p, g.flux, g.limiter, g.variant, g.rk, g.has_rain, b->stream,
+                                       int(g.members.size()), g.max_chunks, g.p, g.flux, g.limiter, g.variant, g.rk, g.has_rain, b->stream,
                                        nullptr);
       else
         rc = enqueue_step_group<double>(b->memb.as<Member<double>>(), g.tiles.as<Tile>(), g.n_tiles,
                                         g.node_tiles.as<Tile>(), g.n_node_tiles, g.ids.as<int>(),
-                                        int(g.members.size()), g.p, g.flux, g.limiter, g.variant, g.rk, g.has_rain, b->stream,
+                                        int(g.members.size()), g.max_chunks, g.p, g.flux, g.limiter, g.variant, g.rk, g.has_rain, b->stream,
                                         nullptr);
       if (rc) return rc;
     }

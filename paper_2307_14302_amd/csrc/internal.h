@@ -19,6 +19,12 @@ constexpr int MAX_SLOTS = 16;
 // min(d/lambda), rain volume, dry count
 enum PartKind { P_OUT0 = 0, P_IN0 = MAX_STAGES, P_VOL = 2 * MAX_STAGES, P_MINR, P_RAIN, P_NDRY, NPART };
 enum RainKind { RAIN_CONST = 0, RAIN_PARAM = 1, RAIN_GRID = 2 };
+// end-of-step reduction: one workgroup per RED_CHUNK tiles writes a record of
+// NRED doubles (the NPART-style sums and the dt minimum); the last workgroup
+// to finish combines the records in chunk order
+constexpr int RED_CHUNK = 256;
+constexpr int NRED = 16;
+__host__ __device__ inline int red_chunks(int n_tiles) { return n_tiles > 0 ? (n_tiles + RED_CHUNK - 1) / RED_CHUNK : 1; }
 
 // Device-resident time/budget/forcing scalars of one member.  Written only
 // by the reduce kernel (the last launch of a step) and by the host between
@@ -74,6 +80,8 @@ struct Member {
   Real* R;                    // [E] element rain rate
   double* rn;                 // [n_nodes] nodal rain rate
   double* part;               // [NPART][n_tiles]
+  double* red;                // [red_chunks(n_tiles)][NRED] chunk records
+  unsigned* red_count;        // chunks finished in the current reduction (0 between launches)
   Scalars* sc;
   Forcing fo;
 };
@@ -109,8 +117,10 @@ hipError_t launch_classify(int P, const Member<Real>* d_members, const Tile* d_t
 template <typename Real>
 hipError_t launch_rain(const Member<Real>* d_members, const Tile* d_tiles, int n_tiles, int always,
                        const Tile* d_node_tiles, int n_node_tiles, hipStream_t s);
+// grid: n_members x max_chunks workgroups (max_chunks = largest red_chunks
+// over the members)
 template <typename Real>
-hipError_t launch_reduce(const Member<Real>* d_members, const int* d_member_ids, int n_members, int init,
-                         const RKInfo& rk, hipStream_t s);
+hipError_t launch_reduce(const Member<Real>* d_members, const int* d_member_ids, int n_members, int max_chunks,
+                         int init, const RKInfo& rk, hipStream_t s);
 
 }  // namespace dg

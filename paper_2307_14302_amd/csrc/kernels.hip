@@ -173,10 +173,12 @@ DG_DEV bool surely_wet(const Real (&w)[3][Tab<P>::NP], const Real (&hb)[3], doub
 // wet element returns at once.
 template <typename Real, int P>
 DG_DEV bool positive_depth(Real (&w)[3][Tab<P>::NP], const Real (&hb)[3], double H0, double (&hv)[3],
-                           double (&qxv)[3], double (&qyv)[3], bool need_v = true) {
+                           double (&qxv)[3], double (&qyv)[3], bool need_v, bool& filled) {
   constexpr int NP = Tab<P>::NP;
   const double Hd = dry_depth(H0);
+  filled = false;
   if (!need_v && surely_wet<Real, P>(w, hb, Hd)) return false;
+  filled = true;
   double z[3];
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
@@ -288,6 +290,37 @@ DG_DEV double cfl_speed(const double (&hv)[3], const double (&qx)[3], const doub
     }
   }
   return lam;
+}
+
+// The same speed for an element known to be wet at every vertex, in the
+// state's precision (FP32 members; the wet test that selects vertices is not
+// needed).
+template <typename Real, int P>
+DG_DEV double element_speed(const Real (&w)[3][Tab<P>::NP], const Real (&hb)[3], Real g) {
+  constexpr int NP = Tab<P>::NP;
+  Real lam = Real(0);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    Real h = hb[i], a = Real(0), c = Real(0);
+#pragma unroll
+    for (int m = 0; m < NP; ++m) {
+      h += Real(B<P>::V(i, m)) * w[0][m];
+      a += Real(B<P>::V(i, m)) * w[1][m];
+      c += Real(B<P>::V(i, m)) * w[2][m];
+    }
+    const Real s = dsqrt(a * a + c * c) * rcp(h) + dsqrt(g * h);
+    lam = dmax(lam, s);
+  }
+  return double(lam);
+}
+
+// CFL speed after the positive-depth operator: from its FP64 vertex values
+// when it computed them, else (FP32 member, surely wet element) in FP32.
+template <typename Real, int P>
+DG_DEV double post_speed(bool filled, const double (&hv)[3], const double (&qxv)[3], const double (&qyv)[3],
+                         const Real (&w)[3][Tab<P>::NP], const Real (&hb)[3], double H0, double g) {
+  if (filled) return cfl_speed(hv, qxv, qyv, H0, g);
+  return element_speed<Real, P>(w, hb, Real(g));
 }
 
 // ------------------------------------------------------ stage building blocks
@@ -461,7 +494,10 @@ DG_DEV void finish_stage(const Member<Real>& M, const StageArgs& A, int tile, in
   double part[5] = {bout, bin, 0.0, __builtin_inf(), 0.0};
   if (LIM == 0) {
     double hv[3], qxv[3], qyv[3];
-    const bool dry = positive_depth<Real, P>(w, hb, M.H0, hv, qxv, qyv, A.last != 0);
+    bool filled;
+    // FP64 members keep the FP64 vertex values for the CFL speed
+    const bool need_v = A.last != 0 && sizeof(Real) == 8;
+    const bool dry = positive_depth<Real, P>(w, hb, M.H0, hv, qxv, qyv, need_v, filled);
     if (valid) {
       DG_G Real* __restrict__ Wout = gp(M.W[A.out_buf]);
 #pragma unroll
@@ -471,7 +507,7 @@ DG_DEV void finish_stage(const Member<Real>& M, const StageArgs& A, int tile, in
       gp(M.F[A.fout])[e] = dry ? 1 : 0;
     }
     if (A.last) {
-      const double lam = cfl_speed(hv, qxv, qyv, M.H0, M.g);
+      const double lam = post_speed<Real, P>(filled, hv, qxv, qyv, w, hb, M.H0, M.g);
       const double area = 0.5 * (double(ex[2]) * double(ey[0]) - double(ex[0]) * double(ey[2]));
       part[2] = valid ? area * (double(w[0][0]) + (double(hb[0]) + double(hb[1]) + double(hb[2])) / 3.0) : 0.0;
       part[3] = (valid && lam > 0.0) ? double(gp(M.din)[ec]) / lam : __builtin_inf();
@@ -959,13 +995,22 @@ __global__ __launch_bounds__(TILE) void post_kernel(const Member<Real>* __restri
 
   if (init != 2 && use_lim) {
     const uint8_t lc = gp(M.limc)[ec];
+    // the neighbours' wet bytes and means are fetched together, before the
+    // test that decides whether they are used (boundary ids read the element
+    // itself), so the gather costs one memory round trip
     int nb[3];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) nb[k] = gp(M.nbr)[k * E + ec];
-    bool ok = (lc & 1) && gp(M.fullwet)[ec];
-    if (ok) {
+    for (int k = 0; k < 3; ++k) {
+      const int n = gp(M.nbr)[k * E + ec];
+      nb[k] = n < 0 ? ec : n;
+    }
+    bool ok = ((lc & 1) != 0) & (gp(M.fullwet)[ec] != 0);
+    Real nmean[3][3];
 #pragma unroll
-      for (int k = 0; k < 3; ++k) ok = ok && gp(M.fullwet)[nb[k]];
+    for (int k = 0; k < 3; ++k) {
+      ok = ok & (gp(M.fullwet)[nb[k]] != 0);
+#pragma unroll
+      for (int v = 0; v < 3; ++v) nmean[v][k] = Wsrc[(v * NP) * E + nb[k]];
     }
     if (ok) {
       Real al[6];
@@ -976,7 +1021,7 @@ __global__ __launch_bounds__(TILE) void post_kernel(const Member<Real>* __restri
         const Real wb = w[v][0];
         Real nbm[3];
 #pragma unroll
-        for (int k = 0; k < 3; ++k) nbm[k] = Wsrc[(v * NP) * E + nb[k]] - wb;
+        for (int k = 0; k < 3; ++k) nbm[k] = nmean[v][k] - wb;
         Real d[3], D[3];
         bool same = true;
 #pragma unroll
@@ -1009,7 +1054,7 @@ __global__ __launch_bounds__(TILE) void post_kernel(const Member<Real>* __restri
       }
     }
   }
-  bool dry;
+  bool dry, filled = true;
   double hv[3], qxv[3], qyv[3];
   if (init == 2) {
     // flags of the state as given
@@ -1029,7 +1074,8 @@ __global__ __launch_bounds__(TILE) void post_kernel(const Member<Real>* __restri
     const double Hd = dry_depth(M.H0);
     dry = (hv[0] <= Hd) & (hv[1] <= Hd) & (hv[2] <= Hd);
   } else {
-    dry = positive_depth<Real, P>(w, hb, M.H0, hv, qxv, qyv, init != 0 || A.last != 0);
+    dry = positive_depth<Real, P>(w, hb, M.H0, hv, qxv, qyv, (init != 0 || A.last != 0) && sizeof(Real) == 8,
+                                  filled);
   }
   const int ob = init ? 0 : A.out_buf;
   const int fo = init ? 0 : A.fout;
@@ -1051,7 +1097,7 @@ __global__ __launch_bounds__(TILE) void post_kernel(const Member<Real>* __restri
       ey[k] = gp(M.ev)[(2 * k + 1) * E + ec];
     }
     const double area = 0.5 * (double(ex[2]) * double(ey[0]) - double(ex[0]) * double(ey[2]));
-    const double lam = cfl_speed(hv, qxv, qyv, M.H0, M.g);
+    const double lam = post_speed<Real, P>(filled, hv, qxv, qyv, w, hb, M.H0, M.g);
     double vals[2] = {valid ? area * (double(w[0][0]) + (double(hb[0]) + double(hb[1]) + double(hb[2])) / 3.0) : 0.0,
                       (valid && dry) ? 1.0 : 0.0};
     const double mr = (valid && lam > 0.0) ? double(gp(M.din)[ec]) / lam : __builtin_inf();
@@ -1177,30 +1223,96 @@ __global__ __launch_bounds__(TILE) void rain_kernel(const Member<Real>* __restri
 // order sums of the tile partials, budgets, t, the next dt (FP64), the
 // latched error, and the forcing values of the coming step (tide and river
 // at every stage time, storm parameters and rain-lattice records at t^n).
-// Every global read is issued up front (scalars, tables staged in LDS), so
-// the kernel pays one memory round trip rather than a chain of them.
+// Grid (members, chunks): workgroup (m, c) sums tiles [c RED_CHUNK, (c+1)
+// RED_CHUNK) of member m, one tile per thread, and stores a chunk record; the
+// workgroup that finishes last (counted with a device-scope atomic) adds the
+// records in chunk order, so the result does not depend on which one that
+// is, and resets the counter for the next launch.
 template <typename Real>
-__global__ __launch_bounds__(1024) void reduce_kernel(const Member<Real>* __restrict__ mem,
-                                                      const int* __restrict__ ids, int init, RKInfo rk) {
-  constexpr int NV = 3 + 2 * MAX_STAGES;
-  constexpr int NW = 16;                       // wavefronts per workgroup
-  constexpr int NT = 256;                      // table entries staged in LDS
+__global__ __launch_bounds__(RED_CHUNK) void reduce_kernel(const Member<Real>* __restrict__ mem,
+                                                           const int* __restrict__ ids, int init, RKInfo rk) {
+  constexpr int NV = 3 + 2 * MAX_STAGES;       // sums: volume, rain, dry count, out/in per stage
+  constexpr int NW = RED_CHUNK / 64;
+  constexpr int NT = 256;                      // forcing-table entries staged in LDS
+  static_assert(NV + 1 <= NRED, "chunk record too small");
   __shared__ double lds[NW * (NV + 1)];
   __shared__ double s_storm[7 * NT];
   __shared__ double s_gt[NT];
   __shared__ double s_tide[3 * NT];
   __shared__ double s_riv[2 * NT];
   __shared__ double s_t, s_dt;
+  __shared__ int s_last;
   const Member<Real>& M = mem[ids[blockIdx.x]];
   DG_G Scalars* __restrict__ sc = gp(M.sc);
   if (!init && !sc->active) return;
+  const int nt = M.n_tiles;
+  const int nch = red_chunks(nt);
+  const int chunk = blockIdx.y;
+  if (chunk >= nch) return;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int ns = init ? 0 : rk.n;
+  // ---- this chunk's tiles
+  double v[NV];
+  double mn;
+  {
+    const DG_G double* __restrict__ pt = gp(M.part);
+    const int t = chunk * RED_CHUNK + tid;
+    const bool ok = t < nt;
+    const int tt = ok ? t : 0;
+    v[0] = ok ? pt[P_VOL * nt + tt] : 0.0;
+    v[1] = ok ? pt[P_RAIN * nt + tt] : 0.0;
+    v[2] = ok ? pt[P_NDRY * nt + tt] : 0.0;
+    mn = ok ? pt[P_MINR * nt + tt] : __builtin_inf();
+#pragma unroll
+    for (int s = 0; s < MAX_STAGES; ++s) {
+      v[3 + s] = (ok && s < ns) ? pt[(P_OUT0 + s) * nt + tt] : 0.0;
+      v[3 + MAX_STAGES + s] = (ok && s < ns) ? pt[(P_IN0 + s) * nt + tt] : 0.0;
+    }
+  }
+  // fixed-order block sums: within each wavefront, then wavefronts 0..NW-1
+  auto block_reduce = [&]() {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      const double x = wave_sum(v[i]);
+      if (lane == 0) lds[wv * (NV + 1) + i] = x;
+    }
+    const double m = wave_min(mn);
+    if (lane == 0) lds[wv * (NV + 1) + NV] = m;
+    __syncthreads();
+    if (tid == 0) {
+#pragma unroll
+      for (int i = 0; i < NV; ++i) {
+        double x = lds[i];
+#pragma unroll
+        for (int w = 1; w < NW; ++w) x += lds[w * (NV + 1) + i];
+        v[i] = x;
+      }
+      double m2 = lds[NV];
+#pragma unroll
+      for (int w = 1; w < NW; ++w) m2 = fmin(m2, lds[w * (NV + 1) + NV]);
+      mn = m2;
+    }
+    __syncthreads();
+  };
+  block_reduce();
+  DG_G double* __restrict__ red = gp(M.red);
+  if (tid == 0) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) red[chunk * NRED + i] = v[i];
+    red[chunk * NRED + NV] = mn;
+    __threadfence();
+    const unsigned done = atomicAdd(M.red_count, 1u);
+    s_last = done == unsigned(nch - 1);
+  }
+  __syncthreads();
+  if (!s_last) return;
+  __threadfence();
+  // ---- last workgroup: forcing tables to LDS, records in chunk order
   const Forcing& f = M.fo;
-  const int tid = threadIdx.x;
-  // stage the forcing tables
   const int nst = f.rain_kind == RAIN_PARAM ? (f.n_storm < NT ? f.n_storm : NT) : 0;
-  for (int i = tid; i < 7 * nst; i += 1024) s_storm[i] = gp(f.storm)[i];
+  for (int i = tid; i < 7 * nst; i += RED_CHUNK) s_storm[i] = gp(f.storm)[i];
   const int ngt = f.rain_kind == RAIN_GRID ? (f.gnrec < NT ? f.gnrec : NT) : 0;
-  for (int i = tid; i < ngt; i += 1024) s_gt[i] = gp(f.gt)[i];
+  for (int i = tid; i < ngt; i += RED_CHUNK) s_gt[i] = gp(f.gt)[i];
   int ntc = 0, nrq = 0;
 #pragma unroll
   for (int s = 0; s < MAX_SLOTS; ++s) {
@@ -1209,82 +1321,28 @@ __global__ __launch_bounds__(1024) void reduce_kernel(const Member<Real>* __rest
   }
   const bool tide_lds = ntc <= NT, riv_lds = nrq <= NT;
   if (tide_lds)
-    for (int i = tid; i < 3 * ntc; i += 1024) s_tide[i] = gp(f.tide_c)[i];
+    for (int i = tid; i < 3 * ntc; i += RED_CHUNK) s_tide[i] = gp(f.tide_c)[i];
   if (riv_lds)
-    for (int i = tid; i < 2 * nrq; i += 1024) s_riv[i] = gp(f.riv_tq)[i];
-  // scalars (thread 0)
+    for (int i = tid; i < 2 * nrq; i += RED_CHUNK) s_riv[i] = gp(f.riv_tq)[i];
   double t0 = 0.0, dt0 = 0.0, rain0 = 0.0, bo0 = 0.0, bi0 = 0.0;
   long long steps0 = 0, target0 = 0;
   if (tid == 0) {
     t0 = sc->t; dt0 = sc->dt; rain0 = sc->rain_in; bo0 = sc->bnd_out; bi0 = sc->bnd_in;
     steps0 = sc->steps; target0 = sc->target;
   }
-  // tile partials
-  const int nt = M.n_tiles;
-  const DG_G double* __restrict__ pt = gp(M.part);
-  double v[NV];
 #pragma unroll
   for (int i = 0; i < NV; ++i) v[i] = 0.0;
-  double mn = __builtin_inf();
-  const int ns = init ? 0 : rk.n;
-  // chunks of U strided tiles per thread: every load of a chunk is issued
-  // before any is consumed; sums still run in increasing tile order
-  constexpr int U = 1;
-  for (int base = 0; base < nt; base += U * NW * 64) {
-    double a[U][4 + 2 * MAX_STAGES];
+  mn = __builtin_inf();
+  for (int c = tid; c < nch; c += RED_CHUNK) {
+    // records written by other workgroups: device-coherent loads
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int t = base + u * NW * 64 + tid;
-      const bool ok = t < nt;
-      const int tt = ok ? t : 0;
-      a[u][0] = ok ? pt[P_VOL * nt + tt] : 0.0;
-      a[u][1] = ok ? pt[P_RAIN * nt + tt] : 0.0;
-      a[u][2] = ok ? pt[P_NDRY * nt + tt] : 0.0;
-      a[u][3] = ok ? pt[P_MINR * nt + tt] : __builtin_inf();
-#pragma unroll
-      for (int s = 0; s < MAX_STAGES; ++s) {
-        a[u][4 + s] = (ok && s < ns) ? pt[(P_OUT0 + s) * nt + tt] : 0.0;
-        a[u][4 + MAX_STAGES + s] = (ok && s < ns) ? pt[(P_IN0 + s) * nt + tt] : 0.0;
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      v[0] += a[u][0];
-      v[1] += a[u][1];
-      v[2] += a[u][2];
-      mn = fmin(mn, a[u][3]);
-#pragma unroll
-      for (int s = 0; s < MAX_STAGES; ++s) {
-        v[3 + s] += a[u][4 + s];
-        v[3 + MAX_STAGES + s] += a[u][4 + MAX_STAGES + s];
-      }
-    }
+    for (int i = 0; i < NV; ++i)
+      v[i] += __hip_atomic_load(M.red + c * NRED + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    mn = fmin(mn, __hip_atomic_load(M.red + c * NRED + NV, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
   }
-  // fixed-order reduction: within each wavefront, then over wavefronts
-  const int lane = tid & 63, wv = tid >> 6;
-#pragma unroll
-  for (int i = 0; i < NV; ++i) {
-    const double x = wave_sum(v[i]);
-    if (lane == 0) lds[wv * (NV + 1) + i] = x;
-  }
-  mn = wave_min(mn);
-  if (lane == 0) lds[wv * (NV + 1) + NV] = mn;
-  __syncthreads();
-  if (tid < 64) {
-    const int w = lane & (NW - 1);
-#pragma unroll
-    for (int i = 0; i < NV; ++i) {
-      double x = lds[w * (NV + 1) + i];
-#pragma unroll
-      for (int o = NW / 2; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
-      v[i] = x;
-    }
-    double x = lds[w * (NV + 1) + NV];
-#pragma unroll
-    for (int o = NW / 2; o > 0; o >>= 1) x = fmin(x, __shfl_xor(x, o, 64));
-    mn = x;
-  }
+  block_reduce();
   if (tid == 0) {
+    __hip_atomic_store(M.red_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     double t = t0;
     long long steps = steps0;
     if (!init) {
@@ -1425,10 +1483,11 @@ hipError_t launch_rain(const Member<Real>* m, const Tile* t, int n, int always, 
 }
 
 template <typename Real>
-hipError_t launch_reduce(const Member<Real>* m, const int* ids, int n_members, int init, const RKInfo& rk,
-                         hipStream_t s) {
+hipError_t launch_reduce(const Member<Real>* m, const int* ids, int n_members, int max_chunks, int init,
+                         const RKInfo& rk, hipStream_t s) {
   if (n_members <= 0) return hipSuccess;
-  hipLaunchKernelGGL((reduce_kernel<Real>), dim3(n_members), dim3(1024), 0, s, m, ids, init, rk);
+  hipLaunchKernelGGL((reduce_kernel<Real>), dim3(n_members, max_chunks < 1 ? 1 : max_chunks), dim3(RED_CHUNK), 0, s,
+                     m, ids, init, rk);
   return hipGetLastError();
 }
 
@@ -1437,7 +1496,7 @@ hipError_t launch_reduce(const Member<Real>* m, const int* ids, int n_members, i
   template hipError_t launch_post<R>(int, int, const Member<R>*, const Tile*, int, StageArgs, int, hipStream_t);  \
   template hipError_t launch_classify<R>(int, const Member<R>*, const Tile*, int, hipStream_t);                   \
   template hipError_t launch_rain<R>(const Member<R>*, const Tile*, int, int, const Tile*, int, hipStream_t);     \
-  template hipError_t launch_reduce<R>(const Member<R>*, const int*, int, int, const RKInfo&, hipStream_t);
+  template hipError_t launch_reduce<R>(const Member<R>*, const int*, int, int, int, const RKInfo&, hipStream_t);
 DG_INST(float)
 DG_INST(double)
 
