@@ -25,6 +25,8 @@ import subprocess
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -109,6 +111,94 @@ def roofline(res, precision, p, limiter):
             "avg_us": round(avg_s * 1e6, 2), "launches": n}
 
 
+def run_ensemble(n_members=64, t_sim=120.0, chunk=10):
+    """64 members (sizes log-uniform in [1e4, 5e5] triangles, even members
+    p = 1, odd members p = 2, FP32), each simulating t_sim seconds, stepped
+    together by one batch: every launch covers all active members of a
+    scheme.  Latency = completion time of a member from the batch start."""
+    import math
+    import meshgen
+    from paper_2307_14302_amd import Batch, Solver
+    t0 = time.perf_counter()
+    members = []
+    for i, n_tri, p in meshgen.ensemble_plan(n_members):
+        sc = meshgen.basin_member(4, i, n_tri, p=p)
+        s = Solver.from_scenario(sc, precision="fp32")
+        dt0 = s.mass()["dt_next"]
+        members.append((s, int(math.ceil(t_sim / dt0)), int(sc.params["rk_stages"]), p))
+    log(f"[ensemble] {len(members)} members, {sum(m[0].n_tri for m in members)} triangles, set-up "
+        f"{time.perf_counter() - t0:.1f}s")
+    b = Batch({"precision": "fp32"})
+    slots = {b.add(s, n): k for k, (s, n, _, _) in enumerate(members)}
+    b.step(0)                                   # builds the member tables
+    b.poll()
+    done_at = {}
+    t0 = time.perf_counter()
+    while len(done_at) < len(slots):
+        b.step(chunk)
+        now = time.perf_counter() - t0
+        for sl in b.poll():
+            done_at.setdefault(sl, now)
+    el = time.perf_counter() - t0
+    work = sum(s.n_tri * st * n for s, n, st, _ in members)
+    lat = np.array([done_at[sl] for sl in slots])
+    out = {"value": round(work / el, 1), "unit": "element-stage updates/s", "members": len(members),
+           "n_tri_total": int(sum(s.n_tri for s, _, _, _ in members)),
+           "p_mix": {"p1": sum(1 for m in members if m[3] == 1), "p2": sum(1 for m in members if m[3] == 2)},
+           "t_sim_s": t_sim, "steps_min": int(min(m[1] for m in members)), "steps_max": int(max(m[1] for m in members)),
+           "wall_s": round(el, 3), "p50_latency_s": round(float(np.percentile(lat, 50)), 4),
+           "p99_latency_s": round(float(np.percentile(lat, 99)), 4), "dtype": "f32"}
+    log(f"[ensemble] {work:.3e} element-stages in {el:.2f}s -> {work / el:.4e}/s; latency p50 "
+        f"{out['p50_latency_s']}s p99 {out['p99_latency_s']}s")
+    for sl in list(slots):
+        b.retire(sl)
+    b.close()
+    for s, _, _, _ in members:
+        s.close()
+    return out
+
+
+def run_serving(n_req=100, rate=20.0, budget_gib=24.0, chunk=20):
+    """Poisson arrivals (mean ``rate``/s) of scenarios on a pool of 64 basin
+    meshes (5e3..2e6 triangles, FP32, p = 1, steps of at most 0.5 s),
+    500..5000 steps each, admitted by footprint under an HBM budget,
+    continuous batching.  Latency = arrival -> result (vertex state) on the
+    host."""
+    import meshgen
+    from paper_2307_14302_amd import Request, Server, latency_summary
+    sizes = meshgen.serving_pool_sizes()
+    trace = meshgen.request_trace(n_req=400, rate=rate, n_meshes=len(sizes))[:n_req]
+    params = dict(precision="fp32", p=1, flux="llf", friction="manning", limiter=True, cfl=0.3, H0=0.05, dt_max=0.5)
+    srv = Server(params, budget_bytes=int(budget_gib * (1 << 30)), chunk_steps=chunk, keep_results=False)
+    t0 = time.perf_counter()
+    pool = {}
+    for k in sorted({r["mesh"] for r in trace}):
+        N = max(4, int(round(np.sqrt(sizes[k] / 2.0))))
+        sc = meshgen.basin(N, meshgen.seed_for(5, 1000 + k))
+        m = sc.mesh
+        srv.register_mesh(k, m.xy, m.hb, m.fric, m.tri, m.bedges, m.btype, m.bslot)
+        pool[k] = sc
+    log(f"[serving] {len(pool)} pool meshes uploaded in {time.perf_counter() - t0:.1f}s")
+    reqs = [Request(id=r["id"], arrival=r["arrival"], mesh=r["mesh"], n_steps=r["n_steps"],
+                    initial=(pool[r["mesh"]].zeta0, pool[r["mesh"]].qx0, pool[r["mesh"]].qy0),
+                    rain={"kind": "parametric", "records": r["track"]}, tides=dict(pool[r["mesh"]].tides))
+            for r in trace]
+    t0 = time.perf_counter()
+    done = srv.run(reqs)
+    el = time.perf_counter() - t0
+    srv.close()
+    work = sum(r.n_tri * 2 * r.n_steps for r in done)
+    ls = latency_summary(done)
+    out = {"value": round(work / el, 1), "unit": "element-stage updates/s", "requests": len(done),
+           "arrival_rate_per_s": rate, "budget_gib": budget_gib, "chunk_steps": chunk, "makespan_s": round(el, 3),
+           "p50_latency_s": round(ls["p50_s"], 4), "p99_latency_s": round(ls["p99_s"], 4),
+           "mean_latency_s": round(ls["mean_s"], 4), "failed": ls["failed"], "dtype": "f32",
+           "trace": f"first {n_req} of a 400-request seeded trace"}
+    log(f"[serving] {len(done)} requests, {work:.3e} element-stages in {el:.2f}s -> {work / el:.4e}/s; "
+        f"latency p50 {out['p50_latency_s']}s p99 {out['p99_latency_s']}s")
+    return out
+
+
 def cpu_baseline(timeout=600):
     """The FP64 oracle on one host core: 2 SSP-RK2 steps of the full mesh."""
     code = r"""
@@ -152,6 +242,9 @@ def main():
     ap.add_argument("--calib-copy", action="store_true", help="also run a 1 GiB device copy (counter calibration)")
     ap.add_argument("--no-events", action="store_true",
                     help="no per-kernel HIP events in the timed region (steps replay a HIP graph)")
+    ap.add_argument("--no-ensemble", action="store_true", help="skip the 64-member FP32 ensemble")
+    ap.add_argument("--no-serving", action="store_true", help="skip the request-loop run")
+    ap.add_argument("--serve-requests", type=int, default=100, help="requests of the 400-request trace to serve")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (see the design notes on sharding); "
@@ -193,6 +286,12 @@ def main():
         out["fp64"] = {"value": round(f["rate"], 1), "ms_per_step": round(f["elapsed"] / args.steps * 1e3, 4),
                        "dtype": "f64", "roofline": roofline(f, "fp64", prm["p"], prm["limiter"]),
                        "fp32_over_fp64": round(r["rate"] / f["rate"], 3)}
+    if not args.no_ensemble:
+        out["ensemble"] = run_ensemble()
+        if "fp64" in res:
+            out["ensemble"]["vs_fp64_single_mesh"] = round(out["ensemble"]["value"] / res["fp64"]["rate"], 3)
+    if not args.no_serving:
+        out["serving"] = run_serving(n_req=args.serve_requests)
     if not args.no_cpu:
         log("timing the oracle on one host core ...")
         out["cpu_baseline"] = cpu_baseline()

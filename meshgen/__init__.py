@@ -20,4 +20,5 @@ from .generators import (  # noqa: F401
     Mesh, Scenario,
     rect_grid, channel_c1, bathtub, basin, basin_window, small_mixed, lake_at_rest,
     parametric_track, gridded_field, seed_for, dam_break, inclined_plane,
+    log_uniform_sizes, basin_member, ensemble_plan, request_trace, serving_pool_sizes,
 )

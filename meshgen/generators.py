@@ -224,7 +224,7 @@ def parametric_track(x_start, y_start, vx, vy, peak, t_end=1.0e6, *,
 
 def basin(N: int = 708, seed: int = seed_for(1), *, L: float = 200e3,
           window=None, jitter: float = 0.2, flux: str = "llf", limiter: bool = True,
-          peak_mmh: float = 50.0, track=None, n_steps: int = 5000) -> Scenario:
+          peak_mmh: float = 50.0, track=None, n_steps: int = 5000, p: int = 1) -> Scenario:
     """Jittered N x N grid cut along the shorter diagonals.
 
     Without ``window`` the grid covers the whole L x L basin: N = 708 gives
@@ -251,7 +251,7 @@ def basin(N: int = 708, seed: int = seed_for(1), *, L: float = 200e3,
         track = parametric_track(0.3 * L, 0.5 * L, 5.0, 0.0, peak,
                                  rm=30e3 * L / 200e3, re=100e3 * L / 200e3)
     return Scenario(f"basin_{N}", mesh, zeta0, np.zeros_like(hb), np.zeros_like(hb),
-                    default_params(flux=flux, friction="manning", limiter=limiter, cfl=0.3, H0=0.05),
+                    default_params(p=p, flux=flux, friction="manning", limiter=limiter, cfl=0.3, H0=0.05),
                     rain={"kind": "parametric", "records": track},
                     tides={0: (0.0, np.zeros((0, 3)))}, n_steps=n_steps)
 
@@ -401,3 +401,66 @@ def inclined_plane(nx: int = 96, *, L: float = 24.0, W: float = 0.196, slope: fl
                     default_params(flux="roe", friction="manning", limiter=False, cfl=0.3, H0=H0,
                                    dt_max=0.02),
                     rain={"kind": "nodal", "r": np.full(len(hb), rain)}, n_steps=0)
+
+
+# ---------------------------------------------------------------------------
+# ensembles and request traces built from the basin generator
+# ---------------------------------------------------------------------------
+def log_uniform_sizes(n: int, lo: float, hi: float, seed: int) -> np.ndarray:
+    """n triangle counts drawn log-uniformly from [lo, hi] (seeded)."""
+    rng = np.random.default_rng(seed)
+    return np.exp(rng.uniform(np.log(lo), np.log(hi), n))
+
+
+def basin_member(config_id: int, i: int, n_tri: float, *, p: int = 1) -> Scenario:
+    """Member i of an ensemble: the basin generator at about n_tri triangles
+    (N x N grid with 2 N^2 ~ n_tri), its own seed, a rain peak ~ U(10, 120)
+    mm/h and a storm track with a seeded start in the western half and a
+    seeded heading, at 5 m/s; time step at most 0.5 s."""
+    seed = seed_for(config_id, i)
+    rng = np.random.default_rng(seed + 7)
+    N = max(4, int(round(np.sqrt(n_tri / 2.0))))
+    L = 200e3
+    peak = rng.uniform(10.0, 120.0)
+    ang = rng.uniform(-0.5 * np.pi, 0.5 * np.pi)
+    track = parametric_track(rng.uniform(0.1, 0.5) * L, rng.uniform(0.2, 0.8) * L, 5.0 * np.cos(ang),
+                             5.0 * np.sin(ang), peak * MM_PER_HOUR)
+    sc = basin(N, seed, peak_mmh=peak, track=track, p=p)
+    sc.name = f"member_{config_id}_{i}"
+    # coarse members would take CFL steps of several seconds, where explicit
+    # Manning friction in thin layers is unstable; cap at the 0.5 s step of
+    # the paper's large-mesh run
+    sc.params["dt_max"] = 0.5
+    return sc
+
+
+def ensemble_plan(n: int = 64, lo: float = 1e4, hi: float = 5e5, config_id: int = 4):
+    """Sizes and orders of an ensemble: log-uniform sizes, even members p = 1,
+    odd members p = 2.  Returns a list of (i, n_tri, p)."""
+    sizes = log_uniform_sizes(n, lo, hi, seed_for(config_id))
+    return [(i, float(sizes[i]), 1 if i % 2 == 0 else 2) for i in range(n)]
+
+
+def request_trace(n_req: int = 400, rate: float = 20.0, n_meshes: int = 64, steps=(500, 5000),
+                  config_id: int = 5):
+    """Poisson arrivals (mean ``rate`` per second) of flood scenarios: for each
+    request its arrival time [s], the index of its mesh in the pool, its step
+    count ~ U{steps} and its storm (peak ~ U(10, 120) mm/h, seeded track).
+    The pool holds ``n_meshes`` basin meshes of log-uniform sizes in
+    [5e3, 2e6] triangles (see :func:`serving_pool_sizes`)."""
+    rng = np.random.default_rng(seed_for(config_id))
+    t = np.cumsum(rng.exponential(1.0 / rate, n_req))
+    mesh = rng.integers(0, n_meshes, n_req)
+    nst = rng.integers(steps[0], steps[1] + 1, n_req)
+    peak = rng.uniform(10.0, 120.0, n_req)
+    ang = rng.uniform(-0.5 * np.pi, 0.5 * np.pi, n_req)
+    x0 = rng.uniform(0.1, 0.5, n_req)
+    y0 = rng.uniform(0.2, 0.8, n_req)
+    return [dict(id=k, arrival=float(t[k]), mesh=int(mesh[k]), n_steps=int(nst[k]),
+                 track=parametric_track(x0[k] * 200e3, y0[k] * 200e3, 5.0 * np.cos(ang[k]),
+                                        5.0 * np.sin(ang[k]), peak[k] * MM_PER_HOUR))
+            for k in range(n_req)]
+
+
+def serving_pool_sizes(n_meshes: int = 64, lo: float = 5e3, hi: float = 2e6, config_id: int = 5):
+    return log_uniform_sizes(n_meshes, lo, hi, seed_for(config_id, 999))

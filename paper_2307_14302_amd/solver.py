@@ -167,6 +167,12 @@ class Solver:
     def footprint(self) -> int:
         return int(N.lib.dgswe_footprint_bytes(C.byref(self._p), self.n_tri, self.n_nodes))
 
+    @staticmethod
+    def footprint_of(params: Dict[str, object], like: "Solver") -> int:
+        """Device bytes of a context with ``params`` on the mesh of ``like``."""
+        p = params_from_dict(params)
+        return int(N.lib.dgswe_footprint_bytes(C.byref(p), like.n_tri, like.n_nodes))
+
     def close(self):
         if getattr(self, "h", None) is not None and self.h.value:
             call("dgswe_destroy", self.h)
