@@ -93,6 +93,32 @@ def run_precision(sc, precision, steps, warmup, variant=1, events=True):
     return dict(rate=rate, elapsed=el, stats=stats, mass=m, E=E, stages=stages)
 
 
+def kernel_sources_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "device_common.h", "internal.h"):
+        with open(os.path.join(ROOT, "paper_2307_14302_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def counted_traffic(kernel, precision):
+    """HBM bytes per launch of ``kernel`` from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE scaled by the copy calibration), or
+    None when the kernel sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "stage_edge_kernel_basin1M_counters.md")
+    try:
+        with open(path) as f:
+            line = next(l for l in f if l.startswith("traffic-json:"))
+        d = json.loads(line.split(":", 1)[1])
+    except (OSError, StopIteration, ValueError):
+        return None
+    if d.get("sources") != kernel_sources_hash():
+        return None
+    name = "stage_edge_kernel" if kernel == "stage" else "post_kernel"
+    return d["bytes"].get(f"{name}/{precision}")
+
+
 def roofline(res, precision, p, limiter):
     rs = 4 if precision == "fp32" else 8
     stats = res["stats"]
@@ -107,7 +133,7 @@ def roofline(res, precision, p, limiter):
     avg_s = ms / n * 1e-3
     ach = byts / avg_s / 1e9
     return {"kernel": dom, "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None, "bytes_per_launch": int(byts),
+            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": counted_traffic(dom, precision), "bytes_per_launch": int(byts),
             "avg_us": round(avg_s * 1e6, 2), "launches": n}
 
 
