@@ -14,7 +14,10 @@ wall time of the timed steps (inputs resident in HBM), reported for the FP32
 path (FP32 state and fluxes; FP64 wet/dry tests, dt and budgets); the FP64
 path is reported beside it.  The dominant kernel's roofline uses the
 algorithmic bytes of :func:`algorithmic_bytes` and its mean duration from
-HIP events recorded by the library on its stream around every launch.
+HIP events recorded by the library on its stream around every launch of
+that kernel inside the timed region.  Then the 64-member FP32 ensemble and
+the request loop (see :func:`run_ensemble`, :func:`run_serving`) and the
+oracle on one host core.
 """
 from __future__ import annotations
 
@@ -63,7 +66,7 @@ def algorithmic_bytes(kernel, E, rs, p, a_nonzero, last, limiter):
     return E * b
 
 
-def run_precision(sc, precision, steps, warmup, variant=1, events=True):
+def run_precision(sc, precision, steps, warmup, variant=1, events=2):
     from paper_2307_14302_amd import Solver
     import torch
 
@@ -73,6 +76,8 @@ def run_precision(sc, precision, steps, warmup, variant=1, events=True):
     log(f"[{precision}] setup {time.perf_counter() - t0:.1f}s  E={s.n_tri}")
     s.step(warmup)
     s.sync()
+    # events around the stage kernel only: the dominant kernel's duration for
+    # the roofline, with the fewest timing packets between launches
     s.profiling(events)
     torch.cuda.synchronize()
     s.sync()
@@ -267,7 +272,8 @@ def main():
     ap.add_argument("--variant", type=int, default=1, help="stage kernel: 0 per element, 1 per edge (default)")
     ap.add_argument("--calib-copy", action="store_true", help="also run a 1 GiB device copy (counter calibration)")
     ap.add_argument("--no-events", action="store_true",
-                    help="no per-kernel HIP events in the timed region (steps replay a HIP graph)")
+                    help="no HIP events in the timed region (steps replay a HIP graph; no roofline)")
+    ap.add_argument("--events-all", action="store_true", help="HIP events around every kernel (per-kernel times)")
     ap.add_argument("--no-ensemble", action="store_true", help="skip the 64-member FP32 ensemble")
     ap.add_argument("--no-serving", action="store_true", help="skip the request-loop run")
     ap.add_argument("--serve-requests", type=int, default=100, help="requests of the 400-request trace to serve")
@@ -285,7 +291,8 @@ def main():
     prm = sc.params
     res = {}
     for prec in (["fp32", "fp64"] if args.precision == "both" else [args.precision]):
-        res[prec] = run_precision(sc, prec, args.steps, args.warmup, args.variant, not args.no_events)
+        mode = 0 if args.no_events else (1 if args.events_all else 2)
+        res[prec] = run_precision(sc, prec, args.steps, args.warmup, args.variant, mode)
     if args.calib_copy:
         a = torch.empty(256 * 1024 * 1024, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)

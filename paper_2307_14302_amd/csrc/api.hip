@@ -155,7 +155,7 @@ struct dgswe_ctx {
   bool in_batch = false;
   hipStream_t batch_stream = nullptr;   // stream of the batch this context belongs to
   // profiling
-  bool prof = false;
+  int prof = 0;                     // 0 off, 1 every kernel, 2 stage kernel only
   std::vector<Pending> pending;
   std::vector<hipEvent_t> free_events;
   int64_t k_launches[K_N] = {0, 0, 0, 0};
@@ -289,14 +289,15 @@ struct ProfScope {
   dgswe_ctx* c;
   int k;
   hipEvent_t a = nullptr;
-  ProfScope(dgswe_ctx* c_, int k_) : c(c_), k(k_) {
-    if (c && c->prof) {
+  ProfScope(dgswe_ctx* c_, int k_) : c((c_ && (c_->prof == 1 || (c_->prof == 2 && k_ == K_STAGE))) ? c_ : nullptr),
+                                      k(k_) {
+    if (c) {
       a = get_event(c);
       (void)hipEventRecord(a, c->stream);
     }
   }
   ~ProfScope() {
-    if (c && c->prof) {
+    if (c) {
       hipEvent_t b = get_event(c);
       (void)hipEventRecord(b, c->stream);
       c->pending.push_back({k, a, b});
@@ -830,8 +831,8 @@ static int build_graph(dgswe_ctx* c) {
   }
   hipGraph_t g = nullptr;
   HIPCHK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-  const bool prof = c->prof;
-  c->prof = false;
+  const int prof = c->prof;
+  c->prof = 0;
   int rc = ctx_enqueue_step(c);
   c->prof = prof;
   hipError_t e = hipStreamEndCapture(c->stream, &g);
@@ -990,7 +991,8 @@ int dgswe_set_profiling(dgswe_ctx* c, int on) {
   if (c->stream) HIPCHK(hipStreamSynchronize(c->stream));
   harvest(c);
   for (int k = 0; k < K_N; ++k) { c->k_launches[k] = 0; c->k_ms[k] = 0.0; }
-  c->prof = on != 0;
+  if (on < 0 || on > 2) return fail(DGSWE_EINVAL, "profiling mode must be 0, 1 or 2");
+  c->prof = on;
   return DGSWE_OK;
 }
 

@@ -402,6 +402,7 @@ DG_DEV void area_terms(const Real (&w)[3][Tab<P>::NP], const Real (&hb)[3], Real
   const Real dhr = Real(0.5) * (hb[1] - hb[0]), dhs = Real(0.5) * (hb[2] - hb[0]);
   const Real dhx = (cx0 * dhr + cx1 * dhs) * idet, dhy = (cy0 * dhr + cy1 * dhs) * idet;
   const Real gn2 = g * fc * fc;
+  Real Sx[3] = {Real(0), Real(0), Real(0)}, Sy[3] = {Real(0), Real(0), Real(0)};
 #pragma unroll
   for (int q = 0; q < NQ; ++q) {
     Real wq[3];
@@ -434,9 +435,17 @@ DG_DEV void area_terms(const Real (&w)[3][Tab<P>::NP], const Real (&hb)[3], Real
     const Real s2 = g * wq[0] * dhy - tau * wq[2];
     const Real Wq = Real(Tab<P>::qw(q));
     const Real wdet = Wq * detJ;
+    if (P == 1) {
+      // linear modes have constant gradients: weight the fluxes first
+#pragma unroll
+      for (int v = 0; v < 3; ++v) {
+        Sx[v] += Wq * Fx[v];
+        Sy[v] += Wq * Fy[v];
+      }
+    }
 #pragma unroll
     for (int m = 0; m < NP; ++m) {
-      if (m > 0) {
+      if (m > 0 && P != 1) {
         const Real dr = Real(B<P>::QR(q, m)), ds = Real(B<P>::QS(q, m));
         const Real gx = Wq * (cx0 * dr + cx1 * ds), gy = Wq * (cy0 * dr + cy1 * ds);
         acc[0][m] += gx * Fx[0] + gy * Fy[0];
@@ -446,6 +455,15 @@ DG_DEV void area_terms(const Real (&w)[3][Tab<P>::NP], const Real (&hb)[3], Real
       const Real ps = wdet * Real(B<P>::Q(q, m));
       acc[1][m] += ps * s1;
       acc[2][m] += ps * s2;
+    }
+  }
+  if (P == 1) {
+#pragma unroll
+    for (int m = 1; m < 3; ++m) {
+      const Real dr = Real(B<P>::QR(0, m)), ds = Real(B<P>::QS(0, m));
+      const Real gx = cx0 * dr + cx1 * ds, gy = cy0 * dr + cy1 * ds;
+#pragma unroll
+      for (int v = 0; v < 3; ++v) acc[v][m] += gx * Sx[v] + gy * Sy[v];
     }
   }
 }
@@ -470,26 +488,42 @@ DG_DEV Real element_rain(const Member<Real>& M, const StageArgs& A, int E, int e
   return gp(M.R)[ec];
 }
 
+// w^n of the element when the stage blends it (a != 0), else zeros; loaded
+// before the edge accumulation so that the loads overlap it.
+template <typename Real, int P>
+DG_DEV void load_blend(const Member<Real>& M, const StageArgs& A, int E, int ec, Real (&w0v)[3][Tab<P>::NP]) {
+  constexpr int NP = Tab<P>::NP;
+  if (A.a != 0.0) {
+    const DG_G Real* __restrict__ W0 = gp(M.W[0]);
+#pragma unroll
+    for (int v = 0; v < 3; ++v)
+#pragma unroll
+      for (int m = 0; m < NP; ++m) w0v[v][m] = W0[(v * NP + m) * E + ec];
+  } else {
+#pragma unroll
+    for (int v = 0; v < 3; ++v)
+#pragma unroll
+      for (int m = 0; m < NP; ++m) w0v[v][m] = Real(0);
+  }
+}
+
 // Inverse mass, SSP combination, positive-depth operator (LIM = 0) or the
 // fully-wet byte (LIM = 1), stores, and the tile partials.
 template <typename Real, int P, int LIM>
 DG_DEV void finish_stage(const Member<Real>& M, const StageArgs& A, int tile, int e, int ec, bool valid, int E,
                          Real (&w)[3][Tab<P>::NP], Real (&acc)[3][Tab<P>::NP], const Real (&hb)[3], const Real (&ex)[3],
                          const Real (&ey)[3], Real detJ, Real idet, double dt, double bout, double bin, Real Rv,
-                         double rain_part, double* lds) {
+                         double rain_part, double* lds, const Real (&w0v)[3][Tab<P>::NP]) {
   constexpr int NP = Tab<P>::NP;
   acc[0][0] += Real(2) * detJ * Rv;
   const Real cdt = Real(A.gam * dt);
   const Real ca = Real(A.a), cb = Real(A.b);
-  const DG_G Real* __restrict__ W0 = gp(M.W[0]);
 #pragma unroll
   for (int v = 0; v < 3; ++v)
 #pragma unroll
     for (int m = 0; m < NP; ++m) {
       const Real L = acc[v][m] * idet * Real(1.0 / mass_(m));
-      Real nw = cb * (w[v][m] + cdt * L);
-      if (A.a != 0.0) nw += ca * W0[(v * NP + m) * E + ec];
-      w[v][m] = nw;
+      w[v][m] = cb * (w[v][m] + cdt * L) + ca * w0v[v][m];
     }
   double part[5] = {bout, bin, 0.0, __builtin_inf(), 0.0};
   if (LIM == 0) {
@@ -624,6 +658,8 @@ __global__ DG_STAGE_ATTR void stage_kernel(const Member<Real>* __restrict__ mem,
   ElemData<Real, P> d;
   load_elem<Real, P>(M, Win, E, ec, d);
   const bool myflag = Fin[ec] & 1;
+  Real w0v[3][NP];
+  load_blend<Real, P>(M, A, E, ec, w0v);
   const uint8_t nkp = gp(M.nk)[ec];
   Real acc[3][NP];
 #pragma unroll
@@ -717,7 +753,7 @@ __global__ DG_STAGE_ATTR void stage_kernel(const Member<Real>* __restrict__ mem,
   const Real Rv = element_rain<Real>(M, A, E, e, ec, valid, d.ex, d.ey, rain_part);
   // lanes past the end of the mesh evaluated a copy of the last element
   finish_stage<Real, P, LIM>(M, A, tl.tile, e, ec, valid, E, d.w, acc, d.hb, d.ex, d.ey, d.detJ, d.idet, dt,
-                             valid ? bout : 0.0, valid ? bin : 0.0, Rv, rain_part, lds);
+                             valid ? bout : 0.0, valid ? bin : 0.0, Rv, rain_part, lds, w0v);
 }
 
 // ---------------------------------------------------- stage kernel, per edge
@@ -943,6 +979,8 @@ __global__ DG_STAGE_ATTR void stage_edge_kernel(const Member<Real>* __restrict__
   __syncthreads();
 
   // ---- phase C: edge contributions, inverse mass, stage combination, post
+  Real w0v[3][NP];
+  load_blend<Real, P>(M, A, E, ec, w0v);
 #pragma unroll
   for (int k = 0; k < 3; ++k)
 #pragma unroll
@@ -958,7 +996,7 @@ __global__ DG_STAGE_ATTR void stage_edge_kernel(const Member<Real>* __restrict__
       }
     }
   finish_stage<Real, P, LIM>(M, A, tl.tile, e, ec, valid, E, d.w, acc, d.hb, d.ex, d.ey, d.detJ, d.idet, dt, bout,
-                             bin, Rv, rain_part, s_lbuf);
+                             bin, Rv, rain_part, s_lbuf, w0v);
 }
 
 // ------------------------------------------------------------ post kernel
@@ -1173,8 +1211,18 @@ __global__ __launch_bounds__(TILE) void rain_node_kernel(const Member<Real>* __r
   if (kind == RAIN_PARAM) {
     const double xc = sc->storm[0], yc = sc->storm[1], pk = sc->storm[2], T0 = sc->storm[3];
     const double rm = sc->storm[4], re = sc->storm[5];
-    const double d = hypot(x - xc, y - yc);
-    r = d < rm ? T0 + (pk - T0) * d / rm : pk * exp(-(d - rm) / re);
+    if constexpr (sizeof(Real) == 4) {
+      // FP32 members evaluate the profile in FP32 (offsets from the centre
+      // are formed in FP64 first)
+      const float dx = float(x - xc), dy = float(y - yc);
+      const float d = __builtin_amdgcn_sqrtf(dx * dx + dy * dy);
+      const float rmf = float(rm), pkf = float(pk), T0f = float(T0);
+      r = d < rmf ? double(T0f + (pkf - T0f) * d / rmf)
+                  : double(pkf * __builtin_amdgcn_exp2f(-(d - rmf) * (1.4426950408889634f / float(re))));
+    } else {
+      const double d = hypot(x - xc, y - yc);
+      r = d < rm ? T0 + (pk - T0) * d / rm : pk * exp(-(d - rm) / re);
+    }
   } else {
     const Forcing& f = M.fo;
     const size_t rs = size_t(f.gnx) * f.gny;

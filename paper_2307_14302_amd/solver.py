@@ -156,8 +156,9 @@ class Solver:
         call("dgswe_get_tuning", self.h, N.TUNE_STAGE_VARIANT, C.byref(v))
         return v.value
 
-    def profiling(self, on: bool = True):
-        call("dgswe_set_profiling", self.h, int(bool(on)))
+    def profiling(self, on=True):
+        """False/0 off, True/1 every kernel, 2 the stage kernel only."""
+        call("dgswe_set_profiling", self.h, int(on))
 
     def kernel_stats(self, name: str):
         n, ms = C.c_int64(), C.c_double()

@@ -266,6 +266,8 @@ def test_full_size_basin_one_step(dg, precision, tol):
     print(precision, "full-size one-step rel L2", err, flush=True)
     assert err.max() < tol, err
     m1 = gpu.mass()
-    assert abs((m1["rain_in"] - m0["rain_in"]) - orc.rain_in) <= 1e-9 * orc.rain_in
+    # FP32 members evaluate the storm profile in FP32
+    rtol = 1e-9 if precision == "fp64" else 1e-6
+    assert abs((m1["rain_in"] - m0["rain_in"]) - orc.rain_in) <= rtol * orc.rain_in
     assert np.array_equal(gpu.flags().astype(bool), orc.flags) or precision == "fp32"
     gpu.close()
