@@ -221,13 +221,40 @@ DG_DEV void num_flux(const W3<R>& a, const W3<R>& b, R hb, R nx, R ny, R g, R H0
   else flux_llf(a, b, hb, nx, ny, g, H0, F);
 }
 
-// Land boundary: the state against its mirror image (normal discharge
-// reversed): zero mass flux, hydrostatic pressure.
+// Land boundary: the numerical flux between the state and its mirror image
+// (normal discharge reversed).  Written out, both solvers give a zero mass
+// flux and a normal momentum flux Phi n with
+//   LLF: Phi = P + q_n (u_n + |u_n| + c),   c = sqrt(g max(H, 0)),
+//   Roe: Phi = P + q_n (u_n + c~),          c~ = sqrt(g max(H, H0))
+// (the Roe average of the pair has zero normal velocity, so the two
+// acoustic waves carry the reflected discharge), u_n = q_n / max(H, H0).
 template <int FLUX, typename R>
 DG_DEV void wall_flux(const W3<R>& a, R hb, R nx, R ny, R g, R H0, R* F) {
+  const R H = a.z + hb;
   const R qn = a.x * nx + a.y * ny;
-  W3<R> m{a.z, a.x - R(2) * qn * nx, a.y - R(2) * qn * ny};
-  num_flux<FLUX>(a, m, hb, nx, ny, g, H0, F);
+  const R P = R(0.5) * g * a.z * (a.z + R(2) * hb);
+  R Phi;
+  if (FLUX == 0) {
+    const R Hs = dmax(H, H0);
+    R ih, c;
+    if constexpr (sizeof(R) == 4) {
+      const float r = __builtin_amdgcn_rsqf(Hs);
+      ih = r * r;
+      c = __builtin_amdgcn_sqrtf(g) * (Hs * r);
+    } else {
+      ih = R(1) / Hs;
+      c = dsqrt(g * Hs);
+    }
+    Phi = P + qn * (qn * ih + c);
+  } else {
+    R ih, c;
+    depth_inv_speed(H, g, H0, ih, c);
+    const R un = qn * ih;
+    Phi = P + qn * (un + dabs(un) + c);
+  }
+  F[0] = R(0);
+  F[1] = Phi * nx;
+  F[2] = Phi * ny;
 }
 
 }  // namespace dg
