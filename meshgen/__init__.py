@@ -22,3 +22,4 @@ from .generators import (  # noqa: F401
     parametric_track, gridded_field, seed_for, dam_break, inclined_plane,
     log_uniform_sizes, basin_member, ensemble_plan, request_trace, serving_pool_sizes,
 )
+from .graded import graded_coast, graded_small  # noqa: F401,E402

@@ -1,0 +1,71 @@
+"""The graded coastal workload on the GPU: element-by-element parity with
+the oracle on a small instance of the same construction, and properties at
+the full size of 3,596,698 triangles (finite state, mass budget, FP32 vs
+FP64 agreement)."""
+import types
+
+import numpy as np
+import pytest
+
+import meshgen
+from oracle.solver import from_scenario
+from tests.parity import rel_l2
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dg():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2307_14302_amd as pkg
+    return pkg
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 1e-4)])
+def test_graded_small_parity(dg, precision, tol):
+    sc = meshgen.graded_small()
+    gpu = dg.Solver.from_scenario(sc, precision=precision)
+    orc = from_scenario(sc)
+    gpu.step(100)
+    orc.step(100)
+    err = rel_l2(gpu.state(), orc.w, orc)
+    print(precision, "graded small", sc.mesh.n_tri, "rel L2", err, flush=True)
+    assert err.max() < tol, err
+    if precision == "fp64":
+        mg, mo = gpu.mass(), orc.mass_totals()
+        for k in ("t", "volume", "rain_in", "bnd_in", "bnd_out"):
+            assert abs(mg[k] - mo[k]) <= 1e-10 * max(1.0, abs(mo[k])), k
+        assert np.array_equal(gpu.flags().astype(bool), orc.flags)
+    gpu.close()
+
+
+@pytest.fixture(scope="module")
+def full_size():
+    return meshgen.graded_coast()
+
+
+def test_graded_full_size_properties(dg, full_size):
+    sc = full_size
+    assert sc.mesh.n_tri == 3596698
+    res = {}
+    for precision in ("fp64", "fp32"):
+        s = dg.Solver.from_scenario(sc, precision=precision)
+        m0 = s.mass()
+        s.step(30)
+        m = s.mass()
+        w = s.state()
+        assert np.isfinite(w).all()
+        resid = m["volume"] - m0["volume"] - m["rain_in"] + m["bnd_out"] - m["bnd_in"]
+        rtol = 1e-12 if precision == "fp64" else 1e-6
+        print(precision, "graded full: t", m["t"], "dt", m["dt_last"], "dry", m["n_dry"], "budget residual",
+              resid / m["volume"], flush=True)
+        assert abs(resid) <= rtol * m["volume"]
+        assert m["steps"] == 30 and m["n_dry"] > 0 and m["bnd_in"] > 0.0
+        res[precision] = (w, m)
+        s.close()
+    like = types.SimpleNamespace(p=1, hbv=sc.mesh.hb[sc.mesh.tri])
+    err = rel_l2(res["fp32"][0], res["fp64"][0], like)
+    print("graded full fp32 vs fp64", err, flush=True)
+    assert err.max() < 1e-4
+    assert abs(res["fp32"][1]["t"] - res["fp64"][1]["t"]) < 1e-5 * res["fp64"][1]["t"]
