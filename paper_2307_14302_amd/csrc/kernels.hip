@@ -396,8 +396,9 @@ DG_DEV void edge_length(Real ex, Real ey, Real& ell, Real& il) {
 
 // Area integrals: volume flux, bed slope and bottom friction (Eq. SWE).
 template <typename Real, int P>
-DG_DEV void area_terms(const Real (&w)[3][Tab<P>::NP], const Real (&hb)[3], Real cx0, Real cx1, Real cy0, Real cy1,
-                       Real detJ, Real idet, Real fc, int friction, Real g, Real H0, Real (&acc)[3][Tab<P>::NP]) {
+DG_DEV void area_terms_unrolled(const Real (&w)[3][Tab<P>::NP], const Real (&hb)[3], Real cx0, Real cx1, Real cy0,
+                                Real cy1, Real detJ, Real idet, Real fc, int friction, Real g, Real H0,
+                                Real (&acc)[3][Tab<P>::NP]) {
   constexpr int NP = Tab<P>::NP, NQ = Tab<P>::NQ;
   const Real dhr = Real(0.5) * (hb[1] - hb[0]), dhs = Real(0.5) * (hb[2] - hb[0]);
   const Real dhx = (cx0 * dhr + cx1 * dhs) * idet, dhy = (cy0 * dhr + cy1 * dhs) * idet;
@@ -466,6 +467,104 @@ DG_DEV void area_terms(const Real (&w)[3][Tab<P>::NP], const Real (&hb)[3], Real
       for (int v = 0; v < 3; ++v) acc[v][m] += gx * Sx[v] + gy * Sy[v];
     }
   }
+}
+
+// Basis values, gradients, barycentric weights and weights at the area
+// points, as a table in constant memory (built at compile time from the
+// same closed forms) for the p = 2 loop below.
+template <typename Real, int P>
+struct AreaTable {
+  Real Q[Tab<P>::NQ][Tab<P>::NP], QR[Tab<P>::NQ][Tab<P>::NP], QS[Tab<P>::NQ][Tab<P>::NP];
+  Real L[Tab<P>::NQ][3], W[Tab<P>::NQ];
+};
+template <typename Real, int P>
+constexpr AreaTable<Real, P> make_area_table() {
+  AreaTable<Real, P> t{};
+  for (int q = 0; q < Tab<P>::NQ; ++q) {
+    for (int m = 0; m < Tab<P>::NP; ++m) {
+      t.Q[q][m] = Real(B<P>::Q(q, m));
+      t.QR[q][m] = Real(B<P>::QR(q, m));
+      t.QS[q][m] = Real(B<P>::QS(q, m));
+    }
+    for (int i = 0; i < 3; ++i) t.L[q][i] = Real(lam_(i, Tab<P>::qr(q), Tab<P>::qs(q)));
+    t.W[q] = Real(Tab<P>::qw(q));
+  }
+  return t;
+}
+__constant__ AreaTable<float, 2> c_area2f = make_area_table<float, 2>();
+__constant__ AreaTable<double, 2> c_area2d = make_area_table<double, 2>();
+
+// p = 2 area integrals: one quadrature point per loop trip with the table
+// above (the unrolled form keeps far more registers live than the 18
+// accumulators need).  Per point the fluxes are mapped once to the
+// reference directions, Gr = w (cx0 Fx + cy0 Fy), Gs = w (cx1 Fx + cy1 Fy),
+// then every mode takes dphi/dr Gr + dphi/ds Gs.
+template <typename Real>
+DG_DEV void area_terms_p2(const Real (&w)[3][6], const Real (&hb)[3], Real cx0, Real cx1, Real cy0, Real cy1,
+                          Real detJ, Real idet, Real fc, int friction, Real g, Real H0, Real (&acc)[3][6]) {
+  const AreaTable<Real, 2>& T = *reinterpret_cast<const AreaTable<Real, 2>*>(
+      sizeof(Real) == 4 ? static_cast<const void*>(&c_area2f) : static_cast<const void*>(&c_area2d));
+  const Real dhr = Real(0.5) * (hb[1] - hb[0]), dhs = Real(0.5) * (hb[2] - hb[0]);
+  const Real dhx = (cx0 * dhr + cx1 * dhs) * idet, dhy = (cy0 * dhr + cy1 * dhs) * idet;
+  const Real gn2 = g * fc * fc;
+#pragma unroll 1
+  for (int q = 0; q < 9; ++q) {
+    Real wq[3];
+#pragma unroll
+    for (int v = 0; v < 3; ++v) {
+      Real s = Real(0);
+#pragma unroll
+      for (int m = 0; m < 6; ++m) s += T.Q[q][m] * w[v][m];
+      wq[v] = s;
+    }
+    const Real hq = T.L[q][0] * hb[0] + T.L[q][1] * hb[1] + T.L[q][2] * hb[2];
+    const Real Hs = dmax(wq[0] + hq, H0);
+    Real iH, Hm43;
+    if constexpr (sizeof(Real) == 4) {
+      const float r = __builtin_amdgcn_rsqf(Hs);
+      iH = r * r;
+      Hm43 = friction == 0 ? __builtin_amdgcn_exp2f(-1.3333333333333333f * __builtin_amdgcn_logf(Hs)) : 0.0f;
+    } else {
+      iH = Real(1) / Hs;
+      Hm43 = friction == 0 ? Real(1) / pow43(Hs) : Real(0);
+    }
+    const Real u = wq[1] * iH, vv_ = wq[2] * iH;
+    const Real Pq = Real(0.5) * g * wq[0] * (wq[0] + Real(2) * hq);
+    const Real spd = dsqrt(wq[1] * wq[1] + wq[2] * wq[2]) * iH;
+    const Real tau = (friction == 0) ? gn2 * spd * Hm43 : fc * spd * iH;
+    const Real Fx[3] = {wq[1], wq[1] * u + Pq, wq[2] * u};
+    const Real Fy[3] = {wq[2], wq[1] * vv_, wq[2] * vv_ + Pq};
+    const Real s1 = g * wq[0] * dhx - tau * wq[1];
+    const Real s2 = g * wq[0] * dhy - tau * wq[2];
+    const Real Wq = T.W[q];
+    const Real wdet = Wq * detJ;
+    Real Gr[3], Gs[3];
+#pragma unroll
+    for (int v = 0; v < 3; ++v) {
+      Gr[v] = Wq * (cx0 * Fx[v] + cy0 * Fy[v]);
+      Gs[v] = Wq * (cx1 * Fx[v] + cy1 * Fy[v]);
+    }
+#pragma unroll
+    for (int m = 0; m < 6; ++m) {
+      if (m > 0) {
+        const Real dr = T.QR[q][m], ds = T.QS[q][m];
+#pragma unroll
+        for (int v = 0; v < 3; ++v) acc[v][m] += dr * Gr[v] + ds * Gs[v];
+      }
+      const Real ps = wdet * T.Q[q][m];
+      acc[1][m] += ps * s1;
+      acc[2][m] += ps * s2;
+    }
+  }
+}
+
+template <typename Real, int P>
+DG_DEV void area_terms(const Real (&w)[3][Tab<P>::NP], const Real (&hb)[3], Real cx0, Real cx1, Real cy0, Real cy1,
+                       Real detJ, Real idet, Real fc, int friction, Real g, Real H0, Real (&acc)[3][Tab<P>::NP]) {
+  if constexpr (P == 2)
+    area_terms_p2<Real>(w, hb, cx0, cx1, cy0, cy1, detJ, idet, fc, friction, g, H0, acc);
+  else
+    area_terms_unrolled<Real, P>(w, hb, cx0, cx1, cy0, cy1, detJ, idet, fc, friction, g, H0, acc);
 }
 
 // Element rain rate (Eq. rain).  With time-dependent rain the first stage of
