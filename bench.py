@@ -143,7 +143,7 @@ def roofline(res, precision, p, limiter):
             "avg_us": round(avg_s * 1e6, 2), "launches": n}
 
 
-def run_ensemble(n_members=64, t_sim=120.0, chunk=10):
+def run_ensemble(n_members=64, t_sim=120.0, chunk=10, autotune=True):
     """64 members (sizes log-uniform in [1e4, 5e5] triangles, even members
     p = 1, odd members p = 2, FP32), each simulating t_sim seconds, stepped
     together by one batch: every launch covers all active members of a
@@ -156,6 +156,8 @@ def run_ensemble(n_members=64, t_sim=120.0, chunk=10):
     for i, n_tri, p in meshgen.ensemble_plan(n_members):
         sc = meshgen.basin_member(4, i, n_tri, p=p)
         s = Solver.from_scenario(sc, precision="fp32")
+        if autotune:
+            s.autotune(3)
         dt0 = s.mass()["dt_next"]
         members.append((s, int(math.ceil(t_sim / dt0)), int(sc.params["rk_stages"]), p))
     log(f"[ensemble] {len(members)} members, {sum(m[0].n_tri for m in members)} triangles, set-up "
@@ -178,6 +180,8 @@ def run_ensemble(n_members=64, t_sim=120.0, chunk=10):
            "n_tri_total": int(sum(s.n_tri for s, _, _, _ in members)),
            "p_mix": {"p1": sum(1 for m in members if m[3] == 1), "p2": sum(1 for m in members if m[3] == 2)},
            "t_sim_s": t_sim, "steps_min": int(min(m[1] for m in members)), "steps_max": int(max(m[1] for m in members)),
+           "stage_variants": {"per_element": sum(1 for m in members if m[0].variant() == 0),
+                              "per_edge": sum(1 for m in members if m[0].variant() == 1)},
            "wall_s": round(el, 3), "p50_latency_s": round(float(np.percentile(lat, 50)), 4),
            "p99_latency_s": round(float(np.percentile(lat, 99)), 4), "dtype": "f32"}
     log(f"[ensemble] {work:.3e} element-stages in {el:.2f}s -> {work / el:.4e}/s; latency p50 "

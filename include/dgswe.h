@@ -219,6 +219,16 @@ int dgswe_kernel_stats(dgswe_ctx* ctx, const char* kernel, int64_t* launches, do
 int dgswe_set_tuning(dgswe_ctx* ctx, int key, int value);
 int dgswe_get_tuning(const dgswe_ctx* ctx, int key, int* value);
 
+/* Autotuner: times n_steps steps of this context with each stage-kernel
+ * variant (after two untimed steps each), keeps the faster one and restores
+ * the state, flags, tile partials and scalars, so the context continues
+ * exactly where it was.  chosen (may be NULL) receives the variant,
+ * ms_per_step[2] (may be NULL) the two timings.  Allocates a copy of the
+ * state for the duration of the call.  EINVAL for n_steps < 1, ESTATE
+ * without mesh or state or inside a batch, ENONFINITE if the context has a
+ * latched error. */
+int dgswe_autotune(dgswe_ctx* ctx, int n_steps, int* chosen, double* ms_per_step);
+
 /* ---------------------------------------------------------------- batches
  * A batch advances many contexts (ensemble members or serving requests)
  * together: each stage is one launch over the element tiles of every active

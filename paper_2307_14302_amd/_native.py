@@ -80,6 +80,7 @@ SIGNATURES = {
     "dgswe_footprint_bytes": (C.c_int64, [C.POINTER(Params), C.c_int64, C.c_int64]),
     "dgswe_set_tuning": (C.c_int, [_P, C.c_int, C.c_int]),
     "dgswe_get_tuning": (C.c_int, [_P, C.c_int, C.POINTER(C.c_int)]),
+    "dgswe_autotune": (C.c_int, [_P, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_double)]),
     "dgswe_set_profiling": (C.c_int, [_P, C.c_int]),
     "dgswe_kernel_stats": (C.c_int, [_P, C.c_char_p, _I64, _D]),
     "dgswe_batch_create": (C.c_int, [C.POINTER(Params), _P, C.c_int64, C.POINTER(_P)]),

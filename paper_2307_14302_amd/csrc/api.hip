@@ -985,6 +985,70 @@ int dgswe_get_tuning(const dgswe_ctx* c, int key, int* value) {
   return DGSWE_OK;
 }
 
+int dgswe_autotune(dgswe_ctx* c, int n_steps, int* chosen, double* ms_per_step) {
+  int rc = check_ctx(c, true, true);
+  if (rc) return rc;
+  if (c->in_batch) return fail(DGSWE_ESTATE, "context is a member of a batch");
+  if (n_steps < 1) return fail(DGSWE_EINVAL, "autotune needs at least one timed step");
+  Scalars s0;
+  rc = read_scalars(c, s0);
+  if (rc) return rc;
+  if (s0.error) return fail(DGSWE_ENONFINITE, "the volume or the time step became non-finite");
+  // what a step carries over: the state, its flags, the tile partials (the
+  // rain partial of constant rain is written once) and the scalars
+  const size_t wb = c->W[0].bytes, fb = c->F[0].bytes, pb = c->part.bytes;
+  DevBuf w0, f0, p0;
+  HIPCHK(w0.alloc(wb));
+  HIPCHK(f0.alloc(fb));
+  HIPCHK(p0.alloc(pb));
+  if (wb) HIPCHK(hipMemcpyAsync(w0.p, c->W[0].p, wb, hipMemcpyDeviceToDevice, c->stream));
+  if (fb) HIPCHK(hipMemcpyAsync(f0.p, c->F[0].p, fb, hipMemcpyDeviceToDevice, c->stream));
+  if (pb) HIPCHK(hipMemcpyAsync(p0.p, c->part.p, pb, hipMemcpyDeviceToDevice, c->stream));
+  auto restore = [&]() -> int {
+    if (wb) HIPCHK(hipMemcpyAsync(c->W[0].p, w0.p, wb, hipMemcpyDeviceToDevice, c->stream));
+    if (fb) HIPCHK(hipMemcpyAsync(c->F[0].p, f0.p, fb, hipMemcpyDeviceToDevice, c->stream));
+    if (pb) HIPCHK(hipMemcpyAsync(c->part.p, p0.p, pb, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(c->sc.p, &s0, sizeof s0, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return DGSWE_OK;
+  };
+  const int saved_prof = c->prof;
+  c->prof = 0;
+  hipEvent_t ea, eb;
+  HIPCHK(hipEventCreate(&ea));
+  HIPCHK(hipEventCreate(&eb));
+  double ms[2] = {0.0, 0.0};
+  int err = DGSWE_OK;
+  for (int v = 0; v < 2 && !err; ++v) {
+    c->variant = v;
+    c->graph_dirty = true;
+    err = dgswe_step(c, 2);                     // builds the step graph, warms caches
+    if (!err) err = restore();
+    if (err) break;
+    if (hipEventRecord(ea, c->stream) != hipSuccess) { err = fail(DGSWE_EHIP, "hipEventRecord"); break; }
+    err = dgswe_step(c, n_steps);
+    if (err) break;
+    if (hipEventRecord(eb, c->stream) != hipSuccess) { err = fail(DGSWE_EHIP, "hipEventRecord"); break; }
+    if (hipEventSynchronize(eb) != hipSuccess) { err = fail(DGSWE_EHIP, "hipEventSynchronize"); break; }
+    float f = 0.0f;
+    (void)hipEventElapsedTime(&f, ea, eb);
+    ms[v] = double(f) / n_steps;
+    err = restore();
+  }
+  (void)hipEventDestroy(ea);
+  (void)hipEventDestroy(eb);
+  c->prof = saved_prof;
+  if (err) {
+    (void)restore();
+    return err;
+  }
+  c->variant = ms[1] <= ms[0] ? 1 : 0;
+  c->graph_dirty = true;
+  if (chosen) *chosen = c->variant;
+  if (ms_per_step) { ms_per_step[0] = ms[0]; ms_per_step[1] = ms[1]; }
+  return DGSWE_OK;
+}
+
 int dgswe_set_profiling(dgswe_ctx* c, int on) {
   int rc = check_ctx(c, false);
   if (rc) return rc;

@@ -151,6 +151,14 @@ class Solver:
     def set_variant(self, variant: int):
         call("dgswe_set_tuning", self.h, N.TUNE_STAGE_VARIANT, int(variant))
 
+    def autotune(self, n_steps: int = 5):
+        """Pick the faster stage-kernel variant for this mesh; the state is
+        left as it was.  Returns (variant, (ms/step variant 0, variant 1))."""
+        v = C.c_int()
+        ms = (C.c_double * 2)()
+        call("dgswe_autotune", self.h, int(n_steps), C.byref(v), ms)
+        return v.value, (ms[0], ms[1])
+
     def variant(self) -> int:
         v = C.c_int()
         call("dgswe_get_tuning", self.h, N.TUNE_STAGE_VARIANT, C.byref(v))

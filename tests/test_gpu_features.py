@@ -271,3 +271,20 @@ def test_full_size_basin_one_step(dg, precision, tol):
     assert abs((m1["rain_in"] - m0["rain_in"]) - orc.rain_in) <= rtol * orc.rain_in
     assert np.array_equal(gpu.flags().astype(bool), orc.flags) or precision == "fp32"
     gpu.close()
+
+
+def test_autotune_keeps_the_state(dg):
+    sc = meshgen.small_mixed(seed=12, nx=24, ny=12, flux="llf", limiter=True, rain_kind="parametric")
+    a = dg.Solver.from_scenario(sc)
+    a.step(7)
+    v, ms = a.autotune(3)
+    assert v in (0, 1) and ms[0] > 0.0 and ms[1] > 0.0
+    assert a.variant() == v and a.mass()["steps"] == 7
+    a.step(10)
+    b = dg.Solver.from_scenario(sc)
+    b.step(7)
+    b.set_variant(v)
+    b.step(10)
+    assert np.array_equal(a.state(), b.state())
+    assert a.mass() == b.mass()
+    a.close(); b.close()
