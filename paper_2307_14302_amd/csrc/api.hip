@@ -197,8 +197,11 @@ struct dgswe_batch {
   };
   std::vector<Group> groups;
   DevBuf memb;
+  hipGraphExec_t graph = nullptr;   // one step of every group, replayed
+  bool graph_dirty = true;
   ~dgswe_batch() {
     if (stream) (void)hipStreamSynchronize(stream);
+    if (graph) (void)hipGraphExecDestroy(graph);
     if (own_stream && stream) (void)hipStreamDestroy(stream);
   }
 };
@@ -1208,26 +1211,65 @@ int dgswe_batch_add(dgswe_batch* b, dgswe_ctx* c, int64_t n_steps, int32_t* slot
   return DGSWE_OK;
 }
 
+static int batch_enqueue_step(dgswe_batch* b) {
+  for (auto& g : b->groups) {
+    int rc;
+    if (b->prm.precision == DGSWE_FP32)
+      rc = enqueue_step_group<float>(b->memb.as<Member<float>>(), g.tiles.as<Tile>(), g.n_tiles,
+                                     g.node_tiles.as<Tile>(), g.n_node_tiles, g.ids.as<int>(),
+                                     int(g.members.size()), g.max_chunks, g.p, g.flux, g.limiter, g.variant, g.rk,
+                                     g.has_rain, b->stream, nullptr);
+    else
+      rc = enqueue_step_group<double>(b->memb.as<Member<double>>(), g.tiles.as<Tile>(), g.n_tiles,
+                                      g.node_tiles.as<Tile>(), g.n_node_tiles, g.ids.as<int>(),
+                                      int(g.members.size()), g.max_chunks, g.p, g.flux, g.limiter, g.variant, g.rk,
+                                      g.has_rain, b->stream, nullptr);
+    if (rc) return rc;
+  }
+  return DGSWE_OK;
+}
+
+// one step of every group captured once per membership and replayed
+static int batch_build_graph(dgswe_batch* b) {
+  if (b->graph) {
+    (void)hipGraphExecDestroy(b->graph);
+    b->graph = nullptr;
+  }
+  hipGraph_t g = nullptr;
+  HIPCHK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+  int rc = batch_enqueue_step(b);
+  hipError_t e = hipStreamEndCapture(b->stream, &g);
+  if (rc) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess) return fail(DGSWE_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+  e = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) return fail(DGSWE_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+  b->graph_dirty = false;
+  return DGSWE_OK;
+}
+
 int dgswe_batch_step(dgswe_batch* b, int64_t max_steps) {
   if (!b) return fail(DGSWE_EINVAL, "null batch");
   if (max_steps < 0) return fail(DGSWE_EINVAL, "negative step count");
   if (b->dirty) {
     int rc = batch_rebuild(b);
     if (rc) return rc;
+    b->graph_dirty = true;
+  }
+  if (b->groups.empty()) return DGSWE_OK;
+  const bool use_graph = max_steps >= 2;
+  if (use_graph && b->graph_dirty) {
+    int rc = batch_build_graph(b);
+    if (rc) return rc;
   }
   for (int64_t i = 0; i < max_steps; ++i) {
-    for (auto& g : b->groups) {
-      int rc;
-      if (b->prm.precision == DGSWE_FP32)
-        rc = enqueue_step_group<float>(b->memb.as<Member<float>>(), g.tiles.as<Tile>(), g.n_tiles,
-                                       g.node_tiles.as<Tile>(), g.n_node_tiles, g.ids.as<int>(),
-                                       int(g.members.size()), g.max_chunks, g.p, g.flux, g.limiter, g.variant, g.rk, g.has_rain, b->stream,
-                                       nullptr);
-      else
-        rc = enqueue_step_group<double>(b->memb.as<Member<double>>(), g.tiles.as<Tile>(), g.n_tiles,
-                                        g.node_tiles.as<Tile>(), g.n_node_tiles, g.ids.as<int>(),
-                                        int(g.members.size()), g.max_chunks, g.p, g.flux, g.limiter, g.variant, g.rk, g.has_rain, b->stream,
-                                        nullptr);
+    if (use_graph) {
+      HIPCHK(hipGraphLaunch(b->graph, b->stream));
+    } else {
+      int rc = batch_enqueue_step(b);
       if (rc) return rc;
     }
   }
