@@ -105,17 +105,46 @@ DG_HD double lag_(int P, int j, double t) {
 }
 
 // ------------------------------------------------------------- arithmetic
+// FP32: the hardware reciprocal / square root / reciprocal square root
+// (about 1 ulp).  FP64: the hardware approximation refined by two
+// Newton-Raphson steps, y <- y + y (1 - x y) for 1/x and
+// y <- y + y (1 - x y^2) / 2 for 1/sqrt(x); each step squares the relative
+// error, so two steps reach double precision (to about 1 ulp, not
+// correctly rounded).  Arguments are positive and finite except where a
+// caller says otherwise.
 template <typename R> DG_DEV R rcp(R x);
-template <> DG_DEV double rcp<double>(double x) { return 1.0 / x; }
+template <> DG_DEV double rcp<double>(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  y = __builtin_fma(y, __builtin_fma(-x, y, 1.0), y);
+  y = __builtin_fma(y, __builtin_fma(-x, y, 1.0), y);
+  return y;
+}
 template <> DG_DEV float rcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+template <typename R> DG_DEV R rsq(R x);
+template <> DG_DEV double rsq<double>(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  y = __builtin_fma(0.5 * y, __builtin_fma(-x * y, y, 1.0), y);
+  y = __builtin_fma(0.5 * y, __builtin_fma(-x * y, y, 1.0), y);
+  return y;
+}
+template <> DG_DEV float rsq<float>(float x) { return __builtin_amdgcn_rsqf(x); }
+// square root of x >= 0 (0 at 0)
 template <typename R> DG_DEV R dsqrt(R x);
-template <> DG_DEV double dsqrt<double>(double x) { return __builtin_sqrt(x); }
+template <> DG_DEV double dsqrt<double>(double x) { return x > 0.0 ? x * rsq<double>(x) : 0.0; }
 template <> DG_DEV float dsqrt<float>(float x) { return __builtin_amdgcn_sqrtf(x); }
-// H^(4/3) = H * cbrt(H)
-template <typename R> DG_DEV R pow43(R x);
-template <> DG_DEV double pow43<double>(double x) { return x * cbrt(x); }
-template <> DG_DEV float pow43<float>(float x) {
-  return __builtin_amdgcn_exp2f(1.3333333333333333f * __builtin_amdgcn_logf(x));
+// x^(-4/3) for x > 0 (Manning): FP32 through exp2/log2; FP64 refines a
+// single-precision guess of y = x^(-1/3) by two Newton steps of
+// y^-3 = x, y <- y (4 - x y^3) / 3, then returns y^4
+template <typename R> DG_DEV R rpow43(R x);
+template <> DG_DEV double rpow43<double>(double x) {
+  double y = double(__builtin_amdgcn_exp2f(-0.33333333333333333f * __builtin_amdgcn_logf(float(x))));
+  y = y * (4.0 - x * (y * y * y)) * (1.0 / 3.0);
+  y = y * (4.0 - x * (y * y * y)) * (1.0 / 3.0);
+  const double y2 = y * y;
+  return y2 * y2;
+}
+template <> DG_DEV float rpow43<float>(float x) {
+  return __builtin_amdgcn_exp2f(-1.3333333333333333f * __builtin_amdgcn_logf(x));
 }
 template <typename R> DG_DEV R dmax(R a, R b) { return a > b ? a : b; }
 template <typename R> DG_DEV R dmin(R a, R b) { return a < b ? a : b; }
@@ -137,7 +166,7 @@ DG_DEV void depth_inv_speed(R H, R g, R H0, R& ih, R& c) {
     ih = H >= H0 ? r * r : __builtin_amdgcn_rcpf(H0);
     c = __builtin_amdgcn_sqrtf(g) * (dmax(H, 0.0f) * r);
   } else {
-    ih = R(1) / dmax(H, H0);
+    ih = rcp(dmax(H, H0));
     c = dsqrt(g * dmax(H, R(0)));
   }
 }
@@ -191,11 +220,13 @@ DG_DEV void flux_roe(const W3<R>& a, const W3<R>& b, R hb, R nx, R ny, R g, R H0
     c = c2 * rc;
     i2c = R(0.5) * rc;
   } else {
-    sa = dsqrt(Ha); sb = dsqrt(Hb);
-    ia = R(1) / Ha; ib = R(1) / Hb;
-    ra = sa * ia; rb = sb * ib;
-    c = dsqrt(R(0.5) * g * (Ha + Hb));
-    i2c = R(1) / (R(2) * c);
+    ra = rsq(Ha); rb = rsq(Hb);
+    sa = Ha * ra; sb = Hb * rb;
+    ia = ra * ra; ib = rb * rb;
+    const R c2 = R(0.5) * g * (Ha + Hb);
+    const R rc = rsq(c2);
+    c = c2 * rc;
+    i2c = R(0.5) * rc;
   }
   const R isum = rcp(sa + sb);
   const R un = (qna * ra + qnb * rb) * isum;
@@ -242,8 +273,9 @@ DG_DEV void wall_flux(const W3<R>& a, R hb, R nx, R ny, R g, R H0, R* F) {
       ih = r * r;
       c = __builtin_amdgcn_sqrtf(g) * (Hs * r);
     } else {
-      ih = R(1) / Hs;
-      c = dsqrt(g * Hs);
+      const R r = rsq(Hs);
+      ih = r * r;
+      c = dsqrt(g) * (Hs * r);
     }
     Phi = P + qn * (qn * ih + c);
   } else {

@@ -285,7 +285,7 @@ DG_DEV double cfl_speed(const double (&hv)[3], const double (&qx)[3], const doub
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
     if (hv[i] > dry_depth(H0)) {
-      const double s = sqrt(qx[i] * qx[i] + qy[i] * qy[i]) / hv[i] + sqrt(g * hv[i]);
+      const double s = dsqrt(qx[i] * qx[i] + qy[i] * qy[i]) * rcp(hv[i]) + dsqrt(g * hv[i]);
       lam = fmax(lam, s);
     }
   }
@@ -389,8 +389,8 @@ DG_DEV void edge_length(Real ex, Real ey, Real& ell, Real& il) {
     il = __builtin_amdgcn_rsqf(l2);
     ell = l2 * il;
   } else {
-    ell = dsqrt(l2);
-    il = Real(1) / ell;
+    il = rsq(l2);
+    ell = l2 * il;
   }
 }
 
@@ -423,8 +423,9 @@ DG_DEV void area_terms_unrolled(const Real (&w)[3][Tab<P>::NP], const Real (&hb)
       iH = r * r;
       Hm43 = friction == 0 ? __builtin_amdgcn_exp2f(-1.3333333333333333f * __builtin_amdgcn_logf(Hs)) : 0.0f;
     } else {
-      iH = Real(1) / Hs;
-      Hm43 = friction == 0 ? Real(1) / pow43(Hs) : Real(0);
+      const Real r = rsq(Hs);
+      iH = r * r;
+      Hm43 = friction == 0 ? rpow43(Hs) : Real(0);
     }
     const Real u = wq[1] * iH, vv_ = wq[2] * iH;
     const Real Pq = Real(0.5) * g * wq[0] * (wq[0] + Real(2) * hq);
@@ -525,8 +526,9 @@ DG_DEV void area_terms_p2(const Real (&w)[3][6], const Real (&hb)[3], Real cx0, 
       iH = r * r;
       Hm43 = friction == 0 ? __builtin_amdgcn_exp2f(-1.3333333333333333f * __builtin_amdgcn_logf(Hs)) : 0.0f;
     } else {
-      iH = Real(1) / Hs;
-      Hm43 = friction == 0 ? Real(1) / pow43(Hs) : Real(0);
+      const Real r = rsq(Hs);
+      iH = r * r;
+      Hm43 = friction == 0 ? rpow43(Hs) : Real(0);
     }
     const Real u = wq[1] * iH, vv_ = wq[2] * iH;
     const Real Pq = Real(0.5) * g * wq[0] * (wq[0] + Real(2) * hq);
@@ -643,7 +645,7 @@ DG_DEV void finish_stage(const Member<Real>& M, const StageArgs& A, int tile, in
       const double lam = post_speed<Real, P>(filled, hv, qxv, qyv, w, hb, M.H0, M.g);
       const double area = 0.5 * (double(ex[2]) * double(ey[0]) - double(ex[0]) * double(ey[2]));
       part[2] = valid ? area * (double(w[0][0]) + (double(hb[0]) + double(hb[1]) + double(hb[2])) / 3.0) : 0.0;
-      part[3] = (valid && lam > 0.0) ? double(gp(M.din)[ec]) / lam : __builtin_inf();
+      part[3] = (valid && lam > 0.0) ? double(gp(M.din)[ec]) * rcp(lam) : __builtin_inf();
       part[4] = (valid && dry) ? 1.0 : 0.0;
     }
   } else {
@@ -1237,7 +1239,7 @@ __global__ __launch_bounds__(TILE) void post_kernel(const Member<Real>* __restri
     const double lam = post_speed<Real, P>(filled, hv, qxv, qyv, w, hb, M.H0, M.g);
     double vals[2] = {valid ? area * (double(w[0][0]) + (double(hb[0]) + double(hb[1]) + double(hb[2])) / 3.0) : 0.0,
                       (valid && dry) ? 1.0 : 0.0};
-    const double mr = (valid && lam > 0.0) ? double(gp(M.din)[ec]) / lam : __builtin_inf();
+    const double mr = (valid && lam > 0.0) ? double(gp(M.din)[ec]) * rcp(lam) : __builtin_inf();
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const double s0 = wave_sum(vals[0]), s1 = double(__popcll(__ballot(vals[1] != 0.0))), mn = wave_min(mr);
     if (lane == 0) { lds[wv * 3 + 0] = s0; lds[wv * 3 + 1] = s1; lds[wv * 3 + 2] = mn; }
