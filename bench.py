@@ -72,8 +72,15 @@ def run_precision(sc, precision, steps, warmup, variant=1, events=2):
 
     t0 = time.perf_counter()
     s = Solver.from_scenario(sc, precision=precision)
-    s.set_variant(variant)
-    log(f"[{precision}] setup {time.perf_counter() - t0:.1f}s  E={s.n_tri}")
+    tuned = None
+    if variant < 0:
+        # the library's autotuner picks the stage kernel on this mesh (the
+        # state is restored, so the run is the same as without it)
+        variant, tuned = s.autotune(5)
+    else:
+        s.set_variant(variant)
+    log(f"[{precision}] setup {time.perf_counter() - t0:.1f}s  E={s.n_tri}  stage variant {variant}"
+        + (f" (autotuned: {tuned[0]:.3f} / {tuned[1]:.3f} ms per step)" if tuned else ""))
     s.step(warmup)
     s.sync()
     # events around the stage kernel only: the dominant kernel's duration for
@@ -95,7 +102,7 @@ def run_precision(sc, precision, steps, warmup, variant=1, events=2):
     log(f"[{precision}] {steps} steps in {el:.3f}s -> {rate:.4e} element-stage/s; t={m['t']:.2f}s dt={m['dt_last']:.4f} "
         f"dry={m['n_dry']} kernels " + ", ".join(f"{k}:{n}x{(ms / max(n, 1)) * 1e3:.1f}us" for k, (n, ms) in stats.items()))
     s.close()
-    return dict(rate=rate, elapsed=el, stats=stats, mass=m, E=E, stages=stages)
+    return dict(rate=rate, elapsed=el, stats=stats, mass=m, E=E, stages=stages, variant=variant)
 
 
 def kernel_sources_hash():
@@ -242,7 +249,7 @@ def run_graded(steps=1000, warmup=20):
     t0 = time.perf_counter()
     sc = meshgen.graded_coast()
     log(f"[graded] {sc.mesh.n_tri} triangles generated in {time.perf_counter() - t0:.1f}s")
-    r = run_precision(sc, "fp32", steps, warmup, 1, 2)
+    r = run_precision(sc, "fp32", steps, warmup, -1, 2)
     n, ms = r["stats"]["stage"]
     return {"value": round(r["rate"], 1), "unit": "element-stage updates/s", "n_tri": r["E"], "steps": steps,
             "ms_per_step": round(r["elapsed"] / steps * 1e3, 4), "stage_avg_us": round(ms / max(n, 1) * 1e3, 2),
@@ -290,7 +297,8 @@ def main():
     ap.add_argument("--N", type=int, default=708, help="quads per side (708 -> 1,002,528 triangles)")
     ap.add_argument("--p", type=int, default=1, choices=[1, 2], help="polynomial degree of the basin run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
-    ap.add_argument("--variant", type=int, default=1, help="stage kernel: 0 per element, 1 per edge (default)")
+    ap.add_argument("--variant", type=int, default=-1,
+                    help="stage kernel: 0 per element, 1 per edge, -1 autotuned on the workload (default)")
     ap.add_argument("--calib-copy", action="store_true", help="also run a 1 GiB device copy (counter calibration)")
     ap.add_argument("--no-events", action="store_true",
                     help="no HIP events in the timed region (steps replay a HIP graph; no roofline)")
@@ -333,13 +341,14 @@ def main():
                                f"p={args.p}, LLF, limiter on, parametric moving rain, wet/dry front, "
                                + ("SSP-RK2 CFL 0.3" if args.p == 1 else "SSP-RK3 CFL 0.15"),
                    "n_tri": r["E"], "p": prm["p"], "rk_stages": r["stages"], "precision": main_prec,
-                   "stage_variant": args.variant,
+                   "stage_variant": r["variant"],
                    "parallelism": "single GPU"},
         "roofline": roofline(r, main_prec, prm["p"], prm["limiter"]),
     }
     if "fp64" in res and main_prec != "fp64":
         f = res["fp64"]
         out["fp64"] = {"value": round(f["rate"], 1), "ms_per_step": round(f["elapsed"] / args.steps * 1e3, 4),
+                       "stage_variant": f["variant"],
                        "dtype": "f64", "roofline": roofline(f, "fp64", prm["p"], prm["limiter"]),
                        "fp32_over_fp64": round(r["rate"] / f["rate"], 3)}
     if not args.no_graded:
