@@ -58,6 +58,20 @@ DG_DEV double lane_f64(double x, int lane) {
   const int hi = __builtin_amdgcn_readlane(int(b >> 32), lane);
   return __longlong_as_double((long long)(unsigned)lo | ((long long)hi << 32));
 }
+// Inclusive prefix sum of an int over the wavefront with DPP: shifts by 1,
+// 2, 4 and 8 lanes within each 16-lane row (zero fill), then the last lane
+// of row 0 and 2 is added to rows 1 and 3 and the last lane of row 1 to
+// rows 2 and 3.
+DG_DEV int wave_incl_scan(int x) {
+  x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xF, 0xF, false);   // row_shr:1
+  x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xF, 0xF, false);   // row_shr:2
+  x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xF, 0xF, false);   // row_shr:4
+  x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xF, 0xF, false);   // row_shr:8
+  x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xA, 0xF, false);   // row_bcast:15
+  x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xC, 0xF, false);   // row_bcast:31
+  return x;
+}
+
 DG_DEV double wave_sum(double v) {
 #pragma unroll
   for (int c = 0; c < 4; ++c) v += dpp_f64(v, c);
@@ -619,13 +633,15 @@ DG_DEV void finish_stage(const Member<Real>& M, const StageArgs& A, int tile, in
   acc[0][0] += Real(2) * detJ * Rv;
   const Real cdt = Real(A.gam * dt);
   const Real ca = Real(A.a), cb = Real(A.b);
+  // w <- a w^n + b w + (b gam dt / (det J m_k)) acc, one coefficient per mode
+  Real km[NP];
+  const Real bcd = cb * cdt * idet;
+#pragma unroll
+  for (int m = 0; m < NP; ++m) km[m] = bcd * Real(1.0 / mass_(m));
 #pragma unroll
   for (int v = 0; v < 3; ++v)
 #pragma unroll
-    for (int m = 0; m < NP; ++m) {
-      const Real L = acc[v][m] * idet * Real(1.0 / mass_(m));
-      w[v][m] = cb * (w[v][m] + cdt * L) + ca * w0v[v][m];
-    }
+    for (int m = 0; m < NP; ++m) w[v][m] = km[m] * acc[v][m] + (cb * w[v][m] + ca * w0v[v][m]);
   double part[5] = {bout, bin, 0.0, __builtin_inf(), 0.0};
   if (LIM == 0) {
     double hv[3], qxv[3], qyv[3];
@@ -940,12 +956,7 @@ __global__ DG_STAGE_ATTR void stage_edge_kernel(const Member<Real>* __restrict__
   }
   // block-wide exclusive scan of the packed counts
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  int incl = packed;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const int y = __shfl_up(incl, o, 64);
-    if (lane >= o) incl += y;
-  }
+  const int incl = wave_incl_scan(packed);
   if (lane == 63) s_wsum[wv] = incl;
   Real acc[3][NP];
 #pragma unroll

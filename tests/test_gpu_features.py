@@ -288,3 +288,40 @@ def test_autotune_keeps_the_state(dg):
     assert np.array_equal(a.state(), b.state())
     assert a.mass() == b.mass()
     a.close(); b.close()
+
+
+def test_graph_replays_match_eager_steps(dg):
+    """Steps replayed from the captured graph (step(n >= 2)) against eager
+    launches (step(1)), compared after every replay, with reads, a profiling
+    window and rain changes between the replays."""
+    sc = meshgen.small_mixed(seed=14, nx=20, ny=10, flux="llf", limiter=True, rain_kind="gridded")
+    eager = dg.Solver.from_scenario(sc)
+    graph = dg.Solver.from_scenario(sc)
+    for rep in range(6):
+        for _ in range(4):
+            eager.step(1)
+        graph.step(4)
+        assert np.array_equal(eager.state(), graph.state()), rep
+        assert eager.mass() == graph.mass(), rep
+        if rep == 2:
+            # eager work of the program between replays: a timing window
+            graph.profiling(True)
+            graph.step(1)
+            graph.profiling(False)
+            eager.step(1)
+    batch_eager = dg.Batch({"precision": "fp64"})
+    batch_graph = dg.Batch({"precision": "fp64"})
+    a = dg.Solver.from_scenario(sc)
+    b = dg.Solver.from_scenario(sc)
+    batch_eager.add(a, 30)
+    batch_graph.add(b, 30)
+    for rep in range(5):
+        for _ in range(6):
+            batch_eager.step(1)
+        batch_graph.step(6)
+        batch_eager.poll()
+        batch_graph.poll()
+        assert np.array_equal(a.state(), b.state()), rep
+    batch_eager.close(); batch_graph.close()
+    for s in (eager, graph, a, b):
+        s.close()
