@@ -114,7 +114,7 @@ def kernel_sources_hash():
     return h.hexdigest()[:16]
 
 
-def counted_traffic(kernel, precision):
+def counted_traffic(kernel, precision, variant=1):
     """HBM bytes per launch of ``kernel`` from the committed rocprofv3 counter
     summary (FETCH_SIZE and WRITE_SIZE scaled by the copy calibration), or
     None when the kernel sources changed since the counters were taken."""
@@ -127,7 +127,7 @@ def counted_traffic(kernel, precision):
         return None
     if d.get("sources") != kernel_sources_hash():
         return None
-    name = "stage_edge_kernel" if kernel == "stage" else "post_kernel"
+    name = ("stage_edge_kernel" if variant == 1 else "stage_kernel") if kernel == "stage" else "post_kernel"
     return d["bytes"].get(f"{name}/{precision}")
 
 
@@ -146,7 +146,8 @@ def roofline(res, precision, p, limiter):
     avg_s = ms / n * 1e-3
     ach = byts / avg_s / 1e9
     return {"kernel": dom, "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": counted_traffic(dom, precision), "bytes_per_launch": int(byts),
+            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": counted_traffic(dom, precision, res.get("variant", 1)),
+            "bytes_per_launch": int(byts),
             "avg_us": round(avg_s * 1e6, 2), "launches": n}
 
 
