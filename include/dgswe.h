@@ -202,11 +202,13 @@ int dgswe_info(const dgswe_ctx* ctx, int64_t* n_tri, int64_t* n_nodes, int64_t* 
 /* Device bytes a context of this size needs (state, mesh, rain, scratch). */
 int64_t dgswe_footprint_bytes(const dgswe_params* params, int64_t n_tri, int64_t n_nodes);
 
-/* Per-kernel timing with HIP events recorded on the context's stream
- * around launches of the named kernel ("stage", "post", "rain", "reduce").
- * on: 0 = off (default; steps then replay a HIP graph), 1 = every kernel,
- * 2 = the stage kernel only (fewest events between launches).  Changing
- * the mode resets the counters; EINVAL for other values. */
+/* Per-kernel timing with HIP events on the context's stream ("stage",
+ * "post", "rain", "reduce").  The stage kernel's events are attached to its
+ * own dispatch (start and end of the kernel itself); the others are marker
+ * events recorded around the launch.  on: 0 = off (default; steps then
+ * replay a HIP graph), 1 = every kernel, 2 = the stage kernel only (no
+ * packets between launches).  Changing the mode resets the counters;
+ * EINVAL for other values. */
 int dgswe_set_profiling(dgswe_ctx* ctx, int on);
 int dgswe_kernel_stats(dgswe_ctx* ctx, const char* kernel, int64_t* launches, double* total_ms);
 

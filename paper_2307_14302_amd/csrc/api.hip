@@ -222,6 +222,7 @@ Member<Real> member_struct(const dgswe_ctx* c) {
   m.cfl = c->prm.cfl;
   m.dt_fixed = c->prm.dt_fixed;
   m.dt_max = c->prm.dt_max;
+  m.feps = 1e-3 * m.H0 * std::sqrt(m.g * m.H0);
   if (md) {
     m.ev = md->ev.as<Real>();
     m.hbv = md->hbv.as<Real>();
@@ -288,21 +289,28 @@ void harvest(dgswe_ctx* c) {
   c->pending.clear();
 }
 
+// Timing of one launch while profiling is on.  With own = true the launcher
+// hands a and b to the kernel's dispatch (start and end of the kernel
+// itself); otherwise marker events are recorded around the launch.
 struct ProfScope {
   dgswe_ctx* c;
   int k;
-  hipEvent_t a = nullptr;
-  ProfScope(dgswe_ctx* c_, int k_) : c((c_ && (c_->prof == 1 || (c_->prof == 2 && k_ == K_STAGE))) ? c_ : nullptr),
-                                      k(k_) {
+  bool own;
+  hipEvent_t a = nullptr, b = nullptr;
+  ProfScope(dgswe_ctx* c_, int k_, bool own_ = false)
+      : c((c_ && (c_->prof == 1 || (c_->prof == 2 && k_ == K_STAGE))) ? c_ : nullptr), k(k_), own(own_) {
     if (c) {
       a = get_event(c);
-      (void)hipEventRecord(a, c->stream);
+      if (own) b = get_event(c);
+      else (void)hipEventRecord(a, c->stream);
     }
   }
   ~ProfScope() {
     if (c) {
-      hipEvent_t b = get_event(c);
-      (void)hipEventRecord(b, c->stream);
+      if (!own) {
+        b = get_event(c);
+        (void)hipEventRecord(b, c->stream);
+      }
       c->pending.push_back({k, a, b});
       if (c->pending.size() > 4096) harvest(c);
     }
@@ -352,14 +360,14 @@ int enqueue_step_group(const Member<Real>* d_m, const Tile* d_t, int n_tiles, co
       StageArgs sa = a;
       sa.out_buf = -1;
       {
-        ProfScope ps(prof, K_STAGE);
-        HIPCHK(launch_stage<Real>(p, flux, 1, variant, d_m, d_t, n_tiles, sa, s));
+        ProfScope ps(prof, K_STAGE, true);
+        HIPCHK(launch_stage<Real>(p, flux, 1, variant, d_m, d_t, n_tiles, sa, s, ps.a, ps.b));
       }
       ProfScope ps(prof, K_POST);
       HIPCHK(launch_post<Real>(p, 1, d_m, d_t, n_tiles, a, 0, s));
     } else {
-      ProfScope ps(prof, K_STAGE);
-      HIPCHK(launch_stage<Real>(p, flux, 0, variant, d_m, d_t, n_tiles, a, s));
+      ProfScope ps(prof, K_STAGE, true);
+      HIPCHK(launch_stage<Real>(p, flux, 0, variant, d_m, d_t, n_tiles, a, s, ps.a, ps.b));
     }
   }
   ProfScope ps(prof, K_REDUCE);
@@ -435,6 +443,8 @@ int upload_boundary_forcing(dgswe_ctx* c) {
     if (c->tide_mean[s] != 0.0 || !c->tide_rows[s].empty()) c->fo.ocean_mask |= 1u << s;
     if (!c->riv_rows[s].empty()) c->fo.river_mask |= 1u << s;
   }
+  c->fo.n_tide = int(tc.size() / 3);
+  c->fo.n_riv = int(rq.size() / 2);
   if (c->stream) HIPCHK(hipStreamSynchronize(c->stream));
   if (tc.empty()) tc.push_back(0.0);
   if (rq.empty()) rq.push_back(0.0);

@@ -55,12 +55,14 @@ struct Forcing {
   int riv_off[MAX_SLOTS], riv_cnt[MAX_SLOTS];     // (t, q) pairs in riv_tq
   const double* tide_c;
   const double* riv_tq;
+  int n_tide, n_riv;          // rows in tide_c (triples) and riv_tq (pairs)
 };
 
 template <typename Real>
 struct Member {
   int E, n_nodes, n_tiles, friction;
   double H0, g, cfl, dt_fixed, dt_max;
+  double feps;                // exchange threshold 1e-3 H0 sqrt(g H0) of a wet-dry edge
   // static mesh data (read-only, shareable between members)
   const Real* ev;             // [6][E] edge vectors v1-v0, v2-v1, v0-v2 (x, y)
   const Real* hbv;            // [3][E] bathymetry at the vertices
@@ -103,9 +105,12 @@ struct RKInfo {
 };
 
 // launchers (kernels.hip)
+// ev0/ev1, when given, receive the start and end time of the stage kernel's
+// own dispatch (no marker packets around it)
 template <typename Real>
 hipError_t launch_stage(int P, int flux, int limiter, int variant, const Member<Real>* d_members,
-                        const Tile* d_tiles, int n_tiles, StageArgs a, hipStream_t s);
+                        const Tile* d_tiles, int n_tiles, StageArgs a, hipStream_t s, hipEvent_t ev0 = nullptr,
+                        hipEvent_t ev1 = nullptr);
 template <typename Real>
 hipError_t launch_post(int P, int use_lim, const Member<Real>* d_members, const Tile* d_tiles, int n_tiles,
                        StageArgs a, int init, hipStream_t s);

@@ -14,6 +14,8 @@
 //
 // FP32 members keep the state and fluxes in float; depth tests of the
 // positive-depth operator, dt and all budgets are done in FP64.
+#include <hip/hip_ext.h>
+
 #include "device_common.h"
 #include "internal.h"
 
@@ -100,9 +102,9 @@ DG_DEV void block_sums(double (&v)[NV], double* lds) {
 
 // Decision margins: the positive-depth operator puts vertices at exactly H0,
 // so the tests that follow use H0 (1 + 1e-3) for "dry", and a wet-dry edge
-// exchanges water only above a mass flux of 1e-3 H0 sqrt(g H0).
+// exchanges water only above a mass flux of 1e-3 H0 sqrt(g H0) (Member::feps,
+// formed on the host).
 DG_DEV double dry_depth(double H0) { return H0 * (1.0 + 1e-3); }
-DG_DEV double exchange_eps(double H0, double g) { return 1e-3 * H0 * sqrt(g * H0); }
 
 // Workgroups are dispatched round-robin over the 8 XCDs, each with its own
 // L2.  The grid is padded to a multiple of 8 and block b takes tile
@@ -768,7 +770,7 @@ __global__ DG_STAGE_ATTR void stage_kernel(const Member<Real>* __restrict__ mem,
   const bool valid = e < E;
   const int ec = valid ? e : E - 1;
   const Real g = Real(M.g), H0 = Real(M.H0);
-  const Real feps = Real(exchange_eps(M.H0, M.g));
+  const Real feps = Real(M.feps);
   const double dt = sc->dt;
   const DG_G Real* __restrict__ Win = gp(M.W[A.in_buf]);
   const DG_G uint8_t* __restrict__ Fin = gp(M.F[A.fin]);
@@ -908,7 +910,7 @@ __global__ DG_STAGE_ATTR void stage_edge_kernel(const Member<Real>* __restrict__
   const bool valid = e < E;
   const int ec = valid ? e : E - 1;
   const Real g = Real(M.g), H0 = Real(M.H0);
-  const Real feps = Real(exchange_eps(M.H0, M.g));
+  const Real feps = Real(M.feps);
   const double dt = sc->dt;
   const DG_G Real* __restrict__ Win = gp(M.W[A.in_buf]);
   const DG_G uint8_t* __restrict__ Fin = gp(M.F[A.fin]);
@@ -1388,12 +1390,14 @@ __global__ __launch_bounds__(TILE) void rain_kernel(const Member<Real>* __restri
 // workgroup that finishes last (counted with a device-scope atomic) adds the
 // records in chunk order, so the result does not depend on which one that
 // is, and resets the counter for the next launch.
+// The kernel is a chain of dependent memory round trips, so each phase
+// issues all of its loads before it uses any of them.
 template <typename Real>
 __global__ __launch_bounds__(RED_CHUNK) void reduce_kernel(const Member<Real>* __restrict__ mem,
                                                            const int* __restrict__ ids, int init, RKInfo rk) {
   constexpr int NV = 3 + 2 * MAX_STAGES;       // sums: volume, rain, dry count, out/in per stage
   constexpr int NW = RED_CHUNK / 64;
-  constexpr int NT = 256;                      // forcing-table entries staged in LDS
+  constexpr int NT = RED_CHUNK;                // forcing-table rows staged in LDS, one per thread
   static_assert(NV + 1 <= NRED, "chunk record too small");
   __shared__ double lds[NW * (NV + 1)];
   __shared__ double s_storm[7 * NT];
@@ -1404,14 +1408,13 @@ __global__ __launch_bounds__(RED_CHUNK) void reduce_kernel(const Member<Real>* _
   __shared__ int s_last;
   const Member<Real>& M = mem[ids[blockIdx.x]];
   DG_G Scalars* __restrict__ sc = gp(M.sc);
-  if (!init && !sc->active) return;
   const int nt = M.n_tiles;
   const int nch = red_chunks(nt);
   const int chunk = blockIdx.y;
   if (chunk >= nch) return;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int ns = init ? 0 : rk.n;
-  // ---- this chunk's tiles
+  // ---- this chunk's tiles, loaded together with the member's active flag
   double v[NV];
   double mn;
   {
@@ -1429,6 +1432,7 @@ __global__ __launch_bounds__(RED_CHUNK) void reduce_kernel(const Member<Real>* _
       v[3 + MAX_STAGES + s] = (ok && s < ns) ? pt[(P_IN0 + s) * nt + tt] : 0.0;
     }
   }
+  const bool act = init || sc->active;
   // fixed-order block sums: within each wavefront, then wavefronts 0..NW-1
   auto block_reduce = [&]() {
 #pragma unroll
@@ -1455,6 +1459,8 @@ __global__ __launch_bounds__(RED_CHUNK) void reduce_kernel(const Member<Real>* _
     __syncthreads();
   };
   block_reduce();
+  // an inactive member (finished or latched) keeps its scalars as they are
+  if (!act) return;
   DG_G double* __restrict__ red = gp(M.red);
   if (tid == 0) {
 #pragma unroll
@@ -1467,23 +1473,21 @@ __global__ __launch_bounds__(RED_CHUNK) void reduce_kernel(const Member<Real>* _
   __syncthreads();
   if (!s_last) return;
   __threadfence();
-  // ---- last workgroup: forcing tables to LDS, records in chunk order
+  // ---- last workgroup: chunk records, step scalars and forcing tables in
+  // one round of loads
   const Forcing& f = M.fo;
   const int nst = f.rain_kind == RAIN_PARAM ? (f.n_storm < NT ? f.n_storm : NT) : 0;
-  for (int i = tid; i < 7 * nst; i += RED_CHUNK) s_storm[i] = gp(f.storm)[i];
   const int ngt = f.rain_kind == RAIN_GRID ? (f.gnrec < NT ? f.gnrec : NT) : 0;
-  for (int i = tid; i < ngt; i += RED_CHUNK) s_gt[i] = gp(f.gt)[i];
-  int ntc = 0, nrq = 0;
+  const bool tide_lds = f.n_tide <= NT, riv_lds = f.n_riv <= NT;
+  const int ntc = tide_lds ? f.n_tide : 0, nrq = riv_lds ? f.n_riv : 0;
+  double r_storm[7], r_tide[3], r_riv[2], r_gt;
 #pragma unroll
-  for (int s = 0; s < MAX_SLOTS; ++s) {
-    ntc = (f.ocean_mask & (1u << s)) ? max(ntc, f.tide_off[s] + f.tide_cnt[s]) : ntc;
-    nrq = (f.river_mask & (1u << s)) ? max(nrq, f.riv_off[s] + f.riv_cnt[s]) : nrq;
-  }
-  const bool tide_lds = ntc <= NT, riv_lds = nrq <= NT;
-  if (tide_lds)
-    for (int i = tid; i < 3 * ntc; i += RED_CHUNK) s_tide[i] = gp(f.tide_c)[i];
-  if (riv_lds)
-    for (int i = tid; i < 2 * nrq; i += RED_CHUNK) s_riv[i] = gp(f.riv_tq)[i];
+  for (int k = 0; k < 7; ++k) r_storm[k] = k * NT + tid < 7 * nst ? gp(f.storm)[k * NT + tid] : 0.0;
+  r_gt = tid < ngt ? gp(f.gt)[tid] : 0.0;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) r_tide[k] = k * NT + tid < 3 * ntc ? gp(f.tide_c)[k * NT + tid] : 0.0;
+#pragma unroll
+  for (int k = 0; k < 2; ++k) r_riv[k] = k * NT + tid < 2 * nrq ? gp(f.riv_tq)[k * NT + tid] : 0.0;
   double t0 = 0.0, dt0 = 0.0, rain0 = 0.0, bo0 = 0.0, bi0 = 0.0;
   long long steps0 = 0, target0 = 0;
   if (tid == 0) {
@@ -1500,6 +1504,16 @@ __global__ __launch_bounds__(RED_CHUNK) void reduce_kernel(const Member<Real>* _
       v[i] += __hip_atomic_load(M.red + c * NRED + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     mn = fmin(mn, __hip_atomic_load(M.red + c * NRED + NV, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
   }
+#pragma unroll
+  for (int k = 0; k < 7; ++k)
+    if (k * NT + tid < 7 * nst) s_storm[k * NT + tid] = r_storm[k];
+  if (tid < ngt) s_gt[tid] = r_gt;
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+    if (k * NT + tid < 3 * ntc) s_tide[k * NT + tid] = r_tide[k];
+#pragma unroll
+  for (int k = 0; k < 2; ++k)
+    if (k * NT + tid < 2 * nrq) s_riv[k * NT + tid] = r_riv[k];
   block_reduce();
   if (tid == 0) {
     __hip_atomic_store(M.red_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1531,7 +1545,18 @@ __global__ __launch_bounds__(RED_CHUNK) void reduce_kernel(const Member<Real>* _
     s_dt = dtn;
   }
   __syncthreads();
-  // forcing for the coming step
+  // forcing for the coming step.  Record times increase strictly (checked
+  // when they are set), so the interval holding ts is found by bisection:
+  // the k with time(k) <= ts < time(k+1), given time(0) < ts < time(n-1).
+  auto bracket = [](auto time, int n, double ts) {
+    int lo = 0, hi = n - 1;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (time(mid) <= ts) lo = mid;
+      else hi = mid;
+    }
+    return lo;
+  };
   const double t = s_t, dt = s_dt;
   if (tid < MAX_SLOTS) {
     const int s = tid;
@@ -1557,8 +1582,7 @@ __global__ __launch_bounds__(RED_CHUNK) void reduce_kernel(const Member<Real>* _
         } else if (ts >= RT(n - 1)) {
           q = RQ(n - 1);
         } else {
-          int k = 0;
-          while (k + 1 < n && RT(k + 1) <= ts) ++k;
+          const int k = bracket(RT, n, ts);
           const double th = (ts - RT(k)) / (RT(k + 1) - RT(k));
           q = (1.0 - th) * RQ(k) + th * RQ(k + 1);
         }
@@ -1569,13 +1593,13 @@ __global__ __launch_bounds__(RED_CHUNK) void reduce_kernel(const Member<Real>* _
   } else if (tid == MAX_SLOTS && f.rain_kind == RAIN_PARAM && f.n_storm > 0) {
     const int n = f.n_storm;
     auto R = [&](int i) { return i < 7 * NT ? s_storm[i] : gp(f.storm)[i]; };
+    auto RT = [&](int k) { return R(7 * k); };
     if (n == 1 || t <= R(0)) {
       for (int i = 0; i < 6; ++i) sc->storm[i] = R(1 + i);
     } else if (t >= R(7 * (n - 1))) {
       for (int i = 0; i < 6; ++i) sc->storm[i] = R(7 * (n - 1) + 1 + i);
     } else {
-      int k = 0;
-      while (k + 1 < n && R(7 * (k + 1)) <= t) ++k;
+      const int k = bracket(RT, n, t);
       const double th = (t - R(7 * k)) / (R(7 * (k + 1)) - R(7 * k));
       for (int i = 0; i < 6; ++i) sc->storm[i] = (1.0 - th) * R(7 * k + 1 + i) + th * R(7 * (k + 1) + 1 + i);
     }
@@ -1587,8 +1611,7 @@ __global__ __launch_bounds__(RED_CHUNK) void reduce_kernel(const Member<Real>* _
     } else if (t >= TR(n - 1)) {
       sc->gk0 = n - 1; sc->gk1 = n - 1; sc->gth = 0.0;
     } else {
-      int k = 0;
-      while (k + 1 < n && TR(k + 1) <= t) ++k;
+      const int k = bracket(TR, n, t);
       sc->gk0 = k; sc->gk1 = k + 1; sc->gth = (t - TR(k)) / (TR(k + 1) - TR(k));
     }
   }
@@ -1597,13 +1620,19 @@ __global__ __launch_bounds__(RED_CHUNK) void reduce_kernel(const Member<Real>* _
 // ------------------------------------------------------------ launchers
 template <typename Real>
 hipError_t launch_stage(int P, int flux, int limiter, int variant, const Member<Real>* m, const Tile* t, int n,
-                        StageArgs a, hipStream_t s) {
+                        StageArgs a, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
   if (n <= 0) return hipSuccess;
   dim3 grid(xcd_grid(n)), block(TILE);
+  const bool timed = ev0 != nullptr || ev1 != nullptr;
 #define DG_STAGE(PP, FF, LL) \
   if (P == PP && flux == FF && limiter == LL) { \
-    if (variant == 1) hipLaunchKernelGGL((stage_edge_kernel<Real, PP, FF, LL>), grid, block, 0, s, m, t, n, a); \
-    else hipLaunchKernelGGL((stage_kernel<Real, PP, FF, LL>), grid, block, 0, s, m, t, n, a); \
+    if (variant == 1) { \
+      if (timed) hipExtLaunchKernelGGL((stage_edge_kernel<Real, PP, FF, LL>), grid, block, 0, s, ev0, ev1, 0, m, t, n, a); \
+      else hipLaunchKernelGGL((stage_edge_kernel<Real, PP, FF, LL>), grid, block, 0, s, m, t, n, a); \
+    } else { \
+      if (timed) hipExtLaunchKernelGGL((stage_kernel<Real, PP, FF, LL>), grid, block, 0, s, ev0, ev1, 0, m, t, n, a); \
+      else hipLaunchKernelGGL((stage_kernel<Real, PP, FF, LL>), grid, block, 0, s, m, t, n, a); \
+    } \
     return hipGetLastError(); \
   }
   DG_STAGE(1, 0, 0) DG_STAGE(1, 1, 0) DG_STAGE(1, 0, 1) DG_STAGE(1, 1, 1)
@@ -1652,7 +1681,8 @@ hipError_t launch_reduce(const Member<Real>* m, const int* ids, int n_members, i
 }
 
 #define DG_INST(R)                                                                                              \
-  template hipError_t launch_stage<R>(int, int, int, int, const Member<R>*, const Tile*, int, StageArgs, hipStream_t); \
+  template hipError_t launch_stage<R>(int, int, int, int, const Member<R>*, const Tile*, int, StageArgs, hipStream_t, \
+                                      hipEvent_t, hipEvent_t);                                              \
   template hipError_t launch_post<R>(int, int, const Member<R>*, const Tile*, int, StageArgs, int, hipStream_t);  \
   template hipError_t launch_classify<R>(int, const Member<R>*, const Tile*, int, hipStream_t);                   \
   template hipError_t launch_rain<R>(const Member<R>*, const Tile*, int, int, const Tile*, int, hipStream_t);     \
