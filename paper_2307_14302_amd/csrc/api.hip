@@ -357,11 +357,11 @@ int enqueue_step_group(const Member<Real>* d_m, const Tile* d_t, int n_tiles, co
   for (int i = 0; i < T.n; ++i) {
     StageArgs a = stage_args(T, i);
     if (limiter) {
-      StageArgs sa = a;
-      sa.out_buf = -1;
+      // the stage writes its raw output to the stage's buffer; the post
+      // pass limits it there
       {
         ProfScope ps(prof, K_STAGE, true);
-        HIPCHK(launch_stage<Real>(p, flux, 1, variant, d_m, d_t, n_tiles, sa, s, ps.a, ps.b));
+        HIPCHK(launch_stage<Real>(p, flux, 1, variant, d_m, d_t, n_tiles, a, s, ps.a, ps.b));
       }
       ProfScope ps(prof, K_POST);
       HIPCHK(launch_post<Real>(p, 1, d_m, d_t, n_tiles, a, 0, s));

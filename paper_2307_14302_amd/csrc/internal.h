@@ -76,7 +76,7 @@ struct Member {
   const uint8_t* limc;        // [E]    bit0: limitable; bit 1+i: second neighbour of midpoint i is i+2
   // dynamic
   Real* W[3];                 // state buffers
-  Real* Wt;                   // unlimited stage output (limiter on)
+  Real* Wt;                   // initial state as given, before the set-up pass
   uint8_t* F[3];              // dry flags of the state in W[i] (bit 0)
   uint8_t* fullwet;           // [E] every vertex depth > H0 (limiter on)
   Real* R;                    // [E] element rain rate
@@ -91,7 +91,7 @@ struct Member {
 struct StageArgs {
   int stage;                  // 0-based stage index
   int last;                   // 1 on the last stage of a step
-  int in_buf, out_buf;        // state buffer indices (out_buf = -1: Wt)
+  int in_buf, out_buf;        // state buffer indices
   int fin, fout;              // flag buffer indices
   double a, b, gam;           // w_out = a w^n + b (w_in + gam dt L(w_in))
 };

@@ -186,15 +186,20 @@ DG_DEV bool surely_wet(const Real (&w)[3][Tab<P>::NP], const Real (&hb)[3], doub
 }
 
 // need_v: the caller needs hv/qxv/qyv (the CFL speed); otherwise a surely
-// wet element returns at once.
+// wet element returns at once.  *changed is set when w was modified.  Both
+// operators keep the element means of depth and momentum (redistribution
+// between vertices), so mode 0 is left as it is, except for the momentum
+// of an element dry at every vertex, which is set to zero.
 template <typename Real, int P>
 DG_DEV bool positive_depth(Real (&w)[3][Tab<P>::NP], const Real (&hb)[3], double H0, double (&hv)[3],
-                           double (&qxv)[3], double (&qyv)[3], bool need_v, bool& filled) {
+                           double (&qxv)[3], double (&qyv)[3], bool need_v, bool& filled,
+                           bool* changed = nullptr) {
   constexpr int NP = Tab<P>::NP;
   const double Hd = dry_depth(H0);
   filled = false;
   if (!need_v && surely_wet<Real, P>(w, hb, Hd)) return false;
   filled = true;
+  bool mod = false;
   double z[3];
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
@@ -221,6 +226,7 @@ DG_DEV bool positive_depth(Real (&w)[3][Tab<P>::NP], const Real (&hb)[3], double
       low |= (s + 0.5 * (double(hb[i]) + double(hb[(i + 1) % 3]))) <= Hd;
     }
     if (!low) return false;   // every vertex depth above the dry margin: nothing to do
+    mod = true;
 #pragma unroll
     for (int v = 0; v < 3; ++v)
 #pragma unroll
@@ -264,10 +270,10 @@ DG_DEV bool positive_depth(Real (&w)[3][Tab<P>::NP], const Real (&hb)[3], double
       hv[i] = hn[i];
       z[i] = hn[i] - double(hb[i]);
     }
-    // linear modes from vertex values
-    w[0][0] = Real((z[0] + z[1] + z[2]) / 3.0);
+    // slopes from the new vertex values (their mean is the old one)
     w[0][1] = Real((z[1] - z[0]) / 2.0);
     w[0][2] = Real((2.0 * z[2] - z[0] - z[1]) / 6.0);
+    mod = true;
   }
   const bool d0 = hv[0] <= Hd, d1 = hv[1] <= Hd, d2 = hv[2] <= Hd;
   const int nd = int(d0) + int(d1) + int(d2);
@@ -287,11 +293,13 @@ DG_DEV bool positive_depth(Real (&w)[3][Tab<P>::NP], const Real (&hb)[3], double
         r2 = d2 ? 0.0 : q[2] + add;
       }
       q[0] = r0; q[1] = r1; q[2] = r2;
-      w[1 + c][0] = Real((r0 + r1 + r2) / 3.0);
+      if (nd == 3) w[1 + c][0] = Real(0);
       w[1 + c][1] = Real((r1 - r0) / 2.0);
       w[1 + c][2] = Real((2.0 * r2 - r0 - r1) / 6.0);
     }
+    mod = true;
   }
+  if (changed) *changed = mod;
   return nd == 3;
 }
 
@@ -668,11 +676,12 @@ DG_DEV void finish_stage(const Member<Real>& M, const StageArgs& A, int tile, in
     }
   } else {
     if (valid) {
-      DG_G Real* __restrict__ Wt = gp(M.Wt);
+      // raw stage output; the post pass limits it in place
+      DG_G Real* __restrict__ Wr = gp(M.W[A.out_buf]);
 #pragma unroll
       for (int v = 0; v < 3; ++v)
 #pragma unroll
-        for (int m = 0; m < NP; ++m) Wt[(v * NP + m) * E + e] = w[v][m];
+        for (int m = 0; m < NP; ++m) Wr[(v * NP + m) * E + e] = w[v][m];
       bool full = surely_wet<Real, P>(w, hb, dry_depth(M.H0));
       if (!full) {
         full = true;
@@ -752,8 +761,8 @@ DG_DEV void load_elem(const Member<Real>& M, const DG_G Real* __restrict__ Win, 
 // ------------------------------------------------- stage kernel, per element
 // Every element evaluates its three edges itself (interior edge fluxes are
 // computed by both neighbours).  LIM = 0: full stage + positive-depth
-// operator; LIM = 1: unlimited stage output to Wt plus the fully-wet byte
-// (the post kernel limits afterwards).
+// operator; LIM = 1: unlimited stage output to the stage's output buffer
+// plus the fully-wet byte (the post kernel limits it there).
 template <typename Real, int P, int FLUX, int LIM>
 __global__ DG_STAGE_ATTR void stage_kernel(const Member<Real>* __restrict__ mem,
                                                      const Tile* __restrict__ tiles, int n_tiles, StageArgs A) {
@@ -1117,8 +1126,15 @@ __global__ DG_STAGE_ATTR void stage_edge_kernel(const Member<Real>* __restrict__
 // Slope limiter (Cockburn-Shu, componentwise on zeta, qx, qy; nu = 1.5; only
 // where the element and its three neighbours are fully wet), then the
 // positive-depth operator, flags, CFL speed and tile partials.
-// init: 0 = after a stage (reads Wt); 1 = initial state in Wt (limiter if
-// the member has it, positive depth); 2 = flags and partials of W[0] only.
+// init: 0 = after a stage, in place on the stage's output buffer: only the
+// elements that either operator modifies are written back; 1 = initial
+// state in Wt (limiter if the member has it, positive depth) into W[0];
+// 2 = flags and partials of W[0] only.
+// In place is safe because a neighbour's means are used only when every
+// element of the stencil is fully wet, and the pass never changes the means
+// of a fully-wet element (the limiter moves slopes only, positive depth
+// keeps means): other workgroups may rewrite those words, with the same
+// bits.
 template <typename Real, int P>
 __global__ __launch_bounds__(TILE) void post_kernel(const Member<Real>* __restrict__ mem,
                                                     const Tile* __restrict__ tiles, int n_tiles, StageArgs A,
@@ -1135,7 +1151,9 @@ __global__ __launch_bounds__(TILE) void post_kernel(const Member<Real>* __restri
   const int e = tl.tile * TILE + int(threadIdx.x);
   const bool valid = e < E;
   const int ec = valid ? e : E - 1;
-  const DG_G Real* __restrict__ Wsrc = gp((init == 2) ? M.W[0] : M.Wt);
+  // not restrict: with init = 0 the same buffer is written below
+  const DG_G Real* Wsrc = gp(init == 2 ? M.W[0] : init == 1 ? M.Wt : M.W[A.out_buf]);
+  bool changed = init == 1;
   Real w[3][NP];
 #pragma unroll
   for (int v = 0; v < 3; ++v)
@@ -1188,6 +1206,7 @@ __global__ __launch_bounds__(TILE) void post_kernel(const Member<Real>* __restri
           same = same && (D[i] == d[i]);
         }
         if (!same) {
+          changed = true;
           const Real s = D[0] + D[1] + D[2];
           if (s != Real(0)) {
             const Real Pp = dmax(D[0], Real(0)) + dmax(D[1], Real(0)) + dmax(D[2], Real(0));
@@ -1226,14 +1245,16 @@ __global__ __launch_bounds__(TILE) void post_kernel(const Member<Real>* __restri
     const double Hd = dry_depth(M.H0);
     dry = (hv[0] <= Hd) & (hv[1] <= Hd) & (hv[2] <= Hd);
   } else {
+    bool pd = false;
     dry = positive_depth<Real, P>(w, hb, M.H0, hv, qxv, qyv, (init != 0 || A.last != 0) && sizeof(Real) == 8,
-                                  filled);
+                                  filled, &pd);
+    changed = changed || pd;
   }
   const int ob = init ? 0 : A.out_buf;
   const int fo = init ? 0 : A.fout;
   if (valid) {
-    if (init != 2) {
-      DG_G Real* __restrict__ Wout = gp(M.W[ob]);
+    if (init != 2 && changed) {
+      DG_G Real* Wout = gp(M.W[ob]);
 #pragma unroll
       for (int v = 0; v < 3; ++v)
 #pragma unroll
