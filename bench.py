@@ -83,8 +83,8 @@ def run_precision(sc, precision, steps, warmup, variant=1, events=2):
         + (f" (autotuned: {tuned[0]:.3f} / {tuned[1]:.3f} ms per step)" if tuned else ""))
     s.step(warmup)
     s.sync()
-    # events around the stage kernel only: the dominant kernel's duration for
-    # the roofline, with the fewest timing packets between launches
+    # events on the stage kernel's own dispatches only: the dominant
+    # kernel's duration for the roofline, with no packets between launches
     s.profiling(events)
     torch.cuda.synchronize()
     s.sync()
@@ -258,6 +258,20 @@ def run_graded(steps=1000, warmup=20):
             "workload": "graded coast 30 m - 15.36 km, 1229 x 922 km, tides, 3 rivers, gridded rain, LLF, limiter"}
 
 
+def run_storm(N=708, steps=1000, warmup=20):
+    """The basin with the storm's wind stress and pressure on the rain track
+    (FP32): the cost of the meteorological forcing."""
+    import meshgen
+    sc = meshgen.basin(N, wind=True)
+    r = run_precision(sc, "fp32", steps, warmup, -1, 2)
+    n, ms = r["stats"]["stage"]
+    return {"value": round(r["rate"], 1), "unit": "element-stage updates/s", "n_tri": r["E"], "steps": steps,
+            "ms_per_step": round(r["elapsed"] / steps * 1e3, 4), "stage_avg_us": round(ms / max(n, 1) * 1e3, 2),
+            "stage_variant": r["variant"], "dtype": "f32",
+            "workload": "single basin as above plus the storm vortex (4,000 Pa, r_max 30 km, B 1.3) on the rain "
+                        "track: wind stress and pressure gradient"}
+
+
 def cpu_baseline(timeout=600):
     """The FP64 oracle on one host core: 2 SSP-RK2 steps of the full mesh."""
     code = r"""
@@ -307,6 +321,7 @@ def main():
     ap.add_argument("--no-ensemble", action="store_true", help="skip the 64-member FP32 ensemble")
     ap.add_argument("--no-graded", action="store_true", help="skip the 3.6M-triangle graded coastal run")
     ap.add_argument("--no-serving", action="store_true", help="skip the request-loop run")
+    ap.add_argument("--no-storm", action="store_true", help="skip the basin run with storm wind and pressure")
     ap.add_argument("--serve-requests", type=int, default=100, help="requests of the 400-request trace to serve")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -352,6 +367,9 @@ def main():
                        "stage_variant": f["variant"],
                        "dtype": "f64", "roofline": roofline(f, "fp64", prm["p"], prm["limiter"]),
                        "fp32_over_fp64": round(r["rate"] / f["rate"], 3)}
+    if not args.no_storm:
+        out["storm"] = run_storm(args.N)
+        out["storm"]["vs_no_wind"] = round(out["storm"]["value"] / r["rate"], 3)
     if not args.no_graded:
         out["graded"] = run_graded()
     if not args.no_ensemble:

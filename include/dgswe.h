@@ -176,6 +176,26 @@ int dgswe_set_rain_gridded(dgswe_ctx* ctx, double x0, double y0, double dx, doub
                            int32_t ny, int32_t n_rec, const double* t_rec, const float* vals);
 int dgswe_clear_rain(dgswe_ctx* ctx);
 
+/* Wind stress and atmospheric pressure: the momentum sources F_x, F_y of
+ * Sec. 2.1 (Eq. SWE) driven by a parametric storm, as Sec. 2.3 and Sec. 3.3
+ * do with their hurricane wind and pressure model.  rec[9*n_rec] rows
+ * (t, xc, yc, dp, rm, B, wf, wbx, wby) with increasing t, interpolated
+ * linearly in time (held outside the record span): a symmetric vortex with
+ * central pressure deficit dp >= 0 (Pa), radius of maximum wind rm > 0 (m)
+ * and shape 0 < B <= 3, whose cyclostrophic wind
+ * V = sqrt(B dp s exp(-s) / rho_a), s = (rm / r)^B, turns counter-clockwise
+ * and is scaled by wf, plus a uniform background wind (wbx, wby) (m/s).
+ * Pressure anomaly -dp (1 - exp(-s)).  Each node gets the kinematic stress
+ * (rho_a / rho_w) C_d |W| W with C_d = min((0.75 + 0.067 |W|) 1e-3, 3.5e-3)
+ * and the head psi = p_anomaly / (rho_w g) (rho_a = 1.15, rho_w = 1000
+ * kg/m^3); inside an element both are linear and the momentum equations
+ * take tau - g H grad psi at the area points.  Evaluated at the start of
+ * each step and used for all its stages, like rain.  Replaces earlier
+ * records; EINVAL on non-finite or out-of-range values.  dgswe_clear_wind
+ * turns the forcing off. */
+int dgswe_set_wind_vortex(dgswe_ctx* ctx, int32_t n_rec, const double* rec);
+int dgswe_clear_wind(dgswe_ctx* ctx);
+
 /* Ocean elevation of a slot (Sec. 2.1): mean + sum_k a_k sin(2 pi t/T_k +
  * phase_k), amp_period_phase[3*n_const].  River normal flux of a slot
  * (Eq. river_bc), outward positive, m^2/s, linear in time between samples

@@ -56,6 +56,8 @@ class Scenario:
     tides: Dict[int, Tuple[float, np.ndarray]] = field(default_factory=dict)
     rivers: Dict[int, Tuple[np.ndarray, np.ndarray]] = field(default_factory=dict)  # slot -> (t, q)
     n_steps: int = 0
+    # storm wind and pressure records (t, xc, yc, dp, rm, B, wf, wbx, wby), or None
+    met: Optional[np.ndarray] = None
 
 
 def default_params(**kw) -> Dict[str, object]:
@@ -222,9 +224,30 @@ def parametric_track(x_start, y_start, vx, vy, peak, t_end=1.0e6, *,
     return rec
 
 
+def vortex_track(x_start, y_start, vx, vy, dp, t_end=1.0e6, *, rm=30e3, B=1.3, wf=1.0,
+                 wb=(0.0, 0.0), n_rec=2):
+    """Wind and pressure records (t, xc, yc, dp, rm, B, wf, wbx, wby) on a
+    straight track: central pressure deficit dp (Pa), radius of maximum
+    wind rm (m), shape B, factor wf on the vortex wind and a uniform
+    background wind wb (m/s)."""
+    t = np.linspace(0.0, t_end, n_rec)
+    rec = np.zeros((n_rec, 9))
+    rec[:, 0] = t
+    rec[:, 1] = x_start + vx * t
+    rec[:, 2] = y_start + vy * t
+    rec[:, 3] = dp
+    rec[:, 4] = rm
+    rec[:, 5] = B
+    rec[:, 6] = wf
+    rec[:, 7] = wb[0]
+    rec[:, 8] = wb[1]
+    return rec
+
+
 def basin(N: int = 708, seed: int = seed_for(1), *, L: float = 200e3,
           window=None, jitter: float = 0.2, flux: str = "llf", limiter: bool = True,
-          peak_mmh: float = 50.0, track=None, n_steps: int = 5000, p: int = 1) -> Scenario:
+          peak_mmh: float = 50.0, track=None, n_steps: int = 5000, p: int = 1,
+          wind: bool = False) -> Scenario:
     """Jittered N x N grid cut along the shorter diagonals.
 
     Without ``window`` the grid covers the whole L x L basin: N = 708 gives
@@ -235,7 +258,9 @@ def basin(N: int = 708, seed: int = seed_for(1), *, L: float = 200e3,
     boundary (zero elevation, slot 0) on the west side, land elsewhere,
     Manning 0.025, parametric rain (peak 50 mm/h, r_m = 30 km,
     r_e = 100 km) whose centre starts at (0.3 L, 0.5 L) and moves east at
-    5 m/s.
+    5 m/s.  ``wind=True`` adds the storm's wind and pressure on the same
+    track: pressure deficit 4,000 Pa, radius of maximum wind 30 km (scaled
+    with L), B = 1.3 (peak wind 40 m/s).
     """
     rng = np.random.default_rng(seed)
     x0, y0, size = (0.0, 0.0, L) if window is None else window
@@ -250,10 +275,11 @@ def basin(N: int = 708, seed: int = seed_for(1), *, L: float = 200e3,
     if track is None:
         track = parametric_track(0.3 * L, 0.5 * L, 5.0, 0.0, peak,
                                  rm=30e3 * L / 200e3, re=100e3 * L / 200e3)
+    met = vortex_track(0.3 * L, 0.5 * L, 5.0, 0.0, 4000.0, rm=30e3 * L / 200e3) if wind else None
     return Scenario(f"basin_{N}", mesh, zeta0, np.zeros_like(hb), np.zeros_like(hb),
                     default_params(p=p, flux=flux, friction="manning", limiter=limiter, cfl=0.3, H0=0.05),
                     rain={"kind": "parametric", "records": track},
-                    tides={0: (0.0, np.zeros((0, 3)))}, n_steps=n_steps)
+                    tides={0: (0.0, np.zeros((0, 3)))}, n_steps=n_steps, met=met)
 
 
 def basin_window(N: int, seed: int = seed_for(1), **kw) -> Scenario:
@@ -296,13 +322,16 @@ def gridded_field(rng, x0, y0, dx, dy, nx, ny, n_rec, dt_rec, *, n_cells=6,
 def small_mixed(seed: int = 7, nx: int = 24, ny: int = 12, *, p: int = 1,
                 flux: str = "roe", limiter: bool = False, friction: str = "manning",
                 rain_kind: str = "gridded", dry_island: bool = True,
-                dt_fixed: float = 0.0) -> Scenario:
+                dt_fixed: float = 0.0, wind: bool = False) -> Scenario:
     """10 km x 5 km jittered basin touching every boundary type.
 
     Left side: OCEAN (slot 0, two tidal constituents).  Right side: lower
     half RIVER (slot 1, inflow series), the two top edges OUTFLOW, LAND in
     between.  Top and bottom: LAND.  The bed deepens seaward with bumps and an island that rises
-    above the surface, so wet/dry fronts exist from the start.
+    above the surface, so wet/dry fronts exist from the start.  ``wind``
+    adds a storm vortex (pressure deficit 3,000 Pa, radius of maximum wind
+    2 km, B = 1.4, peak wind 37 m/s) crossing the basin at (4, 2) m/s over a
+    (3, -1) m/s background wind.
     """
     rng = np.random.default_rng(seed)
     Lx, Ly = 10e3, 5e3
@@ -339,10 +368,12 @@ def small_mixed(seed: int = 7, nx: int = 24, ny: int = 12, *, p: int = 1,
         rain = {"kind": "none"}
     tides = {0: (0.02, np.array([[0.30, 44712.0, 0.3], [0.10, 43200.0, 1.1]]))}
     rivers = {1: (np.array([0.0, 120.0, 600.0, 3600.0]), np.array([-0.2, -0.8, -1.5, -0.5]))}
+    met = (vortex_track(-2e3, 1e3, 4.0, 2.0, 3000.0, 2e4, rm=2e3, B=1.4, wb=(3.0, -1.0), n_rec=3)
+           if wind else None)
     return Scenario(f"small_mixed_{seed}", mesh, zeta0, qx0, qy0,
                     default_params(p=p, flux=flux, friction=friction, limiter=limiter,
                                    cfl=0.3, dt_fixed=dt_fixed, H0=0.05),
-                    rain=rain, tides=tides, rivers=rivers, n_steps=200)
+                    rain=rain, tides=tides, rivers=rivers, n_steps=200, met=met)
 
 
 def lake_at_rest(seed: int = 3, nx: int = 16, ny: int = 10, level: float = 0.7,

@@ -19,6 +19,9 @@ Element Model for Compound Flood Simulations"):
     discharge part, applied after every Runge-Kutta stage, and wet/dry
     element flags;
   * Sec. 2.5: parametric (storm-centred radial) and gridded rain;
+  * Sec. 2.1 (the momentum sources F_x, F_y) with Sec. 2.3 and Sec. 3.3
+    (parametric hurricane wind and pressure): :mod:`oracle.met`, a symmetric
+    parametric vortex standing in for GAHM, whose expressions are not given;
   * Sec. 3: Manning friction, p = 1, Roe flux and two-stage second-order
     SSPRK as the common set-up; LLF for the large mesh; quadratic friction
     0.001 for the bathtub.

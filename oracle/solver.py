@@ -17,7 +17,8 @@ elem_weak_form with the diagonal Dubiner mass of Eq. dubiner):
 
 with s = (R_e, g zeta dhb/dx - tau_b qx, g zeta dhb/dy - tau_b qy): the
 source vector of Sec. 2.2 plus the friction term that Eq. SWE carries on its
-left-hand side (the printed source vector omits it).  Sums run over
+left-hand side (the printed source vector omits it); with meteorological
+forcing the momentum rows also take F = tau_s/rho_w - g H grad psi.  Sums run over
 quadrature points in table order and over local edges 0, 1, 2.
 
 Time integration (Sec. 2.2, Eq. RKSSP; Sec. 3 uses a two-stage second-order
@@ -60,6 +61,10 @@ Readings of silent or garbled points (also listed in the design notes):
     above the round-off of FP64 and FP32 arithmetic;
   * p = 2 wet/dry: if any vertex or edge-midpoint depth is <= H0 the element
     is truncated to its linear part before the p = 1 operator;
+  * wind stress and atmospheric pressure (F_x, F_y of Eq. SWE, optional):
+    nodal kinematic stress and pressure head at t^n (:mod:`oracle.met`),
+    linear in each element, taken at the area points as
+    tau - g H grad psi with H = zeta + h_b; held for every stage like rain;
   * p = 0 (only used to pin the scheme against a finite-volume code): no
     redistribution; a cell is dry when its mean depth is <= H0.
 """
@@ -67,7 +72,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import basis, mesh as meshmod, physics, forcing, wetdry, limiter as limmod
+from . import basis, mesh as meshmod, physics, forcing, wetdry, limiter as limmod, met as metmod
 
 
 def ssp_table(stages):
@@ -115,7 +120,7 @@ class OracleSolver:
     def __init__(self, xy, tri, hb, fric, bedges=None, btype=None, bslot=None, *,
                  p=1, flux="roe", friction="manning", limiter=False, cfl=0.3,
                  dt_fixed=0.0, dt_max=1.0e30, H0=1.0e-3, g=9.81, rk_stages=2,
-                 rain=None, tides=None, rivers=None, mms=None):
+                 rain=None, tides=None, rivers=None, mms=None, met=None):
         self.rk = ssp_table(int(rk_stages))
         self.rk_weights = ssp_flux_weights(self.rk)
         self.xy = np.asarray(xy, dtype=np.float64)
@@ -158,6 +163,7 @@ class OracleSolver:
         self.rain = rain if rain is not None else {"kind": "none"}
         self.tides = dict(tides or {})
         self.rivers = dict(rivers or {})
+        self.met = None if met is None else np.asarray(met, dtype=np.float64).reshape(-1, 9)
         self.mms = mms
         # interior edges, once each, canonical side = lower element id
         nbr = G["nbr"]
@@ -229,8 +235,11 @@ class OracleSolver:
         return np.stack([gz, gx, gy]), qr
 
     # ----------------------------------------------------------------- RHS
-    def rhs(self, w, t, R_e, flags):
-        """L(w) and the boundary mass flux (out, in) of this evaluation."""
+    def rhs(self, w, t, R_e, flags, met=None):
+        """L(w) and the boundary mass flux (out, in) of this evaluation.
+
+        met: nodal (tau_x, tau_y, psi) of :mod:`oracle.met`, or None.
+        """
         T, G = self.T, self.G
         g, H0 = self.g, self.H0
         ng = len(T.gt)
@@ -289,6 +298,18 @@ class OracleSolver:
         s0 = np.broadcast_to(R_e[:, None], wq[0].shape)
         s1 = g * wq[0] * self.dhb[:, 0:1] - tau * wq[1]
         s2 = g * wq[0] * self.dhb[:, 1:2] - tau * wq[2]
+        if met is not None:
+            # wind stress and pressure gradient (oracle.met): nodal values
+            # linear in the element, H = zeta + h_b at the area points
+            tx, ty, psi = (np.asarray(a, dtype=np.float64)[self.tri] for a in met)   # (E, 3) each
+            pr = 0.5 * (psi[:, 1] - psi[:, 0])
+            ps = 0.5 * (psi[:, 2] - psi[:, 0])
+            JT = G["JinvT"]
+            px = JT[:, 0, 0] * pr + JT[:, 0, 1] * ps
+            py = JT[:, 1, 0] * pr + JT[:, 1, 1] * ps
+            Hq = wq[0] + self.hb_q
+            s1 = s1 + tx @ T.lam_q - g * Hq * px[:, None]
+            s2 = s2 + ty @ T.lam_q - g * Hq * py[:, None]
         S = np.stack([s0, s1, s2])
         if self.mms is not None:
             xq, yq = self._area_xy()
@@ -418,10 +439,11 @@ class OracleSolver:
         for _ in range(int(n)):
             t, dt = self.t, self.dt
             R = self.element_rain(t)
+            met = None if self.met is None else metmod.met_nodes(self.met, self.xy, t, self.g)
             w0, wi, fi = self.w, self.w, self.flags
             bout = bin_ = 0.0
             for (a, b, gm, c), ew in zip(self.rk, self.rk_weights):
-                Li, bi = self.rhs(wi, t + c * dt, R, fi)
+                Li, bi = self.rhs(wi, t + c * dt, R, fi, met)
                 wi, fi = self.post(a * w0 + b * (wi + gm * dt * Li))
                 bout += ew * bi[0]
                 bin_ += ew * bi[1]
@@ -450,6 +472,7 @@ def from_scenario(sc, **over):
                      p=prm["p"], flux=prm["flux"], friction=prm["friction"],
                      limiter=prm["limiter"], cfl=prm["cfl"], dt_fixed=prm["dt_fixed"],
                      dt_max=prm["dt_max"], H0=prm["H0"], g=prm["g"],
-                     rk_stages=prm.get("rk_stages", 2), rain=sc.rain, tides=sc.tides, rivers=sc.rivers)
+                     rk_stages=prm.get("rk_stages", 2), rain=sc.rain, tides=sc.tides, rivers=sc.rivers,
+                     met=getattr(sc, "met", None))
     s.set_initial_nodal(sc.zeta0, sc.qx0, sc.qy0)
     return s

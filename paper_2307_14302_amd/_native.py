@@ -69,6 +69,8 @@ SIGNATURES = {
     "dgswe_set_rain_gridded": (C.c_int, [_P, C.c_double, C.c_double, C.c_double, C.c_double, C.c_int32,
                                           C.c_int32, C.c_int32, _D, _F]),
     "dgswe_clear_rain": (C.c_int, [_P]),
+    "dgswe_set_wind_vortex": (C.c_int, [_P, C.c_int32, _D]),
+    "dgswe_clear_wind": (C.c_int, [_P]),
     "dgswe_set_ocean_tide": (C.c_int, [_P, C.c_int32, C.c_double, C.c_int32, _D]),
     "dgswe_set_river_flux": (C.c_int, [_P, C.c_int32, C.c_int32, _D, _D]),
     "dgswe_step": (C.c_int, [_P, C.c_int64]),

@@ -144,9 +144,9 @@ struct dgswe_ctx {
   std::shared_ptr<MeshDev> mesh;
   int n_tiles = 0;
   int variant = 1;                  // stage kernel: 0 per element, 1 per edge
-  DevBuf W[3], Wt, F[3], fullwet, R, part, sc, memb, tiles, ids, rnode, node_tiles;
+  DevBuf W[3], Wt, F[3], fullwet, R, part, sc, memb, tiles, ids, rnode, met, node_tiles;
   int n_node_tiles = 0;
-  DevBuf storm, gt, gvals, tide_c, riv_tq;
+  DevBuf storm, gt, gvals, tide_c, riv_tq, wind;
   Forcing fo{};
   std::vector<double> tide_rows[MAX_SLOTS];
   double tide_mean[MAX_SLOTS] = {0};
@@ -193,7 +193,7 @@ struct dgswe_batch {
     std::vector<int> members;       // indices into the member array
     int n_tiles = 0, n_node_tiles = 0, max_chunks = 1;
     DevBuf tiles, node_tiles, ids;
-    bool has_rain = false;
+    bool node_forcing = false;    // some member needs the per-step node kernel
   };
   std::vector<Group> groups;
   DevBuf memb;
@@ -243,6 +243,7 @@ Member<Real> member_struct(const dgswe_ctx* c) {
   m.fullwet = c->fullwet.as<uint8_t>();
   m.R = c->R.as<Real>();
   m.rn = c->rnode.as<double>();
+  m.met = c->met.as<Real>();
   m.part = c->part.as<double>();
   m.red = m.part ? m.part + size_t(NPART) * std::max(c->n_tiles, 1) : nullptr;
   m.red_count = m.red ? reinterpret_cast<unsigned*>(m.red + size_t(NRED) * red_chunks(c->n_tiles)) : nullptr;
@@ -344,14 +345,15 @@ StageArgs stage_args(const RKTable& T, int i) {
 }
 
 // One time step of a set of members sharing (precision, p, flux, limiter,
-// stages): rain, stages (+ post when limiting), reduce.
+// stages): nodal forcing, stages (+ post when limiting), reduce.
 template <typename Real>
 int enqueue_step_group(const Member<Real>* d_m, const Tile* d_t, int n_tiles, const Tile* d_nt, int n_node_tiles,
                        const int* d_ids, int n_members, int max_chunks, int p, int flux, int limiter, int variant,
-                       const RKTable& T, bool rain, hipStream_t s, dgswe_ctx* prof) {
-  if (rain) {
+                       const RKTable& T, bool node_forcing, hipStream_t s, dgswe_ctx* prof) {
+  if (node_forcing) {
     ProfScope ps(prof, K_RAIN);
-    // nodal rates at t^n; the first stage averages them per element
+    // nodal rain rates, wind stress and pressure head at t^n; the first
+    // stage averages the rain per element
     HIPCHK(launch_rain<Real>(d_m, d_t, 0, 0, d_nt, n_node_tiles, s));
   }
   for (int i = 0; i < T.n; ++i) {
@@ -376,7 +378,7 @@ int enqueue_step_group(const Member<Real>* d_m, const Tile* d_t, int n_tiles, co
 }
 
 int ctx_enqueue_step(dgswe_ctx* c) {
-  const bool rain = c->fo.rain_kind != RAIN_CONST;
+  const bool rain = c->fo.rain_kind != RAIN_CONST || c->fo.met_kind != MET_NONE;
   if (c->rs == 8)
     return enqueue_step_group<double>(c->memb.as<Member<double>>(), c->tiles.as<Tile>(), c->n_tiles,
                                       c->node_tiles.as<Tile>(), c->n_node_tiles, c->ids.as<int>(), 1, red_chunks(c->n_tiles),
@@ -476,6 +478,8 @@ int alloc_state(dgswe_ctx* c) {
   const int64_t nn = c->mesh->host.n_nodes;
   HIPCHK(c->rnode.alloc(size_t(std::max<int64_t>(nn, 1)) * sizeof(double)));
   HIPCHK(hipMemset(c->rnode.p, 0, c->rnode.bytes));
+  HIPCHK(c->met.alloc(size_t(3) * std::max<int64_t>(nn, 1) * c->rs));
+  HIPCHK(hipMemset(c->met.p, 0, c->met.bytes));
   c->n_node_tiles = int((nn + TILE - 1) / TILE);
   std::vector<Tile> ntl(c->n_node_tiles);
   for (int t = 0; t < c->n_node_tiles; ++t) ntl[t] = {0, t};
@@ -569,6 +573,7 @@ int64_t footprint(const dgswe_params* p, int64_t E, int64_t n_nodes) {
   b += 3 * E * 4 + E + 3 * E * 4;                    // neighbours, codes, node ids
   if (p->limiter) b += 6 * E * rs + E;               // limiter stencil
   b += 3 * n_nodes * 8;                              // node coordinates, nodal rain
+  b += 3 * n_nodes * rs;                             // nodal wind stress and pressure head
   b += (NPART * std::max<int64_t>(tiles, 1) + NRED * int64_t(red_chunks(int(tiles))) + 1) * 8 + 4096;
   return b;
 }
@@ -776,6 +781,36 @@ int dgswe_set_rain_parametric(dgswe_ctx* c, int32_t n_rec, const double* rec) {
   c->fo.rain_kind = RAIN_PARAM;
   c->fo.n_storm = n_rec;
   c->fo.storm = c->storm.as<double>();
+  return refresh_forcing(c);
+}
+
+int dgswe_set_wind_vortex(dgswe_ctx* c, int32_t n_rec, const double* rec) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (n_rec < 1 || !rec) return fail(DGSWE_EINVAL, "need at least one wind record");
+  for (int i = 0; i < 9 * n_rec; ++i)
+    if (!std::isfinite(rec[i])) return fail(DGSWE_EINVAL, "non-finite wind record");
+  for (int i = 0; i < n_rec; ++i) {
+    const double* r = rec + 9 * i;
+    if (!(r[3] >= 0.0)) return fail(DGSWE_EINVAL, "pressure deficit must be >= 0");
+    if (!(r[4] > 0.0)) return fail(DGSWE_EINVAL, "radius of maximum wind must be positive");
+    if (!(r[5] > 0.0 && r[5] <= 3.0)) return fail(DGSWE_EINVAL, "vortex shape B must be in (0, 3]");
+    if (i > 0 && !(r[0] > rec[9 * (i - 1)])) return fail(DGSWE_EINVAL, "wind record times must increase");
+  }
+  HIPCHK(hipStreamSynchronize(c->stream));
+  HIPCHK(upload(c->wind, std::vector<double>(rec, rec + 9 * n_rec)));
+  c->fo.met_kind = MET_VORTEX;
+  c->fo.n_wind = n_rec;
+  c->fo.wind = c->wind.as<double>();
+  return refresh_forcing(c);
+}
+
+int dgswe_clear_wind(dgswe_ctx* c) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  HIPCHK(hipStreamSynchronize(c->stream));
+  c->fo.met_kind = MET_NONE;
+  c->fo.n_wind = 0;
   return refresh_forcing(c);
 }
 
@@ -1116,7 +1151,8 @@ int batch_rebuild_t(dgswe_batch* b) {
       it = gi.emplace(key, int(b->groups.size()) - 1).first;
     }
     b->groups[it->second].members.push_back(idx);
-    if (sl.ctx->fo.rain_kind != RAIN_CONST) b->groups[it->second].has_rain = true;
+    if (sl.ctx->fo.rain_kind != RAIN_CONST || sl.ctx->fo.met_kind != MET_NONE)
+      b->groups[it->second].node_forcing = true;
   }
   if (ms.empty()) ms.push_back(Member<Real>{});
   HIPCHK(upload(b->memb, ms));
@@ -1228,12 +1264,12 @@ static int batch_enqueue_step(dgswe_batch* b) {
       rc = enqueue_step_group<float>(b->memb.as<Member<float>>(), g.tiles.as<Tile>(), g.n_tiles,
                                      g.node_tiles.as<Tile>(), g.n_node_tiles, g.ids.as<int>(),
                                      int(g.members.size()), g.max_chunks, g.p, g.flux, g.limiter, g.variant, g.rk,
-                                     g.has_rain, b->stream, nullptr);
+                                     g.node_forcing, b->stream, nullptr);
     else
       rc = enqueue_step_group<double>(b->memb.as<Member<double>>(), g.tiles.as<Tile>(), g.n_tiles,
                                       g.node_tiles.as<Tile>(), g.n_node_tiles, g.ids.as<int>(),
                                       int(g.members.size()), g.max_chunks, g.p, g.flux, g.limiter, g.variant, g.rk,
-                                      g.has_rain, b->stream, nullptr);
+                                      g.node_forcing, b->stream, nullptr);
     if (rc) return rc;
   }
   return DGSWE_OK;

@@ -19,6 +19,10 @@ constexpr int MAX_SLOTS = 16;
 // min(d/lambda), rain volume, dry count
 enum PartKind { P_OUT0 = 0, P_IN0 = MAX_STAGES, P_VOL = 2 * MAX_STAGES, P_MINR, P_RAIN, P_NDRY, NPART };
 enum RainKind { RAIN_CONST = 0, RAIN_PARAM = 1, RAIN_GRID = 2 };
+enum MetKind { MET_NONE = 0, MET_VORTEX = 1 };
+// wind stress and pressure forcing: air and water densities (kg/m^3), cap
+// of the drag coefficient
+constexpr double RHO_AIR = 1.15, RHO_WATER = 1000.0, CD_MAX = 3.5e-3;
 // end-of-step reduction: one workgroup per RED_CHUNK tiles writes a record of
 // NRED doubles (the NPART-style sums and the dt minimum); the last workgroup
 // to finish combines the records in chunk order
@@ -37,6 +41,7 @@ struct Scalars {
   double tide[MAX_STAGES][MAX_SLOTS];   // ocean level at each stage time
   double river[MAX_STAGES][MAX_SLOTS];  // river normal flux at each stage time
   double storm[6];                      // xc, yc, peak, T0, r_m, r_e at t^n
+  double wind[8];                       // xc, yc, dp, rm, B, wf, wbx, wby at t^n
   int gk0, gk1;                         // rain-lattice records around t^n
   double gth;                           // weight of record gk1
 };
@@ -56,6 +61,9 @@ struct Forcing {
   const double* tide_c;
   const double* riv_tq;
   int n_tide, n_riv;          // rows in tide_c (triples) and riv_tq (pairs)
+  int met_kind;               // MetKind
+  int n_wind;                 // wind records (t, xc, yc, dp, rm, B, wf, wbx, wby)
+  const double* wind;
 };
 
 template <typename Real>
@@ -81,6 +89,7 @@ struct Member {
   uint8_t* fullwet;           // [E] every vertex depth > H0 (limiter on)
   Real* R;                    // [E] element rain rate
   double* rn;                 // [n_nodes] nodal rain rate
+  Real* met;                  // [3][n_nodes] kinematic wind stress (x, y) and pressure head at t^n
   double* part;               // [NPART][n_tiles]
   double* red;                // [red_chunks(n_tiles)][NRED] chunk records
   unsigned* red_count;        // chunks finished in the current reduction (0 between launches)

@@ -593,6 +593,67 @@ DG_DEV void area_terms(const Real (&w)[3][Tab<P>::NP], const Real (&hb)[3], Real
     area_terms_unrolled<Real, P>(w, hb, cx0, cx1, cy0, cy1, detJ, idet, fc, friction, g, H0, acc);
 }
 
+// Wind stress and atmospheric pressure (F_x, F_y of Eq. SWE): the nodal
+// kinematic stress and pressure head of t^n are linear in the element, so
+// grad psi is constant; at each area point the momentum rows take
+// tau - g H grad psi with H = zeta + h_b.
+template <typename Real, int P>
+DG_DEV void met_terms(const Member<Real>& M, int E, int ec, const Real (&w)[3][Tab<P>::NP], const Real (&hb)[3],
+                      Real cx0, Real cx1, Real cy0, Real cy1, Real detJ, Real idet, Real g,
+                      Real (&acc)[3][Tab<P>::NP]) {
+  constexpr int NP = Tab<P>::NP;
+  const int nn = M.n_nodes;
+  const DG_G int* __restrict__ tri = gp(M.tri);
+  const DG_G Real* __restrict__ met = gp(M.met);
+  Real tx[3], ty[3], ps[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const int n = tri[i * E + ec];
+    tx[i] = met[n];
+    ty[i] = met[nn + n];
+    ps[i] = met[2 * nn + n];
+  }
+  const Real pr = Real(0.5) * (ps[1] - ps[0]), pq = Real(0.5) * (ps[2] - ps[0]);
+  const Real px = (cx0 * pr + cx1 * pq) * idet, py = (cy0 * pr + cy1 * pq) * idet;
+  auto point = [&](Real L0, Real L1, Real L2, Real zq, Real wdet, const Real* Qm) {
+    const Real Hq = zq + (L0 * hb[0] + L1 * hb[1] + L2 * hb[2]);
+    const Real s1 = (L0 * tx[0] + L1 * tx[1] + L2 * tx[2]) - g * Hq * px;
+    const Real s2 = (L0 * ty[0] + L1 * ty[1] + L2 * ty[2]) - g * Hq * py;
+#pragma unroll
+    for (int m = 0; m < NP; ++m) {
+      const Real c = wdet * Qm[m];
+      acc[1][m] += c * s1;
+      acc[2][m] += c * s2;
+    }
+  };
+  if constexpr (P == 2) {
+    const AreaTable<Real, 2>& T = *reinterpret_cast<const AreaTable<Real, 2>*>(
+        sizeof(Real) == 4 ? static_cast<const void*>(&c_area2f) : static_cast<const void*>(&c_area2d));
+#pragma unroll 1
+    for (int q = 0; q < Tab<2>::NQ; ++q) {
+      Real zq = Real(0);
+#pragma unroll
+      for (int m = 0; m < NP; ++m) zq += T.Q[q][m] * w[0][m];
+      Real Qm[NP];
+#pragma unroll
+      for (int m = 0; m < NP; ++m) Qm[m] = T.Q[q][m];
+      point(T.L[q][0], T.L[q][1], T.L[q][2], zq, T.W[q] * detJ, Qm);
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < Tab<P>::NQ; ++q) {
+      const double qr = Tab<P>::qr(q), qs = Tab<P>::qs(q);
+      Real zq = Real(0), Qm[NP];
+#pragma unroll
+      for (int m = 0; m < NP; ++m) {
+        Qm[m] = Real(B<P>::Q(q, m));
+        zq += Qm[m] * w[0][m];
+      }
+      point(Real(lam_(0, qr, qs)), Real(lam_(1, qr, qs)), Real(lam_(2, qr, qs)), zq, Real(Tab<P>::qw(q)) * detJ, Qm);
+    }
+  }
+}
+
 // Element rain rate (Eq. rain).  With time-dependent rain the first stage of
 // a step averages the nodal rates of t^n (rain_node_kernel), stores R for the
 // later stages and returns the element's rain volume rate in part.
@@ -877,6 +938,8 @@ __global__ DG_STAGE_ATTR void stage_kernel(const Member<Real>* __restrict__ mem,
     }
   }
   area_terms<Real, P>(d.w, d.hb, d.cx0, d.cx1, d.cy0, d.cy1, d.detJ, d.idet, gp(M.fric)[ec], M.friction, g, H0, acc);
+  if (M.fo.met_kind != MET_NONE)
+    met_terms<Real, P>(M, E, ec, d.w, d.hb, d.cx0, d.cx1, d.cy0, d.cy1, d.detJ, d.idet, g, acc);
   double rain_part;
   const Real Rv = element_rain<Real>(M, A, E, e, ec, valid, d.ex, d.ey, rain_part);
   // lanes past the end of the mesh evaluated a copy of the last element
@@ -975,6 +1038,8 @@ __global__ DG_STAGE_ATTR void stage_edge_kernel(const Member<Real>* __restrict__
 #pragma unroll
     for (int m = 0; m < NP; ++m) acc[v][m] = Real(0);
   area_terms<Real, P>(d.w, d.hb, d.cx0, d.cx1, d.cy0, d.cy1, d.detJ, d.idet, gp(M.fric)[ec], M.friction, g, H0, acc);
+  if (M.fo.met_kind != MET_NONE)
+    met_terms<Real, P>(M, E, ec, d.w, d.hb, d.cx0, d.cx1, d.cy0, d.cy1, d.detJ, d.idet, g, acc);
   __syncthreads();
   int base = 0;
 #pragma unroll
@@ -1327,21 +1392,68 @@ DG_DEV double lattice(const DG_G float* __restrict__ v, int nx, int ny, double x
   return (1.0 - ay) * ((1.0 - ax) * v00 + ax * v01) + ay * ((1.0 - ax) * v10 + ax * v11);
 }
 
-// Nodal rain rate at t^n (Sec. 2.5 parametric storm profile or Sec. 3.3
-// rain lattice), one thread per node; block t covers nodes [t TILE, (t+1) TILE).
+// Kinematic wind stress and pressure head of the storm vortex at a node
+// (FP32 members evaluate it in FP32 from offsets formed in FP64).
 template <typename Real>
-__global__ __launch_bounds__(TILE) void rain_node_kernel(const Member<Real>* __restrict__ mem,
-                                                         const Tile* __restrict__ tiles, int n_tiles) {
+DG_DEV void vortex_node(const DG_G Scalars* sc, double x, double y, double g, Real& tx, Real& ty, Real& psi) {
+  const double xc = sc->wind[0], yc = sc->wind[1], dp = sc->wind[2], rm = sc->wind[3], Bh = sc->wind[4];
+  const double wf = sc->wind[5], wbx = sc->wind[6], wby = sc->wind[7];
+  if constexpr (sizeof(Real) == 4) {
+    const float dx = float(x - xc), dy = float(y - yc), rmf = float(rm), Bf = float(Bh), dpf = float(dp);
+    const float r = __builtin_amdgcn_sqrtf(dx * dx + dy * dy);
+    const float rs = dmax(r, 1e-6f * rmf);
+    const float s = __builtin_amdgcn_exp2f(Bf * __builtin_amdgcn_logf(rmf / rs));
+    const float e = __builtin_amdgcn_exp2f(-1.4426950408889634f * s);
+    const float dpa = -dpf * (1.0f - e);
+    const float V = __builtin_amdgcn_sqrtf(Bf * dpf * s * e / float(RHO_AIR));
+    const float Wx = float(wf) * V * (-dy) / rs + float(wbx), Wy = float(wf) * V * dx / rs + float(wby);
+    const float sp = __builtin_amdgcn_sqrtf(Wx * Wx + Wy * Wy);
+    const float k = float(RHO_AIR / RHO_WATER) * dmin((0.75f + 0.067f * sp) * 1e-3f, float(CD_MAX)) * sp;
+    tx = k * Wx;
+    ty = k * Wy;
+    psi = dpa / float(RHO_WATER * g);
+  } else {
+    const double dx = x - xc, dy = y - yc;
+    const double rs = fmax(hypot(dx, dy), 1e-6 * rm);
+    const double s = pow(rm / rs, Bh);
+    const double e = exp(-s);
+    const double dpa = -dp * (1.0 - e);
+    const double V = sqrt(Bh * dp * s * e / RHO_AIR);
+    const double Wx = wf * V * (-dy) / rs + wbx, Wy = wf * V * dx / rs + wby;
+    const double sp = hypot(Wx, Wy);
+    const double k = (RHO_AIR / RHO_WATER) * fmin((0.75 + 0.067 * sp) * 1e-3, CD_MAX) * sp;
+    tx = k * Wx;
+    ty = k * Wy;
+    psi = dpa / (RHO_WATER * g);
+  }
+}
+
+// Nodal forcing at t^n, one thread per node (block t covers nodes
+// [t TILE, (t+1) TILE)): the rain rate (Sec. 2.5 parametric storm profile or
+// Sec. 3.3 rain lattice) and the storm's wind stress and pressure head.
+template <typename Real>
+__global__ __launch_bounds__(TILE) void node_forcing_kernel(const Member<Real>* __restrict__ mem,
+                                                            const Tile* __restrict__ tiles, int n_tiles) {
   const int ti = xcd_tile();
   if (ti >= n_tiles) return;
   const Tile tl = tiles[ti];
   const Member<Real>& M = mem[tl.member];
   const DG_G Scalars* __restrict__ sc = gp((const Scalars*)M.sc);
   const int kind = M.fo.rain_kind;
-  if (!sc->active || kind == RAIN_CONST) return;
+  const bool wind = M.fo.met_kind != MET_NONE;
+  if (!sc->active || (kind == RAIN_CONST && !wind)) return;
   const int n = tl.tile * TILE + int(threadIdx.x);
   if (n >= M.n_nodes) return;
   const double x = gp(M.nxy)[n], y = gp(M.nxy)[M.n_nodes + n];
+  if (wind) {
+    Real tx, ty, psi;
+    vortex_node<Real>(sc, x, y, M.g, tx, ty, psi);
+    DG_G Real* __restrict__ met = gp(M.met);
+    met[n] = tx;
+    met[M.n_nodes + n] = ty;
+    met[2 * M.n_nodes + n] = psi;
+  }
+  if (kind == RAIN_CONST) return;
   double r;
   if (kind == RAIN_PARAM) {
     const double xc = sc->storm[0], yc = sc->storm[1], pk = sc->storm[2], T0 = sc->storm[3];
@@ -1425,6 +1537,8 @@ __global__ __launch_bounds__(RED_CHUNK) void reduce_kernel(const Member<Real>* _
   __shared__ double s_gt[NT];
   __shared__ double s_tide[3 * NT];
   __shared__ double s_riv[2 * NT];
+  constexpr int NTW = 64;                      // wind records staged in LDS
+  __shared__ double s_wind[9 * NTW];
   __shared__ double s_t, s_dt;
   __shared__ int s_last;
   const Member<Real>& M = mem[ids[blockIdx.x]];
@@ -1501,7 +1615,8 @@ __global__ __launch_bounds__(RED_CHUNK) void reduce_kernel(const Member<Real>* _
   const int ngt = f.rain_kind == RAIN_GRID ? (f.gnrec < NT ? f.gnrec : NT) : 0;
   const bool tide_lds = f.n_tide <= NT, riv_lds = f.n_riv <= NT;
   const int ntc = tide_lds ? f.n_tide : 0, nrq = riv_lds ? f.n_riv : 0;
-  double r_storm[7], r_tide[3], r_riv[2], r_gt;
+  const int nwd = f.met_kind == MET_VORTEX ? (f.n_wind < NTW ? f.n_wind : NTW) : 0;
+  double r_storm[7], r_tide[3], r_riv[2], r_gt, r_wind[3];
 #pragma unroll
   for (int k = 0; k < 7; ++k) r_storm[k] = k * NT + tid < 7 * nst ? gp(f.storm)[k * NT + tid] : 0.0;
   r_gt = tid < ngt ? gp(f.gt)[tid] : 0.0;
@@ -1509,6 +1624,9 @@ __global__ __launch_bounds__(RED_CHUNK) void reduce_kernel(const Member<Real>* _
   for (int k = 0; k < 3; ++k) r_tide[k] = k * NT + tid < 3 * ntc ? gp(f.tide_c)[k * NT + tid] : 0.0;
 #pragma unroll
   for (int k = 0; k < 2; ++k) r_riv[k] = k * NT + tid < 2 * nrq ? gp(f.riv_tq)[k * NT + tid] : 0.0;
+  static_assert(9 * NTW <= 3 * NT, "wind staging");
+#pragma unroll
+  for (int k = 0; k < 3; ++k) r_wind[k] = k * NT + tid < 9 * nwd ? gp(f.wind)[k * NT + tid] : 0.0;
   double t0 = 0.0, dt0 = 0.0, rain0 = 0.0, bo0 = 0.0, bi0 = 0.0;
   long long steps0 = 0, target0 = 0;
   if (tid == 0) {
@@ -1535,6 +1653,9 @@ __global__ __launch_bounds__(RED_CHUNK) void reduce_kernel(const Member<Real>* _
 #pragma unroll
   for (int k = 0; k < 2; ++k)
     if (k * NT + tid < 2 * nrq) s_riv[k * NT + tid] = r_riv[k];
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+    if (k * NT + tid < 9 * nwd) s_wind[k * NT + tid] = r_wind[k];
   block_reduce();
   if (tid == 0) {
     __hip_atomic_store(M.red_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1624,7 +1745,22 @@ __global__ __launch_bounds__(RED_CHUNK) void reduce_kernel(const Member<Real>* _
       const double th = (t - R(7 * k)) / (R(7 * (k + 1)) - R(7 * k));
       for (int i = 0; i < 6; ++i) sc->storm[i] = (1.0 - th) * R(7 * k + 1 + i) + th * R(7 * (k + 1) + 1 + i);
     }
-  } else if (tid == MAX_SLOTS + 1 && f.rain_kind == RAIN_GRID && f.gnrec > 0) {
+  }
+  if (tid == MAX_SLOTS + 2 && f.met_kind == MET_VORTEX && f.n_wind > 0) {
+    const int n = f.n_wind;
+    auto R = [&](int i) { return i < 9 * NTW ? s_wind[i] : gp(f.wind)[i]; };
+    auto RT = [&](int k) { return R(9 * k); };
+    if (n == 1 || t <= R(0)) {
+      for (int i = 0; i < 8; ++i) sc->wind[i] = R(1 + i);
+    } else if (t >= R(9 * (n - 1))) {
+      for (int i = 0; i < 8; ++i) sc->wind[i] = R(9 * (n - 1) + 1 + i);
+    } else {
+      const int k = bracket(RT, n, t);
+      const double th = (t - R(9 * k)) / (R(9 * (k + 1)) - R(9 * k));
+      for (int i = 0; i < 8; ++i) sc->wind[i] = (1.0 - th) * R(9 * k + 1 + i) + th * R(9 * (k + 1) + 1 + i);
+    }
+  }
+  if (tid == MAX_SLOTS + 1 && f.rain_kind == RAIN_GRID && f.gnrec > 0) {
     const int n = f.gnrec;
     auto TR = [&](int i) { return i < NT ? s_gt[i] : gp(f.gt)[i]; };
     if (n == 1 || t <= TR(0)) {
@@ -1686,7 +1822,7 @@ template <typename Real>
 hipError_t launch_rain(const Member<Real>* m, const Tile* t, int n, int always, const Tile* node_tiles, int n_node_tiles,
                        hipStream_t s) {
   if (!always && node_tiles && n_node_tiles > 0)
-    hipLaunchKernelGGL((rain_node_kernel<Real>), dim3(xcd_grid(n_node_tiles)), dim3(TILE), 0, s, m, node_tiles,
+    hipLaunchKernelGGL((node_forcing_kernel<Real>), dim3(xcd_grid(n_node_tiles)), dim3(TILE), 0, s, m, node_tiles,
                        n_node_tiles);
   if (n > 0) hipLaunchKernelGGL((rain_kernel<Real>), dim3(xcd_grid(n)), dim3(TILE), 0, s, m, t, n, always);
   return hipGetLastError();

@@ -107,6 +107,15 @@ class Solver:
         else:
             raise ValueError(kind)
 
+    def set_wind(self, records):
+        """Storm wind and pressure records (t, xc, yc, dp, rm, B, wf, wbx, wby),
+        one row each, or None to turn the forcing off."""
+        if records is None:
+            call("dgswe_clear_wind", self.h)
+            return
+        rec = _f64(np.asarray(records, dtype=np.float64).reshape(-1, 9))
+        call("dgswe_set_wind_vortex", self.h, rec.shape[0], dptr(rec))
+
     def set_tide(self, slot: int, mean: float, rows):
         rows = _f64(np.asarray(rows, dtype=np.float64).reshape(-1, 3))
         buf = rows if rows.size else np.zeros(3)
@@ -198,7 +207,7 @@ class Solver:
     def from_scenario(cls, sc, stream=None, mesh_from: Optional["Solver"] = None, **over):
         """Build a solver from a workload description with attributes
         mesh (xy, tri, hb, fric, bedges, btype, bslot), zeta0/qx0/qy0,
-        params, rain, tides, rivers."""
+        params, rain, tides, rivers and (optional) met."""
         prm = dict(sc.params)
         prm.update(over)
         s = cls(prm, stream=stream)
@@ -212,6 +221,8 @@ class Solver:
         for slot, (t, q) in sc.rivers.items():
             s.set_river(slot, t, q)
         s.set_rain(sc.rain)
+        if getattr(sc, "met", None) is not None:
+            s.set_wind(sc.met)
         s.set_initial_nodal(sc.zeta0, sc.qx0, sc.qy0)
         return s
 
