@@ -61,11 +61,14 @@ class Scenario:
 
 
 def default_params(**kw) -> Dict[str, object]:
-    """Solver settings; p = 2 defaults to three SSP stages at CFL 0.15."""
+    """Solver settings; p = 2 defaults to three SSP stages at CFL 0.15,
+    p = 3 to three stages at CFL 0.1."""
     p = dict(p=1, flux="roe", friction="manning", limiter=False, cfl=0.3,
              dt_fixed=0.0, dt_max=1.0e30, H0=1.0e-3, g=9.81, rk_stages=2)
     if kw.get("p", 1) == 2:
         p.update(rk_stages=3, cfl=0.15)
+    if kw.get("p", 1) == 3:
+        p.update(rk_stages=3, cfl=0.1)
     p.update(kw)
     if p["p"] == 2 and "cfl" in kw and kw["cfl"] == 0.3:
         p["cfl"] = 0.15

@@ -111,26 +111,27 @@ def area_rule(p: int):
 
     p <= 1: the 3-point interior rule with barycentric points
     (2/3,1/6,1/6) and permutations, weight 2/3 each (exact for degree 2).
-    p = 2: Gauss-Legendre 3 x 3 mapped by the Duffy collapse
+    p = 2, 3: Gauss-Legendre (p+1) x (p+1) mapped by the Duffy collapse
     r = (1 + a)(1 - b)/2 - 1, s = b with Jacobian (1 - b)/2 (exact for
-    degree 4).  Points are listed with b outermost.
+    degree 2p: 4 and 6).  Points are listed with b outermost.
     """
     if p <= 1:
         bary = np.array([[2 / 3, 1 / 6, 1 / 6], [1 / 6, 2 / 3, 1 / 6], [1 / 6, 1 / 6, 2 / 3]])
         pts = bary @ REF_VERTS
         w = np.full(3, REF_AREA / 3.0)
         return pts[:, 0].copy(), pts[:, 1].copy(), w
-    if p == 2:
-        a, wa = np.polynomial.legendre.leggauss(3)
+    if p in (2, 3):
+        n = p + 1
+        a, wa = np.polynomial.legendre.leggauss(n)
         rs, ss, ws = [], [], []
-        for ib in range(3):
-            for ia in range(3):
+        for ib in range(n):
+            for ia in range(n):
                 b = a[ib]
                 rs.append(0.5 * (1.0 + a[ia]) * (1.0 - b) - 1.0)
                 ss.append(b)
                 ws.append(wa[ia] * wa[ib] * 0.5 * (1.0 - b))
         return np.array(rs), np.array(ss), np.array(ws)
-    raise ValueError("p must be 0, 1 or 2")
+    raise ValueError("p must be 0, 1, 2 or 3")
 
 
 def edge_rule(p: int):

@@ -27,7 +27,7 @@ def tri_integral(f):
     return sp.integrate(sp.integrate(f, (r, -1, -s)), (s, -1, 1))
 
 
-@pytest.mark.parametrize("p", [1, 2])
+@pytest.mark.parametrize("p", [1, 2, 3])
 def test_mass_closed_form_and_orthogonality(p):
     modes = basis.mode_list(p)
     syms = [sym_dubiner(i, j) for i, j in modes]
@@ -47,7 +47,7 @@ def test_p1_explicit_forms():
     assert sp.simplify(sym_dubiner(0, 1) - (1 + 3 * s) / 2) == 0
 
 
-@pytest.mark.parametrize("p", [0, 1, 2])
+@pytest.mark.parametrize("p", [0, 1, 2, 3])
 def test_values_and_gradients_match_definition(p):
     rng = np.random.default_rng(1)
     pts = []
@@ -67,7 +67,7 @@ def test_values_and_gradients_match_definition(p):
             assert abs(ds[m, n] - float(fs.subs({r: a, s: b}))) < 1e-12
 
 
-@pytest.mark.parametrize("p,degree", [(0, 2), (1, 2), (2, 4)])
+@pytest.mark.parametrize("p,degree", [(0, 2), (1, 2), (2, 4), (3, 6)])
 def test_area_rule_exact_to_its_degree(p, degree):
     qr, qs, qw = basis.area_rule(p)
     for a, b in itertools.product(range(degree + 1), repeat=2):
@@ -84,7 +84,7 @@ def test_area_rule_p2_not_exact_beyond_degree_4():
     assert abs(np.sum(qw * qs ** 5) - exact) > 1e-6
 
 
-@pytest.mark.parametrize("p", [0, 1, 2])
+@pytest.mark.parametrize("p", [0, 1, 2, 3])
 def test_edge_rule_exact_degree_2p_plus_1(p):
     t, w = basis.edge_rule(p)
     x = sp.symbols("x")

@@ -5,7 +5,7 @@
 * SSP stability polynomials (closed forms);
 * mass budget closes to round-off (rain, boundaries, wet/dry, limiter);
 * friction ODE for uniform flow on a flat bed (closed form, order 2);
-* manufactured solution: L2 convergence rates p + 1;
+* manufactured solution: L2 convergence rates p + 1 (p = 1, 2, 3);
 * p = 0 equals an independent first-order finite-volume code;
 * the vectorised oracle equals the element-by-element loop version.
 The bathtub experiment of Sec. 3.1 is in test_oracle_bathtub.py.
@@ -27,7 +27,7 @@ def _solver(sc, **kw):
     return from_scenario(sc, **kw)
 
 
-@pytest.mark.parametrize("p,flux", [(1, "roe"), (1, "llf"), (2, "roe"), (2, "llf")])
+@pytest.mark.parametrize("p,flux", [(1, "roe"), (1, "llf"), (2, "roe"), (2, "llf"), (3, "roe"), (3, "llf")])
 def test_lake_at_rest_rhs_vanishes(p, flux):
     sc = meshgen.lake_at_rest(p=p, flux=flux)
     s = _solver(sc)
@@ -141,7 +141,7 @@ def _project(s, fun, t):
     return np.einsum("veq,q,mq->evm", f, wq, phi) / basis.mass_diag(s.p)[None, None, :], (x, y, wq, phi)
 
 
-@pytest.mark.parametrize("p,rate", [(1, 1.8), (2, 2.7)])
+@pytest.mark.parametrize("p,rate", [(1, 1.8), (2, 2.7), (3, 3.6)])
 def test_mms_convergence_rate(p, rate):
     mms = MMS()
     errs = []
@@ -226,12 +226,13 @@ def test_p0_equals_finite_volume(kind):
     np.testing.assert_allclose(s.w[:, :, 0], U, rtol=1e-13, atol=1e-13)
 
 
-@pytest.mark.parametrize("case", ["p1_roe", "p2_llf_lim", "p1_llf_lim_nodal", "p2_roe"])
+@pytest.mark.parametrize("case", ["p1_roe", "p2_llf_lim", "p1_llf_lim_nodal", "p2_roe", "p3_llf_lim"])
 def test_vectorised_equals_loop(case):
     kw = dict(p1_roe=dict(p=1, flux="roe", limiter=False, rain_kind="gridded"),
               p2_llf_lim=dict(p=2, flux="llf", limiter=True, rain_kind="parametric"),
               p1_llf_lim_nodal=dict(p=1, flux="llf", limiter=True, rain_kind="nodal"),
-              p2_roe=dict(p=2, flux="roe", limiter=False, rain_kind="none"))[case]
+              p2_roe=dict(p=2, flux="roe", limiter=False, rain_kind="none"),
+              p3_llf_lim=dict(p=3, flux="llf", limiter=True, rain_kind="gridded"))[case]
     sc = meshgen.small_mixed(seed=11, nx=8, ny=5, **kw)
     m = sc.mesh
     s = from_scenario(sc)

@@ -60,7 +60,7 @@ def _limiter_solver(seed=4):
                         tides=sc.tides)
 
 
-@pytest.mark.parametrize("p", [1, 2])
+@pytest.mark.parametrize("p", [1, 2, 3])
 def test_limiter_keeps_linear_data_and_means(p):
     s = _limiter_solver()
     T = basis.Tables(p)
