@@ -55,7 +55,7 @@ def algorithmic_bytes(kernel, E, rs, p, a_nonzero, last, limiter):
            state 3 Np rs and a flag; the last stage reads edge vectors and
            d_in (7 rs) for the volume and dt partials.
     """
-    Np = 3 if p == 1 else 6
+    Np = (p + 1) * (p + 2) // 2
     st = 3 * Np * rs
     if kernel == "stage":
         b = st + (st if a_nonzero else 0) + 11 * rs + 14 + st + 1
@@ -310,7 +310,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--precision", choices=["both", "fp32", "fp64"], default="both")
     ap.add_argument("--N", type=int, default=708, help="quads per side (708 -> 1,002,528 triangles)")
-    ap.add_argument("--p", type=int, default=1, choices=[1, 2], help="polynomial degree of the basin run")
+    ap.add_argument("--p", type=int, default=1, choices=[1, 2, 3], help="polynomial degree of the basin run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--variant", type=int, default=-1,
                     help="stage kernel: 0 per element, 1 per edge, -1 autotuned on the workload (default)")
@@ -355,7 +355,7 @@ def main():
         "vs_baseline": None, "dtype": "f32" if main_prec == "fp32" else "f64", "data": "synthetic",
         "config": {"workload": f"single basin, {r['E']} triangles (jittered {args.N}x{args.N} grid over 200 km), "
                                f"p={args.p}, LLF, limiter on, parametric moving rain, wet/dry front, "
-                               + ("SSP-RK2 CFL 0.3" if args.p == 1 else "SSP-RK3 CFL 0.15"),
+                               + f"SSP-RK{r['stages']} CFL {prm['cfl']}",
                    "n_tri": r["E"], "p": prm["p"], "rk_stages": r["stages"], "precision": main_prec,
                    "stage_variant": r["variant"],
                    "parallelism": "single GPU"},

@@ -82,7 +82,7 @@ extern "C" {
  * paper's set-up; p = 2 needs rk_stages = 3 for linear stability;
  * rk_stages = 5 selects the optimal five-stage second-order SSP scheme. */
 typedef struct dgswe_params {
-  int32_t p;            /* polynomial degree: 1 or 2                          */
+  int32_t p;            /* polynomial degree: 1, 2 or 3                       */
   int32_t precision;    /* DGSWE_FP64 | DGSWE_FP32                            */
   int32_t flux;         /* DGSWE_ROE | DGSWE_LLF                              */
   int32_t rk_stages;    /* 2, 3 or 5                                          */
@@ -155,9 +155,10 @@ int dgswe_set_initial_nodal(dgswe_ctx* ctx, const double* zeta, const double* qx
 
 /* Set the state directly.  layout DGSWE_MODAL: w[n_tri][3][Np] with
  * variables (zeta, qx, qy) and Dubiner modes ordered (0,0),(1,0),(0,1),
- * (2,0),(1,1),(0,2) (Np = 3 for p = 1, 6 for p = 2).  The state is used as
- * given (no limiter or positive-depth pass); flags and dt are derived from
- * it.  The budgets restart at time t.  EINVAL on non-finite input. */
+ * (2,0),(1,1),(0,2),(3,0),(2,1),(1,2),(0,3) (Np = 3, 6, 10 for p = 1, 2, 3).
+ * The state is used as given (no limiter or positive-depth pass); flags and
+ * dt are derived from it.  The budgets restart at time t.  EINVAL on
+ * non-finite input. */
 int dgswe_set_state(dgswe_ctx* ctx, int layout, const double* w, double t);
 
 /* Rain (Sec. 2.3 Eq. rain; Sec. 2.5; Sec. 3.3).  Each replaces the previous
@@ -234,9 +235,10 @@ int dgswe_kernel_stats(dgswe_ctx* ctx, const char* kernel, int64_t* launches, do
 
 /* Kernel choices (same arithmetic, different work layout; results differ
  * only by summation order).  DGSWE_TUNE_STAGE_VARIANT: 0 = every element
- * evaluates its three edges; 1 (default) = the tile's point values are
- * staged in LDS and each edge inside a tile is evaluated once.  EINVAL for
- * unknown keys or values; ESTATE while the context is in a batch. */
+ * evaluates its three edges; 1 (default for p <= 2) = the tile's point
+ * values are staged in LDS and each edge inside a tile is evaluated once
+ * (p <= 2 only; p = 3 uses variant 0).  EINVAL for unknown keys or values
+ * and for variant 1 with p = 3; ESTATE while the context is in a batch. */
 #define DGSWE_TUNE_STAGE_VARIANT 1
 int dgswe_set_tuning(dgswe_ctx* ctx, int key, int value);
 int dgswe_get_tuning(const dgswe_ctx* ctx, int key, int* value);
@@ -245,7 +247,8 @@ int dgswe_get_tuning(const dgswe_ctx* ctx, int key, int* value);
  * variant (after two untimed steps each), keeps the faster one and restores
  * the state, flags, tile partials and scalars, so the context continues
  * exactly where it was.  chosen (may be NULL) receives the variant,
- * ms_per_step[2] (may be NULL) the two timings.  Allocates a copy of the
+ * ms_per_step[2] (may be NULL) the two timings (with p = 3 only variant 0
+ * runs and ms_per_step[1] is 0).  Allocates a copy of the
  * state for the duration of the call.  EINVAL for n_steps < 1, ESTATE
  * without mesh or state or inside a batch, ENONFINITE if the context has a
  * latched error. */

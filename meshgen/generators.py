@@ -70,8 +70,6 @@ def default_params(**kw) -> Dict[str, object]:
     if kw.get("p", 1) == 3:
         p.update(rk_stages=3, cfl=0.1)
     p.update(kw)
-    if p["p"] == 2 and "cfl" in kw and kw["cfl"] == 0.3:
-        p["cfl"] = 0.15
     return p
 
 
@@ -280,7 +278,7 @@ def basin(N: int = 708, seed: int = seed_for(1), *, L: float = 200e3,
                                  rm=30e3 * L / 200e3, re=100e3 * L / 200e3)
     met = vortex_track(0.3 * L, 0.5 * L, 5.0, 0.0, 4000.0, rm=30e3 * L / 200e3) if wind else None
     return Scenario(f"basin_{N}", mesh, zeta0, np.zeros_like(hb), np.zeros_like(hb),
-                    default_params(p=p, flux=flux, friction="manning", limiter=limiter, cfl=0.3, H0=0.05),
+                    default_params(p=p, flux=flux, friction="manning", limiter=limiter, H0=0.05),
                     rain={"kind": "parametric", "records": track},
                     tides={0: (0.0, np.zeros((0, 3)))}, n_steps=n_steps, met=met)
 
@@ -375,7 +373,7 @@ def small_mixed(seed: int = 7, nx: int = 24, ny: int = 12, *, p: int = 1,
            if wind else None)
     return Scenario(f"small_mixed_{seed}", mesh, zeta0, qx0, qy0,
                     default_params(p=p, flux=flux, friction=friction, limiter=limiter,
-                                   cfl=0.3, dt_fixed=dt_fixed, H0=0.05),
+                                   dt_fixed=dt_fixed, H0=0.05),
                     rain=rain, tides=tides, rivers=rivers, n_steps=200, met=met)
 
 

@@ -80,8 +80,10 @@ def ssp_table(stages):
 
     Stage i: w(i) = a_i w^n + b_i (w(i-1) + g_i dt L(w(i-1), t^n + c_i dt)).
       2 stages: SSP(2,2), the two-stage second-order scheme of Sec. 3;
-      3 stages: SSP(3,3), needed for p = 2 (an order-(p+1) RK is required for
-                linear stability of RKDG with degree-p elements);
+      3 stages: SSP(3,3), used for p = 2 and p = 3 (a two-stage order-2
+                scheme is linearly unstable with p >= 2 elements: its
+                stability region holds no segment of the imaginary axis;
+                SSP(3,3)'s does, so p = 3 runs at a reduced CFL, 0.1);
       5 stages: SSP(5,2), the optimal five-stage second-order scheme, a
                 stand-in for the five-stage scheme used for Hurricane Harvey
                 in Sec. 3 (whose optimised coefficients are not given).

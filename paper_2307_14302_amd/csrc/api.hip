@@ -172,7 +172,7 @@ struct dgswe_ctx {
     if (own_stream && stream) (void)hipStreamDestroy(stream);
   }
   int E() const { return mesh ? int(mesh->host.E) : 0; }
-  int NP() const { return prm.p == 1 ? 3 : 6; }
+  int NP() const { return prm.p == 1 ? 3 : prm.p == 2 ? 6 : 10; }
 };
 
 struct dgswe_batch {
@@ -564,7 +564,7 @@ int post_initial(dgswe_ctx* c, int init) {
 
 int64_t footprint(const dgswe_params* p, int64_t E, int64_t n_nodes) {
   const int64_t rs = p->precision == DGSWE_FP32 ? 4 : 8;
-  const int64_t NP = p->p == 2 ? 6 : 3;
+  const int64_t NP = p->p == 1 ? 3 : p->p == 2 ? 6 : 10;
   const int64_t tiles = (E + TILE - 1) / TILE;
   int64_t b = 4 * 3 * NP * E * rs;                   // W0..W2 + Wt
   b += 3 * E + (p->limiter ? E : 0);                 // flags, fully-wet bytes
@@ -604,7 +604,7 @@ int dgswe_default_params(dgswe_params* out) {
 
 static int check_params(const dgswe_params* p) {
   if (!p) return fail(DGSWE_EINVAL, "null params");
-  if (p->p != 1 && p->p != 2) return fail(DGSWE_EINVAL, "p must be 1 or 2");
+  if (p->p < 1 || p->p > 3) return fail(DGSWE_EINVAL, "p must be 1, 2 or 3");
   if (p->precision != DGSWE_FP32 && p->precision != DGSWE_FP64) return fail(DGSWE_EINVAL, "bad precision");
   if (p->flux != DGSWE_ROE && p->flux != DGSWE_LLF) return fail(DGSWE_EINVAL, "bad flux");
   if (p->rk_stages != 2 && p->rk_stages != 3 && p->rk_stages != 5) return fail(DGSWE_EINVAL, "rk_stages must be 2, 3 or 5");
@@ -624,6 +624,7 @@ int dgswe_create(const dgswe_params* params, void* hip_stream, dgswe_ctx** out) 
   c->prm = *params;
   c->rs = params->precision == DGSWE_FP32 ? 4 : 8;
   make_rk(params->rk_stages, c->rk);
+  c->variant = params->p == 3 ? 0 : 1;
   if (hip_stream) {
     c->stream = static_cast<hipStream_t>(hip_stream);
   } else {
@@ -1019,6 +1020,7 @@ int dgswe_set_tuning(dgswe_ctx* c, int key, int value) {
   if (c->in_batch) return fail(DGSWE_ESTATE, "context is a member of a batch");
   if (key != DGSWE_TUNE_STAGE_VARIANT) return fail(DGSWE_EINVAL, "unknown tuning key");
   if (value != 0 && value != 1) return fail(DGSWE_EINVAL, "stage variant must be 0 or 1");
+  if (value == 1 && c->prm.p == 3) return fail(DGSWE_EINVAL, "the per-edge stage kernel supports p <= 2");
   if (c->stream) HIPCHK(hipStreamSynchronize(c->stream));
   c->variant = value;
   c->graph_dirty = true;
@@ -1067,7 +1069,8 @@ int dgswe_autotune(dgswe_ctx* c, int n_steps, int* chosen, double* ms_per_step) 
   HIPCHK(hipEventCreate(&eb));
   double ms[2] = {0.0, 0.0};
   int err = DGSWE_OK;
-  for (int v = 0; v < 2 && !err; ++v) {
+  const int nv = c->prm.p == 3 ? 1 : 2;         // p = 3 has the per-element kernel only
+  for (int v = 0; v < nv && !err; ++v) {
     c->variant = v;
     c->graph_dirty = true;
     err = dgswe_step(c, 2);                     // builds the step graph, warms caches
@@ -1090,7 +1093,7 @@ int dgswe_autotune(dgswe_ctx* c, int n_steps, int* chosen, double* ms_per_step) 
     (void)restore();
     return err;
   }
-  c->variant = ms[1] <= ms[0] ? 1 : 0;
+  c->variant = (nv == 2 && ms[1] <= ms[0]) ? 1 : 0;
   c->graph_dirty = true;
   if (chosen) *chosen = c->variant;
   if (ms_per_step) { ms_per_step[0] = ms[0]; ms_per_step[1] = ms[1]; }

@@ -3,12 +3,16 @@
 //
 // Reference triangle v0 = (-1,-1), v1 = (1,-1), v2 = (-1,1); local edge k
 // runs v_k -> v_{k+1}.  Dubiner modes (Sec. 2.2, Eq. dubiner) in the order
-// (0,0),(1,0),(0,1),(2,0),(1,1),(0,2), written as explicit polynomials with
-// x = r + (1+s)/2 and b = (1-s)/2 (the collapsed Legendre factor
-// P_i(a) b^i is a polynomial in x and b):
+// (0,0),(1,0),(0,1),(2,0),(1,1),(0,2),(3,0),(2,1),(1,2),(0,3), written as
+// explicit polynomials with x = r + (1+s)/2 and b = (1-s)/2 (the collapsed
+// Legendre factor P_i(a) b^i is a polynomial in x and b; the second factor
+// is the Jacobi polynomial P_j^(2i+1,0)(s)):
 //   phi00 = 1                  phi10 = x              phi01 = (1 + 3s)/2
 //   phi20 = (3x^2 - b^2)/2     phi11 = x (5s + 3)/2   phi02 = (5s^2 + 2s - 1)/2
-// Diagonal mass int phi^2 = 2/((2i+1)(i+j+1)) = 2, 1/3, 1, 2/15, 2/9, 2/3.
+//   phi30 = (5x^3 - 3x b^2)/2  phi21 = phi20 (7s + 5)/2
+//   phi12 = x (21s^2 + 18s + 1)/4                     phi03 = (35s^3 + 15s^2 - 15s - 3)/8
+// Diagonal mass int phi^2 = 2/((2i+1)(i+j+1)) = 2, 1/3, 1, 2/15, 2/9, 2/3,
+// 1/14, 1/10, 1/6, 1/2.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -28,17 +32,27 @@ DG_HD double phi_(int m, double r, double s) {
     case 2: return 0.5 * (1.0 + 3.0 * s);
     case 3: return 0.5 * (3.0 * x * x - b * b);
     case 4: return 0.5 * x * (5.0 * s + 3.0);
-    default: return 0.5 * (5.0 * s * s + 2.0 * s - 1.0);
+    case 5: return 0.5 * (5.0 * s * s + 2.0 * s - 1.0);
+    case 6: return 0.5 * x * (5.0 * x * x - 3.0 * b * b);
+    case 7: return 0.25 * (3.0 * x * x - b * b) * (7.0 * s + 5.0);
+    case 8: return 0.25 * x * (21.0 * s * s + 18.0 * s + 1.0);
+    default: return 0.125 * (((35.0 * s + 15.0) * s - 15.0) * s - 3.0);
   }
 }
+// d/dr acts on x only (dx/dr = 1); d/ds on x (dx/ds = 1/2), b (db/ds = -1/2)
+// and s itself
 DG_HD double dphi_dr_(int m, double r, double s) {
-  const double x = r + 0.5 * (1.0 + s);
+  const double x = r + 0.5 * (1.0 + s), b = 0.5 * (1.0 - s);
   switch (m) {
     case 0: return 0.0;
     case 1: return 1.0;
     case 2: return 0.0;
     case 3: return 3.0 * x;
     case 4: return 0.5 * (5.0 * s + 3.0);
+    case 5: return 0.0;
+    case 6: return 0.5 * (15.0 * x * x - 3.0 * b * b);
+    case 7: return 1.5 * x * (7.0 * s + 5.0);
+    case 8: return 0.25 * (21.0 * s * s + 18.0 * s + 1.0);
     default: return 0.0;
   }
 }
@@ -50,22 +64,32 @@ DG_HD double dphi_ds_(int m, double r, double s) {
     case 2: return 1.5;
     case 3: return 0.5 * (3.0 * x + b);
     case 4: return 0.25 * (5.0 * s + 3.0) + 2.5 * x;
-    default: return 5.0 * s + 1.0;
+    case 5: return 5.0 * s + 1.0;
+    case 6: return 0.25 * (15.0 * x * x - 3.0 * b * b) + 1.5 * x * b;
+    case 7: return 0.25 * (3.0 * x + b) * (7.0 * s + 5.0) + 1.75 * (3.0 * x * x - b * b);
+    case 8: return 0.125 * (21.0 * s * s + 18.0 * s + 1.0) + 0.5 * x * (21.0 * s + 9.0);
+    default: return 0.125 * (105.0 * s * s + 30.0 * s - 15.0);
   }
 }
 DG_HD double mass_(int m) {
-  return m == 0 ? 2.0 : m == 1 ? 1.0 / 3.0 : m == 2 ? 1.0 : m == 3 ? 2.0 / 15.0 : m == 4 ? 2.0 / 9.0 : 2.0 / 3.0;
+  return m == 0 ? 2.0 : m == 1 ? 1.0 / 3.0 : m == 2 ? 1.0 : m == 3 ? 2.0 / 15.0 : m == 4 ? 2.0 / 9.0
+       : m == 5 ? 2.0 / 3.0 : m == 6 ? 1.0 / 14.0 : m == 7 ? 0.1 : m == 8 ? 1.0 / 6.0 : 0.5;
 }
 DG_HD double vr_(int i) { return i == 1 ? 1.0 : -1.0; }
 DG_HD double vs_(int i) { return i == 2 ? 1.0 : -1.0; }
 
-// Gauss-Legendre nodes/weights on [-1,1] (p+1 points, ascending).
+// Gauss-Legendre nodes/weights on [-1,1] (p+1 points, ascending); the
+// 4-point rule is sqrt(3/7 -+ (2/7) sqrt(6/5)) with weights (18 +- sqrt(30))/36.
 DG_HD double gl_t(int P, int g) {
-  return P == 1 ? (g == 0 ? -0.57735026918962576451 : 0.57735026918962576451)
-                : (g == 0 ? -0.77459666924148337704 : g == 1 ? 0.0 : 0.77459666924148337704);
+  if (P == 1) return g == 0 ? -0.57735026918962576451 : 0.57735026918962576451;
+  if (P == 2) return g == 0 ? -0.77459666924148337704 : g == 1 ? 0.0 : 0.77459666924148337704;
+  return g == 0 ? -0.86113631159405257522 : g == 1 ? -0.33998104358485626480
+       : g == 2 ? 0.33998104358485626480 : 0.86113631159405257522;
 }
 DG_HD double gl_w(int P, int g) {
-  return P == 1 ? 1.0 : (g == 1 ? 8.0 / 9.0 : 5.0 / 9.0);
+  if (P == 1) return 1.0;
+  if (P == 2) return g == 1 ? 8.0 / 9.0 : 5.0 / 9.0;
+  return (g == 1 || g == 2) ? 0.65214515486254614263 : 0.34785484513745385737;
 }
 
 template <int P> struct Tab;
@@ -85,6 +109,16 @@ template <> struct Tab<2> {
   DG_HD static double qr(int q) { return 0.5 * (1.0 + qa(q)) * (1.0 - qb(q)) - 1.0; }
   DG_HD static double qs(int q) { return qb(q); }
   DG_HD static double qw(int q) { return gl_w(2, q % 3) * gl_w(2, q / 3) * 0.5 * (1.0 - qb(q)); }
+};
+
+// p = 3: collapsed 4 x 4 Gauss-Legendre (b outer, a inner)
+template <> struct Tab<3> {
+  static constexpr int NP = 10, NQ = 16, NG = 4;
+  DG_HD static double qa(int q) { return gl_t(3, q % 4); }
+  DG_HD static double qb(int q) { return gl_t(3, q / 4); }
+  DG_HD static double qr(int q) { return 0.5 * (1.0 + qa(q)) * (1.0 - qb(q)) - 1.0; }
+  DG_HD static double qs(int q) { return qb(q); }
+  DG_HD static double qw(int q) { return gl_w(3, q % 4) * gl_w(3, q / 4) * 0.5 * (1.0 - qb(q)); }
 };
 
 // barycentric weights of a reference point

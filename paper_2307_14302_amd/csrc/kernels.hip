@@ -16,6 +16,9 @@
 // positive-depth operator, dt and all budgets are done in FP64.
 #include <hip/hip_ext.h>
 
+#include <type_traits>
+#include <utility>
+
 #include "device_common.h"
 #include "internal.h"
 
@@ -25,6 +28,16 @@ namespace dg {
 #define DG_STAGE_WAVES 1
 #endif
 #define DG_STAGE_ATTR __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(DG_STAGE_WAVES)))
+
+// f(std::integral_constant<int, i>) for i = 0 .. N-1, expanded at compile time
+template <typename F, int... I>
+DG_DEV void static_for_(F& f, std::integer_sequence<int, I...>) {
+  (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, typename F>
+DG_DEV void static_for(F&& f) {
+  static_for_(f, std::make_integer_sequence<int, N>{});
+}
 
 // Pointers read from the member descriptor are generic to the compiler; all
 // device arrays live in global memory, so they are re-typed to the global
@@ -140,17 +153,47 @@ DG_DEV void edge_nodes(const Real (&w)[3][Tab<P>::NP], Real (&vv)[3][3], Real (&
 #pragma unroll
       for (int m = 0; m < NP; ++m) {
         s += Real(B<P>::V(i, m)) * w[v][m];
-        if (P == 2) t += Real(B<P>::M(i, m)) * w[v][m];
+        if (P >= 2) t += Real(B<P>::M(i, m)) * w[v][m];
       }
       vv[v][i] = s;
       mv[v][i] = t;
     }
 }
 
+// Basis values at the edge Gauss points, evaluated at compile time (a
+// constexpr table: a select between entries stays a select of literals).
+template <int P> struct EdgeTable {
+  double v[3][Tab<P>::NG][Tab<P>::NP];
+};
+template <int P>
+constexpr EdgeTable<P> make_edge_table() {
+  EdgeTable<P> t{};
+  for (int k = 0; k < 3; ++k)
+    for (int g = 0; g < Tab<P>::NG; ++g)
+      for (int m = 0; m < Tab<P>::NP; ++m) t.v[k][g][m] = B<P>::EG(k, g, m);
+  return t;
+}
+
+// trace of the modes w at Gauss point G of local edge k (k may be a runtime
+// value: the three edges' basis values are selected)
+template <typename Real, int P, int G>
+DG_DEV Real trace_modal(const Real (&w)[Tab<P>::NP], int k) {
+  constexpr EdgeTable<P> T = make_edge_table<P>();
+  Real s = Real(0);
+#pragma unroll
+  for (int m = 0; m < Tab<P>::NP; ++m) {
+    const Real c = k == 0 ? Real(T.v[0][G][m]) : k == 1 ? Real(T.v[1][G][m]) : Real(T.v[2][G][m]);
+    s += c * w[m];
+  }
+  return s;
+}
+
 // trace along an edge from its start-vertex value a, midpoint value c
-// (p = 2) and end-vertex value b, at the edge's Gauss point g
+// (p = 2) and end-vertex value b, at the edge's Gauss point g (p <= 2: the
+// trace is the 1-D interpolant of those point values)
 template <typename Real, int P>
 DG_DEV Real trace(Real a, Real c, Real b, int g) {
+  static_assert(P <= 2, "point-value traces are exact for p <= 2 only");
   const double t = gl_t(P, g);
   if (P == 1) return Real(lag_(1, 0, t)) * a + Real(lag_(1, 1, t)) * b;
   return Real(lag_(2, 0, t)) * a + Real(lag_(2, 1, t)) * c + Real(lag_(2, 2, t)) * b;
@@ -159,7 +202,7 @@ DG_DEV Real trace(Real a, Real c, Real b, int g) {
 // Positive-depth operator (Sec. 2.4) on one element, FP64 decisions.
 // Returns the dry flag; hv/qxv/qyv receive the final vertex depths and
 // discharges (for the CFL speed).
-// True when every vertex (and, for p = 2, edge-midpoint) depth is above the
+// True when every vertex (and, for p >= 2, edge-midpoint) depth is above the
 // dry margin by more than the rounding error of evaluating it in Real: then
 // the exact FP64 tests below would find the element fully wet and leave it
 // unchanged, so they can be skipped.
@@ -174,10 +217,10 @@ DG_DEV bool surely_wet(const Real (&w)[3][Tab<P>::NP], const Real (&hb)[3], doub
 #pragma unroll
     for (int m = 0; m < NP; ++m) {
       s += Real(B<P>::V(i, m)) * w[0][m];
-      if (P == 2) t += Real(B<P>::M(i, m)) * w[0][m];
+      if (P >= 2) t += Real(B<P>::M(i, m)) * w[0][m];
     }
     ok &= (s + hb[i]) > Real(Hd) + rel * (dabs(s) + dabs(hb[i]) + Real(1));
-    if (P == 2) {
+    if (P >= 2) {
       const Real hm = Real(0.5) * (hb[i] + hb[(i + 1) % 3]);
       ok &= (t + hm) > Real(Hd) + rel * (dabs(t) + dabs(hm) + Real(1));
     }
@@ -215,7 +258,7 @@ DG_DEV bool positive_depth(Real (&w)[3][Tab<P>::NP], const Real (&hb)[3], double
     qyv[i] = c;
     hv[i] = s + double(hb[i]);
   }
-  if (P == 2) {
+  if (P >= 2) {
     // any vertex or edge-midpoint depth <= H0: keep only the linear part
     bool low = (hv[0] <= Hd) | (hv[1] <= Hd) | (hv[2] <= Hd);
 #pragma unroll
@@ -518,28 +561,42 @@ constexpr AreaTable<Real, P> make_area_table() {
 }
 __constant__ AreaTable<float, 2> c_area2f = make_area_table<float, 2>();
 __constant__ AreaTable<double, 2> c_area2d = make_area_table<double, 2>();
+__constant__ AreaTable<float, 3> c_area3f = make_area_table<float, 3>();
+__constant__ AreaTable<double, 3> c_area3d = make_area_table<double, 3>();
 
-// p = 2 area integrals: one quadrature point per loop trip with the table
-// above (the unrolled form keeps far more registers live than the 18
+template <typename Real, int P>
+DG_DEV const AreaTable<Real, P>& area_table() {
+  static_assert(P == 2 || P == 3, "tables for p = 2 and 3");
+  if constexpr (P == 2)
+    return *reinterpret_cast<const AreaTable<Real, 2>*>(
+        sizeof(Real) == 4 ? static_cast<const void*>(&c_area2f) : static_cast<const void*>(&c_area2d));
+  else
+    return *reinterpret_cast<const AreaTable<Real, 3>*>(
+        sizeof(Real) == 4 ? static_cast<const void*>(&c_area3f) : static_cast<const void*>(&c_area3d));
+}
+
+// p >= 2 area integrals: one quadrature point per loop trip with the table
+// above (the unrolled form keeps far more registers live than the 3 Np
 // accumulators need).  Per point the fluxes are mapped once to the
 // reference directions, Gr = w (cx0 Fx + cy0 Fy), Gs = w (cx1 Fx + cy1 Fy),
 // then every mode takes dphi/dr Gr + dphi/ds Gs.
-template <typename Real>
-DG_DEV void area_terms_p2(const Real (&w)[3][6], const Real (&hb)[3], Real cx0, Real cx1, Real cy0, Real cy1,
-                          Real detJ, Real idet, Real fc, int friction, Real g, Real H0, Real (&acc)[3][6]) {
-  const AreaTable<Real, 2>& T = *reinterpret_cast<const AreaTable<Real, 2>*>(
-      sizeof(Real) == 4 ? static_cast<const void*>(&c_area2f) : static_cast<const void*>(&c_area2d));
+template <typename Real, int P>
+DG_DEV void area_terms_table(const Real (&w)[3][Tab<P>::NP], const Real (&hb)[3], Real cx0, Real cx1, Real cy0,
+                             Real cy1, Real detJ, Real idet, Real fc, int friction, Real g, Real H0,
+                             Real (&acc)[3][Tab<P>::NP]) {
+  constexpr int NP = Tab<P>::NP;
+  const AreaTable<Real, P>& T = area_table<Real, P>();
   const Real dhr = Real(0.5) * (hb[1] - hb[0]), dhs = Real(0.5) * (hb[2] - hb[0]);
   const Real dhx = (cx0 * dhr + cx1 * dhs) * idet, dhy = (cy0 * dhr + cy1 * dhs) * idet;
   const Real gn2 = g * fc * fc;
 #pragma unroll 1
-  for (int q = 0; q < 9; ++q) {
+  for (int q = 0; q < Tab<P>::NQ; ++q) {
     Real wq[3];
 #pragma unroll
     for (int v = 0; v < 3; ++v) {
       Real s = Real(0);
 #pragma unroll
-      for (int m = 0; m < 6; ++m) s += T.Q[q][m] * w[v][m];
+      for (int m = 0; m < NP; ++m) s += T.Q[q][m] * w[v][m];
       wq[v] = s;
     }
     const Real hq = T.L[q][0] * hb[0] + T.L[q][1] * hb[1] + T.L[q][2] * hb[2];
@@ -571,7 +628,7 @@ DG_DEV void area_terms_p2(const Real (&w)[3][6], const Real (&hb)[3], Real cx0, 
       Gs[v] = Wq * (cx1 * Fx[v] + cy1 * Fy[v]);
     }
 #pragma unroll
-    for (int m = 0; m < 6; ++m) {
+    for (int m = 0; m < NP; ++m) {
       if (m > 0) {
         const Real dr = T.QR[q][m], ds = T.QS[q][m];
 #pragma unroll
@@ -587,8 +644,8 @@ DG_DEV void area_terms_p2(const Real (&w)[3][6], const Real (&hb)[3], Real cx0, 
 template <typename Real, int P>
 DG_DEV void area_terms(const Real (&w)[3][Tab<P>::NP], const Real (&hb)[3], Real cx0, Real cx1, Real cy0, Real cy1,
                        Real detJ, Real idet, Real fc, int friction, Real g, Real H0, Real (&acc)[3][Tab<P>::NP]) {
-  if constexpr (P == 2)
-    area_terms_p2<Real>(w, hb, cx0, cx1, cy0, cy1, detJ, idet, fc, friction, g, H0, acc);
+  if constexpr (P >= 2)
+    area_terms_table<Real, P>(w, hb, cx0, cx1, cy0, cy1, detJ, idet, fc, friction, g, H0, acc);
   else
     area_terms_unrolled<Real, P>(w, hb, cx0, cx1, cy0, cy1, detJ, idet, fc, friction, g, H0, acc);
 }
@@ -626,11 +683,10 @@ DG_DEV void met_terms(const Member<Real>& M, int E, int ec, const Real (&w)[3][T
       acc[2][m] += c * s2;
     }
   };
-  if constexpr (P == 2) {
-    const AreaTable<Real, 2>& T = *reinterpret_cast<const AreaTable<Real, 2>*>(
-        sizeof(Real) == 4 ? static_cast<const void*>(&c_area2f) : static_cast<const void*>(&c_area2d));
+  if constexpr (P >= 2) {
+    const AreaTable<Real, P>& T = area_table<Real, P>();
 #pragma unroll 1
-    for (int q = 0; q < Tab<2>::NQ; ++q) {
+    for (int q = 0; q < Tab<P>::NQ; ++q) {
       Real zq = Real(0);
 #pragma unroll
       for (int m = 0; m < NP; ++m) zq += T.Q[q][m] * w[0][m];
@@ -694,7 +750,8 @@ DG_DEV void load_blend(const Member<Real>& M, const StageArgs& A, int E, int ec,
 }
 
 // Inverse mass, SSP combination, positive-depth operator (LIM = 0) or the
-// fully-wet byte (LIM = 1), stores, and the tile partials.
+// fully-wet byte (LIM = 1), stores, and the tile partials (lds: 4 x 6
+// doubles of the caller's shared memory).
 template <typename Real, int P, int LIM>
 DG_DEV void finish_stage(const Member<Real>& M, const StageArgs& A, int tile, int e, int ec, bool valid, int E,
                          Real (&w)[3][Tab<P>::NP], Real (&acc)[3][Tab<P>::NP], const Real (&hb)[3], const Real (&ex)[3],
@@ -828,7 +885,7 @@ template <typename Real, int P, int FLUX, int LIM>
 __global__ DG_STAGE_ATTR void stage_kernel(const Member<Real>* __restrict__ mem,
                                                      const Tile* __restrict__ tiles, int n_tiles, StageArgs A) {
   constexpr int NP = Tab<P>::NP, NG = Tab<P>::NG;
-  __shared__ double lds[4 * 5];
+  __shared__ double lds[4 * 6];                        // finish_stage: six sums per wavefront
   const int ti = xcd_tile();
   if (ti >= n_tiles) return;
   const Tile tl = tiles[ti];
@@ -858,9 +915,11 @@ __global__ DG_STAGE_ATTR void stage_kernel(const Member<Real>* __restrict__ mem,
   Real vv[3][3], mv[3][3];
   edge_nodes<Real, P>(d.w, vv, mv);
   double bout = 0.0, bin = 0.0;
-#pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    const int k1 = (k + 1) % 3;
+  // edges and Gauss points are expanded at compile time, so every basis
+  // value below is a constant (p = 3 bodies are too large for the unroller)
+  static_for<3>([&](auto kc) {
+    constexpr int k = decltype(kc)::value;
+    constexpr int k1 = (k + 1) % 3;
     Real ell, il;
     edge_length<Real>(d.ex[k], d.ey[k], ell, il);
     const Real nx = d.ey[k] * il, ny = -d.ex[k] * il;
@@ -891,13 +950,26 @@ __global__ DG_STAGE_ATTR void stage_kernel(const Member<Real>* __restrict__ mem,
       const Real hLa = meL ? d.hb[k] : d.hb[k1], hLb = meL ? d.hb[k1] : d.hb[k];
       const Real lnx = meL ? nx : -nx, lny = meL ? ny : -ny;
       const bool dryL = meL ? myflag : nflag, dryR = meL ? nflag : myflag;
+      static_for<NG>([&](auto gc) {
+        constexpr int gL = decltype(gc)::value;
+        constexpr int gR = NG - 1 - gL;
+        W3<Real> a, b;
+        if constexpr (P <= 2) {
+          a = {trace<Real, P>(La[0], Lc[0], Lb[0], gL), trace<Real, P>(La[1], Lc[1], Lb[1], gL),
+               trace<Real, P>(La[2], Lc[2], Lb[2], gL)};
+          b = {trace<Real, P>(Ra[0], Rc[0], Rb[0], gR), trace<Real, P>(Ra[1], Rc[1], Rb[1], gR),
+               trace<Real, P>(Ra[2], Rc[2], Rb[2], gR)};
+        } else {
+          // cubic traces come from the modes (L side at gL, R side at gR)
+          Real tL[3], tR[3];
 #pragma unroll
-      for (int gL = 0; gL < NG; ++gL) {
-        const int gR = NG - 1 - gL;
-        W3<Real> a{trace<Real, P>(La[0], Lc[0], Lb[0], gL), trace<Real, P>(La[1], Lc[1], Lb[1], gL),
-                   trace<Real, P>(La[2], Lc[2], Lb[2], gL)};
-        W3<Real> b{trace<Real, P>(Ra[0], Rc[0], Rb[0], gR), trace<Real, P>(Ra[1], Rc[1], Rb[1], gR),
-                   trace<Real, P>(Ra[2], Rc[2], Rb[2], gR)};
+          for (int v = 0; v < 3; ++v) {
+            tL[v] = meL ? trace_modal<Real, P, gL>(d.w[v], k) : trace_modal<Real, P, gL>(wn[v], kn);
+            tR[v] = meL ? trace_modal<Real, P, gR>(wn[v], kn) : trace_modal<Real, P, gR>(d.w[v], k);
+          }
+          a = {tL[0], tL[1], tL[2]};
+          b = {tR[0], tR[1], tR[2]};
+        }
         const Real hg = Real(lag_(1, 0, gl_t(P, gL))) * hLa + Real(lag_(1, 1, gl_t(P, gL))) * hLb;
         Real FL[3], FR[3];
         interior_point<FLUX>(a, b, hg, lnx, lny, g, H0, feps, dryL, dryR, meL, !meL, FL, FR);
@@ -910,17 +982,21 @@ __global__ DG_STAGE_ATTR void stage_kernel(const Member<Real>* __restrict__ mem,
           acc[1][m] -= c * (meL ? FL[1] : FR[1]);
           acc[2][m] -= c * (meL ? FL[2] : FR[2]);
         }
-      }
+      });
     } else {
       const int code = -1 - nb;
       const int type = code & 3, slot = code >> 2;
       const Real tide = Real(sc->tide[A.stage][slot]), qr = Real(sc->river[A.stage][slot]);
       double fm = 0.0;
-#pragma unroll
-      for (int gi = 0; gi < NG; ++gi) {
-        W3<Real> a{trace<Real, P>(vv[0][k], mv[0][k], vv[0][k1], gi),
-                   trace<Real, P>(vv[1][k], mv[1][k], vv[1][k1], gi),
-                   trace<Real, P>(vv[2][k], mv[2][k], vv[2][k1], gi)};
+      static_for<NG>([&](auto gc) {
+        constexpr int gi = decltype(gc)::value;
+        W3<Real> a;
+        if constexpr (P <= 2)
+          a = {trace<Real, P>(vv[0][k], mv[0][k], vv[0][k1], gi), trace<Real, P>(vv[1][k], mv[1][k], vv[1][k1], gi),
+               trace<Real, P>(vv[2][k], mv[2][k], vv[2][k1], gi)};
+        else
+          a = {trace_modal<Real, P, gi>(d.w[0], k), trace_modal<Real, P, gi>(d.w[1], k),
+               trace_modal<Real, P, gi>(d.w[2], k)};
         const Real hg = Real(lag_(1, 0, gl_t(P, gi))) * d.hb[k] + Real(lag_(1, 1, gl_t(P, gi))) * d.hb[k1];
         Real F[3];
         boundary_point<FLUX>(a, hg, nx, ny, g, H0, type, tide, qr, F);
@@ -933,10 +1009,10 @@ __global__ DG_STAGE_ATTR void stage_kernel(const Member<Real>* __restrict__ mem,
           acc[1][m] -= c * F[1];
           acc[2][m] -= c * F[2];
         }
-      }
+      });
       if (fm > 0.0) bout += fm; else bin -= fm;
     }
-  }
+  });
   area_terms<Real, P>(d.w, d.hb, d.cx0, d.cx1, d.cy0, d.cy1, d.detJ, d.idet, gp(M.fric)[ec], M.friction, g, H0, acc);
   if (M.fo.met_kind != MET_NONE)
     met_terms<Real, P>(M, E, ec, d.w, d.hb, d.cx0, d.cx1, d.cy0, d.cy1, d.detJ, d.idet, g, acc);
@@ -1795,6 +1871,17 @@ hipError_t launch_stage(int P, int flux, int limiter, int variant, const Member<
   DG_STAGE(1, 0, 0) DG_STAGE(1, 1, 0) DG_STAGE(1, 0, 1) DG_STAGE(1, 1, 1)
   DG_STAGE(2, 0, 0) DG_STAGE(2, 1, 0) DG_STAGE(2, 0, 1) DG_STAGE(2, 1, 1)
 #undef DG_STAGE
+  // p = 3: the per-element kernel only (the per-edge kernel's LDS staging of
+  // point values is written for traces of degree <= 2)
+#define DG_STAGE3(FF, LL) \
+  if (P == 3 && flux == FF && limiter == LL) { \
+    if (variant != 0) return hipErrorInvalidValue; \
+    if (timed) hipExtLaunchKernelGGL((stage_kernel<Real, 3, FF, LL>), grid, block, 0, s, ev0, ev1, 0, m, t, n, a); \
+    else hipLaunchKernelGGL((stage_kernel<Real, 3, FF, LL>), grid, block, 0, s, m, t, n, a); \
+    return hipGetLastError(); \
+  }
+  DG_STAGE3(0, 0) DG_STAGE3(1, 0) DG_STAGE3(0, 1) DG_STAGE3(1, 1)
+#undef DG_STAGE3
   return hipErrorInvalidValue;
 }
 
@@ -1805,6 +1892,7 @@ hipError_t launch_post(int P, int use_lim, const Member<Real>* m, const Tile* t,
   dim3 grid(xcd_grid(n)), block(TILE);
   if (P == 1) hipLaunchKernelGGL((post_kernel<Real, 1>), grid, block, 0, s, m, t, n, a, init, use_lim);
   else if (P == 2) hipLaunchKernelGGL((post_kernel<Real, 2>), grid, block, 0, s, m, t, n, a, init, use_lim);
+  else if (P == 3) hipLaunchKernelGGL((post_kernel<Real, 3>), grid, block, 0, s, m, t, n, a, init, use_lim);
   else return hipErrorInvalidValue;
   return hipGetLastError();
 }
@@ -1814,7 +1902,8 @@ hipError_t launch_classify(int P, const Member<Real>* m, const Tile* t, int n, h
   if (n <= 0) return hipSuccess;
   dim3 grid(xcd_grid(n)), block(TILE);
   if (P == 1) hipLaunchKernelGGL((classify_kernel<Real, 1>), grid, block, 0, s, m, t, n);
-  else hipLaunchKernelGGL((classify_kernel<Real, 2>), grid, block, 0, s, m, t, n);
+  else if (P == 2) hipLaunchKernelGGL((classify_kernel<Real, 2>), grid, block, 0, s, m, t, n);
+  else hipLaunchKernelGGL((classify_kernel<Real, 3>), grid, block, 0, s, m, t, n);
   return hipGetLastError();
 }
 

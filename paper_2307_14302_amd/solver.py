@@ -57,7 +57,7 @@ class Solver:
     def __init__(self, params: Dict[str, object], stream=None):
         self.params = dict(params)
         self._p = params_from_dict(self.params)
-        self.np = 3 if self._p.p == 1 else 6
+        self.np = (self._p.p + 1) * (self._p.p + 2) // 2
         h = C.c_void_p()
         call("dgswe_create", C.byref(self._p), _stream_handle(stream), C.byref(h))
         self.h = h

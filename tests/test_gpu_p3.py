@@ -1,0 +1,127 @@
+"""Cubic elements (p = 3, ten Dubiner modes, collapsed 4 x 4 area rule, four
+Gauss points per edge, SSP(3,3) at CFL 0.1: the generators' default) on the GPU against the oracle.
+
+* small mixed basins (every boundary type, wet/dry fronts; Roe with gridded
+  rain, LLF with the limiter and parametric rain, and with a storm's wind
+  and pressure): one step to 1e-12, fifty steps to 1e-10 (FP64), flags and
+  budgets equal;
+* a closed wet basin under a moving storm in FP32 to 1e-4;
+* lake at rest stays at rest;
+* the per-edge kernel is refused for p = 3 and the autotuner keeps the
+  per-element one;
+* a 20,000-triangle window of the benchmark basin: one step from a GPU
+  state, every element against the oracle.
+"""
+import numpy as np
+import pytest
+
+import meshgen
+from meshgen.generators import Mesh, Scenario, _bnd, default_params, rect_grid
+from oracle.solver import from_scenario
+from tests.parity import rel_l2
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dg():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2307_14302_amd as pkg
+    return pkg
+
+
+CASES = {
+    "roe_gridded": dict(flux="roe", limiter=False, rain_kind="gridded"),
+    "llf_param_lim": dict(flux="llf", limiter=True, rain_kind="parametric"),
+    "llf_lim_storm": dict(flux="llf", limiter=True, rain_kind="parametric", wind=True),
+}
+
+
+def _mixed(case, **kw):
+    return meshgen.small_mixed(seed=5, nx=20, ny=10, p=3, **CASES[case], **kw)
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_p3_parity_fp64(dg, case):
+    sc = _mixed(case)
+    print(f"p=3 case {case}: E={sc.mesh.n_tri}", flush=True)
+    gpu = dg.Solver.from_scenario(sc, precision="fp64")
+    assert gpu.variant() == 0
+    orc = from_scenario(sc)
+    e0 = rel_l2(gpu.state("modal"), orc.w, orc)
+    assert e0.max() < 1e-13, e0
+    gpu.step(1)
+    orc.step(1)
+    e1 = rel_l2(gpu.state("modal"), orc.w, orc)
+    assert e1.max() < 1e-12, e1
+    gpu.step(49)
+    orc.step(49)
+    err = rel_l2(gpu.state("modal"), orc.w, orc)
+    print(case, "rel L2 after 50 steps", err, flush=True)
+    assert err.max() < 1e-10, err
+    np.testing.assert_array_equal(gpu.flags().astype(bool), orc.flags)
+    mg, mo = gpu.mass(), orc.mass_totals()
+    for k in ("t", "volume", "rain_in", "bnd_in", "bnd_out"):
+        assert abs(mg[k] - mo[k]) <= 1e-10 * max(1.0, abs(mo[k])), (k, mg[k], mo[k])
+    gpu.close()
+
+
+def test_p3_closed_basin_storm_fp32(dg):
+    rec = [[0.0, 20e3, 40e3, 5000.0, 15e3, 1.4, 1.0, 2.0, 1.0],
+           [4.0e3, 60e3, 40e3, 5000.0, 15e3, 1.4, 1.0, 2.0, 1.0]]
+    xy, tri, sides = rect_grid(24, 24, 80e3, 80e3, jitter=0.15, rng=np.random.default_rng(5), diagonal="short")
+    hb = 15.0 + 5.0 * np.sin(xy[:, 0] / 2e4) * np.cos(xy[:, 1] / 3e4)
+    be, bt, bs = _bnd(sides, {})
+    z = np.zeros(len(hb))
+    sc = Scenario("closed_p3", Mesh(xy, tri, hb, np.full(len(hb), 0.025), be, bt, bs), z, z.copy(), z.copy(),
+                  default_params(p=3, flux="roe", friction="manning", H0=0.01), met=np.asarray(rec))
+    gpu = dg.Solver.from_scenario(sc, precision="fp32")
+    orc = from_scenario(sc)
+    gpu.step(100)
+    orc.step(100)
+    err = rel_l2(gpu.state("modal"), orc.w, orc)
+    print("p=3 closed basin FP32 rel L2", err, flush=True)
+    assert np.abs(orc.w[:, 1:, 0]).max() > 1e-2
+    assert err.max() < 1e-4, err
+    gpu.close()
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-11), ("fp32", 1e-4)])
+def test_p3_lake_at_rest(dg, precision, tol):
+    sc = meshgen.lake_at_rest(p=3)
+    gpu = dg.Solver.from_scenario(sc, precision=precision)
+    gpu.step(50)
+    v = gpu.state("vertex")
+    assert np.abs(v[:, 1:]).max() < tol
+    assert np.abs(v[:, 0] - 0.7).max() < tol
+    gpu.close()
+
+
+def test_p3_kernel_choice(dg):
+    from paper_2307_14302_amd import _native as N
+    sc = _mixed("roe_gridded")
+    s = dg.Solver.from_scenario(sc)
+    with pytest.raises(N.DgsweError, match="p <= 2"):
+        s.set_variant(1)
+    v, ms = s.autotune(2)
+    assert v == 0 and ms[0] > 0.0 and ms[1] == 0.0
+    s.close()
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-11), ("fp32", 5e-5)])
+def test_p3_basin_window_one_step(dg, precision, tol):
+    sc = meshgen.basin_window(100, p=3)
+    gpu = dg.Solver.from_scenario(sc, precision=precision)
+    gpu.step(10)
+    w = gpu.state()
+    m0 = gpu.mass()
+    orc = from_scenario(sc)
+    orc.set_state(w, m0["t"], post=False)
+    orc.dt = m0["dt_next"]
+    gpu.step(1)
+    orc.step(1)
+    err = rel_l2(gpu.state(), orc.w, orc)
+    print(precision, "p=3 basin window one-step rel L2", err, flush=True)
+    assert err.max() < tol, err
+    gpu.close()
