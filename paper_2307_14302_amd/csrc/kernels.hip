@@ -1067,6 +1067,26 @@ __global__ DG_STAGE_ATTR void stage_edge_kernel(const Member<Real>* __restrict__
   // ---- phase A: own data, point values to LDS, owned-edge list, area terms
   ElemData<Real, P> d;
   load_elem<Real, P>(M, Win, E, ec, d);
+  // neighbour ids, their edge codes, the dry flag and the friction are read
+  // together with the element's own data, so phase A waits for memory once
+  int nbv[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) nbv[k] = nbr[k * E + ec];
+  const int nkp = gp(M.nk)[ec];
+  const uint8_t fin = Fin[ec];
+  const Real fric = gp(M.fric)[ec];
+  // element rain (Eq. rain): the first stage of a step with time-dependent
+  // rain averages the nodal rates of t^n (node ids now, rates before phase
+  // B, the mean at the end); later stages read the stored value
+  // (the stored value is read in both cases: a load in one branch only would
+  // make the other wait for every load in flight before reusing its register)
+  const bool rain_avg = A.stage == 0 && M.fo.rain_kind != RAIN_CONST;
+  Real Rv = gp(M.R)[ec];
+  int tn[3] = {0, 0, 0};
+  if (rain_avg) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) tn[i] = gp(M.tri)[i * E + ec];
+  }
   {
     Real vv[3][3], mv[3][3];
     edge_nodes<Real, P>(d.w, vv, mv);
@@ -1084,10 +1104,7 @@ __global__ DG_STAGE_ATTR void stage_edge_kernel(const Member<Real>* __restrict__
     s_ev[2 * k][el] = d.ex[k];
     s_ev[2 * k + 1][el] = d.ey[k];
   }
-  s_flag[el] = Fin[ec] & 1;
-  const int nkp = gp(M.nk)[ec];
-  double rain_part;
-  const Real Rv = element_rain<Real>(M, A, E, e, ec, valid, d.ex, d.ey, rain_part);
+  s_flag[el] = fin & 1;
   // The edges this element evaluates, in three classes listed one after the
   // other so that a wavefront mostly runs one code path: (0) interior edges
   // inside the tile, owned by the lower id; (1) edges to other tiles;
@@ -1097,7 +1114,7 @@ __global__ DG_STAGE_ATTR void stage_edge_kernel(const Member<Real>* __restrict__
   int packed = 0;                                    // 10-bit count per class
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    const int nb = nbr[k * E + ec];
+    const int nb = nbv[k];
     const int kn = (nkp >> (2 * k)) & 3;
     const bool inside = nb >= t0 && nb < tend;
     cls[k] = !valid ? 3 : nb < 0 ? 2 : !inside ? 1 : (e < nb ? 0 : 3);
@@ -1113,7 +1130,7 @@ __global__ DG_STAGE_ATTR void stage_edge_kernel(const Member<Real>* __restrict__
   for (int v = 0; v < 3; ++v)
 #pragma unroll
     for (int m = 0; m < NP; ++m) acc[v][m] = Real(0);
-  area_terms<Real, P>(d.w, d.hb, d.cx0, d.cx1, d.cy0, d.cy1, d.detJ, d.idet, gp(M.fric)[ec], M.friction, g, H0, acc);
+  area_terms<Real, P>(d.w, d.hb, d.cx0, d.cx1, d.cy0, d.cy1, d.detJ, d.idet, fric, M.friction, g, H0, acc);
   if (M.fo.met_kind != MET_NONE)
     met_terms<Real, P>(M, E, ec, d.w, d.hb, d.cx0, d.cx1, d.cy0, d.cy1, d.detJ, d.idet, g, acc);
   __syncthreads();
@@ -1136,6 +1153,13 @@ __global__ DG_STAGE_ATTR void stage_edge_kernel(const Member<Real>* __restrict__
     }
   }
   __syncthreads();
+
+  // nodal rain rates, consumed after phase B
+  double rn3[3] = {0.0, 0.0, 0.0};
+  if (rain_avg) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) rn3[i] = gp(M.rn)[tn[i]];
+  }
 
   // ---- phase B: edge fluxes, scaled by (l/2) w_g, into s_flux
   double bout = 0.0, bin = 0.0;
@@ -1259,6 +1283,13 @@ __global__ DG_STAGE_ATTR void stage_edge_kernel(const Member<Real>* __restrict__
         acc[2][m] -= ph * f2;
       }
     }
+  double rain_part = 0.0;
+  if (rain_avg) {
+    Rv = Real((rn3[0] + rn3[1] + rn3[2]) / 3.0);
+    if (valid) gp(M.R)[e] = Rv;
+    const double area = 0.5 * (double(d.ex[2]) * double(d.ey[0]) - double(d.ex[0]) * double(d.ey[2]));
+    rain_part = valid ? area * double(Rv) : 0.0;
+  }
   finish_stage<Real, P, LIM>(M, A, tl.tile, e, ec, valid, E, d.w, acc, d.hb, d.ex, d.ey, d.detJ, d.idet, dt, bout,
                              bin, Rv, rain_part, s_lbuf, w0v);
 }
