@@ -349,7 +349,7 @@ StageArgs stage_args(const RKTable& T, int i) {
 template <typename Real>
 int enqueue_step_group(const Member<Real>* d_m, const Tile* d_t, int n_tiles, const Tile* d_nt, int n_node_tiles,
                        const int* d_ids, int n_members, int max_chunks, int p, int flux, int limiter, int variant,
-                       const RKTable& T, bool node_forcing, hipStream_t s, dgswe_ctx* prof) {
+                       const RKTable& T, bool node_forcing, hipStream_t s, dgswe_ctx* prof, bool single) {
   if (node_forcing) {
     ProfScope ps(prof, K_RAIN);
     // nodal rain rates, wind stress and pressure head at t^n; the first
@@ -358,6 +358,7 @@ int enqueue_step_group(const Member<Real>* d_m, const Tile* d_t, int n_tiles, co
   }
   for (int i = 0; i < T.n; ++i) {
     StageArgs a = stage_args(T, i);
+    a.single = single ? 1 : 0;
     if (limiter) {
       // the stage writes its raw output to the stage's buffer; the post
       // pass limits it there
@@ -382,10 +383,10 @@ int ctx_enqueue_step(dgswe_ctx* c) {
   if (c->rs == 8)
     return enqueue_step_group<double>(c->memb.as<Member<double>>(), c->tiles.as<Tile>(), c->n_tiles,
                                       c->node_tiles.as<Tile>(), c->n_node_tiles, c->ids.as<int>(), 1, red_chunks(c->n_tiles),
-                                      c->prm.p, c->prm.flux, c->prm.limiter, c->variant, c->rk, rain, c->stream, c);
+                                      c->prm.p, c->prm.flux, c->prm.limiter, c->variant, c->rk, rain, c->stream, c, true);
   return enqueue_step_group<float>(c->memb.as<Member<float>>(), c->tiles.as<Tile>(), c->n_tiles,
                                    c->node_tiles.as<Tile>(), c->n_node_tiles, c->ids.as<int>(), 1, red_chunks(c->n_tiles),
-                                   c->prm.p, c->prm.flux, c->prm.limiter, c->variant, c->rk, rain, c->stream, c);
+                                   c->prm.p, c->prm.flux, c->prm.limiter, c->variant, c->rk, rain, c->stream, c, true);
 }
 
 int ctx_reduce_init(dgswe_ctx* c) {
@@ -1267,12 +1268,12 @@ static int batch_enqueue_step(dgswe_batch* b) {
       rc = enqueue_step_group<float>(b->memb.as<Member<float>>(), g.tiles.as<Tile>(), g.n_tiles,
                                      g.node_tiles.as<Tile>(), g.n_node_tiles, g.ids.as<int>(),
                                      int(g.members.size()), g.max_chunks, g.p, g.flux, g.limiter, g.variant, g.rk,
-                                     g.node_forcing, b->stream, nullptr);
+                                     g.node_forcing, b->stream, nullptr, false);
     else
       rc = enqueue_step_group<double>(b->memb.as<Member<double>>(), g.tiles.as<Tile>(), g.n_tiles,
                                       g.node_tiles.as<Tile>(), g.n_node_tiles, g.ids.as<int>(),
                                       int(g.members.size()), g.max_chunks, g.p, g.flux, g.limiter, g.variant, g.rk,
-                                      g.node_forcing, b->stream, nullptr);
+                                      g.node_forcing, b->stream, nullptr, false);
     if (rc) return rc;
   }
   return DGSWE_OK;

@@ -103,6 +103,7 @@ struct StageArgs {
   int in_buf, out_buf;        // state buffer indices
   int fin, fout;              // flag buffer indices
   double a, b, gam;           // w_out = a w^n + b (w_in + gam dt L(w_in))
+  int single;                 // 1: one member, tile i of the launch is tile i of member 0
 };
 
 struct Tile { int member, tile; };

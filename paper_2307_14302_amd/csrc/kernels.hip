@@ -888,7 +888,7 @@ __global__ DG_STAGE_ATTR void stage_kernel(const Member<Real>* __restrict__ mem,
   __shared__ double lds[4 * 6];                        // finish_stage: six sums per wavefront
   const int ti = xcd_tile();
   if (ti >= n_tiles) return;
-  const Tile tl = tiles[ti];
+  const Tile tl = A.single ? Tile{0, ti} : tiles[ti];
   const Member<Real>& M = mem[tl.member];
   const DG_G Scalars* __restrict__ sc = gp((const Scalars*)M.sc);
   if (!sc->active) return;
@@ -1046,7 +1046,7 @@ __global__ DG_STAGE_ATTR void stage_edge_kernel(const Member<Real>* __restrict__
   __shared__ int s_wsum[4];
   const int ti = xcd_tile();
   if (ti >= n_tiles) return;
-  const Tile tl = tiles[ti];
+  const Tile tl = A.single ? Tile{0, ti} : tiles[ti];
   const Member<Real>& M = mem[tl.member];
   const DG_G Scalars* __restrict__ sc = gp((const Scalars*)M.sc);
   if (!sc->active) return;
@@ -1315,7 +1315,7 @@ __global__ __launch_bounds__(TILE) void post_kernel(const Member<Real>* __restri
   __shared__ double lds[4 * 5];
   const int ti = xcd_tile();
   if (ti >= n_tiles) return;
-  const Tile tl = tiles[ti];
+  const Tile tl = A.single ? Tile{0, ti} : tiles[ti];
   const Member<Real>& M = mem[tl.member];
   const DG_G Scalars* __restrict__ sc = gp((const Scalars*)M.sc);
   if (!sc->active && init == 0) return;
