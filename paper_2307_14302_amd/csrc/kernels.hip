@@ -915,6 +915,26 @@ __global__ DG_STAGE_ATTR void stage_kernel(const Member<Real>* __restrict__ mem,
   Real vv[3][3], mv[3][3];
   edge_nodes<Real, P>(d.w, vv, mv);
   double bout = 0.0, bin = 0.0;
+  // Neighbour ids, then (where registers allow) the three neighbours' modes
+  // and flags, are read together, so the edges wait for memory once rather
+  // than once each.  A boundary edge reads the element itself (unused).
+  constexpr bool kHoist = P == 1 || (P == 2 && sizeof(Real) == 4);
+  int nbv[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) nbv[k] = gp(M.nbr)[k * E + ec];
+  Real wnb[kHoist ? 3 : 1][3][NP];
+  bool nfl[3] = {false, false, false};
+  if constexpr (kHoist) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const int n = nbv[k] < 0 ? ec : nbv[k];
+#pragma unroll
+      for (int v = 0; v < 3; ++v)
+#pragma unroll
+        for (int m = 0; m < NP; ++m) wnb[k][v][m] = Win[(v * NP + m) * E + n];
+      nfl[k] = Fin[n] & 1;
+    }
+  }
   // edges and Gauss points are expanded at compile time, so every basis
   // value below is a constant (p = 3 bodies are too large for the unroller)
   static_for<3>([&](auto kc) {
@@ -924,15 +944,24 @@ __global__ DG_STAGE_ATTR void stage_kernel(const Member<Real>* __restrict__ mem,
     edge_length<Real>(d.ex[k], d.ey[k], ell, il);
     const Real nx = d.ey[k] * il, ny = -d.ex[k] * il;
     const Real half = Real(0.5) * ell;
-    const int nb = gp(M.nbr)[k * E + ec];
+    const int nb = nbv[k];
     if (nb >= 0) {
       const int kn = (nkp >> (2 * k)) & 3;
       Real wn[3][NP];
+      bool nflag;
+      if constexpr (kHoist) {
 #pragma unroll
-      for (int v = 0; v < 3; ++v)
+        for (int v = 0; v < 3; ++v)
 #pragma unroll
-        for (int m = 0; m < NP; ++m) wn[v][m] = Win[(v * NP + m) * E + nb];
-      const bool nflag = Fin[nb] & 1;
+          for (int m = 0; m < NP; ++m) wn[v][m] = wnb[k][v][m];
+        nflag = nfl[k];
+      } else {
+#pragma unroll
+        for (int v = 0; v < 3; ++v)
+#pragma unroll
+          for (int m = 0; m < NP; ++m) wn[v][m] = Win[(v * NP + m) * E + nb];
+        nflag = Fin[nb] & 1;
+      }
       Real nvv[3][3], nmv[3][3];
       edge_nodes<Real, P>(wn, nvv, nmv);
       const int kn1 = kn == 2 ? 0 : kn + 1;
