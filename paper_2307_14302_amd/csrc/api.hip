@@ -354,7 +354,7 @@ int enqueue_step_group(const Member<Real>* d_m, const Tile* d_t, int n_tiles, co
     ProfScope ps(prof, K_RAIN);
     // nodal rain rates, wind stress and pressure head at t^n; the first
     // stage averages the rain per element
-    HIPCHK(launch_rain<Real>(d_m, d_t, 0, 0, d_nt, n_node_tiles, s));
+    HIPCHK(launch_rain<Real>(d_m, d_t, 0, 0, d_nt, n_node_tiles, s, single ? 1 : 0));
   }
   for (int i = 0; i < T.n; ++i) {
     StageArgs a = stage_args(T, i);
@@ -374,7 +374,7 @@ int enqueue_step_group(const Member<Real>* d_m, const Tile* d_t, int n_tiles, co
     }
   }
   ProfScope ps(prof, K_REDUCE);
-  HIPCHK(launch_reduce<Real>(d_m, d_ids, n_members, max_chunks, 0, rk_info(T), s));
+  HIPCHK(launch_reduce<Real>(d_m, single ? nullptr : d_ids, n_members, max_chunks, 0, rk_info(T), s));
   return DGSWE_OK;
 }
 
@@ -391,10 +391,10 @@ int ctx_enqueue_step(dgswe_ctx* c) {
 
 int ctx_reduce_init(dgswe_ctx* c) {
   if (c->rs == 8)
-    HIPCHK(launch_reduce<double>(c->memb.as<Member<double>>(), c->ids.as<int>(), 1, red_chunks(c->n_tiles), 1,
+    HIPCHK(launch_reduce<double>(c->memb.as<Member<double>>(), nullptr, 1, red_chunks(c->n_tiles), 1,
                                  rk_info(c->rk), c->stream));
   else
-    HIPCHK(launch_reduce<float>(c->memb.as<Member<float>>(), c->ids.as<int>(), 1, red_chunks(c->n_tiles), 1,
+    HIPCHK(launch_reduce<float>(c->memb.as<Member<float>>(), nullptr, 1, red_chunks(c->n_tiles), 1,
                                 rk_info(c->rk), c->stream));
   return DGSWE_OK;
 }

@@ -131,9 +131,10 @@ hipError_t launch_classify(int P, const Member<Real>* d_members, const Tile* d_t
 // always = 1 only averages (constant nodal rain at set-up)
 template <typename Real>
 hipError_t launch_rain(const Member<Real>* d_members, const Tile* d_tiles, int n_tiles, int always,
-                       const Tile* d_node_tiles, int n_node_tiles, hipStream_t s);
+                       const Tile* d_node_tiles, int n_node_tiles, hipStream_t s,
+                       int single = 0);
 // grid: n_members x max_chunks workgroups (max_chunks = largest red_chunks
-// over the members)
+// over the members); d_member_ids == nullptr for a single context (member 0)
 template <typename Real>
 hipError_t launch_reduce(const Member<Real>* d_members, const int* d_member_ids, int n_members, int max_chunks,
                          int init, const RKInfo& rk, hipStream_t s);

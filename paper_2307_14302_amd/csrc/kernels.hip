@@ -1569,10 +1569,10 @@ DG_DEV void vortex_node(const DG_G Scalars* sc, double x, double y, double g, Re
 // Sec. 3.3 rain lattice) and the storm's wind stress and pressure head.
 template <typename Real>
 __global__ __launch_bounds__(TILE) void node_forcing_kernel(const Member<Real>* __restrict__ mem,
-                                                            const Tile* __restrict__ tiles, int n_tiles) {
+                                                            const Tile* __restrict__ tiles, int n_tiles, int single) {
   const int ti = xcd_tile();
   if (ti >= n_tiles) return;
-  const Tile tl = tiles[ti];
+  const Tile tl = single ? Tile{0, ti} : tiles[ti];
   const Member<Real>& M = mem[tl.member];
   const DG_G Scalars* __restrict__ sc = gp((const Scalars*)M.sc);
   const int kind = M.fo.rain_kind;
@@ -1677,7 +1677,8 @@ __global__ __launch_bounds__(RED_CHUNK) void reduce_kernel(const Member<Real>* _
   __shared__ double s_wind[9 * NTW];
   __shared__ double s_t, s_dt;
   __shared__ int s_last;
-  const Member<Real>& M = mem[ids[blockIdx.x]];
+  // ids == nullptr: a single context, member 0 (no id to read first)
+  const Member<Real>& M = mem[ids ? ids[blockIdx.x] : 0];
   DG_G Scalars* __restrict__ sc = gp(M.sc);
   const int nt = M.n_tiles;
   const int nch = red_chunks(nt);
@@ -1969,10 +1970,10 @@ hipError_t launch_classify(int P, const Member<Real>* m, const Tile* t, int n, h
 
 template <typename Real>
 hipError_t launch_rain(const Member<Real>* m, const Tile* t, int n, int always, const Tile* node_tiles, int n_node_tiles,
-                       hipStream_t s) {
+                       hipStream_t s, int single) {
   if (!always && node_tiles && n_node_tiles > 0)
     hipLaunchKernelGGL((node_forcing_kernel<Real>), dim3(xcd_grid(n_node_tiles)), dim3(TILE), 0, s, m, node_tiles,
-                       n_node_tiles);
+                       n_node_tiles, single);
   if (n > 0) hipLaunchKernelGGL((rain_kernel<Real>), dim3(xcd_grid(n)), dim3(TILE), 0, s, m, t, n, always);
   return hipGetLastError();
 }
@@ -1991,7 +1992,7 @@ hipError_t launch_reduce(const Member<Real>* m, const int* ids, int n_members, i
                                       hipEvent_t, hipEvent_t);                                              \
   template hipError_t launch_post<R>(int, int, const Member<R>*, const Tile*, int, StageArgs, int, hipStream_t);  \
   template hipError_t launch_classify<R>(int, const Member<R>*, const Tile*, int, hipStream_t);                   \
-  template hipError_t launch_rain<R>(const Member<R>*, const Tile*, int, int, const Tile*, int, hipStream_t);     \
+  template hipError_t launch_rain<R>(const Member<R>*, const Tile*, int, int, const Tile*, int, hipStream_t, int); \
   template hipError_t launch_reduce<R>(const Member<R>*, const int*, int, int, int, const RKInfo&, hipStream_t);
 DG_INST(float)
 DG_INST(double)
