@@ -659,6 +659,19 @@ int dgswe_upload_mesh(dgswe_ctx* c, int64_t n_nodes, const double* xy, const dou
   if (rc) return rc;
   if (c->mesh) return fail(DGSWE_ESTATE, "mesh already uploaded");
   if (n_bedges > 0 && !bedge_nodes) return fail(DGSWE_EINVAL, "null boundary edge array");
+  {
+    // the kernels address every array with 32-bit byte offsets: the largest
+    // per-element array is the modal state (3 Np values per element), the
+    // largest per-node one the storm forcing (3 values per node, at most 8
+    // bytes each)
+    const int64_t np = int64_t(c->prm.p + 1) * (c->prm.p + 2) / 2;
+    const int64_t lim = int64_t(1) << 32;
+    if (n_tri > 0 && 3 * np * n_tri * int64_t(c->rs) >= lim)
+      return fail(DGSWE_EINVAL, "mesh too large for one context: the modal state array would exceed 4 GiB (" +
+                                    std::to_string(lim / (3 * np * int64_t(c->rs))) + " triangles at most at this p and precision)");
+    if (n_nodes > 0 && 3 * n_nodes * 8 >= lim)
+      return fail(DGSWE_EINVAL, "mesh too large for one context: too many nodes for 32-bit array offsets");
+  }
   auto md = std::make_shared<MeshDev>();
   std::string err;
   if (build_mesh(n_nodes, xy, hb, fric, n_tri, tri, n_bedges, bedge_nodes, bedge_type, bedge_slot, md->host, err))

@@ -46,6 +46,38 @@ DG_DEV void static_for(F&& f) {
 template <typename T> DG_DEV DG_G T* gp(T* p) { return (DG_G T*)p; }
 template <typename T> DG_DEV const DG_G T* gp(const T* p) { return (const DG_G T*)p; }
 
+// Element- and node-indexed access through buffer instructions: the array's
+// base goes into a scalar resource descriptor, the column's offset into a
+// scalar offset and the lane's index into a 32-bit byte offset, so an access
+// costs no vector address arithmetic (global addressing forms a 64-bit
+// address per access) and a kernel keeps one descriptor per array.  The
+// element index must be valid (the descriptor's record count is the
+// maximum, so there is no range check) and every byte offset within an
+// array below 2^32; the library refuses meshes whose arrays would exceed it.
+// ldc(base, col, i) reads base[col + i] with col uniform over the wavefront.
+DG_DEV __amdgpu_buffer_rsrc_t rsrc(const void* p) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), 0, -1, 0x00020000);
+}
+typedef unsigned int dg_u2 __attribute__((ext_vector_type(2)));
+template <typename T> DG_DEV T ldc(const DG_G T* base, int col, int i) {
+  static_assert(sizeof(T) == 1 || sizeof(T) == 4 || sizeof(T) == 8, "1, 4 or 8 byte elements");
+  const uint32_t off = uint32_t(i) * uint32_t(sizeof(T)), so = uint32_t(col) * uint32_t(sizeof(T));
+  const __amdgpu_buffer_rsrc_t r = rsrc((const void*)base);
+  if constexpr (sizeof(T) == 1) return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b8(r, off, so, 0));
+  else if constexpr (sizeof(T) == 4) return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, off, so, 0));
+  else return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, off, so, 0));
+}
+template <typename T> DG_DEV T ldx(const DG_G T* base, int i) { return ldc(base, 0, i); }
+template <typename T> DG_DEV void stc(DG_G T* base, int col, int i, T v) {
+  static_assert(sizeof(T) == 1 || sizeof(T) == 4 || sizeof(T) == 8, "1, 4 or 8 byte elements");
+  const uint32_t off = uint32_t(i) * uint32_t(sizeof(T)), so = uint32_t(col) * uint32_t(sizeof(T));
+  const __amdgpu_buffer_rsrc_t r = rsrc((const void*)base);
+  if constexpr (sizeof(T) == 1) __builtin_amdgcn_raw_buffer_store_b8(__builtin_bit_cast(unsigned char, v), r, off, so, 0);
+  else if constexpr (sizeof(T) == 4) __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, off, so, 0);
+  else __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(dg_u2, v), r, off, so, 0);
+}
+template <typename T> DG_DEV void stx(DG_G T* base, int i, T v) { stc(base, 0, i, v); }
+
 // ------------------------------------------------------------ reductions
 // Wavefront reductions in a fixed order with DPP lane moves (VALU only; no
 // LDS traffic): within each 16-lane row, swap neighbours, swap pairs, rotate
@@ -665,10 +697,10 @@ DG_DEV void met_terms(const Member<Real>& M, int E, int ec, const Real (&w)[3][T
   Real tx[3], ty[3], ps[3];
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
-    const int n = tri[i * E + ec];
-    tx[i] = met[n];
-    ty[i] = met[nn + n];
-    ps[i] = met[2 * nn + n];
+    const int n = ldc(tri, i * E, ec);
+    tx[i] = ldx(met, n);
+    ty[i] = ldc(met, nn, n);
+    ps[i] = ldc(met, 2 * nn, n);
   }
   const Real pr = Real(0.5) * (ps[1] - ps[0]), pq = Real(0.5) * (ps[2] - ps[0]);
   const Real px = (cx0 * pr + cx1 * pq) * idet, py = (cy0 * pr + cy1 * pq) * idet;
@@ -719,15 +751,15 @@ DG_DEV Real element_rain(const Member<Real>& M, const StageArgs& A, int E, int e
   if (A.stage == 0 && M.fo.rain_kind != RAIN_CONST) {
     const DG_G double* __restrict__ rn = gp(M.rn);
     const DG_G int* __restrict__ tri = gp(M.tri);
-    const double r = (rn[tri[ec]] + rn[tri[E + ec]] + rn[tri[2 * E + ec]]) / 3.0;
+    const double r = (ldx(rn, ldx(tri, ec)) + ldx(rn, ldc(tri, E, ec)) + ldx(rn, ldc(tri, 2 * E, ec))) / 3.0;
     const Real R = Real(r);
-    if (valid) gp(M.R)[e] = R;
+    if (valid) stx(gp(M.R), e, R);
     const double area = 0.5 * (double(ex[2]) * double(ey[0]) - double(ex[0]) * double(ey[2]));
     part = valid ? area * double(R) : 0.0;
     return R;
   }
   part = 0.0;
-  return gp(M.R)[ec];
+  return ldx(gp(M.R), ec);
 }
 
 // w^n of the element when the stage blends it (a != 0), else zeros; loaded
@@ -740,7 +772,7 @@ DG_DEV void load_blend(const Member<Real>& M, const StageArgs& A, int E, int ec,
 #pragma unroll
     for (int v = 0; v < 3; ++v)
 #pragma unroll
-      for (int m = 0; m < NP; ++m) w0v[v][m] = W0[(v * NP + m) * E + ec];
+      for (int m = 0; m < NP; ++m) w0v[v][m] = ldc(W0, (v * NP + m) * E, ec);
   } else {
 #pragma unroll
     for (int v = 0; v < 3; ++v)
@@ -782,14 +814,14 @@ DG_DEV void finish_stage(const Member<Real>& M, const StageArgs& A, int tile, in
 #pragma unroll
       for (int v = 0; v < 3; ++v)
 #pragma unroll
-        for (int m = 0; m < NP; ++m) Wout[(v * NP + m) * E + e] = w[v][m];
-      gp(M.F[A.fout])[e] = dry ? 1 : 0;
+        for (int m = 0; m < NP; ++m) stc(Wout, (v * NP + m) * E, e, w[v][m]);
+      stx(gp(M.F[A.fout]), e, uint8_t(dry ? 1 : 0));
     }
     if (A.last) {
       const double lam = post_speed<Real, P>(filled, hv, qxv, qyv, w, hb, M.H0, M.g);
       const double area = 0.5 * (double(ex[2]) * double(ey[0]) - double(ex[0]) * double(ey[2]));
       part[2] = valid ? area * (double(w[0][0]) + (double(hb[0]) + double(hb[1]) + double(hb[2])) / 3.0) : 0.0;
-      part[3] = (valid && lam > 0.0) ? double(gp(M.din)[ec]) * rcp(lam) : __builtin_inf();
+      part[3] = (valid && lam > 0.0) ? double(ldx(gp(M.din), ec)) * rcp(lam) : __builtin_inf();
       part[4] = (valid && dry) ? 1.0 : 0.0;
     }
   } else {
@@ -799,7 +831,7 @@ DG_DEV void finish_stage(const Member<Real>& M, const StageArgs& A, int tile, in
 #pragma unroll
       for (int v = 0; v < 3; ++v)
 #pragma unroll
-        for (int m = 0; m < NP; ++m) Wr[(v * NP + m) * E + e] = w[v][m];
+        for (int m = 0; m < NP; ++m) stc(Wr, (v * NP + m) * E, e, w[v][m]);
       bool full = surely_wet<Real, P>(w, hb, dry_depth(M.H0));
       if (!full) {
         full = true;
@@ -811,7 +843,7 @@ DG_DEV void finish_stage(const Member<Real>& M, const StageArgs& A, int tile, in
           full &= (s + double(hb[i])) > dry_depth(M.H0);
         }
       }
-      gp(M.fullwet)[e] = full ? 1 : 0;
+      stx(gp(M.fullwet), e, uint8_t(full ? 1 : 0));
     }
   }
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -860,12 +892,12 @@ DG_DEV void load_elem(const Member<Real>& M, const DG_G Real* __restrict__ Win, 
 #pragma unroll
   for (int v = 0; v < 3; ++v)
 #pragma unroll
-    for (int m = 0; m < NP; ++m) d.w[v][m] = Win[(v * NP + m) * E + ec];
+    for (int m = 0; m < NP; ++m) d.w[v][m] = ldc(Win, (v * NP + m) * E, ec);
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    d.ex[k] = gp(M.ev)[(2 * k) * E + ec];
-    d.ey[k] = gp(M.ev)[(2 * k + 1) * E + ec];
-    d.hb[k] = gp(M.hbv)[k * E + ec];
+    d.ex[k] = ldc(gp(M.ev), (2 * k) * E, ec);
+    d.ey[k] = ldc(gp(M.ev), (2 * k + 1) * E, ec);
+    d.hb[k] = ldc(gp(M.hbv), k * E, ec);
   }
   d.detJ = Real(0.25) * (d.ex[2] * d.ey[0] - d.ex[0] * d.ey[2]);
   d.idet = rcp(d.detJ);
@@ -903,10 +935,10 @@ __global__ DG_STAGE_ATTR void stage_kernel(const Member<Real>* __restrict__ mem,
   const DG_G uint8_t* __restrict__ Fin = gp(M.F[A.fin]);
   ElemData<Real, P> d;
   load_elem<Real, P>(M, Win, E, ec, d);
-  const bool myflag = Fin[ec] & 1;
+  const bool myflag = ldx(Fin, ec) & 1;
   Real w0v[3][NP];
   load_blend<Real, P>(M, A, E, ec, w0v);
-  const uint8_t nkp = gp(M.nk)[ec];
+  const uint8_t nkp = ldx(gp(M.nk), ec);
   Real acc[3][NP];
 #pragma unroll
   for (int v = 0; v < 3; ++v)
@@ -921,7 +953,7 @@ __global__ DG_STAGE_ATTR void stage_kernel(const Member<Real>* __restrict__ mem,
   constexpr bool kHoist = P == 1 || (P == 2 && sizeof(Real) == 4);
   int nbv[3];
 #pragma unroll
-  for (int k = 0; k < 3; ++k) nbv[k] = gp(M.nbr)[k * E + ec];
+  for (int k = 0; k < 3; ++k) nbv[k] = ldc(gp(M.nbr), k * E, ec);
   Real wnb[kHoist ? 3 : 1][3][NP];
   bool nfl[3] = {false, false, false};
   if constexpr (kHoist) {
@@ -931,8 +963,8 @@ __global__ DG_STAGE_ATTR void stage_kernel(const Member<Real>* __restrict__ mem,
 #pragma unroll
       for (int v = 0; v < 3; ++v)
 #pragma unroll
-        for (int m = 0; m < NP; ++m) wnb[k][v][m] = Win[(v * NP + m) * E + n];
-      nfl[k] = Fin[n] & 1;
+        for (int m = 0; m < NP; ++m) wnb[k][v][m] = ldc(Win, (v * NP + m) * E, n);
+      nfl[k] = ldx(Fin, n) & 1;
     }
   }
   // edges and Gauss points are expanded at compile time, so every basis
@@ -959,8 +991,8 @@ __global__ DG_STAGE_ATTR void stage_kernel(const Member<Real>* __restrict__ mem,
 #pragma unroll
         for (int v = 0; v < 3; ++v)
 #pragma unroll
-          for (int m = 0; m < NP; ++m) wn[v][m] = Win[(v * NP + m) * E + nb];
-        nflag = Fin[nb] & 1;
+          for (int m = 0; m < NP; ++m) wn[v][m] = ldc(Win, (v * NP + m) * E, nb);
+        nflag = ldx(Fin, nb) & 1;
       }
       Real nvv[3][3], nmv[3][3];
       edge_nodes<Real, P>(wn, nvv, nmv);
@@ -1042,7 +1074,7 @@ __global__ DG_STAGE_ATTR void stage_kernel(const Member<Real>* __restrict__ mem,
       if (fm > 0.0) bout += fm; else bin -= fm;
     }
   });
-  area_terms<Real, P>(d.w, d.hb, d.cx0, d.cx1, d.cy0, d.cy1, d.detJ, d.idet, gp(M.fric)[ec], M.friction, g, H0, acc);
+  area_terms<Real, P>(d.w, d.hb, d.cx0, d.cx1, d.cy0, d.cy1, d.detJ, d.idet, ldx(gp(M.fric), ec), M.friction, g, H0, acc);
   if (M.fo.met_kind != MET_NONE)
     met_terms<Real, P>(M, E, ec, d.w, d.hb, d.cx0, d.cx1, d.cy0, d.cy1, d.detJ, d.idet, g, acc);
   double rain_part;
@@ -1100,21 +1132,21 @@ __global__ DG_STAGE_ATTR void stage_edge_kernel(const Member<Real>* __restrict__
   // together with the element's own data, so phase A waits for memory once
   int nbv[3];
 #pragma unroll
-  for (int k = 0; k < 3; ++k) nbv[k] = nbr[k * E + ec];
-  const int nkp = gp(M.nk)[ec];
-  const uint8_t fin = Fin[ec];
-  const Real fric = gp(M.fric)[ec];
+  for (int k = 0; k < 3; ++k) nbv[k] = ldc(nbr, k * E, ec);
+  const int nkp = ldx(gp(M.nk), ec);
+  const uint8_t fin = ldx(Fin, ec);
+  const Real fric = ldx(gp(M.fric), ec);
   // element rain (Eq. rain): the first stage of a step with time-dependent
   // rain averages the nodal rates of t^n (node ids now, rates before phase
   // B, the mean at the end); later stages read the stored value
   // (the stored value is read in both cases: a load in one branch only would
   // make the other wait for every load in flight before reusing its register)
   const bool rain_avg = A.stage == 0 && M.fo.rain_kind != RAIN_CONST;
-  Real Rv = gp(M.R)[ec];
+  Real Rv = ldx(gp(M.R), ec);
   int tn[3] = {0, 0, 0};
   if (rain_avg) {
 #pragma unroll
-    for (int i = 0; i < 3; ++i) tn[i] = gp(M.tri)[i * E + ec];
+    for (int i = 0; i < 3; ++i) tn[i] = ldc(gp(M.tri), i * E, ec);
   }
   {
     Real vv[3][3], mv[3][3];
@@ -1187,7 +1219,7 @@ __global__ DG_STAGE_ATTR void stage_edge_kernel(const Member<Real>* __restrict__
   double rn3[3] = {0.0, 0.0, 0.0};
   if (rain_avg) {
 #pragma unroll
-    for (int i = 0; i < 3; ++i) rn3[i] = gp(M.rn)[tn[i]];
+    for (int i = 0; i < 3; ++i) rn3[i] = ldx(gp(M.rn), tn[i]);
   }
 
   // ---- phase B: edge fluxes, scaled by (l/2) w_g, into s_flux
@@ -1199,7 +1231,7 @@ __global__ DG_STAGE_ATTR void stage_edge_kernel(const Member<Real>* __restrict__
     const int eg = t0 + l;
     const bool in_tile = it < n0;
     // class 0: the neighbour's id is in the entry; otherwise re-read (cached)
-    const int nb = in_tile ? t0 + int(ent >> 12) : nbr[k * E + eg];
+    const int nb = in_tile ? t0 + int(ent >> 12) : ldc(nbr, k * E, eg);
     const Real exk = s_ev[2 * k][l], eyk = s_ev[2 * k + 1][l];
     Real ell, il;
     edge_length<Real>(exk, eyk, ell, il);
@@ -1231,7 +1263,7 @@ __global__ DG_STAGE_ATTR void stage_edge_kernel(const Member<Real>* __restrict__
 #pragma unroll
         for (int v = 0; v < 3; ++v)
 #pragma unroll
-          for (int m = 0; m < NP; ++m) wn[v][m] = Win[(v * NP + m) * E + nb];
+          for (int m = 0; m < NP; ++m) wn[v][m] = ldc(Win, (v * NP + m) * E, nb);
         Real nvv[3][3], nmv[3][3];
         edge_nodes<Real, P>(wn, nvv, nmv);
 #pragma unroll
@@ -1240,7 +1272,7 @@ __global__ DG_STAGE_ATTR void stage_edge_kernel(const Member<Real>* __restrict__
           Nb[v] = kn1 == 0 ? nvv[v][0] : kn1 == 1 ? nvv[v][1] : nvv[v][2];
           Nc[v] = kn == 0 ? nmv[v][0] : kn == 1 ? nmv[v][1] : nmv[v][2];
         }
-        nflag = Fin[nb] & 1;
+        nflag = ldx(Fin, nb) & 1;
       }
       const bool myflag = s_flag[l];
       const bool meL = eg < nb;
@@ -1315,7 +1347,7 @@ __global__ DG_STAGE_ATTR void stage_edge_kernel(const Member<Real>* __restrict__
   double rain_part = 0.0;
   if (rain_avg) {
     Rv = Real((rn3[0] + rn3[1] + rn3[2]) / 3.0);
-    if (valid) gp(M.R)[e] = Rv;
+    if (valid) stx(gp(M.R), e, Rv);
     const double area = 0.5 * (double(d.ex[2]) * double(d.ey[0]) - double(d.ex[0]) * double(d.ey[2]));
     rain_part = valid ? area * double(Rv) : 0.0;
   }
@@ -1359,34 +1391,34 @@ __global__ __launch_bounds__(TILE) void post_kernel(const Member<Real>* __restri
 #pragma unroll
   for (int v = 0; v < 3; ++v)
 #pragma unroll
-    for (int m = 0; m < NP; ++m) w[v][m] = Wsrc[(v * NP + m) * E + ec];
+    for (int m = 0; m < NP; ++m) w[v][m] = ldc(Wsrc, (v * NP + m) * E, ec);
   Real hb[3];
 #pragma unroll
-  for (int k = 0; k < 3; ++k) hb[k] = gp(M.hbv)[k * E + ec];
+  for (int k = 0; k < 3; ++k) hb[k] = ldc(gp(M.hbv), k * E, ec);
 
   if (init != 2 && use_lim) {
-    const uint8_t lc = gp(M.limc)[ec];
+    const uint8_t lc = ldx(gp(M.limc), ec);
     // the neighbours' wet bytes and means are fetched together, before the
     // test that decides whether they are used (boundary ids read the element
     // itself), so the gather costs one memory round trip
     int nb[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      const int n = gp(M.nbr)[k * E + ec];
+      const int n = ldc(gp(M.nbr), k * E, ec);
       nb[k] = n < 0 ? ec : n;
     }
-    bool ok = ((lc & 1) != 0) & (gp(M.fullwet)[ec] != 0);
+    bool ok = ((lc & 1) != 0) & (ldx(gp(M.fullwet), ec) != 0);
     Real nmean[3][3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      ok = ok & (gp(M.fullwet)[nb[k]] != 0);
+      ok = ok & (ldx(gp(M.fullwet), nb[k]) != 0);
 #pragma unroll
-      for (int v = 0; v < 3; ++v) nmean[v][k] = Wsrc[(v * NP) * E + nb[k]];
+      for (int v = 0; v < 3; ++v) nmean[v][k] = ldc(Wsrc, (v * NP) * E, nb[k]);
     }
     if (ok) {
       Real al[6];
 #pragma unroll
-      for (int j = 0; j < 6; ++j) al[j] = gp(M.lima)[j * E + ec];
+      for (int j = 0; j < 6; ++j) al[j] = ldc(gp(M.lima), j * E, ec);
 #pragma unroll
       for (int v = 0; v < 3; ++v) {
         const Real wb = w[v][0];
@@ -1459,22 +1491,22 @@ __global__ __launch_bounds__(TILE) void post_kernel(const Member<Real>* __restri
 #pragma unroll
       for (int v = 0; v < 3; ++v)
 #pragma unroll
-        for (int m = 0; m < NP; ++m) Wout[(v * NP + m) * E + e] = w[v][m];
+        for (int m = 0; m < NP; ++m) stc(Wout, (v * NP + m) * E, e, w[v][m]);
     }
-    gp(M.F[fo])[e] = dry ? 1 : 0;
+    stx(gp(M.F[fo]), e, uint8_t(dry ? 1 : 0));
   }
   if (init || A.last) {
     Real ex[3], ey[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      ex[k] = gp(M.ev)[(2 * k) * E + ec];
-      ey[k] = gp(M.ev)[(2 * k + 1) * E + ec];
+      ex[k] = ldc(gp(M.ev), (2 * k) * E, ec);
+      ey[k] = ldc(gp(M.ev), (2 * k + 1) * E, ec);
     }
     const double area = 0.5 * (double(ex[2]) * double(ey[0]) - double(ex[0]) * double(ey[2]));
     const double lam = post_speed<Real, P>(filled, hv, qxv, qyv, w, hb, M.H0, M.g);
     double vals[2] = {valid ? area * (double(w[0][0]) + (double(hb[0]) + double(hb[1]) + double(hb[2])) / 3.0) : 0.0,
                       (valid && dry) ? 1.0 : 0.0};
-    const double mr = (valid && lam > 0.0) ? double(gp(M.din)[ec]) * rcp(lam) : __builtin_inf();
+    const double mr = (valid && lam > 0.0) ? double(ldx(gp(M.din), ec)) * rcp(lam) : __builtin_inf();
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const double s0 = wave_sum(vals[0]), s1 = double(__popcll(__ballot(vals[1] != 0.0))), mn = wave_min(mr);
     if (lane == 0) { lds[wv * 3 + 0] = s0; lds[wv * 3 + 1] = s1; lds[wv * 3 + 2] = mn; }
@@ -1634,9 +1666,10 @@ __global__ __launch_bounds__(TILE) void rain_kernel(const Member<Real>* __restri
   const bool valid = e < E;
   const int ec = valid ? e : E - 1;
   const DG_G double* __restrict__ rn = gp(M.rn);
-  const double r0 = rn[gp(M.tri)[ec]], r1 = rn[gp(M.tri)[E + ec]], r2 = rn[gp(M.tri)[2 * E + ec]];
+  const double r0 = ldx(rn, ldx(gp(M.tri), ec)), r1 = ldx(rn, ldc(gp(M.tri), E, ec)),
+               r2 = ldx(rn, ldc(gp(M.tri), 2 * E, ec));
   const Real Re = Real((r0 + r1 + r2) / 3.0);
-  if (valid) gp(M.R)[e] = Re;
+  if (valid) stx(gp(M.R), e, Re);
   const double area = 0.5 * (double(gp(M.ev)[4 * E + ec]) * double(gp(M.ev)[1 * E + ec]) -
                              double(gp(M.ev)[0 * E + ec]) * double(gp(M.ev)[5 * E + ec]));
   double v = valid ? area * double(Re) : 0.0;
