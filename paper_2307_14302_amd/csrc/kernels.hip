@@ -206,18 +206,21 @@ constexpr EdgeTable<P> make_edge_table() {
   return t;
 }
 
-// trace of the modes w at Gauss point G of local edge k (k may be a runtime
-// value: the three edges' basis values are selected)
+// trace of the modes w at Gauss point G of local edge k.  k may be a
+// runtime value: then the three edges' traces are formed with constant
+// coefficients and one is selected (selecting the coefficients instead
+// turns them into a table in memory read per lane).
 template <typename Real, int P, int G>
 DG_DEV Real trace_modal(const Real (&w)[Tab<P>::NP], int k) {
   constexpr EdgeTable<P> T = make_edge_table<P>();
-  Real s = Real(0);
+  Real s0 = Real(0), s1 = Real(0), s2 = Real(0);
 #pragma unroll
   for (int m = 0; m < Tab<P>::NP; ++m) {
-    const Real c = k == 0 ? Real(T.v[0][G][m]) : k == 1 ? Real(T.v[1][G][m]) : Real(T.v[2][G][m]);
-    s += c * w[m];
+    s0 += Real(T.v[0][G][m]) * w[m];
+    s1 += Real(T.v[1][G][m]) * w[m];
+    s2 += Real(T.v[2][G][m]) * w[m];
   }
-  return s;
+  return k == 0 ? s0 : k == 1 ? s1 : s2;
 }
 
 // trace along an edge from its start-vertex value a, midpoint value c
