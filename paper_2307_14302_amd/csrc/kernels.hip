@@ -939,8 +939,12 @@ __global__ DG_STAGE_ATTR void stage_kernel(const Member<Real>* __restrict__ mem,
   ElemData<Real, P> d;
   load_elem<Real, P>(M, Win, E, ec, d);
   const bool myflag = ldx(Fin, ec) & 1;
+  // w^n for the blend: read before the edges, so that its loads overlap
+  // them, except at p = 3, where holding it through the edge loop would cost
+  // 30 registers per value (15 more wavefronts' worth of registers)
+  constexpr bool kLateBlend = P >= 3;
   Real w0v[3][NP];
-  load_blend<Real, P>(M, A, E, ec, w0v);
+  if constexpr (!kLateBlend) load_blend<Real, P>(M, A, E, ec, w0v);
   const uint8_t nkp = ldx(gp(M.nk), ec);
   Real acc[3][NP];
 #pragma unroll
@@ -984,12 +988,29 @@ __global__ DG_STAGE_ATTR void stage_kernel(const Member<Real>* __restrict__ mem,
       const int kn = (nkp >> (2 * k)) & 3;
       Real wn[3][NP];
       bool nflag;
+      // p = 3: both sides' traces at every Gauss point of their own
+      // parametrisation, the neighbour's one variable at a time, so that only
+      // ten of its modes are held at once
+      Real tO[3][NG], tN[3][NG];
       if constexpr (kHoist) {
 #pragma unroll
         for (int v = 0; v < 3; ++v)
 #pragma unroll
           for (int m = 0; m < NP; ++m) wn[v][m] = wnb[k][v][m];
         nflag = nfl[k];
+      } else if constexpr (P >= 3) {
+#pragma unroll
+        for (int v = 0; v < 3; ++v) {
+          Real wv[NP];
+#pragma unroll
+          for (int m = 0; m < NP; ++m) wv[m] = ldc(Win, (v * NP + m) * E, nb);
+          static_for<NG>([&](auto gc) {
+            constexpr int gg = decltype(gc)::value;
+            tO[v][gg] = trace_modal<Real, P, gg>(d.w[v], k);
+            tN[v][gg] = trace_modal<Real, P, gg>(wv, kn);
+          });
+        }
+        nflag = ldx(Fin, nb) & 1;
       } else {
 #pragma unroll
         for (int v = 0; v < 3; ++v)
@@ -998,12 +1019,12 @@ __global__ DG_STAGE_ATTR void stage_kernel(const Member<Real>* __restrict__ mem,
         nflag = ldx(Fin, nb) & 1;
       }
       Real nvv[3][3], nmv[3][3];
-      edge_nodes<Real, P>(wn, nvv, nmv);
+      if constexpr (P <= 2) edge_nodes<Real, P>(wn, nvv, nmv);
       const int kn1 = kn == 2 ? 0 : kn + 1;
       const bool meL = e < nb;
       Real La[3], Lc[3], Lb[3], Ra[3], Rc[3], Rb[3];
 #pragma unroll
-      for (int v = 0; v < 3; ++v) {
+      for (int v = 0; v < 3 && P <= 2; ++v) {
         const Real oa = vv[v][k], oc = mv[v][k], ob = vv[v][k1];
         const Real na = kn == 0 ? nvv[v][0] : kn == 1 ? nvv[v][1] : nvv[v][2];
         const Real nc = kn == 0 ? nmv[v][0] : kn == 1 ? nmv[v][1] : nmv[v][2];
@@ -1028,8 +1049,8 @@ __global__ DG_STAGE_ATTR void stage_kernel(const Member<Real>* __restrict__ mem,
           Real tL[3], tR[3];
 #pragma unroll
           for (int v = 0; v < 3; ++v) {
-            tL[v] = meL ? trace_modal<Real, P, gL>(d.w[v], k) : trace_modal<Real, P, gL>(wn[v], kn);
-            tR[v] = meL ? trace_modal<Real, P, gR>(wn[v], kn) : trace_modal<Real, P, gR>(d.w[v], k);
+            tL[v] = meL ? tO[v][gL] : tN[v][gL];
+            tR[v] = meL ? tN[v][gR] : tO[v][gR];
           }
           a = {tL[0], tL[1], tL[2]};
           b = {tR[0], tR[1], tR[2]};
@@ -1077,6 +1098,7 @@ __global__ DG_STAGE_ATTR void stage_kernel(const Member<Real>* __restrict__ mem,
       if (fm > 0.0) bout += fm; else bin -= fm;
     }
   });
+  if constexpr (kLateBlend) load_blend<Real, P>(M, A, E, ec, w0v);
   area_terms<Real, P>(d.w, d.hb, d.cx0, d.cx1, d.cy0, d.cy1, d.detJ, d.idet, ldx(gp(M.fric), ec), M.friction, g, H0, acc);
   if (M.fo.met_kind != MET_NONE)
     met_terms<Real, P>(M, E, ec, d.w, d.hb, d.cx0, d.cx1, d.cy0, d.cy1, d.detJ, d.idet, g, acc);
