@@ -121,6 +121,24 @@ int dgswe_default_params(dgswe_params* out);
 int dgswe_create(const dgswe_params* params, void* hip_stream, dgswe_ctx** out);
 int dgswe_destroy(dgswe_ctx* ctx);
 
+/* Hand the context device memory owned by the caller (for example the
+ * storage of a torch tensor): from now on every device array of the context
+ * (mesh arrays, states, flags, partials, forcing tables, the autotuner's
+ * temporary copy) is placed in [dev_ptr, dev_ptr + bytes) by a first-fit
+ * sub-allocator with 256-byte blocks, and the arrays made at creation move
+ * there.  The library never frees dev_ptr; the caller keeps it valid until
+ * the context, and every context that shares its mesh, is destroyed.
+ * Sizing: dgswe_footprint_bytes(params, n_tri, n_nodes) + 64 KiB covers the
+ * mesh and state; the forcing tables (storm and wind records, rain lattice)
+ * and dgswe_autotune (one more state copy, 3 Np n_tri bytes-per-value +
+ * n_tri bytes) need their own room.  Must be called before
+ * dgswe_upload_mesh / dgswe_share_mesh, once per context.  EINVAL for a null
+ * or unaligned pointer, host memory or less than 64 KiB; ESTATE when a mesh
+ * or a workspace is already there or the context is in a batch; a later
+ * allocation that does not fit returns ENOMEM (nothing falls back to
+ * hipMalloc).  Batches keep allocating their own small arrays. */
+int dgswe_workspace_bind(dgswe_ctx* ctx, void* dev_ptr, size_t bytes);
+
 /* Upload the mesh (Sec. 2.1 domain, Sec. 2.3 element-local operator).
  *   xy[2*n_nodes]            node coordinates (x0, y0, x1, y1, ...), m
  *   hb[n_nodes]              bathymetry, positive downward, m
@@ -134,7 +152,11 @@ int dgswe_destroy(dgswe_ctx* ctx);
  * Boundary edges not listed are LAND.  EINVAL for node ids out of range,
  * zero-area triangles, edges shared by more than two triangles, listed
  * edges that are not on the boundary, bad types or slots, non-finite
- * coordinates.  Elements are reordered along a Hilbert curve internally;
+ * coordinates, and for meshes too large for the kernels' 32-bit array
+ * offsets: 3 Np n_tri bytes-per-value (the modal state) and 24 n_nodes must
+ * stay below 2^32, i.e. at most 119M triangles at p = 1 in FP32, 59M in
+ * FP64, 17.8M at p = 3 in FP64; an ensemble of separate contexts has no
+ * such bound.  Elements are reordered along a Hilbert curve internally;
  * every array passed in or out uses the caller's element order.
  * Allowed once per context; n_tri = 0 is allowed (empty mesh). */
 int dgswe_upload_mesh(dgswe_ctx* ctx, int64_t n_nodes, const double* xy, const double* hb,
@@ -277,6 +299,11 @@ int dgswe_batch_step(dgswe_batch* b, int64_t max_steps);
 int dgswe_batch_poll(dgswe_batch* b, int32_t* done_slots, int32_t cap, int32_t* n_done);
 /* Remove a member (done or not); its context stays valid. */
 int dgswe_batch_retire(dgswe_batch* b, int32_t slot);
+/* Synchronous read of a live member by slot: its state as dgswe_read_state
+ * (layout, out; skipped when out is NULL) and its totals as
+ * dgswe_mass_totals (skipped when mass is NULL), after the batch's queued
+ * work.  EINVAL for an unknown slot or layout. */
+int dgswe_batch_read(dgswe_batch* b, int32_t slot, int layout, double* out, dgswe_mass* mass);
 /* Number of members, summed footprint. Either pointer may be NULL. */
 int dgswe_batch_info(const dgswe_batch* b, int32_t* n_members, int64_t* footprint);
 

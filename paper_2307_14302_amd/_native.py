@@ -60,6 +60,7 @@ SIGNATURES = {
     "dgswe_default_params": (C.c_int, [C.POINTER(Params)]),
     "dgswe_create": (C.c_int, [C.POINTER(Params), _P, C.POINTER(_P)]),
     "dgswe_destroy": (C.c_int, [_P]),
+    "dgswe_workspace_bind": (C.c_int, [_P, _P, C.c_size_t]),
     "dgswe_upload_mesh": (C.c_int, [_P, C.c_int64, _D, _D, _D, C.c_int64, _I, C.c_int64, _I, _I, _I]),
     "dgswe_share_mesh": (C.c_int, [_P, _P]),
     "dgswe_set_initial_nodal": (C.c_int, [_P, _D, _D, _D]),
@@ -91,6 +92,7 @@ SIGNATURES = {
     "dgswe_batch_step": (C.c_int, [_P, C.c_int64]),
     "dgswe_batch_poll": (C.c_int, [_P, _I, C.c_int32, _I]),
     "dgswe_batch_retire": (C.c_int, [_P, C.c_int32]),
+    "dgswe_batch_read": (C.c_int, [_P, C.c_int32, C.c_int, _D, C.POINTER(Mass)]),
     "dgswe_batch_info": (C.c_int, [_P, _I, _I64]),
     "dgswe_last_error": (C.c_char_p, []),
 }

@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstring>
 #include <limits>
+#include <iterator>
 #include <map>
 #include <memory>
 #include <string>
@@ -32,21 +33,85 @@ int fail(int code, const std::string& msg) {
 #define HIPCHK(x)                                                                              \
   do {                                                                                         \
     hipError_t e_ = (x);                                                                       \
+    if (e_ == hipErrorOutOfMemory)                                                             \
+      return fail(DGSWE_ENOMEM, std::string(#x) + ": " + oom_message());                       \
     if (e_ != hipSuccess) return fail(DGSWE_EHIP, std::string(#x) + ": " + hipGetErrorString(e_)); \
   } while (0)
+
+// Device memory handed over by the caller (dgswe_workspace_bind): a
+// first-fit sub-allocator over [base, base + cap) with 256-byte blocks and
+// coalescing of freed neighbours.  The caller keeps ownership of the memory.
+struct Arena {
+  static constexpr size_t ALIGN = 256;
+  char* base = nullptr;
+  size_t cap = 0;
+  std::map<size_t, size_t> free_;      // offset -> length of free ranges
+  Arena(void* p, size_t n) : base(static_cast<char*>(p)), cap(n / ALIGN * ALIGN) { free_[0] = cap; }
+  void* take(size_t n) {
+    n = (n + ALIGN - 1) / ALIGN * ALIGN;
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second < n) continue;
+      const size_t off = it->first, len = it->second;
+      free_.erase(it);
+      if (len > n) free_[off + n] = len - n;
+      return base + off;
+    }
+    return nullptr;
+  }
+  void give(void* p, size_t n) {
+    n = (n + ALIGN - 1) / ALIGN * ALIGN;
+    size_t off = size_t(static_cast<char*>(p) - base);
+    auto next = free_.lower_bound(off);
+    if (next != free_.end() && off + n == next->first) {
+      n += next->second;
+      next = free_.erase(next);
+    }
+    if (next != free_.begin()) {
+      auto prev = std::prev(next);
+      if (prev->first + prev->second == off) {
+        prev->second += n;
+        return;
+      }
+    }
+    free_[off] = n;
+  }
+  size_t largest_free() const {
+    size_t m = 0;
+    for (const auto& f : free_) m = std::max(m, f.second);
+    return m;
+  }
+};
+
+// Arena of the context whose API call is running on this thread (null: the
+// allocations go to hipMalloc).  Set for the duration of a call by ArenaScope.
+thread_local std::shared_ptr<Arena> t_arena;
+struct ArenaScope {
+  std::shared_ptr<Arena> prev;
+  explicit ArenaScope(const std::shared_ptr<Arena>& a) : prev(t_arena) { t_arena = a; }
+  ~ArenaScope() { t_arena = prev; }
+};
+
+std::string oom_message() {
+  if (t_arena)
+    return "the bound workspace is exhausted (largest free block " + std::to_string(t_arena->largest_free()) +
+           " bytes)";
+  return "out of device memory";
+}
 
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
+  std::shared_ptr<Arena> arena;      // set when the block came from a bound workspace
   DevBuf() = default;
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
-  DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+  DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes), arena(std::move(o.arena)) { o.p = nullptr; o.bytes = 0; }
   DevBuf& operator=(DevBuf&& o) noexcept {
     if (this != &o) {
       release();
       p = o.p;
       bytes = o.bytes;
+      arena = std::move(o.arena);
       o.p = nullptr;
       o.bytes = 0;
     }
@@ -54,13 +119,24 @@ struct DevBuf {
   }
   ~DevBuf() { release(); }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p) {
+      if (arena) arena->give(p, bytes);
+      else (void)hipFree(p);
+    }
     p = nullptr;
     bytes = 0;
+    arena.reset();
   }
   hipError_t alloc(size_t n) {
     release();
     if (n == 0) return hipSuccess;
+    if (t_arena) {
+      p = t_arena->take(n);
+      if (!p) return hipErrorOutOfMemory;
+      arena = t_arena;
+      bytes = n;
+      return hipSuccess;
+    }
     hipError_t e = hipMalloc(&p, n);
     if (e == hipSuccess) bytes = n;
     return e;
@@ -142,6 +218,7 @@ struct dgswe_ctx {
   hipStream_t stream = nullptr;
   bool own_stream = false;
   std::shared_ptr<MeshDev> mesh;
+  std::shared_ptr<Arena> arena;     // caller's device memory (dgswe_workspace_bind), or null
   int n_tiles = 0;
   int variant = 1;                  // stage kernel: 0 per element, 1 per edge
   DevBuf W[3], Wt, F[3], fullwet, R, part, sc, memb, tiles, ids, rnode, met, node_tiles;
@@ -652,11 +729,47 @@ int dgswe_destroy(dgswe_ctx* c) {
   return DGSWE_OK;
 }
 
+int dgswe_workspace_bind(dgswe_ctx* c, void* dev_ptr, size_t bytes) {
+  int rc = check_ctx(c, false);
+  if (rc) return rc;
+  if (c->in_batch) return fail(DGSWE_ESTATE, "context is a member of a batch");
+  if (c->mesh) return fail(DGSWE_ESTATE, "bind the workspace before uploading or sharing a mesh");
+  if (c->arena) return fail(DGSWE_ESTATE, "a workspace is already bound");
+  if (!dev_ptr || reinterpret_cast<uintptr_t>(dev_ptr) % Arena::ALIGN != 0)
+    return fail(DGSWE_EINVAL, "workspace must be a non-null device pointer aligned to 256 bytes");
+  if (bytes < 65536) return fail(DGSWE_EINVAL, "workspace smaller than 64 KiB");
+  hipPointerAttribute_t at{};
+  if (hipPointerGetAttributes(&at, dev_ptr) != hipSuccess || at.type != hipMemoryTypeDevice) {
+    (void)hipGetLastError();
+    return fail(DGSWE_EINVAL, "workspace is not device memory");
+  }
+  if (c->stream) HIPCHK(hipStreamSynchronize(c->stream));
+  auto arena = std::make_shared<Arena>(dev_ptr, bytes);
+  ArenaScope arena_scope(arena);
+  // the buffers made at creation move into the workspace
+  for (DevBuf* b : {&c->sc, &c->memb, &c->ids, &c->tide_c, &c->riv_tq, &c->storm, &c->wind, &c->gt, &c->gvals}) {
+    if (!b->p) continue;
+    DevBuf nb;
+    HIPCHK(nb.alloc(b->bytes));
+    HIPCHK(hipMemcpy(nb.p, b->p, b->bytes, hipMemcpyDeviceToDevice));
+    *b = std::move(nb);
+  }
+  c->fo.tide_c = c->tide_c.as<double>();
+  c->fo.riv_tq = c->riv_tq.as<double>();
+  c->fo.storm = c->storm.as<double>();
+  c->fo.wind = c->wind.as<double>();
+  c->fo.gt = c->gt.as<double>();
+  c->fo.gvals = c->gvals.as<float>();
+  c->arena = arena;
+  return push_member(c);
+}
+
 int dgswe_upload_mesh(dgswe_ctx* c, int64_t n_nodes, const double* xy, const double* hb, const double* fric,
                       int64_t n_tri, const int32_t* tri, int64_t n_bedges, const int32_t* bedge_nodes,
                       const int32_t* bedge_type, const int32_t* bedge_slot) {
   int rc = check_ctx(c, false);
   if (rc) return rc;
+  ArenaScope arena_scope(c->arena);
   if (c->mesh) return fail(DGSWE_ESTATE, "mesh already uploaded");
   if (n_bedges > 0 && !bedge_nodes) return fail(DGSWE_EINVAL, "null boundary edge array");
   {
@@ -690,6 +803,7 @@ int dgswe_share_mesh(dgswe_ctx* dst, const dgswe_ctx* src) {
   if (rc) return rc;
   rc = check_ctx(src, true);
   if (rc) return rc;
+  ArenaScope arena_scope(dst->arena);
   if (dst->mesh) return fail(DGSWE_ESTATE, "mesh already uploaded");
   if (dst->rs != src->rs || dst->prm.p != src->prm.p || dst->prm.limiter != src->prm.limiter)
     return fail(DGSWE_EINVAL, "precision, p and limiter must match to share a mesh");
@@ -700,6 +814,7 @@ int dgswe_share_mesh(dgswe_ctx* dst, const dgswe_ctx* src) {
 int dgswe_set_initial_nodal(dgswe_ctx* c, const double* zeta, const double* qx, const double* qy) {
   int rc = check_ctx(c);
   if (rc) return rc;
+  ArenaScope arena_scope(c->arena);
   if (c->in_batch) return fail(DGSWE_ESTATE, "context is a member of a batch");
   const HostMesh& h = c->mesh->host;
   const int64_t E = h.E, NP = c->NP();
@@ -727,6 +842,7 @@ int dgswe_set_initial_nodal(dgswe_ctx* c, const double* zeta, const double* qx, 
 int dgswe_set_state(dgswe_ctx* c, int layout, const double* w, double t) {
   int rc = check_ctx(c);
   if (rc) return rc;
+  ArenaScope arena_scope(c->arena);
   if (c->in_batch) return fail(DGSWE_ESTATE, "context is a member of a batch");
   if (layout != DGSWE_MODAL) return fail(DGSWE_EINVAL, "set_state takes DGSWE_MODAL");
   if (!std::isfinite(t)) return fail(DGSWE_EINVAL, "non-finite time");
@@ -753,6 +869,7 @@ int dgswe_set_state(dgswe_ctx* c, int layout, const double* w, double t) {
 int dgswe_set_rain_nodal(dgswe_ctx* c, const double* r) {
   int rc = check_ctx(c);
   if (rc) return rc;
+  ArenaScope arena_scope(c->arena);
   const HostMesh& h = c->mesh->host;
   if (h.n_nodes > 0 && !r) return fail(DGSWE_EINVAL, "null rain array");
   for (int64_t i = 0; i < h.n_nodes; ++i)
@@ -773,6 +890,7 @@ int dgswe_set_rain_nodal(dgswe_ctx* c, const double* r) {
 int dgswe_clear_rain(dgswe_ctx* c) {
   int rc = check_ctx(c);
   if (rc) return rc;
+  ArenaScope arena_scope(c->arena);
   HIPCHK(hipStreamSynchronize(c->stream));
   if (c->R.bytes) HIPCHK(hipMemset(c->R.p, 0, c->R.bytes));
   HIPCHK(hipMemset(c->part.as<double>() + size_t(P_RAIN) * std::max(c->n_tiles, 1), 0,
@@ -784,6 +902,7 @@ int dgswe_clear_rain(dgswe_ctx* c) {
 int dgswe_set_rain_parametric(dgswe_ctx* c, int32_t n_rec, const double* rec) {
   int rc = check_ctx(c);
   if (rc) return rc;
+  ArenaScope arena_scope(c->arena);
   if (n_rec < 1 || !rec) return fail(DGSWE_EINVAL, "need at least one storm record");
   for (int i = 0; i < 7 * n_rec; ++i)
     if (!std::isfinite(rec[i])) return fail(DGSWE_EINVAL, "non-finite storm record");
@@ -802,6 +921,7 @@ int dgswe_set_rain_parametric(dgswe_ctx* c, int32_t n_rec, const double* rec) {
 int dgswe_set_wind_vortex(dgswe_ctx* c, int32_t n_rec, const double* rec) {
   int rc = check_ctx(c);
   if (rc) return rc;
+  ArenaScope arena_scope(c->arena);
   if (n_rec < 1 || !rec) return fail(DGSWE_EINVAL, "need at least one wind record");
   for (int i = 0; i < 9 * n_rec; ++i)
     if (!std::isfinite(rec[i])) return fail(DGSWE_EINVAL, "non-finite wind record");
@@ -823,6 +943,7 @@ int dgswe_set_wind_vortex(dgswe_ctx* c, int32_t n_rec, const double* rec) {
 int dgswe_clear_wind(dgswe_ctx* c) {
   int rc = check_ctx(c);
   if (rc) return rc;
+  ArenaScope arena_scope(c->arena);
   HIPCHK(hipStreamSynchronize(c->stream));
   c->fo.met_kind = MET_NONE;
   c->fo.n_wind = 0;
@@ -833,6 +954,7 @@ int dgswe_set_rain_gridded(dgswe_ctx* c, double x0, double y0, double dx, double
                            int32_t n_rec, const double* t_rec, const float* vals) {
   int rc = check_ctx(c);
   if (rc) return rc;
+  ArenaScope arena_scope(c->arena);
   if (nx < 2 || ny < 2 || n_rec < 1 || !t_rec || !vals) return fail(DGSWE_EINVAL, "lattice needs nx, ny >= 2 and a record");
   if (!(dx > 0.0) || !(dy > 0.0) || !std::isfinite(x0) || !std::isfinite(y0)) return fail(DGSWE_EINVAL, "bad lattice geometry");
   for (int i = 1; i < n_rec; ++i)
@@ -859,6 +981,7 @@ int dgswe_set_rain_gridded(dgswe_ctx* c, double x0, double y0, double dx, double
 int dgswe_set_ocean_tide(dgswe_ctx* c, int32_t slot, double mean, int32_t n_const, const double* apt) {
   int rc = check_ctx(c, false);
   if (rc) return rc;
+  ArenaScope arena_scope(c->arena);
   if (slot < 0 || slot >= MAX_SLOTS) return fail(DGSWE_EINVAL, "slot out of range");
   if (n_const < 0 || (n_const > 0 && !apt)) return fail(DGSWE_EINVAL, "bad constituent array");
   if (!std::isfinite(mean)) return fail(DGSWE_EINVAL, "non-finite mean level");
@@ -874,6 +997,7 @@ int dgswe_set_ocean_tide(dgswe_ctx* c, int32_t slot, double mean, int32_t n_cons
 int dgswe_set_river_flux(dgswe_ctx* c, int32_t slot, int32_t n, const double* t, const double* q) {
   int rc = check_ctx(c, false);
   if (rc) return rc;
+  ArenaScope arena_scope(c->arena);
   if (slot < 0 || slot >= MAX_SLOTS) return fail(DGSWE_EINVAL, "slot out of range");
   if (n < 1 || !t || !q) return fail(DGSWE_EINVAL, "need at least one river sample");
   std::vector<double> rows;
@@ -1052,6 +1176,7 @@ int dgswe_get_tuning(const dgswe_ctx* c, int key, int* value) {
 int dgswe_autotune(dgswe_ctx* c, int n_steps, int* chosen, double* ms_per_step) {
   int rc = check_ctx(c, true, true);
   if (rc) return rc;
+  ArenaScope arena_scope(c->arena);
   if (c->in_batch) return fail(DGSWE_ESTATE, "context is a member of a batch");
   if (n_steps < 1) return fail(DGSWE_EINVAL, "autotune needs at least one timed step");
   Scalars s0;
@@ -1373,6 +1498,18 @@ int dgswe_batch_retire(dgswe_batch* b, int32_t slot) {
   rc = write_scalars(c, s);
   if (rc) return rc;
   b->dirty = true;
+  return DGSWE_OK;
+}
+
+int dgswe_batch_read(dgswe_batch* b, int32_t slot, int layout, double* out, dgswe_mass* mass) {
+  if (!b) return fail(DGSWE_EINVAL, "null batch");
+  if (slot < 0 || size_t(slot) >= b->slots.size() || !b->slots[slot].live) return fail(DGSWE_EINVAL, "no such slot");
+  dgswe_ctx* c = b->slots[slot].ctx;
+  if (out) {
+    const int rc = dgswe_read_state(c, layout, out);
+    if (rc) return rc;
+  }
+  if (mass) return dgswe_mass_totals(c, mass);
   return DGSWE_OK;
 }
 

@@ -65,6 +65,13 @@ class Solver:
         self.n_nodes = 0
 
     # ------------------------------------------------------------- set-up
+    def bind_workspace(self, ptr: int, nbytes: int):
+        """Place every device array of this context in caller-owned device
+        memory (e.g. ``t.data_ptr()`` of a torch tensor kept alive by the
+        caller); call before the mesh is uploaded."""
+        call("dgswe_workspace_bind", self.h, C.c_void_p(int(ptr)), C.c_size_t(int(nbytes)))
+        return self
+
     def upload_mesh(self, xy, hb, fric, tri, bedges=None, btype=None, bslot=None):
         xy, hb, fric, tri = _f64(xy), _f64(hb), _f64(fric), _i32(tri)
         nb = 0 if bedges is None else len(bedges)
@@ -204,13 +211,16 @@ class Solver:
 
     # ----------------------------------------------------------- helpers
     @classmethod
-    def from_scenario(cls, sc, stream=None, mesh_from: Optional["Solver"] = None, **over):
+    def from_scenario(cls, sc, stream=None, mesh_from: Optional["Solver"] = None, workspace=None, **over):
         """Build a solver from a workload description with attributes
         mesh (xy, tri, hb, fric, bedges, btype, bslot), zeta0/qx0/qy0,
-        params, rain, tides, rivers and (optional) met."""
+        params, rain, tides, rivers and (optional) met.  workspace =
+        (device pointer, bytes) places the context's arrays there."""
         prm = dict(sc.params)
         prm.update(over)
         s = cls(prm, stream=stream)
+        if workspace is not None:
+            s.bind_workspace(*workspace)
         m = sc.mesh
         if mesh_from is not None:
             s.share_mesh(mesh_from)
@@ -250,6 +260,15 @@ class Batch:
         n = C.c_int32()
         call("dgswe_batch_poll", self.h, iptr(buf), cap, C.byref(n))
         return [int(x) for x in buf[: min(n.value, cap)]]
+
+    def read(self, slot: int, layout: str = "modal"):
+        """State and totals of a live member, by slot."""
+        s = self.members.get(slot)
+        out = np.empty((s.n_tri, 3, s.np if layout == "modal" else 3)) if s is not None else None
+        m = N.Mass()
+        call("dgswe_batch_read", self.h, int(slot), N.MODAL if layout == "modal" else N.VERTEX,
+             dptr(out) if out is not None else None, C.byref(m))
+        return out, m.as_dict()
 
     def retire(self, slot: int) -> Solver:
         call("dgswe_batch_retire", self.h, int(slot))

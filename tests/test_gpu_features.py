@@ -119,6 +119,13 @@ def test_batch_members_match_alone_bitwise(dg):
     for m, (w, mass) in zip(members, alone):
         assert np.array_equal(m.state(), w)
         assert m.mass() == mass
+    # the same through the batch, by slot
+    for sl, (w, mass) in zip(slots, alone):
+        wb, mb = b.read(sl)
+        assert np.array_equal(wb, w) and mb == mass
+    from paper_2307_14302_amd import _native as N
+    with pytest.raises(N.DgsweError, match="no such slot"):
+        b.read(99)
     for sl in slots:
         b.retire(sl)
     # retired members can run on their own again
@@ -175,6 +182,20 @@ def test_invalid_inputs_are_rejected(dg):
         s.set_tide(99, 0.0, [])
     with pytest.raises(N.DgsweError):
         s.set_river(1, [0.0, 0.0], [1.0, 2.0])
+    s.close()
+
+
+def test_meshes_beyond_32bit_offsets_are_refused(dg):
+    """The kernels address arrays with 32-bit byte offsets: a p = 3 FP64
+    context (240 bytes of modal state per triangle) refuses 18M triangles
+    before reading the arrays (untouched zero pages here)."""
+    from paper_2307_14302_amd import _native as N
+    n = 18_000_000
+    s = dg.Solver(dict(p=3, precision="fp64", flux="llf", cfl=0.1, dt_max=1.0, rk_stages=3))
+    tri = np.zeros((n, 3), dtype=np.int32)
+    xy = np.zeros((4, 2)); hb = np.ones(4); fr = np.full(4, 0.02)
+    with pytest.raises(N.DgsweError, match="exceed 4 GiB"):
+        s.upload_mesh(xy, hb, fr, tri)
     s.close()
 
 
@@ -325,3 +346,58 @@ def test_graph_replays_match_eager_steps(dg):
     batch_eager.close(); batch_graph.close()
     for s in (eager, graph, a, b):
         s.close()
+
+
+def test_workspace_bind_places_the_context_in_caller_memory(dg):
+    """A context bound to a torch tensor's storage runs bit for bit like one
+    that allocates by itself, its arrays really are in that storage (zeroing
+    the tensor zeroes the state and totals), a workspace that is too small
+    gives ENOMEM, and misuse is refused."""
+    import ctypes as C
+    import torch
+    from paper_2307_14302_amd import _native as N
+    from paper_2307_14302_amd.solver import params_from_dict
+    sc = meshgen.small_mixed(seed=12, nx=24, ny=12, flux="llf", limiter=True, rain_kind="gridded")
+    for precision in ("fp64", "fp32"):
+        prm = dict(sc.params, precision=precision)
+        fp = int(N.lib.dgswe_footprint_bytes(C.byref(params_from_dict(prm)), sc.mesh.n_tri, sc.mesh.n_nodes))
+        np_ = (prm["p"] + 1) * (prm["p"] + 2) // 2
+        copy = 3 * np_ * sc.mesh.n_tri * 8 + sc.mesh.n_tri          # the autotuner's state copy
+        ws = torch.empty(fp + copy + (2 << 20), dtype=torch.uint8, device="cuda")
+        a = dg.Solver.from_scenario(sc, precision=precision, workspace=(ws.data_ptr(), ws.numel()))
+        b = dg.Solver.from_scenario(sc, precision=precision)
+        a.step(30); b.step(30)
+        assert np.array_equal(a.state(), b.state())
+        assert a.mass() == b.mass()
+        a.autotune(2)
+        b.autotune(2)
+        a.step(5); b.step(5)
+        assert np.array_equal(a.state(), b.state())
+        a.sync()
+        ws.zero_()
+        torch.cuda.synchronize()
+        assert not a.state().any()
+        assert a.mass()["steps"] == 0 and a.mass()["volume"] == 0.0
+        a.close(); b.close()
+        del ws
+    tiny = torch.empty(1 << 16, dtype=torch.uint8, device="cuda")
+    with pytest.raises(N.DgsweError, match="workspace is exhausted") as ei:
+        dg.Solver.from_scenario(sc, workspace=(tiny.data_ptr(), tiny.numel()))
+    assert ei.value.code == N.DGSWE_ENOMEM
+    ws = torch.empty(1 << 20, dtype=torch.uint8, device="cuda")
+    s = dg.Solver(dict(sc.params))
+    with pytest.raises(N.DgsweError, match="aligned"):
+        s.bind_workspace(ws.data_ptr() + 4, 1 << 19)
+    host = np.zeros(1 << 17, dtype=np.uint8)
+    with pytest.raises(N.DgsweError, match="not device memory"):
+        s.bind_workspace(host.ctypes.data - host.ctypes.data % 256 + 256, 1 << 16)
+    with pytest.raises(N.DgsweError, match="64 KiB"):
+        s.bind_workspace(ws.data_ptr(), 1024)
+    s.bind_workspace(ws.data_ptr(), ws.numel())
+    with pytest.raises(N.DgsweError, match="already bound"):
+        s.bind_workspace(ws.data_ptr(), ws.numel())
+    s.close()
+    t = dg.Solver.from_scenario(sc)
+    with pytest.raises(N.DgsweError, match="before uploading"):
+        t.bind_workspace(ws.data_ptr(), ws.numel())
+    t.close()
