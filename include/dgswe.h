@@ -257,10 +257,10 @@ int dgswe_kernel_stats(dgswe_ctx* ctx, const char* kernel, int64_t* launches, do
 
 /* Kernel choices (same arithmetic, different work layout; results differ
  * only by summation order).  DGSWE_TUNE_STAGE_VARIANT: 0 = every element
- * evaluates its three edges; 1 (default for p <= 2) = the tile's point
- * values are staged in LDS and each edge inside a tile is evaluated once
- * (p <= 2 only; p = 3 uses variant 0).  EINVAL for unknown keys or values
- * and for variant 1 with p = 3; ESTATE while the context is in a batch. */
+ * evaluates its three edges; 1 (default) = the tile's point values (p <= 2)
+ * or edge traces (p = 3) are staged in LDS and each edge inside a tile is
+ * evaluated once.  EINVAL for unknown keys or values; ESTATE while the
+ * context is in a batch. */
 #define DGSWE_TUNE_STAGE_VARIANT 1
 int dgswe_set_tuning(dgswe_ctx* ctx, int key, int value);
 int dgswe_get_tuning(const dgswe_ctx* ctx, int key, int* value);
@@ -269,8 +269,7 @@ int dgswe_get_tuning(const dgswe_ctx* ctx, int key, int* value);
  * variant (after two untimed steps each), keeps the faster one and restores
  * the state, flags, tile partials and scalars, so the context continues
  * exactly where it was.  chosen (may be NULL) receives the variant,
- * ms_per_step[2] (may be NULL) the two timings (with p = 3 only variant 0
- * runs and ms_per_step[1] is 0).  Allocates a copy of the
+ * ms_per_step[2] (may be NULL) the two timings.  Allocates a copy of the
  * state for the duration of the call.  EINVAL for n_steps < 1, ESTATE
  * without mesh or state or inside a batch, ENONFINITE if the context has a
  * latched error. */

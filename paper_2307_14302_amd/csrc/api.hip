@@ -702,7 +702,7 @@ int dgswe_create(const dgswe_params* params, void* hip_stream, dgswe_ctx** out) 
   c->prm = *params;
   c->rs = params->precision == DGSWE_FP32 ? 4 : 8;
   make_rk(params->rk_stages, c->rk);
-  c->variant = params->p == 3 ? 0 : 1;
+  c->variant = 1;
   if (hip_stream) {
     c->stream = static_cast<hipStream_t>(hip_stream);
   } else {
@@ -1158,7 +1158,6 @@ int dgswe_set_tuning(dgswe_ctx* c, int key, int value) {
   if (c->in_batch) return fail(DGSWE_ESTATE, "context is a member of a batch");
   if (key != DGSWE_TUNE_STAGE_VARIANT) return fail(DGSWE_EINVAL, "unknown tuning key");
   if (value != 0 && value != 1) return fail(DGSWE_EINVAL, "stage variant must be 0 or 1");
-  if (value == 1 && c->prm.p == 3) return fail(DGSWE_EINVAL, "the per-edge stage kernel supports p <= 2");
   if (c->stream) HIPCHK(hipStreamSynchronize(c->stream));
   c->variant = value;
   c->graph_dirty = true;
@@ -1208,8 +1207,7 @@ int dgswe_autotune(dgswe_ctx* c, int n_steps, int* chosen, double* ms_per_step) 
   HIPCHK(hipEventCreate(&eb));
   double ms[2] = {0.0, 0.0};
   int err = DGSWE_OK;
-  const int nv = c->prm.p == 3 ? 1 : 2;         // p = 3 has the per-element kernel only
-  for (int v = 0; v < nv && !err; ++v) {
+  for (int v = 0; v < 2 && !err; ++v) {
     c->variant = v;
     c->graph_dirty = true;
     err = dgswe_step(c, 2);                     // builds the step graph, warms caches
@@ -1232,7 +1230,7 @@ int dgswe_autotune(dgswe_ctx* c, int n_steps, int* chosen, double* ms_per_step) 
     (void)restore();
     return err;
   }
-  c->variant = (nv == 2 && ms[1] <= ms[0]) ? 1 : 0;
+  c->variant = ms[1] <= ms[0] ? 1 : 0;
   c->graph_dirty = true;
   if (chosen) *chosen = c->variant;
   if (ms_per_step) { ms_per_step[0] = ms[0]; ms_per_step[1] = ms[1]; }

@@ -1120,7 +1120,10 @@ template <typename Real, int P, int FLUX, int LIM>
 __global__ DG_STAGE_ATTR void stage_edge_kernel(const Member<Real>* __restrict__ mem,
                                                           const Tile* __restrict__ tiles, int n_tiles, StageArgs A) {
   constexpr int NP = Tab<P>::NP, NG = Tab<P>::NG;
-  constexpr int NN = P == 1 ? 3 : 6;                  // point values per variable (vertices, midpoints)
+  // point values per variable (vertices, midpoints); p = 3 keeps its traces
+  // in s_flux instead (each slot holds the element's own trace at that edge
+  // point until phase B overwrites it with the flux there)
+  constexpr int NN = P == 1 ? 3 : P == 2 ? 6 : 1;
   __shared__ Real s_node[3 * NN][TILE];
   __shared__ Real s_hb[3][TILE];
   __shared__ Real s_flux[3 * NG * 3][TILE];            // [(k NG + g) 3 + var][element], scaled by (l/2) w_g
@@ -1173,7 +1176,7 @@ __global__ DG_STAGE_ATTR void stage_edge_kernel(const Member<Real>* __restrict__
 #pragma unroll
     for (int i = 0; i < 3; ++i) tn[i] = ldc(gp(M.tri), i * E, ec);
   }
-  {
+  if constexpr (P <= 2) {
     Real vv[3][3], mv[3][3];
     edge_nodes<Real, P>(d.w, vv, mv);
 #pragma unroll
@@ -1183,6 +1186,15 @@ __global__ DG_STAGE_ATTR void stage_edge_kernel(const Member<Real>* __restrict__
         s_node[v * NN + i][el] = vv[v][i];
         if (P == 2) s_node[v * NN + 3 + i][el] = mv[v][i];
       }
+  } else {
+    static_for<3>([&](auto kc) {
+      constexpr int k = decltype(kc)::value;
+      static_for<NG>([&](auto gc) {
+        constexpr int gg = decltype(gc)::value;
+#pragma unroll
+        for (int v = 0; v < 3; ++v) s_flux[(k * NG + gg) * 3 + v][el] = trace_modal<Real, P, gg>(d.w[v], k);
+      });
+    });
   }
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
@@ -1249,6 +1261,93 @@ __global__ DG_STAGE_ATTR void stage_edge_kernel(const Member<Real>* __restrict__
 
   // ---- phase B: edge fluxes, scaled by (l/2) w_g, into s_flux
   double bout = 0.0, bin = 0.0;
+  if constexpr (P >= 3) {
+    // traces come from s_flux (own side, and the neighbour's when it is in
+    // the tile) or from the neighbour's modes; only the thread of an edge
+    // touches that edge's slots, so it reads them all before writing fluxes
+    for (int it = threadIdx.x; it < n_list; it += TILE) {
+      const uint32_t ent = s_list[it];
+      const int l = ent & 255, k = (ent >> 8) & 3, kn = (ent >> 10) & 3;
+      const int k1 = k == 2 ? 0 : k + 1;
+      const int eg = t0 + l;
+      const bool in_tile = it < n0;
+      const int nb = in_tile ? t0 + int(ent >> 12) : ldc(nbr, k * E, eg);
+      const Real exk = s_ev[2 * k][l], eyk = s_ev[2 * k + 1][l];
+      Real ell, il;
+      edge_length<Real>(exk, eyk, ell, il);
+      const Real nx = eyk * il, ny = -exk * il;
+      const Real half = Real(0.5) * ell;
+      Real tO[3][NG];
+#pragma unroll
+      for (int gg = 0; gg < NG; ++gg)
+#pragma unroll
+        for (int v = 0; v < 3; ++v) tO[v][gg] = s_flux[(k * NG + gg) * 3 + v][l];
+      const Real hA = s_hb[k][l], hB = s_hb[k1][l];
+      if (nb >= 0) {
+        Real tN[3][NG];
+        bool nflag;
+        if (in_tile) {
+          const int ln = nb - t0;
+#pragma unroll
+          for (int gg = 0; gg < NG; ++gg)
+#pragma unroll
+            for (int v = 0; v < 3; ++v) tN[v][gg] = s_flux[(kn * NG + gg) * 3 + v][ln];
+          nflag = s_flag[ln];
+        } else {
+#pragma unroll
+          for (int v = 0; v < 3; ++v) {
+            Real wv[NP];
+#pragma unroll
+            for (int m = 0; m < NP; ++m) wv[m] = ldc(Win, (v * NP + m) * E, nb);
+            static_for<NG>([&](auto gc) {
+              constexpr int gg = decltype(gc)::value;
+              tN[v][gg] = trace_modal<Real, P, gg>(wv, kn);
+            });
+          }
+          nflag = ldx(Fin, nb) & 1;
+        }
+        const bool myflag = s_flag[l];
+        const bool meL = eg < nb;
+        const Real hLa = meL ? hA : hB, hLb = meL ? hB : hA;
+        const Real lnx = meL ? nx : -nx, lny = meL ? ny : -ny;
+        const bool dryL = meL ? myflag : nflag, dryR = meL ? nflag : myflag;
+        static_for<NG>([&](auto gc) {
+          constexpr int gL = decltype(gc)::value;
+          constexpr int gR = NG - 1 - gL;
+          const W3<Real> a{meL ? tO[0][gL] : tN[0][gL], meL ? tO[1][gL] : tN[1][gL], meL ? tO[2][gL] : tN[2][gL]};
+          const W3<Real> b{meL ? tN[0][gR] : tO[0][gR], meL ? tN[1][gR] : tO[1][gR], meL ? tN[2][gR] : tO[2][gR]};
+          const Real hg = Real(lag_(1, 0, gl_t(P, gL))) * hLa + Real(lag_(1, 1, gl_t(P, gL))) * hLb;
+          Real FL[3], FR[3];
+          interior_point<FLUX>(a, b, hg, lnx, lny, g, H0, feps, dryL, dryR, meL, !meL || in_tile, FL, FR);
+          const Real wg = half * Real(gl_w(P, gL));
+          const int gm = meL ? gL : gR;
+#pragma unroll
+          for (int v = 0; v < 3; ++v) s_flux[(k * NG + gm) * 3 + v][l] = wg * (meL ? FL[v] : FR[v]);
+          if (in_tile) {
+#pragma unroll
+            for (int v = 0; v < 3; ++v) s_flux[(kn * NG + gR) * 3 + v][nb - t0] = wg * FR[v];
+          }
+        });
+      } else {
+        const int code = -1 - nb;
+        const int type = code & 3, slot = code >> 2;
+        const Real tide = Real(sc->tide[A.stage][slot]), qr = Real(sc->river[A.stage][slot]);
+        double fm = 0.0;
+        static_for<NG>([&](auto gc) {
+          constexpr int gi = decltype(gc)::value;
+          const W3<Real> a{tO[0][gi], tO[1][gi], tO[2][gi]};
+          const Real hg = Real(lag_(1, 0, gl_t(P, gi))) * hA + Real(lag_(1, 1, gl_t(P, gi))) * hB;
+          Real F[3];
+          boundary_point<FLUX>(a, hg, nx, ny, g, H0, type, tide, qr, F);
+          const Real wg = half * Real(gl_w(P, gi));
+          fm += double(wg * F[0]);
+#pragma unroll
+          for (int v = 0; v < 3; ++v) s_flux[(k * NG + gi) * 3 + v][l] = wg * F[v];
+        });
+        if (fm > 0.0) bout += fm; else bin -= fm;
+      }
+    }
+  } else
   for (int it = threadIdx.x; it < n_list; it += TILE) {
     const uint32_t ent = s_list[it];
     const int l = ent & 255, k = (ent >> 8) & 3, kn = (ent >> 10) & 3;
@@ -1355,6 +1454,24 @@ __global__ DG_STAGE_ATTR void stage_edge_kernel(const Member<Real>* __restrict__
   // ---- phase C: edge contributions, inverse mass, stage combination, post
   Real w0v[3][NP];
   load_blend<Real, P>(M, A, E, ec, w0v);
+  if constexpr (P >= 3) {
+    // expanded at compile time so that every basis value is a constant
+    static_for<3>([&](auto kc) {
+      constexpr int k = decltype(kc)::value;
+      static_for<NG>([&](auto gc) {
+        constexpr int gi = decltype(gc)::value;
+        const Real f0 = s_flux[(k * NG + gi) * 3 + 0][el], f1 = s_flux[(k * NG + gi) * 3 + 1][el],
+                   f2 = s_flux[(k * NG + gi) * 3 + 2][el];
+#pragma unroll
+        for (int m = 0; m < NP; ++m) {
+          const Real ph = Real(B<P>::EG(k, gi, m));
+          acc[0][m] -= ph * f0;
+          acc[1][m] -= ph * f1;
+          acc[2][m] -= ph * f2;
+        }
+      });
+    });
+  } else {
 #pragma unroll
   for (int k = 0; k < 3; ++k)
 #pragma unroll
@@ -1369,6 +1486,7 @@ __global__ DG_STAGE_ATTR void stage_edge_kernel(const Member<Real>* __restrict__
         acc[2][m] -= ph * f2;
       }
     }
+  }
   double rain_part = 0.0;
   if (rain_avg) {
     Rv = Real((rn3[0] + rn3[1] + rn3[2]) / 3.0);
@@ -1989,18 +2107,8 @@ hipError_t launch_stage(int P, int flux, int limiter, int variant, const Member<
   }
   DG_STAGE(1, 0, 0) DG_STAGE(1, 1, 0) DG_STAGE(1, 0, 1) DG_STAGE(1, 1, 1)
   DG_STAGE(2, 0, 0) DG_STAGE(2, 1, 0) DG_STAGE(2, 0, 1) DG_STAGE(2, 1, 1)
+  DG_STAGE(3, 0, 0) DG_STAGE(3, 1, 0) DG_STAGE(3, 0, 1) DG_STAGE(3, 1, 1)
 #undef DG_STAGE
-  // p = 3: the per-element kernel only (the per-edge kernel's LDS staging of
-  // point values is written for traces of degree <= 2)
-#define DG_STAGE3(FF, LL) \
-  if (P == 3 && flux == FF && limiter == LL) { \
-    if (variant != 0) return hipErrorInvalidValue; \
-    if (timed) hipExtLaunchKernelGGL((stage_kernel<Real, 3, FF, LL>), grid, block, 0, s, ev0, ev1, 0, m, t, n, a); \
-    else hipLaunchKernelGGL((stage_kernel<Real, 3, FF, LL>), grid, block, 0, s, m, t, n, a); \
-    return hipGetLastError(); \
-  }
-  DG_STAGE3(0, 0) DG_STAGE3(1, 0) DG_STAGE3(0, 1) DG_STAGE3(1, 1)
-#undef DG_STAGE3
   return hipErrorInvalidValue;
 }
 

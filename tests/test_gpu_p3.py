@@ -7,8 +7,8 @@ Gauss points per edge, SSP(3,3) at CFL 0.1: the generators' default) on the GPU 
   budgets equal;
 * a closed wet basin under a moving storm in FP32 to 1e-4;
 * lake at rest stays at rest;
-* the per-edge kernel is refused for p = 3 and the autotuner keeps the
-  per-element one;
+* both stage kernels (per element; per edge with the tile's traces staged
+  in LDS) in every case; the autotuner times both;
 * a 20,000-triangle window of the benchmark basin: one step from a GPU
   state, every element against the oracle.
 """
@@ -42,12 +42,13 @@ def _mixed(case, **kw):
     return meshgen.small_mixed(seed=5, nx=20, ny=10, p=3, **CASES[case], **kw)
 
 
+@pytest.mark.parametrize("variant", [0, 1])
 @pytest.mark.parametrize("case", list(CASES))
-def test_p3_parity_fp64(dg, case):
+def test_p3_parity_fp64(dg, case, variant):
     sc = _mixed(case)
-    print(f"p=3 case {case}: E={sc.mesh.n_tri}", flush=True)
+    print(f"p=3 case {case} variant {variant}: E={sc.mesh.n_tri}", flush=True)
     gpu = dg.Solver.from_scenario(sc, precision="fp64")
-    assert gpu.variant() == 0
+    gpu.set_variant(variant)
     orc = from_scenario(sc)
     e0 = rel_l2(gpu.state("modal"), orc.w, orc)
     assert e0.max() < 1e-13, e0
@@ -67,7 +68,8 @@ def test_p3_parity_fp64(dg, case):
     gpu.close()
 
 
-def test_p3_closed_basin_storm_fp32(dg):
+@pytest.mark.parametrize("variant", [0, 1])
+def test_p3_closed_basin_storm_fp32(dg, variant):
     rec = [[0.0, 20e3, 40e3, 5000.0, 15e3, 1.4, 1.0, 2.0, 1.0],
            [4.0e3, 60e3, 40e3, 5000.0, 15e3, 1.4, 1.0, 2.0, 1.0]]
     xy, tri, sides = rect_grid(24, 24, 80e3, 80e3, jitter=0.15, rng=np.random.default_rng(5), diagonal="short")
@@ -77,6 +79,7 @@ def test_p3_closed_basin_storm_fp32(dg):
     sc = Scenario("closed_p3", Mesh(xy, tri, hb, np.full(len(hb), 0.025), be, bt, bs), z, z.copy(), z.copy(),
                   default_params(p=3, flux="roe", friction="manning", H0=0.01), met=np.asarray(rec))
     gpu = dg.Solver.from_scenario(sc, precision="fp32")
+    gpu.set_variant(variant)
     orc = from_scenario(sc)
     gpu.step(100)
     orc.step(100)
@@ -87,10 +90,12 @@ def test_p3_closed_basin_storm_fp32(dg):
     gpu.close()
 
 
+@pytest.mark.parametrize("variant", [0, 1])
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-11), ("fp32", 1e-4)])
-def test_p3_lake_at_rest(dg, precision, tol):
+def test_p3_lake_at_rest(dg, precision, tol, variant):
     sc = meshgen.lake_at_rest(p=3)
     gpu = dg.Solver.from_scenario(sc, precision=precision)
+    gpu.set_variant(variant)
     gpu.step(50)
     v = gpu.state("vertex")
     assert np.abs(v[:, 1:]).max() < tol
@@ -98,21 +103,29 @@ def test_p3_lake_at_rest(dg, precision, tol):
     gpu.close()
 
 
-def test_p3_kernel_choice(dg):
-    from paper_2307_14302_amd import _native as N
-    sc = _mixed("roe_gridded")
-    s = dg.Solver.from_scenario(sc)
-    with pytest.raises(N.DgsweError, match="p <= 2"):
-        s.set_variant(1)
-    v, ms = s.autotune(2)
-    assert v == 0 and ms[0] > 0.0 and ms[1] == 0.0
-    s.close()
+def test_p3_kernels_agree_and_autotune(dg):
+    """The two stage kernels differ only in summation order; the autotuner
+    times both and leaves the state as it was."""
+    sc = _mixed("llf_lim_storm")
+    a = dg.Solver.from_scenario(sc, precision="fp64")
+    b = dg.Solver.from_scenario(sc, precision="fp64")
+    a.set_variant(0); b.set_variant(1)
+    a.step(30); b.step(30)
+    err = rel_l2(a.state(), b.state(), from_scenario(sc))
+    assert err.max() < 1e-12, err
+    w = b.state()
+    v, ms = b.autotune(2)
+    assert v in (0, 1) and ms[0] > 0.0 and ms[1] > 0.0
+    assert np.array_equal(b.state(), w)
+    a.close(); b.close()
 
 
+@pytest.mark.parametrize("variant", [0, 1])
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-11), ("fp32", 5e-5)])
-def test_p3_basin_window_one_step(dg, precision, tol):
+def test_p3_basin_window_one_step(dg, precision, tol, variant):
     sc = meshgen.basin_window(100, p=3)
     gpu = dg.Solver.from_scenario(sc, precision=precision)
+    gpu.set_variant(variant)
     gpu.step(10)
     w = gpu.state()
     m0 = gpu.mass()
