@@ -1127,7 +1127,10 @@ __global__ DG_STAGE_ATTR void stage_edge_kernel(const Member<Real>* __restrict__
   __shared__ Real s_node[3 * NN][TILE];
   __shared__ Real s_hb[3][TILE];
   __shared__ Real s_flux[3 * NG * 3][TILE];            // [(k NG + g) 3 + var][element], scaled by (l/2) w_g
-  __shared__ Real s_ev[6][TILE];
+  // edge vectors in LDS, except for FP32 p = 2, where dropping them (phase B
+  // reads them from the cache instead) lets three workgroups share a CU
+  constexpr bool kEvLds = !(P == 2 && sizeof(Real) == 4);
+  __shared__ Real s_ev[kEvLds ? 6 : 1][TILE];
   __shared__ uint8_t s_flag[TILE];
   // edge list; after phase B the same memory holds the block's partial sums
   __shared__ double s_lbuf[3 * TILE / 2];
@@ -1199,8 +1202,10 @@ __global__ DG_STAGE_ATTR void stage_edge_kernel(const Member<Real>* __restrict__
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     s_hb[k][el] = d.hb[k];
-    s_ev[2 * k][el] = d.ex[k];
-    s_ev[2 * k + 1][el] = d.ey[k];
+    if constexpr (kEvLds) {
+      s_ev[2 * k][el] = d.ex[k];
+      s_ev[2 * k + 1][el] = d.ey[k];
+    }
   }
   s_flag[el] = fin & 1;
   // The edges this element evaluates, in three classes listed one after the
@@ -1356,7 +1361,8 @@ __global__ DG_STAGE_ATTR void stage_edge_kernel(const Member<Real>* __restrict__
     const bool in_tile = it < n0;
     // class 0: the neighbour's id is in the entry; otherwise re-read (cached)
     const int nb = in_tile ? t0 + int(ent >> 12) : ldc(nbr, k * E, eg);
-    const Real exk = s_ev[2 * k][l], eyk = s_ev[2 * k + 1][l];
+    const Real exk = kEvLds ? s_ev[2 * k][l] : ldc(gp(M.ev), (2 * k) * E, eg);
+    const Real eyk = kEvLds ? s_ev[2 * k + 1][l] : ldc(gp(M.ev), (2 * k + 1) * E, eg);
     Real ell, il;
     edge_length<Real>(exk, eyk, ell, il);
     const Real nx = eyk * il, ny = -exk * il;
