@@ -689,22 +689,25 @@ DG_DEV void area_terms(const Real (&w)[3][Tab<P>::NP], const Real (&hb)[3], Real
 // kinematic stress and pressure head of t^n are linear in the element, so
 // grad psi is constant; at each area point the momentum rows take
 // tau - g H grad psi with H = zeta + h_b.
-template <typename Real, int P>
-DG_DEV void met_terms(const Member<Real>& M, int E, int ec, const Real (&w)[3][Tab<P>::NP], const Real (&hb)[3],
-                      Real cx0, Real cx1, Real cy0, Real cy1, Real detJ, Real idet, Real g,
-                      Real (&acc)[3][Tab<P>::NP]) {
-  constexpr int NP = Tab<P>::NP;
+// The storm's kinematic wind stress (tx, ty) and pressure head (ps) at the
+// element's three vertices (node ids tn), from the nodal arrays of t^n.
+template <typename Real>
+DG_DEV void met_nodes(const Member<Real>& M, const int (&tn)[3], Real (&tx)[3], Real (&ty)[3], Real (&ps)[3]) {
   const int nn = M.n_nodes;
-  const DG_G int* __restrict__ tri = gp(M.tri);
   const DG_G Real* __restrict__ met = gp(M.met);
-  Real tx[3], ty[3], ps[3];
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
-    const int n = ldc(tri, i * E, ec);
-    tx[i] = ldx(met, n);
-    ty[i] = ldc(met, nn, n);
-    ps[i] = ldc(met, 2 * nn, n);
+    tx[i] = ldx(met, tn[i]);
+    ty[i] = ldc(met, nn, tn[i]);
+    ps[i] = ldc(met, 2 * nn, tn[i]);
   }
+}
+
+template <typename Real, int P>
+DG_DEV void met_terms(const Real (&tx)[3], const Real (&ty)[3], const Real (&ps)[3], const Real (&w)[3][Tab<P>::NP],
+                      const Real (&hb)[3], Real cx0, Real cx1, Real cy0, Real cy1, Real detJ, Real idet, Real g,
+                      Real (&acc)[3][Tab<P>::NP]) {
+  constexpr int NP = Tab<P>::NP;
   const Real pr = Real(0.5) * (ps[1] - ps[0]), pq = Real(0.5) * (ps[2] - ps[0]);
   const Real px = (cx0 * pr + cx1 * pq) * idet, py = (cy0 * pr + cy1 * pq) * idet;
   auto point = [&](Real L0, Real L1, Real L2, Real zq, Real wdet, const Real* Qm) {
@@ -1100,8 +1103,14 @@ __global__ DG_STAGE_ATTR void stage_kernel(const Member<Real>* __restrict__ mem,
   });
   if constexpr (kLateBlend) load_blend<Real, P>(M, A, E, ec, w0v);
   area_terms<Real, P>(d.w, d.hb, d.cx0, d.cx1, d.cy0, d.cy1, d.detJ, d.idet, ldx(gp(M.fric), ec), M.friction, g, H0, acc);
-  if (M.fo.met_kind != MET_NONE)
-    met_terms<Real, P>(M, E, ec, d.w, d.hb, d.cx0, d.cx1, d.cy0, d.cy1, d.detJ, d.idet, g, acc);
+  if (M.fo.met_kind != MET_NONE) {
+    int tn[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) tn[i] = ldc(gp(M.tri), i * E, ec);
+    Real tx[3], ty[3], ps[3];
+    met_nodes<Real>(M, tn, tx, ty, ps);
+    met_terms<Real, P>(tx, ty, ps, d.w, d.hb, d.cx0, d.cx1, d.cy0, d.cy1, d.detJ, d.idet, g, acc);
+  }
   double rain_part;
   const Real Rv = element_rain<Real>(M, A, E, e, ec, valid, d.ex, d.ey, rain_part);
   // lanes past the end of the mesh evaluated a copy of the last element
@@ -1173,12 +1182,16 @@ __global__ DG_STAGE_ATTR void stage_edge_kernel(const Member<Real>* __restrict__
   // (the stored value is read in both cases: a load in one branch only would
   // make the other wait for every load in flight before reusing its register)
   const bool rain_avg = A.stage == 0 && M.fo.rain_kind != RAIN_CONST;
+  const bool met_on = M.fo.met_kind != MET_NONE;
   Real Rv = ldx(gp(M.R), ec);
   int tn[3] = {0, 0, 0};
-  if (rain_avg) {
+  if (rain_avg || met_on) {
 #pragma unroll
     for (int i = 0; i < 3; ++i) tn[i] = ldc(gp(M.tri), i * E, ec);
   }
+  // storm wind and pressure at the vertices, read before phase A's arithmetic
+  Real mtx[3] = {Real(0), Real(0), Real(0)}, mty[3] = {Real(0), Real(0), Real(0)}, mps[3] = {Real(0), Real(0), Real(0)};
+  if (met_on) met_nodes<Real>(M, tn, mtx, mty, mps);
   if constexpr (P <= 2) {
     Real vv[3][3], mv[3][3];
     edge_nodes<Real, P>(d.w, vv, mv);
@@ -1234,8 +1247,7 @@ __global__ DG_STAGE_ATTR void stage_edge_kernel(const Member<Real>* __restrict__
 #pragma unroll
     for (int m = 0; m < NP; ++m) acc[v][m] = Real(0);
   area_terms<Real, P>(d.w, d.hb, d.cx0, d.cx1, d.cy0, d.cy1, d.detJ, d.idet, fric, M.friction, g, H0, acc);
-  if (M.fo.met_kind != MET_NONE)
-    met_terms<Real, P>(M, E, ec, d.w, d.hb, d.cx0, d.cx1, d.cy0, d.cy1, d.detJ, d.idet, g, acc);
+  if (met_on) met_terms<Real, P>(mtx, mty, mps, d.w, d.hb, d.cx0, d.cx1, d.cy0, d.cy1, d.detJ, d.idet, g, acc);
   __syncthreads();
   int base = 0;
 #pragma unroll
