@@ -325,8 +325,8 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=100, help="requests of the 400-request trace to serve")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (see the design notes on sharding); "
-              "run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: the library drives one GPU per process and has no multi-GPU "
+              "path; run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     import torch
     import meshgen

@@ -66,3 +66,14 @@ def test_product_path_has_no_fallback():
     src += open(os.path.join(ROOT, "paper_2307_14302_amd", "solver.py")).read()
     assert "oracle" not in src
     assert "import numpy" in src  # argument marshalling only
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU and says so for --gpus N > 1 (before any
+    device work)."""
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and "--gpus 1" in r.stderr
