@@ -1183,15 +1183,18 @@ __global__ DG_STAGE_ATTR void stage_edge_kernel(const Member<Real>* __restrict__
   // make the other wait for every load in flight before reusing its register)
   const bool rain_avg = A.stage == 0 && M.fo.rain_kind != RAIN_CONST;
   const bool met_on = M.fo.met_kind != MET_NONE;
+  // FP32: the storm's wind and pressure at the vertices are read before
+  // phase A's arithmetic (FP64, with twice the registers per value, reads
+  // them just before the area terms, which measured faster there)
+  constexpr bool kMetEarly = sizeof(Real) == 4;
   Real Rv = ldx(gp(M.R), ec);
   int tn[3] = {0, 0, 0};
-  if (rain_avg || met_on) {
+  if (rain_avg || (kMetEarly && met_on)) {
 #pragma unroll
     for (int i = 0; i < 3; ++i) tn[i] = ldc(gp(M.tri), i * E, ec);
   }
-  // storm wind and pressure at the vertices, read before phase A's arithmetic
   Real mtx[3] = {Real(0), Real(0), Real(0)}, mty[3] = {Real(0), Real(0), Real(0)}, mps[3] = {Real(0), Real(0), Real(0)};
-  if (met_on) met_nodes<Real>(M, tn, mtx, mty, mps);
+  if (kMetEarly && met_on) met_nodes<Real>(M, tn, mtx, mty, mps);
   if constexpr (P <= 2) {
     Real vv[3][3], mv[3][3];
     edge_nodes<Real, P>(d.w, vv, mv);
@@ -1247,7 +1250,15 @@ __global__ DG_STAGE_ATTR void stage_edge_kernel(const Member<Real>* __restrict__
 #pragma unroll
     for (int m = 0; m < NP; ++m) acc[v][m] = Real(0);
   area_terms<Real, P>(d.w, d.hb, d.cx0, d.cx1, d.cy0, d.cy1, d.detJ, d.idet, fric, M.friction, g, H0, acc);
-  if (met_on) met_terms<Real, P>(mtx, mty, mps, d.w, d.hb, d.cx0, d.cx1, d.cy0, d.cy1, d.detJ, d.idet, g, acc);
+  if (met_on) {
+    if constexpr (!kMetEarly) {
+      int tm[3];
+#pragma unroll
+      for (int i = 0; i < 3; ++i) tm[i] = ldc(gp(M.tri), i * E, ec);
+      met_nodes<Real>(M, tm, mtx, mty, mps);
+    }
+    met_terms<Real, P>(mtx, mty, mps, d.w, d.hb, d.cx0, d.cx1, d.cy0, d.cy1, d.detJ, d.idet, g, acc);
+  }
   __syncthreads();
   int base = 0;
 #pragma unroll
