@@ -401,3 +401,38 @@ def test_workspace_bind_places_the_context_in_caller_memory(dg):
     with pytest.raises(N.DgsweError, match="before uploading"):
         t.bind_workspace(ws.data_ptr(), ws.numel())
     t.close()
+
+
+def test_workspace_with_shared_mesh_and_batch(dg):
+    """A mesh uploaded into a bound workspace can be shared by a context that
+    allocates by itself, which keeps running after the first context is
+    destroyed (the workspace tensor stays alive); a bound context steps in a
+    batch bit for bit like the same context alone."""
+    import ctypes as C
+    import torch
+    from paper_2307_14302_amd import _native as N
+    from paper_2307_14302_amd.solver import params_from_dict
+    sc = meshgen.small_mixed(seed=14, nx=20, ny=10, flux="llf", limiter=True, rain_kind="parametric")
+    prm = dict(sc.params, precision="fp32")
+    fp = int(N.lib.dgswe_footprint_bytes(C.byref(params_from_dict(prm)), sc.mesh.n_tri, sc.mesh.n_nodes))
+    ws = torch.empty(fp + (2 << 20), dtype=torch.uint8, device="cuda")
+    a = dg.Solver.from_scenario(sc, precision="fp32", workspace=(ws.data_ptr(), ws.numel()))
+    b = dg.Solver.from_scenario(sc, precision="fp32", mesh_from=a)
+    ref = dg.Solver.from_scenario(sc, precision="fp32")
+    a.close()
+    b.step(25); ref.step(25)
+    assert np.array_equal(b.state(), ref.state())
+    b.close()
+    # a bound member in a batch
+    ws2 = torch.empty(fp + (2 << 20), dtype=torch.uint8, device="cuda")
+    m = dg.Solver.from_scenario(sc, precision="fp32", workspace=(ws2.data_ptr(), ws2.numel()))
+    batch = dg.Batch({"precision": "fp32"})
+    slot = batch.add(m, 25)
+    for _ in range(30):
+        batch.step(1)
+        if batch.poll():
+            break
+    assert batch.poll() == [slot]
+    assert np.array_equal(m.state(), ref.state())
+    batch.retire(slot)
+    batch.close(); m.close(); ref.close()
