@@ -242,7 +242,10 @@ class LoopSolver:
         full = []
         for e in range(self.E):
             hbv = [self.hbn[i] for i in self.tri[e]]
-            full.append(all(sum(w[e][0][m] * T.phi_v[i][m] for m in range(T.np)) + hbv[i] > self.H_dry for i in range(3)))
+            fw = all(sum(w[e][0][m] * T.phi_v[i][m] for m in range(T.np)) + hbv[i] > self.H_dry for i in range(3))
+            if self.p >= 2:
+                fw = fw and w[e][0][0] + (hbv[0] + hbv[1] + hbv[2]) / 3.0 > self.H_dry
+            full.append(fw)
         cen = [tuple(sum(P[i][d] for i in range(3)) / 3.0 for d in range(2)) for P, _, _, _ in self.geo]
         out = [[list(r) for r in we] for we in w]
         pinv = np.linalg.pinv(T.phi_m[:, 1:3])

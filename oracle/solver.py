@@ -51,7 +51,10 @@ Readings of silent or garbled points (also listed in the design notes):
     mirrored), which keeps a dry cell at rest in hydrostatic balance;
     decided per Gauss point; boundary edges ignore the flags;
   * the limiter acts only where the element and its three neighbours have
-    every vertex depth > H0 (no limiting across a wet/dry front);
+    every vertex depth > H0 (no limiting across a wet/dry front), and for
+    p >= 2 also a mean depth > H0 (a curved element can be wet at its
+    vertices and dry on average; the positive-depth pass would then change
+    the means the limiter of its neighbours reads);
   * decision margins: the positive-depth operator itself puts vertices at
     exactly H0, and at a front the mass flux between two such traces is pure
     round-off, so the tests that follow it are ties.  Every "is this vertex
@@ -393,6 +396,11 @@ class OracleSolver:
         if self.use_limiter:
             Hv0 = np.einsum("em,im->ei", w[:, 0, :], T.phi_v) + self.hbv
             full = np.all(Hv0 > self.H_dry, axis=1)
+            if self.p >= 2:
+                # p >= 2: the vertex depths do not bound the mean depth, which
+                # must be wet too (then the positive-depth pass that follows
+                # keeps the element's means, the limiter's neighbour data)
+                full &= (w[:, 0, 0] + self.hbar) > self.H_dry
             nb = self.G["nbr"]
             stencil_wet = full & np.all(np.where(nb >= 0, full[np.maximum(nb, 0)], False), axis=1)
             w = limmod.apply(w, self.G, self.stencil, T, stencil_wet)

@@ -263,6 +263,33 @@ DG_DEV bool surely_wet(const Real (&w)[3][Tab<P>::NP], const Real (&hb)[3], doub
   return ok;
 }
 
+// The limiter's condition on an element (Sec. 2.3 limiter, Sec. 2.4 fronts):
+// every vertex depth above the dry margin and, for p >= 2, the mean depth
+// too (the vertices do not bound the mean of a curved element).  Decided in
+// FP64 as the positive-depth tests are.  A fully-wet element keeps its means
+// through the positive-depth pass that follows the limiter: its mean depth
+// stays above the margin, so at least one vertex stays wet and the discharge
+// means are not zeroed.
+template <typename Real, int P>
+DG_DEV bool fully_wet(const Real (&w)[3][Tab<P>::NP], const Real (&hb)[3], double H0) {
+  constexpr int NP = Tab<P>::NP;
+  const double Hd = dry_depth(H0);
+  // the exact vertex tests are skipped where the element is surely wet
+  bool full = surely_wet<Real, P>(w, hb, Hd);
+  if (!full) {
+    full = true;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      double s = 0.0;
+#pragma unroll
+      for (int m = 0; m < NP; ++m) s += B<P>::V(i, m) * double(w[0][m]);
+      full &= (s + double(hb[i])) > Hd;
+    }
+  }
+  if (P >= 2) full &= (double(w[0][0]) + (double(hb[0]) + double(hb[1]) + double(hb[2])) / 3.0) > Hd;
+  return full;
+}
+
 // need_v: the caller needs hv/qxv/qyv (the CFL speed); otherwise a surely
 // wet element returns at once.  *changed is set when w was modified.  Both
 // operators keep the element means of depth and momentum (redistribution
@@ -838,18 +865,7 @@ DG_DEV void finish_stage(const Member<Real>& M, const StageArgs& A, int tile, in
       for (int v = 0; v < 3; ++v)
 #pragma unroll
         for (int m = 0; m < NP; ++m) stc(Wr, (v * NP + m) * E, e, w[v][m]);
-      bool full = surely_wet<Real, P>(w, hb, dry_depth(M.H0));
-      if (!full) {
-        full = true;
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-          double s = 0.0;
-#pragma unroll
-          for (int m = 0; m < NP; ++m) s += B<P>::V(i, m) * double(w[0][m]);
-          full &= (s + double(hb[i])) > dry_depth(M.H0);
-        }
-      }
-      stx(gp(M.fullwet), e, uint8_t(full ? 1 : 0));
+      stx(gp(M.fullwet), e, uint8_t(fully_wet<Real, P>(w, hb, M.H0) ? 1 : 0));
     }
   }
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -1705,15 +1721,15 @@ __global__ __launch_bounds__(TILE) void classify_kernel(const Member<Real>* __re
   const int E = M.E;
   const int e = tl.tile * TILE + int(threadIdx.x);
   if (e >= E) return;
-  bool full = true;
+  Real w[3][NP], hb[3];
 #pragma unroll
-  for (int i = 0; i < 3; ++i) {
-    double s = 0.0;
-#pragma unroll
-    for (int m = 0; m < NP; ++m) s += B<P>::V(i, m) * double(gp(M.Wt)[(0 * NP + m) * E + e]);
-    full &= (s + double(gp(M.hbv)[i * E + e])) > dry_depth(M.H0);
+  for (int m = 0; m < NP; ++m) {
+    w[0][m] = gp(M.Wt)[(0 * NP + m) * E + e];
+    w[1][m] = w[2][m] = Real(0);
   }
-  gp(M.fullwet)[e] = full ? 1 : 0;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) hb[i] = gp(M.hbv)[i * E + e];
+  gp(M.fullwet)[e] = fully_wet<Real, P>(w, hb, M.H0) ? 1 : 0;
 }
 
 // -------------------------------------------------------------- rain

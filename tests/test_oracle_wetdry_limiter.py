@@ -95,3 +95,41 @@ def test_limiter_flattens_isolated_extremum():
     w[e, 0, 2] = -0.2
     w2 = limiter.apply(w.copy(), G, limiter.stencil(G), T)
     assert w2[e, 0, 0] == 1.0 and w2[e, 0, 1] == 0.0 and w2[e, 0, 2] == 0.0
+
+
+def test_fully_wet_needs_a_wet_mean_at_p2():
+    """A p = 2 element can be wet at its vertices and dry on average (low edge
+    midpoints).  The positive-depth pass truncates it to its linear part and,
+    with the mean below the margin, dries every vertex and zeroes its
+    discharge means.  Such an element is not fully wet, so no neighbour's
+    limiter reads its means; every fully-wet element keeps its means."""
+    s = _limiter_solver()
+    s.p = 2
+    s.T = basis.Tables(2)
+    T = s.T
+    G = s.G
+    s.hb_m = s.hbv @ T.lam_m.T
+    inner = np.nonzero(np.all(G["nbr"] >= 0, axis=1))[0]
+    e = inner[len(inner) // 2]
+    # depth 1 m at every vertex and -0.5 m at every edge midpoint of e, a
+    # uniform current; the rest of the mesh at 0.7 m depth, at rest
+    P6 = np.vstack([T.phi_v, T.phi_m])                   # (6 points, 6 modes)
+    w = np.zeros((s.E, 3, 6))
+    Hpts = np.concatenate([np.full(3, 0.7), np.full(3, 0.7)])
+    for k in range(s.E):
+        hbp = np.concatenate([s.hbv[k], s.hb_m[k]])
+        H = np.concatenate([np.full(3, 1.0), np.full(3, -0.5)]) if k == e else Hpts
+        w[k, 0] = np.linalg.solve(P6, H - hbp)
+    w[e, 1, 0], w[e, 2, 0] = 0.4, -0.3
+    mean_depth = w[e, 0, 0] + s.hbar[e]
+    assert mean_depth < 0 and np.all(T.phi_v @ w[e, 0] + s.hbv[e] > 0.9)
+    s.use_limiter = True
+    s.stencil = limiter.stencil(G)
+    w2, flags = s.post(w)
+    # e itself: truncated, every vertex at the (negative) mean, dry, discharge zeroed
+    assert flags[e] and w2[e, 1, 0] == 0.0 and w2[e, 2, 0] == 0.0
+    # the same definition as the limiter's: vertices and mean above the margin
+    Hv = np.einsum("em,im->ei", w[:, 0], T.phi_v) + s.hbv
+    full = np.all(Hv > s.H_dry, axis=1) & (w[:, 0, 0] + s.hbar > s.H_dry)
+    assert not full[e]
+    assert np.array_equal(w2[full][:, :, 0], w[full][:, :, 0])
