@@ -55,7 +55,10 @@ extern "C" {
 #define DGSWE_ENOMEM     -2   /* device or host allocation failed           */
 #define DGSWE_EHIP       -3   /* a HIP runtime call failed                  */
 #define DGSWE_ESTATE     -4   /* call out of order (e.g. step before mesh)  */
-#define DGSWE_ENONFINITE -5   /* latched: the volume became NaN/Inf         */
+#define DGSWE_ENONFINITE -5   /* latched: an element's state, the volume or
+                                 the time step became NaN/Inf (the message
+                                 and dgswe_mass.bad_element name the first
+                                 element)                                   */
 #define DGSWE_EBUDGET    -6   /* batch admission would exceed the budget    */
 
 #define DGSWE_FP64 0          /* state, fluxes and reductions in FP64       */
@@ -106,6 +109,13 @@ typedef struct dgswe_mass {
   double  bnd_out;      /* cumulative volume leaving through the boundary     */
   int64_t steps;        /* time steps taken                                   */
   int64_t n_dry;        /* elements flagged dry now                           */
+  int64_t n_negative;   /* elements whose mean depth is negative now: the
+                           positive-depth operator of Sec. 2.4 keeps each
+                           element's water volume, so a negative mean is not
+                           clamped; reported as a diagnostic (read only)     */
+  int64_t bad_element;  /* caller's id of the first element whose mean depth
+                           or wave speed became non-finite, -1 if none (read
+                           only)                                            */
 } dgswe_mass;
 
 typedef struct dgswe_ctx dgswe_ctx;
@@ -128,10 +138,12 @@ int dgswe_destroy(dgswe_ctx* ctx);
  * sub-allocator with 256-byte blocks, and the arrays made at creation move
  * there.  The library never frees dev_ptr; the caller keeps it valid until
  * the context, and every context that shares its mesh, is destroyed.
- * Sizing: dgswe_footprint_bytes(params, n_tri, n_nodes) + 64 KiB covers the
- * mesh and state; the forcing tables (storm and wind records, rain lattice)
- * and dgswe_autotune (one more state copy, 3 Np n_tri bytes-per-value +
- * n_tri bytes) need their own room.  Must be called before
+ * Sizing: dgswe_footprint_bytes(params, n_tri, n_nodes) bytes hold the
+ * mesh, the state and everything made at creation; the forcing tables
+ * (storm and wind records, rain lattice and its times, tide and river
+ * series beyond one value each) need their own room, each rounded up to
+ * 256 bytes, and so does dgswe_autotune (one more copy of the state, flags
+ * and tile partials).  Must be called before
  * dgswe_upload_mesh / dgswe_share_mesh, once per context.  EINVAL for a null
  * or unaligned pointer, host memory or less than 64 KiB; ESTATE when a mesh
  * or a workspace is already there or the context is in a batch; a later
@@ -175,16 +187,30 @@ int dgswe_share_mesh(dgswe_ctx* dst, const dgswe_ctx* src);
  * budgets restart.  EINVAL on non-finite input. */
 int dgswe_set_initial_nodal(dgswe_ctx* ctx, const double* zeta, const double* qx, const double* qy);
 
-/* Set the state directly.  layout DGSWE_MODAL: w[n_tri][3][Np] with
- * variables (zeta, qx, qy) and Dubiner modes ordered (0,0),(1,0),(0,1),
- * (2,0),(1,1),(0,2),(3,0),(2,1),(1,2),(0,3) (Np = 3, 6, 10 for p = 1, 2, 3).
- * The state is used as given (no limiter or positive-depth pass); flags and
- * dt are derived from it.  The budgets restart at time t.  EINVAL on
- * non-finite input. */
-int dgswe_set_state(dgswe_ctx* ctx, int layout, const double* w, double t);
+/* Set the state directly, for example to resume from a checkpoint taken
+ * with dgswe_read_state and dgswe_mass_totals (Sec. 3.3 starts its storm run
+ * from a tidal spin-up; Sec. 2.4 accounts for the water volume).
+ *   layout DGSWE_MODAL:  w[n_tri][3][Np] with variables (zeta, qx, qy) and
+ *                        Dubiner modes ordered (0,0),(1,0),(0,1),(2,0),
+ *                        (1,1),(0,2),(3,0),(2,1),(1,2),(0,3) (Np = 3, 6, 10
+ *                        for p = 1, 2, 3);
+ *   layout DGSWE_VERTEX: w[n_tri][3][3], each variable's values at the three
+ *                        vertices; the element takes their linear
+ *                        interpolant (modes beyond the linear ones are zero).
+ * The state is used as given (no limiter or positive-depth pass); flags, the
+ * volume and (unless acc gives it) dt are derived from it.
+ * acc == NULL: the budgets and the step count restart at time t.
+ * acc != NULL: the run continues from these totals: rain_in, bnd_in, bnd_out,
+ * steps, dt_last, and dt_next as the size of the next step (dt_next <= 0:
+ * derived from the state); acc->t must equal t, the other fields are
+ * ignored.  A state and totals read after step n and set again continue
+ * bit for bit as the uninterrupted run.  EINVAL on non-finite input or a bad
+ * layout; ESTATE inside a batch. */
+int dgswe_set_state(dgswe_ctx* ctx, int layout, const double* w, double t, const dgswe_mass* acc);
 
 /* Rain (Sec. 2.3 Eq. rain; Sec. 2.5; Sec. 3.3).  Each replaces the previous
- * rain source.  Nodal rain r[n_nodes] (m/s) is held until replaced.
+ * rain source.  Like every forcing setter below, ESTATE while the context is
+ * a member of a batch (retire it first).  Nodal rain r[n_nodes] (m/s) is held until replaced.
  * Parametric rain: rec[7*n_rec] rows (t, xc, yc, peak, T0, r_m, r_e) with
  * increasing t; parameters are interpolated linearly in time (held outside
  * the record span) and each node gets T0 + (peak - T0) r / r_m inside r_m
@@ -222,14 +248,17 @@ int dgswe_clear_wind(dgswe_ctx* ctx);
 /* Ocean elevation of a slot (Sec. 2.1): mean + sum_k a_k sin(2 pi t/T_k +
  * phase_k), amp_period_phase[3*n_const].  River normal flux of a slot
  * (Eq. river_bc), outward positive, m^2/s, linear in time between samples
- * t[n], q[n] and held outside.  Both are evaluated at every stage time. */
+ * t[n], q[n] and held outside.  Both are evaluated at every stage time.
+ * ESTATE while the context is a member of a batch. */
 int dgswe_set_ocean_tide(dgswe_ctx* ctx, int32_t slot, double mean, int32_t n_const,
                          const double* amp_period_phase);
 int dgswe_set_river_flux(dgswe_ctx* ctx, int32_t slot, int32_t n, const double* t, const double* q);
 
 /* Advance n_steps time steps (asynchronous; see the conventions above). */
 int dgswe_step(dgswe_ctx* ctx, int64_t n_steps);
-/* Wait for queued work; returns the latched device error if any. */
+/* Wait for queued work; returns the latched device error if any
+ * (ENONFINITE, whose message names the first element whose state became
+ * non-finite). */
 int dgswe_sync(dgswe_ctx* ctx);
 
 /* Read the state as FP64 in the caller's element order:
@@ -242,7 +271,13 @@ int dgswe_mass_totals(dgswe_ctx* ctx, dgswe_mass* out);
 /* Mesh and bookkeeping sizes: any pointer may be NULL. */
 int dgswe_info(const dgswe_ctx* ctx, int64_t* n_tri, int64_t* n_nodes, int64_t* n_edges,
                int64_t* n_flipped);
-/* Device bytes a context of this size needs (state, mesh, rain, scratch). */
+/* Device bytes of a context of this size with its own mesh: every array
+ * made by dgswe_create, dgswe_upload_mesh and the state (mesh, three state
+ * buffers and the staged initial state, flags, rain, nodal forcing, tile
+ * lists and partials), each rounded up to 256 bytes; not the forcing tables
+ * beyond one value per series.  A context that shares a mesh needs less.
+ * Batch admission adds these numbers.  Returns DGSWE_EINVAL for bad
+ * params or negative sizes. */
 int64_t dgswe_footprint_bytes(const dgswe_params* params, int64_t n_tri, int64_t n_nodes);
 
 /* Per-kernel timing with HIP events on the context's stream ("stage",

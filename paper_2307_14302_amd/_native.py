@@ -37,7 +37,8 @@ class Params(C.Structure):
 class Mass(C.Structure):
     _fields_ = [("t", C.c_double), ("dt_last", C.c_double), ("dt_next", C.c_double),
                 ("volume", C.c_double), ("rain_in", C.c_double), ("bnd_in", C.c_double),
-                ("bnd_out", C.c_double), ("steps", C.c_int64), ("n_dry", C.c_int64)]
+                ("bnd_out", C.c_double), ("steps", C.c_int64), ("n_dry", C.c_int64),
+                ("n_negative", C.c_int64), ("bad_element", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -64,7 +65,7 @@ SIGNATURES = {
     "dgswe_upload_mesh": (C.c_int, [_P, C.c_int64, _D, _D, _D, C.c_int64, _I, C.c_int64, _I, _I, _I]),
     "dgswe_share_mesh": (C.c_int, [_P, _P]),
     "dgswe_set_initial_nodal": (C.c_int, [_P, _D, _D, _D]),
-    "dgswe_set_state": (C.c_int, [_P, C.c_int, _D, C.c_double]),
+    "dgswe_set_state": (C.c_int, [_P, C.c_int, _D, C.c_double, C.POINTER(Mass)]),
     "dgswe_set_rain_nodal": (C.c_int, [_P, _D]),
     "dgswe_set_rain_parametric": (C.c_int, [_P, C.c_int32, _D]),
     "dgswe_set_rain_gridded": (C.c_int, [_P, C.c_double, C.c_double, C.c_double, C.c_double, C.c_int32,

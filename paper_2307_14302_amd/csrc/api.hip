@@ -466,14 +466,25 @@ int ctx_enqueue_step(dgswe_ctx* c) {
                                    c->prm.p, c->prm.flux, c->prm.limiter, c->variant, c->rk, rain, c->stream, c, true);
 }
 
-int ctx_reduce_init(dgswe_ctx* c) {
+// Set-up reduction (mode 1: dt from the state; mode 2: keep a dt > 0 that is
+// already in the scalars).
+int ctx_reduce_init(dgswe_ctx* c, int mode) {
   if (c->rs == 8)
-    HIPCHK(launch_reduce<double>(c->memb.as<Member<double>>(), nullptr, 1, red_chunks(c->n_tiles), 1,
+    HIPCHK(launch_reduce<double>(c->memb.as<Member<double>>(), nullptr, 1, red_chunks(c->n_tiles), mode,
                                  rk_info(c->rk), c->stream));
   else
-    HIPCHK(launch_reduce<float>(c->memb.as<Member<float>>(), nullptr, 1, red_chunks(c->n_tiles), 1,
+    HIPCHK(launch_reduce<float>(c->memb.as<Member<float>>(), nullptr, 1, red_chunks(c->n_tiles), mode,
                                 rk_info(c->rk), c->stream));
   return DGSWE_OK;
+}
+
+// Message of a latched device error, naming the first element (caller's
+// order) whose state became non-finite when there is one.
+std::string nonfinite_message(const dgswe_ctx* c, const Scalars& s) {
+  std::string m = "the state, the volume or the time step became non-finite";
+  if (c->mesh && s.bad >= 0.0 && s.bad < double(c->mesh->host.E))
+    m += " (first non-finite element: " + std::to_string(c->mesh->host.perm[int64_t(s.bad)]) + ")";
+  return m;
 }
 
 int check_ctx(const dgswe_ctx* c, bool need_mesh = true, bool need_state = false) {
@@ -500,7 +511,8 @@ int refresh_forcing(dgswe_ctx* c) {
   int rc = push_member(c);
   if (rc) return rc;
   if (!c->have_state) return DGSWE_OK;
-  rc = ctx_reduce_init(c);
+  // the forcing of the coming step at the current t and dt
+  rc = ctx_reduce_init(c, 2);
   if (rc) return rc;
   HIPCHK(hipStreamSynchronize(c->stream));
   return DGSWE_OK;
@@ -632,7 +644,7 @@ int post_initial(dgswe_ctx* c, int init) {
     if (init == 1 && c->prm.limiter) HIPCHK(launch_classify<float>(p, m, c->tiles.as<Tile>(), c->n_tiles, c->stream));
     HIPCHK(launch_post<float>(p, init == 1 ? c->prm.limiter : 0, m, c->tiles.as<Tile>(), c->n_tiles, a, init, c->stream));
   }
-  int rc = ctx_reduce_init(c);
+  int rc = ctx_reduce_init(c, init == 1 ? 1 : 2);
   if (rc) return rc;
   HIPCHK(hipStreamSynchronize(c->stream));
   c->have_state = true;
@@ -640,19 +652,33 @@ int post_initial(dgswe_ctx* c, int init) {
   return DGSWE_OK;
 }
 
+// Device bytes of a context with its own mesh: every allocation of
+// dgswe_create, dgswe_upload_mesh and the state, each rounded up to the
+// 256-byte blocks of a bound workspace, as they are made (the forcing
+// tables beyond one value per series, and the autotuner's copy, are not
+// included).
 int64_t footprint(const dgswe_params* p, int64_t E, int64_t n_nodes) {
   const int64_t rs = p->precision == DGSWE_FP32 ? 4 : 8;
   const int64_t NP = p->p == 1 ? 3 : p->p == 2 ? 6 : 10;
-  const int64_t tiles = (E + TILE - 1) / TILE;
-  int64_t b = 4 * 3 * NP * E * rs;                   // W0..W2 + Wt
-  b += 3 * E + (p->limiter ? E : 0);                 // flags, fully-wet bytes
-  b += E * rs;                                       // element rain
-  b += (6 + 3 + 1 + 1) * E * rs;                     // edge vectors, hb, friction, d_in
-  b += 3 * E * 4 + E + 3 * E * 4;                    // neighbours, codes, node ids
-  if (p->limiter) b += 6 * E * rs + E;               // limiter stencil
-  b += 3 * n_nodes * 8;                              // node coordinates, nodal rain
-  b += 3 * n_nodes * rs;                             // nodal wind stress and pressure head
-  b += (NPART * std::max<int64_t>(tiles, 1) + NRED * int64_t(red_chunks(int(tiles))) + 1) * 8 + 4096;
+  const int64_t tiles = (E + TILE - 1) / TILE, node_tiles = (n_nodes + TILE - 1) / TILE;
+  const int64_t nn = std::max<int64_t>(n_nodes, 1);
+  auto blk = [](int64_t n) -> int64_t { return n <= 0 ? 0 : (n + 255) / 256 * 256; };
+  const int64_t memb = int64_t(std::max(sizeof(Member<double>), sizeof(Member<float>)));
+  // made with the context: scalars, member record, member id, one tide and
+  // one river value
+  int64_t b = blk(sizeof(Scalars)) + blk(memb) + blk(sizeof(int)) + 2 * blk(sizeof(double));
+  // mesh: edge vectors, vertex bathymetry, friction, inscribed diameter,
+  // neighbours, edge codes, node ids, node coordinates, limiter stencil
+  b += blk(6 * E * rs) + blk(3 * E * rs) + blk(E * rs) + blk(E * rs) + blk(3 * E * 4) + blk(E) + blk(3 * E * 4) +
+       blk(2 * n_nodes * 8);
+  if (p->limiter) b += blk(6 * E * rs) + blk(E);
+  // state: three buffers and the staged initial state, flags, fully-wet
+  // bytes, element rain, nodal rain, nodal wind and pressure, tile lists,
+  // tile partials with the reduction's records and counter
+  b += 4 * blk(3 * NP * E * rs) + 3 * blk(E) + (p->limiter ? blk(E) : 0) + blk(E * rs);
+  b += blk(nn * 8) + blk(3 * nn * rs);
+  b += blk(std::max<int64_t>(node_tiles, 1) * int64_t(sizeof(Tile))) + blk(std::max<int64_t>(tiles, 1) * int64_t(sizeof(Tile)));
+  b += blk((NPART * std::max<int64_t>(tiles, 1) + NRED * int64_t(red_chunks(int(tiles))) + 1) * 8);
   return b;
 }
 
@@ -839,27 +865,56 @@ int dgswe_set_initial_nodal(dgswe_ctx* c, const double* zeta, const double* qx, 
   return post_initial(c, 1);
 }
 
-int dgswe_set_state(dgswe_ctx* c, int layout, const double* w, double t) {
+int dgswe_set_state(dgswe_ctx* c, int layout, const double* w, double t, const dgswe_mass* acc) {
   int rc = check_ctx(c);
   if (rc) return rc;
   ArenaScope arena_scope(c->arena);
   if (c->in_batch) return fail(DGSWE_ESTATE, "context is a member of a batch");
-  if (layout != DGSWE_MODAL) return fail(DGSWE_EINVAL, "set_state takes DGSWE_MODAL");
+  if (layout != DGSWE_MODAL && layout != DGSWE_VERTEX) return fail(DGSWE_EINVAL, "bad layout");
   if (!std::isfinite(t)) return fail(DGSWE_EINVAL, "non-finite time");
+  if (acc) {
+    if (acc->t != t) return fail(DGSWE_EINVAL, "acc->t differs from t");
+    if (!std::isfinite(acc->rain_in) || !std::isfinite(acc->bnd_in) || !std::isfinite(acc->bnd_out) ||
+        !std::isfinite(acc->dt_last) || !std::isfinite(acc->dt_next) || acc->steps < 0)
+      return fail(DGSWE_EINVAL, "non-finite or negative totals in acc");
+  }
   const HostMesh& h = c->mesh->host;
   const int64_t E = h.E, NP = c->NP();
   if (E > 0 && !w) return fail(DGSWE_EINVAL, "null state array");
-  std::vector<double> wi(size_t(3) * NP * E);
+  std::vector<double> wi(size_t(3) * NP * E, 0.0);
   for (int64_t i = 0; i < E; ++i) {
     const int64_t e = h.perm[i];
-    for (int v = 0; v < 3; ++v)
-      for (int m = 0; m < NP; ++m) {
-        const double x = w[(e * 3 + v) * NP + m];
-        if (!std::isfinite(x)) return fail(DGSWE_EINVAL, "non-finite state value");
-        wi[(v * NP + m) * E + i] = x;
+    for (int v = 0; v < 3; ++v) {
+      if (layout == DGSWE_MODAL) {
+        for (int m = 0; m < NP; ++m) {
+          const double x = w[(e * 3 + v) * NP + m];
+          if (!std::isfinite(x)) return fail(DGSWE_EINVAL, "non-finite state value");
+          wi[(v * NP + m) * E + i] = x;
+        }
+      } else {
+        const double* n = w + (e * 3 + v) * 3;
+        if (!std::isfinite(n[0]) || !std::isfinite(n[1]) || !std::isfinite(n[2]))
+          return fail(DGSWE_EINVAL, "non-finite state value");
+        double md[3];
+        modal_from_vertex(n[0], n[1], n[2], md);
+        for (int m = 0; m < 3; ++m) wi[(v * NP + m) * E + i] = md[m];
       }
+    }
   }
-  rc = reset_scalars(c, t);
+  Scalars s{};
+  s.t = t;
+  s.active = 1;
+  s.target = std::numeric_limits<long long>::max();
+  if (acc) {
+    // continue the budgets, the step count and the step size of the run
+    s.rain_in = acc->rain_in;
+    s.bnd_in = acc->bnd_in;
+    s.bnd_out = acc->bnd_out;
+    s.steps = acc->steps;
+    s.dt_last = acc->dt_last;
+    s.dt = acc->dt_next > 0.0 ? acc->dt_next : 0.0;
+  }
+  rc = write_scalars(c, s);
   if (rc) return rc;
   rc = upload_state(c, wi, c->W[0]);
   if (rc) return rc;
@@ -870,6 +925,7 @@ int dgswe_set_rain_nodal(dgswe_ctx* c, const double* r) {
   int rc = check_ctx(c);
   if (rc) return rc;
   ArenaScope arena_scope(c->arena);
+  if (c->in_batch) return fail(DGSWE_ESTATE, "context is a member of a batch; retire it first");
   const HostMesh& h = c->mesh->host;
   if (h.n_nodes > 0 && !r) return fail(DGSWE_EINVAL, "null rain array");
   for (int64_t i = 0; i < h.n_nodes; ++i)
@@ -891,6 +947,7 @@ int dgswe_clear_rain(dgswe_ctx* c) {
   int rc = check_ctx(c);
   if (rc) return rc;
   ArenaScope arena_scope(c->arena);
+  if (c->in_batch) return fail(DGSWE_ESTATE, "context is a member of a batch; retire it first");
   HIPCHK(hipStreamSynchronize(c->stream));
   if (c->R.bytes) HIPCHK(hipMemset(c->R.p, 0, c->R.bytes));
   HIPCHK(hipMemset(c->part.as<double>() + size_t(P_RAIN) * std::max(c->n_tiles, 1), 0,
@@ -903,6 +960,7 @@ int dgswe_set_rain_parametric(dgswe_ctx* c, int32_t n_rec, const double* rec) {
   int rc = check_ctx(c);
   if (rc) return rc;
   ArenaScope arena_scope(c->arena);
+  if (c->in_batch) return fail(DGSWE_ESTATE, "context is a member of a batch; retire it first");
   if (n_rec < 1 || !rec) return fail(DGSWE_EINVAL, "need at least one storm record");
   for (int i = 0; i < 7 * n_rec; ++i)
     if (!std::isfinite(rec[i])) return fail(DGSWE_EINVAL, "non-finite storm record");
@@ -922,6 +980,7 @@ int dgswe_set_wind_vortex(dgswe_ctx* c, int32_t n_rec, const double* rec) {
   int rc = check_ctx(c);
   if (rc) return rc;
   ArenaScope arena_scope(c->arena);
+  if (c->in_batch) return fail(DGSWE_ESTATE, "context is a member of a batch; retire it first");
   if (n_rec < 1 || !rec) return fail(DGSWE_EINVAL, "need at least one wind record");
   for (int i = 0; i < 9 * n_rec; ++i)
     if (!std::isfinite(rec[i])) return fail(DGSWE_EINVAL, "non-finite wind record");
@@ -944,6 +1003,7 @@ int dgswe_clear_wind(dgswe_ctx* c) {
   int rc = check_ctx(c);
   if (rc) return rc;
   ArenaScope arena_scope(c->arena);
+  if (c->in_batch) return fail(DGSWE_ESTATE, "context is a member of a batch; retire it first");
   HIPCHK(hipStreamSynchronize(c->stream));
   c->fo.met_kind = MET_NONE;
   c->fo.n_wind = 0;
@@ -955,6 +1015,7 @@ int dgswe_set_rain_gridded(dgswe_ctx* c, double x0, double y0, double dx, double
   int rc = check_ctx(c);
   if (rc) return rc;
   ArenaScope arena_scope(c->arena);
+  if (c->in_batch) return fail(DGSWE_ESTATE, "context is a member of a batch; retire it first");
   if (nx < 2 || ny < 2 || n_rec < 1 || !t_rec || !vals) return fail(DGSWE_EINVAL, "lattice needs nx, ny >= 2 and a record");
   if (!(dx > 0.0) || !(dy > 0.0) || !std::isfinite(x0) || !std::isfinite(y0)) return fail(DGSWE_EINVAL, "bad lattice geometry");
   for (int i = 1; i < n_rec; ++i)
@@ -982,6 +1043,7 @@ int dgswe_set_ocean_tide(dgswe_ctx* c, int32_t slot, double mean, int32_t n_cons
   int rc = check_ctx(c, false);
   if (rc) return rc;
   ArenaScope arena_scope(c->arena);
+  if (c->in_batch) return fail(DGSWE_ESTATE, "context is a member of a batch; retire it first");
   if (slot < 0 || slot >= MAX_SLOTS) return fail(DGSWE_EINVAL, "slot out of range");
   if (n_const < 0 || (n_const > 0 && !apt)) return fail(DGSWE_EINVAL, "bad constituent array");
   if (!std::isfinite(mean)) return fail(DGSWE_EINVAL, "non-finite mean level");
@@ -998,6 +1060,7 @@ int dgswe_set_river_flux(dgswe_ctx* c, int32_t slot, int32_t n, const double* t,
   int rc = check_ctx(c, false);
   if (rc) return rc;
   ArenaScope arena_scope(c->arena);
+  if (c->in_batch) return fail(DGSWE_ESTATE, "context is a member of a batch; retire it first");
   if (slot < 0 || slot >= MAX_SLOTS) return fail(DGSWE_EINVAL, "slot out of range");
   if (n < 1 || !t || !q) return fail(DGSWE_EINVAL, "need at least one river sample");
   std::vector<double> rows;
@@ -1062,7 +1125,7 @@ int dgswe_sync(dgswe_ctx* c) {
   Scalars s;
   rc = read_scalars(c, s);
   if (rc) return rc;
-  if (s.error) return fail(DGSWE_ENONFINITE, "the volume or the time step became non-finite");
+  if (s.error) return fail(DGSWE_ENONFINITE, nonfinite_message(c, s));
   return DGSWE_OK;
 }
 
@@ -1131,7 +1194,10 @@ int dgswe_mass_totals(dgswe_ctx* c, dgswe_mass* out) {
   out->bnd_out = s.bnd_out;
   out->steps = s.steps;
   out->n_dry = s.n_dry;
-  if (s.error) return fail(DGSWE_ENONFINITE, "the volume or the time step became non-finite");
+  out->n_negative = s.n_neg;
+  out->bad_element = -1;
+  if (c->mesh && s.bad >= 0.0 && s.bad < double(c->mesh->host.E)) out->bad_element = c->mesh->host.perm[int64_t(s.bad)];
+  if (s.error) return fail(DGSWE_ENONFINITE, nonfinite_message(c, s));
   return DGSWE_OK;
 }
 
@@ -1181,7 +1247,7 @@ int dgswe_autotune(dgswe_ctx* c, int n_steps, int* chosen, double* ms_per_step) 
   Scalars s0;
   rc = read_scalars(c, s0);
   if (rc) return rc;
-  if (s0.error) return fail(DGSWE_ENONFINITE, "the volume or the time step became non-finite");
+  if (s0.error) return fail(DGSWE_ENONFINITE, nonfinite_message(c, s0));
   // what a step carries over: the state, its flags, the tile partials (the
   // rain partial of constant rain is written once) and the scalars
   const size_t wb = c->W[0].bytes, fb = c->F[0].bytes, pb = c->part.bytes;

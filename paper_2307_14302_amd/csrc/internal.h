@@ -16,16 +16,21 @@ constexpr int TILE = 256;          // elements per workgroup (4 wavefronts)
 constexpr int MAX_STAGES = 5;
 constexpr int MAX_SLOTS = 16;
 // per-tile FP64 partial sums: boundary out/in flux per stage, volume,
-// min(d/lambda), rain volume, dry count
-enum PartKind { P_OUT0 = 0, P_IN0 = MAX_STAGES, P_VOL = 2 * MAX_STAGES, P_MINR, P_RAIN, P_NDRY, NPART };
+// min(d/lambda), rain volume, dry count, count of elements with a negative
+// mean depth, smallest element id with a non-finite mean depth or wave
+// speed (infinity if none)
+enum PartKind {
+  P_OUT0 = 0, P_IN0 = MAX_STAGES, P_VOL = 2 * MAX_STAGES, P_MINR, P_RAIN, P_NDRY, P_NNEG, P_BAD, NPART
+};
 enum RainKind { RAIN_CONST = 0, RAIN_PARAM = 1, RAIN_GRID = 2 };
 enum MetKind { MET_NONE = 0, MET_VORTEX = 1 };
 // wind stress and pressure forcing: air and water densities (kg/m^3), cap
 // of the drag coefficient
 constexpr double RHO_AIR = 1.15, RHO_WATER = 1000.0, CD_MAX = 3.5e-3;
 // end-of-step reduction: one workgroup per RED_CHUNK tiles writes a record of
-// NRED doubles (the NPART-style sums and the dt minimum); the last workgroup
-// to finish combines the records in chunk order
+// NRED doubles (the NPART-style sums, the dt minimum and the first
+// non-finite element); the last workgroup to finish combines the records in
+// chunk order
 constexpr int RED_CHUNK = 256;
 constexpr int NRED = 16;
 __host__ __device__ inline int red_chunks(int n_tiles) { return n_tiles > 0 ? (n_tiles + RED_CHUNK - 1) / RED_CHUNK : 1; }
@@ -37,6 +42,8 @@ struct Scalars {
   double t, dt, dt_last;
   double volume, rain_in, bnd_in, bnd_out;
   long long steps, n_dry, target;
+  long long n_neg;                      // elements with a negative mean depth
+  double bad;                           // first element (internal order) with a non-finite state, or inf
   int active, error;
   double tide[MAX_STAGES][MAX_SLOTS];   // ocean level at each stage time
   double river[MAX_STAGES][MAX_SLOTS];  // river normal flux at each stage time
@@ -134,7 +141,9 @@ hipError_t launch_rain(const Member<Real>* d_members, const Tile* d_tiles, int n
                        const Tile* d_node_tiles, int n_node_tiles, hipStream_t s,
                        int single = 0);
 // grid: n_members x max_chunks workgroups (max_chunks = largest red_chunks
-// over the members); d_member_ids == nullptr for a single context (member 0)
+// over the members); d_member_ids == nullptr for a single context (member 0).
+// init: 0 = end of a step; 1 = set-up (dt from the state); 2 = set-up that
+// keeps a dt > 0 already in the scalars (restored or current)
 template <typename Real>
 hipError_t launch_reduce(const Member<Real>* d_members, const int* d_member_ids, int n_members, int max_chunks,
                          int init, const RKInfo& rk, hipStream_t s);

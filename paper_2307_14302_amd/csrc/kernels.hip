@@ -130,6 +130,12 @@ DG_DEV double wave_min(double v) {
   return fmin(fmin(lane_f64(v, 0), lane_f64(v, 16)), fmin(lane_f64(v, 32), lane_f64(v, 48)));
 }
 
+// Element id of the lowest set lane of a ballot (base = id of lane 0), or
+// infinity when no lane is set.
+DG_DEV double first_lane_id(unsigned long long mask, int base) {
+  return mask ? double(base + __builtin_ctzll(mask)) : __builtin_inf();
+}
+
 // Sums a per-thread value over the workgroup in a fixed order.
 template <int NV>
 DG_DEV void block_sums(double (&v)[NV], double* lds) {
@@ -815,7 +821,7 @@ DG_DEV void load_blend(const Member<Real>& M, const StageArgs& A, int E, int ec,
 }
 
 // Inverse mass, SSP combination, positive-depth operator (LIM = 0) or the
-// fully-wet byte (LIM = 1), stores, and the tile partials (lds: 4 x 6
+// fully-wet byte (LIM = 1), stores, and the tile partials (lds: 4 x 8
 // doubles of the caller's shared memory).
 template <typename Real, int P, int LIM>
 DG_DEV void finish_stage(const Member<Real>& M, const StageArgs& A, int tile, int e, int ec, bool valid, int E,
@@ -836,6 +842,7 @@ DG_DEV void finish_stage(const Member<Real>& M, const StageArgs& A, int tile, in
 #pragma unroll
     for (int m = 0; m < NP; ++m) w[v][m] = km[m] * acc[v][m] + (cb * w[v][m] + ca * w0v[v][m]);
   double part[5] = {bout, bin, 0.0, __builtin_inf(), 0.0};
+  bool neg = false, bad = false;      // negative / non-finite mean depth or speed (last stage)
   if (LIM == 0) {
     double hv[3], qxv[3], qyv[3];
     bool filled;
@@ -853,9 +860,12 @@ DG_DEV void finish_stage(const Member<Real>& M, const StageArgs& A, int tile, in
     if (A.last) {
       const double lam = post_speed<Real, P>(filled, hv, qxv, qyv, w, hb, M.H0, M.g);
       const double area = 0.5 * (double(ex[2]) * double(ey[0]) - double(ex[0]) * double(ey[2]));
-      part[2] = valid ? area * (double(w[0][0]) + (double(hb[0]) + double(hb[1]) + double(hb[2])) / 3.0) : 0.0;
+      const double md = double(w[0][0]) + (double(hb[0]) + double(hb[1]) + double(hb[2])) / 3.0;
+      part[2] = valid ? area * md : 0.0;
       part[3] = (valid && lam > 0.0) ? double(ldx(gp(M.din), ec)) * rcp(lam) : __builtin_inf();
       part[4] = (valid && dry) ? 1.0 : 0.0;
+      neg = valid && md < 0.0;
+      bad = valid && !(__builtin_isfinite(md) && __builtin_isfinite(lam));
     }
   } else {
     if (valid) {
@@ -874,29 +884,33 @@ DG_DEV void finish_stage(const Member<Real>& M, const StageArgs& A, int tile, in
   // most tiles have no boundary edge: skip those sums when the wavefront holds only zeros
   const bool any_b = __any(part[0] != 0.0 || part[1] != 0.0);
   const double s0 = any_b ? wave_sum(part[0]) : 0.0, s1 = any_b ? wave_sum(part[1]) : 0.0;
-  double s2 = 0.0, s4 = 0.0, s5 = 0.0, mn = __builtin_inf();
+  double s2 = 0.0, s4 = 0.0, s5 = 0.0, s6 = 0.0, mn = __builtin_inf(), fb = __builtin_inf();
   if (LIM == 0 && A.last) {
     s2 = wave_sum(part[2]);
     s4 = double(__popcll(__ballot(part[4] != 0.0)));
     mn = wave_min(part[3]);
+    s6 = double(__popcll(__ballot(neg)));
+    fb = first_lane_id(__ballot(bad), tile * TILE + wv * 64);
   }
   if (rain_here) s5 = wave_sum(rain_part);
   if (lane == 0) {
-    lds[wv * 6 + 0] = s0; lds[wv * 6 + 1] = s1; lds[wv * 6 + 2] = s2; lds[wv * 6 + 3] = mn; lds[wv * 6 + 4] = s4;
-    lds[wv * 6 + 5] = s5;
+    double* l = lds + wv * 8;
+    l[0] = s0; l[1] = s1; l[2] = s2; l[3] = mn; l[4] = s4; l[5] = s5; l[6] = s6; l[7] = fb;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
     DG_G double* __restrict__ pt = gp(M.part);
     const int nt = M.n_tiles;
-    pt[(P_OUT0 + A.stage) * nt + tile] = (lds[0] + lds[6]) + (lds[12] + lds[18]);
-    pt[(P_IN0 + A.stage) * nt + tile] = (lds[1] + lds[7]) + (lds[13] + lds[19]);
+    pt[(P_OUT0 + A.stage) * nt + tile] = (lds[0] + lds[8]) + (lds[16] + lds[24]);
+    pt[(P_IN0 + A.stage) * nt + tile] = (lds[1] + lds[9]) + (lds[17] + lds[25]);
     if (LIM == 0 && A.last) {
-      pt[P_VOL * nt + tile] = (lds[2] + lds[8]) + (lds[14] + lds[20]);
-      pt[P_MINR * nt + tile] = fmin(fmin(lds[3], lds[9]), fmin(lds[15], lds[21]));
-      pt[P_NDRY * nt + tile] = (lds[4] + lds[10]) + (lds[16] + lds[22]);
+      pt[P_VOL * nt + tile] = (lds[2] + lds[10]) + (lds[18] + lds[26]);
+      pt[P_MINR * nt + tile] = fmin(fmin(lds[3], lds[11]), fmin(lds[19], lds[27]));
+      pt[P_NDRY * nt + tile] = (lds[4] + lds[12]) + (lds[20] + lds[28]);
+      pt[P_NNEG * nt + tile] = (lds[6] + lds[14]) + (lds[22] + lds[30]);
+      pt[P_BAD * nt + tile] = fmin(fmin(lds[7], lds[15]), fmin(lds[23], lds[31]));
     }
-    if (rain_here) pt[P_RAIN * nt + tile] = (lds[5] + lds[11]) + (lds[17] + lds[23]);
+    if (rain_here) pt[P_RAIN * nt + tile] = (lds[5] + lds[13]) + (lds[21] + lds[29]);
   }
 }
 
@@ -939,7 +953,7 @@ template <typename Real, int P, int FLUX, int LIM>
 __global__ DG_STAGE_ATTR void stage_kernel(const Member<Real>* __restrict__ mem,
                                                      const Tile* __restrict__ tiles, int n_tiles, StageArgs A) {
   constexpr int NP = Tab<P>::NP, NG = Tab<P>::NG;
-  __shared__ double lds[4 * 6];                        // finish_stage: six sums per wavefront
+  __shared__ double lds[4 * 8];                        // finish_stage: eight values per wavefront
   const int ti = xcd_tile();
   if (ti >= n_tiles) return;
   const Tile tl = A.single ? Tile{0, ti} : tiles[ti];
@@ -1692,19 +1706,27 @@ __global__ __launch_bounds__(TILE) void post_kernel(const Member<Real>* __restri
     }
     const double area = 0.5 * (double(ex[2]) * double(ey[0]) - double(ex[0]) * double(ey[2]));
     const double lam = post_speed<Real, P>(filled, hv, qxv, qyv, w, hb, M.H0, M.g);
-    double vals[2] = {valid ? area * (double(w[0][0]) + (double(hb[0]) + double(hb[1]) + double(hb[2])) / 3.0) : 0.0,
-                      (valid && dry) ? 1.0 : 0.0};
+    const double md = double(w[0][0]) + (double(hb[0]) + double(hb[1]) + double(hb[2])) / 3.0;
+    const double vol = valid ? area * md : 0.0;
     const double mr = (valid && lam > 0.0) ? double(ldx(gp(M.din), ec)) * rcp(lam) : __builtin_inf();
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const double s0 = wave_sum(vals[0]), s1 = double(__popcll(__ballot(vals[1] != 0.0))), mn = wave_min(mr);
-    if (lane == 0) { lds[wv * 3 + 0] = s0; lds[wv * 3 + 1] = s1; lds[wv * 3 + 2] = mn; }
+    const double s0 = wave_sum(vol), s1 = double(__popcll(__ballot(valid && dry))), mn = wave_min(mr);
+    const double s2 = double(__popcll(__ballot(valid && md < 0.0)));
+    const double fb = first_lane_id(__ballot(valid && !(__builtin_isfinite(md) && __builtin_isfinite(lam))),
+                                    tl.tile * TILE + wv * 64);
+    if (lane == 0) {
+      double* l = lds + wv * 5;
+      l[0] = s0; l[1] = s1; l[2] = mn; l[3] = s2; l[4] = fb;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
       DG_G double* __restrict__ pt = gp(M.part);
       const int nt = M.n_tiles, t = tl.tile;
-      pt[P_VOL * nt + t] = (lds[0] + lds[3]) + (lds[6] + lds[9]);
-      pt[P_NDRY * nt + t] = (lds[1] + lds[4]) + (lds[7] + lds[10]);
-      pt[P_MINR * nt + t] = fmin(fmin(lds[2], lds[5]), fmin(lds[8], lds[11]));
+      pt[P_VOL * nt + t] = (lds[0] + lds[5]) + (lds[10] + lds[15]);
+      pt[P_NDRY * nt + t] = (lds[1] + lds[6]) + (lds[11] + lds[16]);
+      pt[P_MINR * nt + t] = fmin(fmin(lds[2], lds[7]), fmin(lds[12], lds[17]));
+      pt[P_NNEG * nt + t] = (lds[3] + lds[8]) + (lds[13] + lds[18]);
+      pt[P_BAD * nt + t] = fmin(fmin(lds[4], lds[9]), fmin(lds[14], lds[19]));
     }
   }
 }
@@ -1885,11 +1907,14 @@ __global__ __launch_bounds__(TILE) void rain_kernel(const Member<Real>* __restri
 template <typename Real>
 __global__ __launch_bounds__(RED_CHUNK) void reduce_kernel(const Member<Real>* __restrict__ mem,
                                                            const int* __restrict__ ids, int init, RKInfo rk) {
-  constexpr int NV = 3 + 2 * MAX_STAGES;       // sums: volume, rain, dry count, out/in per stage
+  // sums: volume, rain, dry count, out/in per stage, negative-depth count;
+  // minima: d/lambda and the first non-finite element
+  constexpr int NV = 4 + 2 * MAX_STAGES;
+  constexpr int INEG = 3 + 2 * MAX_STAGES;
   constexpr int NW = RED_CHUNK / 64;
   constexpr int NT = RED_CHUNK;                // forcing-table rows staged in LDS, one per thread
-  static_assert(NV + 1 <= NRED, "chunk record too small");
-  __shared__ double lds[NW * (NV + 1)];
+  static_assert(NV + 2 <= NRED, "chunk record too small");
+  __shared__ double lds[NW * (NV + 2)];
   __shared__ double s_storm[7 * NT];
   __shared__ double s_gt[NT];
   __shared__ double s_tide[3 * NT];
@@ -1909,7 +1934,7 @@ __global__ __launch_bounds__(RED_CHUNK) void reduce_kernel(const Member<Real>* _
   const int ns = init ? 0 : rk.n;
   // ---- this chunk's tiles, loaded together with the member's active flag
   double v[NV];
-  double mn;
+  double mn, fb;
   {
     const DG_G double* __restrict__ pt = gp(M.part);
     const int t = chunk * RED_CHUNK + tid;
@@ -1924,6 +1949,8 @@ __global__ __launch_bounds__(RED_CHUNK) void reduce_kernel(const Member<Real>* _
       v[3 + s] = (ok && s < ns) ? pt[(P_OUT0 + s) * nt + tt] : 0.0;
       v[3 + MAX_STAGES + s] = (ok && s < ns) ? pt[(P_IN0 + s) * nt + tt] : 0.0;
     }
+    v[INEG] = ok ? pt[P_NNEG * nt + tt] : 0.0;
+    fb = ok ? pt[P_BAD * nt + tt] : __builtin_inf();
   }
   const bool act = init || sc->active;
   // fixed-order block sums: within each wavefront, then wavefronts 0..NW-1
@@ -1931,23 +1958,30 @@ __global__ __launch_bounds__(RED_CHUNK) void reduce_kernel(const Member<Real>* _
 #pragma unroll
     for (int i = 0; i < NV; ++i) {
       const double x = wave_sum(v[i]);
-      if (lane == 0) lds[wv * (NV + 1) + i] = x;
+      if (lane == 0) lds[wv * (NV + 2) + i] = x;
     }
-    const double m = wave_min(mn);
-    if (lane == 0) lds[wv * (NV + 1) + NV] = m;
+    const double m = wave_min(mn), b = wave_min(fb);
+    if (lane == 0) {
+      lds[wv * (NV + 2) + NV] = m;
+      lds[wv * (NV + 2) + NV + 1] = b;
+    }
     __syncthreads();
     if (tid == 0) {
 #pragma unroll
       for (int i = 0; i < NV; ++i) {
         double x = lds[i];
 #pragma unroll
-        for (int w = 1; w < NW; ++w) x += lds[w * (NV + 1) + i];
+        for (int w = 1; w < NW; ++w) x += lds[w * (NV + 2) + i];
         v[i] = x;
       }
-      double m2 = lds[NV];
+      double m2 = lds[NV], b2 = lds[NV + 1];
 #pragma unroll
-      for (int w = 1; w < NW; ++w) m2 = fmin(m2, lds[w * (NV + 1) + NV]);
+      for (int w = 1; w < NW; ++w) {
+        m2 = fmin(m2, lds[w * (NV + 2) + NV]);
+        b2 = fmin(b2, lds[w * (NV + 2) + NV + 1]);
+      }
       mn = m2;
+      fb = b2;
     }
     __syncthreads();
   };
@@ -1959,6 +1993,7 @@ __global__ __launch_bounds__(RED_CHUNK) void reduce_kernel(const Member<Real>* _
 #pragma unroll
     for (int i = 0; i < NV; ++i) red[chunk * NRED + i] = v[i];
     red[chunk * NRED + NV] = mn;
+    red[chunk * NRED + NV + 1] = fb;
     __threadfence();
     const unsigned done = atomicAdd(M.red_count, 1u);
     s_last = done == unsigned(nch - 1);
@@ -1994,12 +2029,14 @@ __global__ __launch_bounds__(RED_CHUNK) void reduce_kernel(const Member<Real>* _
 #pragma unroll
   for (int i = 0; i < NV; ++i) v[i] = 0.0;
   mn = __builtin_inf();
+  fb = __builtin_inf();
   for (int c = tid; c < nch; c += RED_CHUNK) {
     // records written by other workgroups: device-coherent loads
 #pragma unroll
     for (int i = 0; i < NV; ++i)
       v[i] += __hip_atomic_load(M.red + c * NRED + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     mn = fmin(mn, __hip_atomic_load(M.red + c * NRED + NV, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    fb = fmin(fb, __hip_atomic_load(M.red + c * NRED + NV + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
   }
 #pragma unroll
   for (int k = 0; k < 7; ++k)
@@ -2036,8 +2073,14 @@ __global__ __launch_bounds__(RED_CHUNK) void reduce_kernel(const Member<Real>* _
     }
     sc->volume = v[0];
     sc->n_dry = (long long)(v[2]);
-    const double dtn = M.dt_fixed > 0.0 ? M.dt_fixed : fmin(M.dt_max, M.cfl * mn);
-    const bool bad = !(v[0] == v[0]) || v[0] == __builtin_inf() || v[0] == -__builtin_inf() || !(dtn > 0.0);
+    sc->n_neg = (long long)(v[INEG]);
+    sc->bad = fb;
+    // init 2 keeps a step already set (restored from a checkpoint, or the
+    // current one when forcing changes between steps)
+    const double dtn = M.dt_fixed > 0.0 ? M.dt_fixed
+                       : (init == 2 && dt0 > 0.0) ? dt0 : fmin(M.dt_max, M.cfl * mn);
+    const bool bad = !(v[0] == v[0]) || v[0] == __builtin_inf() || v[0] == -__builtin_inf() || !(dtn > 0.0) ||
+                     fb != __builtin_inf();
     if (bad) sc->error = 1;
     if (bad || steps >= target0) sc->active = 0;
     sc->dt = dtn;

@@ -92,9 +92,19 @@ class Solver:
         z, a, b = _f64(zeta), _f64(qx), _f64(qy)
         call("dgswe_set_initial_nodal", self.h, dptr(z), dptr(a), dptr(b))
 
-    def set_state(self, w, t: float = 0.0):
+    def set_state(self, w, t: float = 0.0, totals: Optional[Dict[str, float]] = None, layout: str = "modal"):
+        """State (modal (n_tri, 3, Np) or vertex (n_tri, 3, 3) values) at time
+        t; ``totals`` (a dict as returned by :meth:`mass`) continues the
+        budgets, step count and step size of an earlier run."""
         w = _f64(w)
-        call("dgswe_set_state", self.h, N.MODAL, dptr(w), float(t))
+        acc = None
+        if totals is not None:
+            m = N.Mass()
+            for k, _ in N.Mass._fields_:
+                if k in totals:
+                    setattr(m, k, totals[k])
+            acc = C.byref(m)
+        call("dgswe_set_state", self.h, N.MODAL if layout == "modal" else N.VERTEX, dptr(w), float(t), acc)
 
     def set_rain(self, rain: Optional[Dict[str, object]]):
         kind = (rain or {}).get("kind", "none")

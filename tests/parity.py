@@ -1,6 +1,8 @@
 """Helpers shared by the GPU parity tests (comparison norms only).
 
-Parity norm: at vertex values (p = 1) or area-point values (p = 2),
+Parity norm: at vertex values (p = 1) or at the area quadrature points of
+the degree's own rule (p >= 2: 9 points at p = 2, 16 at p = 3, so that every
+mode of the element enters the comparison),
   err_zeta = ||zeta_gpu - zeta_orc|| / max(||zeta_orc||, 1e-3 sqrt(n) D)
   err_q    = ||q_gpu - q_orc||       / max(||q_orc||,    1e-3 sqrt(n) D c)
 with q the discharge vector (qx, qy) at every point, D the RMS water depth
@@ -8,6 +10,10 @@ of the oracle state and c = sqrt(g D).  The momentum error is taken on the
 vector field, so that a component that vanishes identically (a 1-D flow)
 does not turn round-off into a relative error of order one; the floors keep
 a fluid at rest from dividing by round-off.
+
+Wet/dry flags: where FP32 and the FP64 oracle take a threshold decision on
+different sides, the flip is reported with its margin (the oracle's largest
+vertex depth minus the dry margin H0 (1 + 1e-3)), see :func:`flag_flips`.
 """
 import numpy as np
 
@@ -15,16 +21,16 @@ from oracle import basis
 
 
 def point_values(w, p):
-    """Vertex values (p <= 1) or area-point values (p = 2) of modal states."""
-    if p == 2:
-        T = basis.Tables(2)
+    """Vertex values (p <= 1) or area-point values (p >= 2) of modal states."""
+    if p >= 2:
+        T = basis.Tables(p)
         return np.einsum("evm,mq->evq", w, T.phi_q)
     T = basis.Tables(1)
     return np.einsum("evm,im->evi", w[:, :, :3], T.phi_v)
 
 
 def point_hb(orc):
-    if orc.p == 2:
+    if orc.p >= 2:
         return orc.hb_q
     return orc.hbv
 
@@ -41,3 +47,14 @@ def rel_l2(w_gpu, w_orc, orc, g=9.81):
     ez = np.linalg.norm(a[:, 0] - b[:, 0]) / max(np.linalg.norm(b[:, 0]), fz)
     eq = np.linalg.norm(a[:, 1:] - b[:, 1:]) / max(np.linalg.norm(b[:, 1:]), fq)
     return np.array([ez, eq])
+
+
+def flag_flips(gpu_flags, orc):
+    """Elements whose dry flag differs from the oracle's, with the margin of
+    the oracle's decision: an element is dry when every vertex depth is at
+    most H_dry, so the margin is (largest vertex depth) - H_dry.  Returns
+    (ids, margins)."""
+    g = np.asarray(gpu_flags).astype(bool)
+    ids = np.nonzero(g != orc.flags)[0]
+    Hv = np.einsum("em,im->ei", orc.w[:, 0, :], orc.T.phi_v) + orc.hbv
+    return ids, Hv[ids].max(axis=1) - orc.H_dry

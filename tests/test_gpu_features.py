@@ -75,19 +75,175 @@ def test_bathtub_72h_matches_paper(dg, precision):
     s.close()
 
 
-def test_checkpoint_resume_is_bitwise(dg):
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_checkpoint_resume_is_bitwise(dg, precision):
+    """State and totals read after 60 steps, set into a new context: the next
+    40 steps equal the uninterrupted run bit for bit, in the state, the flags
+    and every field of the totals (budgets, step count, dt)."""
     sc = meshgen.small_mixed(seed=21, nx=24, ny=12, flux="llf", limiter=True, rain_kind="parametric")
-    a = dg.Solver.from_scenario(sc)
+    a = dg.Solver.from_scenario(sc, precision=precision)
     a.step(60)
     w = a.state("modal")
-    t = a.mass()["t"]
+    m60 = a.mass()
     a.step(40)
-    b = dg.Solver.from_scenario(sc)
-    b.set_state(w, t)
+    b = dg.Solver.from_scenario(sc, precision=precision)
+    b.set_state(w, m60["t"], totals=m60)
+    assert b.mass() == m60
     b.step(40)
     assert np.array_equal(a.state(), b.state())
-    assert a.mass()["t"] == b.mass()["t"]
-    a.close(); b.close()
+    assert np.array_equal(a.flags(), b.flags())
+    assert a.mass() == b.mass()
+    # without totals the budgets restart at t
+    c = dg.Solver.from_scenario(sc, precision=precision)
+    c.set_state(w, m60["t"])
+    mc = c.mass()
+    assert mc["t"] == m60["t"] and mc["steps"] == 0 and mc["rain_in"] == 0.0 and mc["volume"] == m60["volume"]
+    from paper_2307_14302_amd import _native as N
+    bad = dict(m60, t=m60["t"] + 1.0)
+    with pytest.raises(N.DgsweError, match="acc->t"):
+        c.set_state(w, m60["t"], totals=bad)
+    a.close(); b.close(); c.close()
+
+
+def test_set_state_vertex_layout(dg):
+    """A state given by vertex values equals the same state given by the modal
+    coefficients of its linear interpolant (p = 1 and p = 2)."""
+    for p in (1, 2):
+        sc = meshgen.small_mixed(seed=22, nx=16, ny=8, p=p, flux="llf", limiter=True)
+        a = dg.Solver.from_scenario(sc)
+        a.step(20)
+        v = a.state("vertex")
+        from oracle import basis
+        wl = np.zeros_like(a.state("modal"))
+        wl[:, :, :3] = np.einsum("mi,evi->evm", basis.Tables(1).V1inv, v)
+        b = dg.Solver.from_scenario(sc)
+        b.set_state(v, 5.0, layout="vertex")
+        c = dg.Solver.from_scenario(sc)
+        c.set_state(wl, 5.0)
+        np.testing.assert_allclose(b.state(), c.state(), rtol=0, atol=1e-14 * np.abs(wl).max())
+        b.step(5); c.step(5)
+        np.testing.assert_allclose(b.state(), c.state(), rtol=0, atol=1e-12 * np.abs(wl).max())
+        a.close(); b.close(); c.close()
+
+
+def test_forcing_setters_refused_in_a_batch(dg):
+    """Forcing of a live batch member cannot change under the batch: every
+    setter returns ESTATE until the member is retired."""
+    from paper_2307_14302_amd import _native as N
+    sc = meshgen.small_mixed(seed=23, nx=12, ny=6, rain_kind="gridded")
+    s = dg.Solver.from_scenario(sc, precision="fp32")
+    b = dg.Batch({"precision": "fp32"})
+    slot = b.add(s, 10)
+    calls = [lambda: s.set_rain({"kind": "none"}),
+             lambda: s.set_rain({"kind": "nodal", "r": np.zeros(sc.mesh.n_nodes)}),
+             lambda: s.set_rain(meshgen.small_mixed(seed=23, nx=12, ny=6, rain_kind="parametric").rain),
+             lambda: s.set_rain(sc.rain),
+             lambda: s.set_wind([[0.0, 0.0, 0.0, 100.0, 1e3, 1.2, 1.0, 0.0, 0.0]]),
+             lambda: s.set_wind(None),
+             lambda: s.set_tide(0, 0.1, []),
+             lambda: s.set_river(1, [0.0, 1.0], [-1.0, -1.0])]
+    for k, f in enumerate(calls):
+        with pytest.raises(N.DgsweError) as ei:
+            f()
+        assert ei.value.code == N.DGSWE_ESTATE, k
+    b.step(3)
+    b.retire(slot)
+    s.set_rain({"kind": "none"})               # allowed again
+    s.step(2)
+    assert s.mass()["steps"] == 5
+    b.close(); s.close()
+
+
+def test_nonfinite_state_names_the_element(dg):
+    """An element whose wave speed overflows latches ENONFINITE at the next
+    reduction; the message and the totals name that element (caller's
+    order)."""
+    from paper_2307_14302_amd import _native as N
+    sc = meshgen.small_mixed(seed=3, nx=8, ny=4)
+    m = sc.mesh
+    depth = sc.zeta0[m.tri].mean(axis=1) + m.hb[m.tri].mean(axis=1)
+    k = int(np.argmax(depth))                          # a wet element
+    # FP64: (1e200)^2 overflows in the wave speed at set-up
+    s = dg.Solver.from_scenario(sc, precision="fp64")
+    w = s.state()
+    w[k, 1, 0] = 1e200
+    s.set_state(w, 0.0)
+    with pytest.raises(N.DgsweError, match=f"first non-finite element: {k}") as ei:
+        s.mass()
+    assert ei.value.code == N.DGSWE_ENONFINITE
+    with pytest.raises(N.DgsweError, match=f"element: {k}"):
+        s.sync()
+    s.close()
+    # FP32: 1e30 is finite, its flux overflows within a step; the named
+    # element lies within two neighbour rings of k (two stages)
+    edges = {}
+    for e, t in enumerate(m.tri):
+        for a in range(3):
+            edges.setdefault(tuple(sorted((t[a], t[(a + 1) % 3]))), []).append(e)
+    nb = {e: set() for e in range(m.n_tri)}
+    for lst in edges.values():
+        if len(lst) == 2:
+            nb[lst[0]].add(lst[1]); nb[lst[1]].add(lst[0])
+    ring = {k} | nb[k]
+    ring = ring | set().union(*(nb[e] for e in ring))
+    s = dg.Solver.from_scenario(sc, precision="fp32")
+    w = s.state()
+    w[k, 1, 0] = 1e30
+    s.set_state(w, 0.0)
+    s.step(1)
+    with pytest.raises(N.DgsweError) as ei:
+        s.sync()
+    assert ei.value.code == N.DGSWE_ENONFINITE
+    import re
+    named = int(re.search(r"element: (\d+)", str(ei.value)).group(1))
+    assert named in ring, (named, k)
+    s.close()
+
+
+def test_negative_mean_depth_is_counted(dg):
+    """Elements with a negative mean depth are counted (not clamped)."""
+    sc = meshgen.small_mixed(seed=3, nx=8, ny=4)
+    s = dg.Solver.from_scenario(sc)
+    w = s.state()
+    assert s.mass()["n_negative"] == 0
+    hbar = sc.mesh.hb[sc.mesh.tri].mean(axis=1)
+    ks = [1, 5, 9]
+    for k in ks:
+        w[k, 0, :] = 0.0
+        w[k, 0, 0] = -hbar[k] - 0.01          # mean depth -1 cm
+    s.set_state(w, 0.0)
+    m = s.mass()
+    assert m["n_negative"] == len(ks) and m["bad_element"] == -1
+    s.close()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_footprint_covers_a_large_mesh_in_a_workspace(dg, precision):
+    """dgswe_footprint_bytes is exact: a workspace of that size plus the room
+    of the forcing tables (one rain record set, rounded to 256 bytes) holds a
+    1.6M-triangle mesh with the limiter, and a step runs in it."""
+    import ctypes as C
+    import torch
+    from paper_2307_14302_amd import _native as N
+    from paper_2307_14302_amd.solver import params_from_dict
+    n = 900
+    xy, tri, sides = meshgen.rect_grid(n, n, 200e3, 200e3, diagonal="short")
+    be = np.concatenate(list(sides.values()))
+    prm = dict(precision=precision, p=1, flux="llf", limiter=True, H0=0.05, cfl=0.3)
+    fp = int(N.lib.dgswe_footprint_bytes(C.byref(params_from_dict(prm)), len(tri), len(xy)))
+    track = meshgen.parametric_track(60e3, 100e3, 5.0, 0.0, 50 * meshgen.MM_PER_HOUR)
+    extra = (track.size * 8 + 255) // 256 * 256
+    ws = torch.empty(fp + extra, dtype=torch.uint8, device="cuda")
+    s = dg.Solver(prm)
+    s.bind_workspace(ws.data_ptr(), ws.numel())
+    s.upload_mesh(xy, np.full(len(xy), 10.0), np.full(len(xy), 0.025), tri, be, np.zeros(len(be)), np.zeros(len(be)))
+    s.set_rain({"kind": "parametric", "records": track})
+    s.set_initial_nodal(np.zeros(len(xy)), np.zeros(len(xy)), np.zeros(len(xy)))
+    s.step(2)
+    m = s.mass()
+    assert m["steps"] == 2 and m["rain_in"] > 0.0
+    s.close()
+    del ws
 
 
 def _member(dg, sc, precision="fp32", **over):

@@ -1,0 +1,143 @@
+"""GPU (HIP, gfx950) against the FP64 oracle on the configurations the short
+parity cases leave out:
+
+* 1000 steps with the slope limiter on and wet/dry fronts (Sec. 2.3
+  limiter, Sec. 2.4 wetting and drying): a window of the basin across its
+  coast with dry land, and the small instance of the graded coastal mesh
+  (tides, rivers, gridded rain); FP64 to 1e-10, FP32 to 1e-4, budgets, and
+  the dry flags (equal in FP64; in FP32 every flip is reported with the
+  margin of the oracle's decision and must sit at the threshold);
+* FP32 at p = 2 (the per-edge kernel's FP32 p = 2 code path), both stage
+  kernels, with and without the limiter;
+* members of an FP32 ensemble batch (p = 1 and p = 2 together) against the
+  oracle run of each member alone.
+The oracle of each case runs once per module and serves both precisions.
+"""
+import numpy as np
+import pytest
+
+import meshgen
+from oracle.solver import from_scenario
+from tests.parity import flag_flips, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dg():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2307_14302_amd as pkg
+    return pkg
+
+
+def coast_window(N=36, x0=168e3):
+    """N x N piece of the 200 km basin at its own element size across the
+    coast (x from 168 km): ocean, shelf, beach and dry land (about a quarter
+    of the elements dry)."""
+    size = N * 200e3 / 708
+    return meshgen.basin(N, meshgen.seed_for(1), window=(x0, 100e3 - 0.5 * size, size))
+
+
+_ORACLE = {}
+
+
+def oracle_after(key, sc, steps):
+    if (key, steps) not in _ORACLE:
+        o = from_scenario(sc)
+        o.step(steps)
+        _ORACLE[(key, steps)] = o
+    return _ORACLE[(key, steps)]
+
+
+def check_budgets(gpu, orc, rtol):
+    mg, mo = gpu.mass(), orc.mass_totals()
+    for k in ("t", "volume", "rain_in", "bnd_in", "bnd_out"):
+        assert abs(mg[k] - mo[k]) <= rtol * max(1.0, abs(mo[k])), (k, mg[k], mo[k])
+    assert mg["steps"] == mo["steps"]
+
+
+def check_flags(gpu, orc, precision, H0):
+    ids, margins = flag_flips(gpu.flags(), orc)
+    print(f"  flag flips: {len(ids)}" + (f", margins {np.array2string(margins, precision=2)} m" if len(ids) else ""),
+          flush=True)
+    if precision == "fp64":
+        assert len(ids) == 0
+    else:
+        # FP32 states differ from the oracle by ~1e-6 of the depth: a flip is
+        # only allowed where the oracle's decision was that close to H_dry
+        assert len(ids) <= max(2, orc.E // 500)
+        assert np.all(np.abs(margins) <= 1e-2 * H0), margins
+
+
+LONG = {"coast_window": coast_window, "graded_small": meshgen.graded_small}
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("case", list(LONG))
+def test_thousand_steps_limiter_and_fronts(dg, case, precision):
+    sc = LONG[case]()
+    assert sc.params["limiter"]
+    print(f"case {case} {precision}: E={sc.mesh.n_tri}, 1000 steps", flush=True)
+    orc = oracle_after(case, sc, 1000)
+    assert orc.flags.sum() > 0.05 * orc.E          # dry land is part of the run
+    gpu = dg.Solver.from_scenario(sc, precision=precision)
+    gpu.step(1000)
+    err = rel_l2(gpu.state(), orc.w, orc)
+    print(f"  rel L2 (zeta, q) = {err}", flush=True)
+    assert err.max() <= (1e-10 if precision == "fp64" else 1e-4), err
+    check_budgets(gpu, orc, 1e-10 if precision == "fp64" else 1e-5)
+    check_flags(gpu, orc, precision, sc.params["H0"])
+    gpu.close()
+
+
+P2 = {
+    "p2_roe_gridded": dict(p=2, flux="roe", limiter=False, rain_kind="gridded"),
+    "p2_llf_param_lim": dict(p=2, flux="llf", limiter=True, rain_kind="parametric"),
+}
+
+
+@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("case", list(P2))
+def test_fp32_p2_sixty_steps(dg, case, variant):
+    sc = meshgen.small_mixed(seed=5, nx=20, ny=10, **P2[case])
+    print(f"case {case} fp32 variant {variant}: E={sc.mesh.n_tri}", flush=True)
+    orc = oracle_after(case, sc, 60)
+    gpu = dg.Solver.from_scenario(sc, precision="fp32")
+    gpu.set_variant(variant)
+    gpu.step(60)
+    err = rel_l2(gpu.state(), orc.w, orc)
+    print(f"  rel L2 (zeta, q) = {err}", flush=True)
+    assert err.max() <= 1e-4, err
+    check_budgets(gpu, orc, 1e-5)
+    check_flags(gpu, orc, "fp32", sc.params["H0"])
+    gpu.close()
+
+
+def test_ensemble_members_against_the_oracle(dg):
+    """An FP32 batch of a p = 1 and a p = 2 basin member and a mixed-boundary
+    case: every member's state after its own step count is within the FP32
+    bar of the oracle run of that member alone."""
+    scs = [meshgen.basin_member(4, 0, 3000.0, p=1), meshgen.basin_member(4, 1, 2000.0, p=2),
+           meshgen.small_mixed(seed=33, nx=20, ny=10, flux="llf", limiter=True, rain_kind="gridded")]
+    steps = [80, 50, 60]
+    members = [dg.Solver.from_scenario(sc, precision="fp32") for sc in scs]
+    b = dg.Batch({"precision": "fp32"})
+    slots = [b.add(m, n) for m, n in zip(members, steps)]
+    for _ in range(100):
+        b.step(5)
+        if len(b.poll()) == len(slots):
+            break
+    assert sorted(b.poll()) == sorted(slots)
+    for k, (sc, n, sl) in enumerate(zip(scs, steps, slots)):
+        orc = oracle_after(f"member{k}", sc, n)
+        w, m = b.read(sl)
+        err = rel_l2(w, orc.w, orc)
+        print(f"member {k} ({sc.name}, p={sc.params['p']}, E={sc.mesh.n_tri}): rel L2 {err}", flush=True)
+        assert err.max() <= 1e-4, (k, err)
+        assert m["steps"] == n and abs(m["t"] - orc.t) <= 1e-6 * orc.t
+    for sl in slots:
+        b.retire(sl)
+    b.close()
+    for s in members:
+        s.close()

@@ -102,3 +102,28 @@ def test_admission_waits_for_memory(dg):
     for r in done:
         w, _ = alone(dg, scs[r.mesh], r)
         assert np.array_equal(r.result, w)
+
+
+def test_served_request_against_the_oracle(dg):
+    """One request of a mix, its modal result against the FP64 oracle run of
+    the same scenario (mesh, initial state, storm track, tide)."""
+    from oracle.solver import OracleSolver
+    from tests.parity import rel_l2
+    scs = pool()
+    reqs = requests(dg, scs, [0.0, 0.0, 0.001])
+    srv = dg.Server(PARAMS, budget_bytes=8 << 30, chunk_steps=7, result_layout="modal")
+    for k, sc in enumerate(scs):
+        m = sc.mesh
+        srv.register_mesh(k, m.xy, m.hb, m.fric, m.tri, m.bedges, m.btype, m.bslot)
+    done = srv.run(reqs)
+    srv.close()
+    r = min(done, key=lambda q: scs[q.mesh].mesh.n_tri)
+    m = scs[r.mesh].mesh
+    prm = {k: v for k, v in PARAMS.items() if k != "precision"}
+    orc = OracleSolver(m.xy, m.tri, m.hb, m.fric, m.bedges, m.btype, m.bslot, rain=r.rain, tides=r.tides, **prm)
+    orc.set_initial_nodal(*r.initial)
+    orc.step(r.n_steps)
+    err = rel_l2(r.result, orc.w, orc)
+    print(f"request {r.id} (E={m.n_tri}, {r.n_steps} steps): rel L2 {err}", flush=True)
+    assert err.max() <= 1e-4, err
+    assert r.mass["steps"] == r.n_steps and abs(r.mass["t"] - orc.t) <= 1e-6 * orc.t
