@@ -41,7 +41,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes(kernel, E, rs, p, a_nonzero, last, limiter):
+def algorithmic_bytes(kernel, E, rs, p, a_nonzero, last, limiter, fused=False):
     """Bytes one launch must move from/to HBM (each array streamed once;
     neighbour gathers are cache traffic and not counted).
 
@@ -49,7 +49,10 @@ def algorithmic_bytes(kernel, E, rs, p, a_nonzero, last, limiter):
            vectors 6 rs, vertex bathymetry 3 rs, friction rs, rain rs,
            neighbour ids 12, edge codes 1, flag 1; writes the new state
            3 Np rs and one flag byte; the last stage without limiter also
-           reads d_in (rs).
+           reads d_in (rs).  A fused stage (it post-processes its input)
+           also reads the limiter weights 6 rs, code 1 and wet byte 1, its
+           neighbour slots 4 and the tile's halo lists (about 0.5 entries
+           of 8 bytes per element), and reads no flag.
     post:  reads the unlimited state 3 Np rs, bathymetry 3 rs, neighbour
            ids 12, limiter weights 6 rs and code 1, wet byte 1; writes the
            state 3 Np rs and a flag; the last stage reads edge vectors and
@@ -61,12 +64,32 @@ def algorithmic_bytes(kernel, E, rs, p, a_nonzero, last, limiter):
         b = st + (st if a_nonzero else 0) + 11 * rs + 14 + st + 1
         if last and not limiter:
             b += rs
+        if fused:
+            b += 6 * rs + 1 + 1 + 4 + 4 - 1
     else:
         b = st + 3 * rs + 12 + 6 * rs + 1 + 1 + st + 1 + (7 * rs if last else 0)
     return E * b
 
 
-def run_precision(sc, precision, steps, warmup, variant=1, events=2):
+def step_bytes(E, n_nodes, rs, p, stages, limiter, fused, node_forcing=True):
+    """Algorithmic bytes of one whole step (every launch): the stages (the
+    first blends no w^n for the SSP schemes used), the post passes (after
+    the last stage only when fused, else after every stage, when the limiter
+    is on), the nodal forcing pass (16 B read and 8 B written per node) and
+    the reduction (13 doubles per tile)."""
+    b = 0
+    for i in range(stages):
+        last = i == stages - 1
+        b += algorithmic_bytes("stage", E, rs, p, i > 0, last, limiter, fused and i > 0)
+        if limiter and (last or not fused):
+            b += algorithmic_bytes("post", E, rs, p, False, last, limiter)
+    if node_forcing:
+        b += 24 * n_nodes
+    b += 13 * 8 * ((E + 255) // 256)
+    return b
+
+
+def run_precision(sc, precision, steps, warmup, variant=1, events=2, save_dir=None, fused=-1):
     from paper_2307_14302_amd import Solver
     import torch
 
@@ -79,8 +102,12 @@ def run_precision(sc, precision, steps, warmup, variant=1, events=2):
         variant, tuned = s.autotune(5)
     else:
         s.set_variant(variant)
-    log(f"[{precision}] setup {time.perf_counter() - t0:.1f}s  E={s.n_tri}  stage variant {variant}"
-        + (f" (autotuned: {tuned[0]:.3f} / {tuned[1]:.3f} ms per step)" if tuned else ""))
+    if fused >= 0:
+        s.set_fused(fused)
+    fused = s.fused()
+    log(f"[{precision}] setup {time.perf_counter() - t0:.1f}s  E={s.n_tri}  stage variant {variant} fused {fused}"
+        + (f" (autotuned ms/step: per-element {tuned[0]:.3f}, per-edge {tuned[1]:.3f}, fused {tuned[2]:.3f})"
+           if tuned else ""))
     s.step(warmup)
     s.sync()
     # events on the stage kernel's own dispatches only: the dominant
@@ -118,8 +145,19 @@ def run_precision(sc, precision, steps, warmup, variant=1, events=2):
         graph = {"value": round(E * stages * gsteps / gel, 1), "ms_per_step": round(gel / gsteps * 1e3, 4),
                  "steps": gsteps}
         log(f"[{precision}] graph replay: {gsteps} steps in {gel:.3f}s -> {E * stages * gsteps / gel:.4e} element-stage/s")
+    if save_dir:
+        # the state after the run and after one more step, for the oracle's
+        # one-step comparison in the CPU leg
+        m0 = s.mass()
+        np.save(os.path.join(save_dir, f"basin_{precision}_w0.npy"), s.state())
+        with open(os.path.join(save_dir, f"basin_{precision}_m0.json"), "w") as f:
+            json.dump({"t": m0["t"], "dt_next": m0["dt_next"]}, f)
+        s.step(1)
+        np.save(os.path.join(save_dir, f"basin_{precision}_w1.npy"), s.state())
+    n_nodes = s.n_nodes
     s.close()
-    return dict(rate=rate, elapsed=el, stats=stats, mass=m, E=E, stages=stages, variant=variant, graph=graph)
+    return dict(rate=rate, elapsed=el, stats=stats, mass=m, E=E, stages=stages, variant=variant, graph=graph,
+                fused=fused, tuned=tuned, steps=steps, n_nodes=n_nodes)
 
 
 def kernel_sources_hash():
@@ -148,6 +186,21 @@ def counted_traffic(kernel, precision, variant=1):
     return d["bytes"].get(f"{name}/{precision}")
 
 
+def stream_ceiling():
+    """Rate of the library's streaming probe (three arrays read, one written,
+    the stage kernel's read:write mix): with 512 MiB arrays (HBM-resident)
+    and with 32 MiB arrays (the four fit the 256 MB Infinity Cache)."""
+    import ctypes as C
+    from paper_2307_14302_amd import _native as N
+    out = {}
+    for label, nbytes in (("hbm_4x512MiB", 512 << 20), ("mall_4x32MiB", 32 << 20)):
+        g = C.c_double()
+        rc = N.lib.dgswe_stream_probe(3, nbytes, 20, C.byref(g))
+        out[label] = round(g.value, 1) if rc == 0 else None
+    log(f"stream probe (3 read : 1 write): {out} GB/s")
+    return out
+
+
 def roofline(res, precision, p, limiter):
     rs = 4 if precision == "fp32" else 8
     stats = res["stats"]
@@ -158,14 +211,31 @@ def roofline(res, precision, p, limiter):
     # SSP(2,2): stage 0 does not blend w^n, stage 1 does and is the last;
     # SSP(3,3): stages 1 and 2 blend, stage 2 is the last
     ns = res["stages"]
-    per_launch = [algorithmic_bytes(dom, res["E"], rs, p, i > 0, i == ns - 1, limiter) for i in range(ns)]
+    fused = bool(res.get("fused"))
+    per_launch = [algorithmic_bytes(dom, res["E"], rs, p, i > 0, i == ns - 1, limiter, fused and i > 0)
+                  for i in range(ns)]
     byts = sum(per_launch) / len(per_launch)
     avg_s = ms / n * 1e-3
     ach = byts / avg_s / 1e9
-    return {"kernel": dom, "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": counted_traffic(dom, precision, res.get("variant", 1)),
-            "bytes_per_launch": int(byts),
-            "avg_us": round(avg_s * 1e6, 2), "launches": n}
+    traffic = counted_traffic(dom, precision, res.get("variant", 1))
+    out = {"kernel": dom, "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
+           "traffic_source": ("FETCH_SIZE and WRITE_SIZE per launch from the committed rocprofv3 summary "
+                              "profiles/stage_edge_kernel_basin1M_counters.md (same kernel sources), scaled by "
+                              "its copy calibration; not counted in this run") if traffic else
+                             "null: the committed counter summary is for other kernel sources",
+           "bytes_per_launch": int(byts),
+           "avg_us": round(avg_s * 1e6, 2), "launches": n}
+    # the whole step against the same peak: every launch's algorithmic bytes
+    # over the measured time per step
+    sb = step_bytes(res["E"], res.get("n_nodes", 0), rs, p, ns, limiter, fused)
+    step_s = res["elapsed"] / res["steps"]
+    out["step"] = {"bytes": int(sb), "ms": round(step_s * 1e3, 4), "achieved": round(sb / step_s / 1e9, 1),
+                   "frac": round(sb / step_s / 1e9 / HBM_PEAK_GBS, 4)}
+    if res.get("graph"):
+        gs = res["graph"]["ms_per_step"] * 1e-3
+        out["step"]["graph_replay_frac"] = round(sb / gs / 1e9 / HBM_PEAK_GBS, 4)
+    return out
 
 
 def run_ensemble(n_members=64, t_sim=120.0, chunk=10, autotune=True):
@@ -200,6 +270,9 @@ def run_ensemble(n_members=64, t_sim=120.0, chunk=10, autotune=True):
             done_at.setdefault(sl, now)
     el = time.perf_counter() - t0
     work = sum(s.n_tri * st * n for s, n, st, _ in members)
+    # algorithmic bytes of every member's steps (each array streamed once
+    # per launch, as for the single-mesh roofline), over the batch's time
+    byts = sum(step_bytes(s.n_tri, s.n_nodes, 4, p, st, True, bool(s.fused())) * n for s, n, st, p in members)
     lat = np.array([done_at[sl] for sl in slots])
     out = {"value": round(work / el, 1), "unit": "element-stage updates/s", "members": len(members),
            "n_tri_total": int(sum(s.n_tri for s, _, _, _ in members)),
@@ -207,8 +280,13 @@ def run_ensemble(n_members=64, t_sim=120.0, chunk=10, autotune=True):
            "t_sim_s": t_sim, "steps_min": int(min(m[1] for m in members)), "steps_max": int(max(m[1] for m in members)),
            "stage_variants": {"per_element": sum(1 for m in members if m[0].variant() == 0),
                               "per_edge": sum(1 for m in members if m[0].variant() == 1)},
+           "fused_members": sum(1 for m in members if m[0].fused()),
            "wall_s": round(el, 3), "p50_latency_s": round(float(np.percentile(lat, 50)), 4),
-           "p99_latency_s": round(float(np.percentile(lat, 99)), 4), "dtype": "f32"}
+           "p99_latency_s": round(float(np.percentile(lat, 99)), 4), "dtype": "f32",
+           "roofline": {"bound": "hbm", "achieved": round(byts / el / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(byts / el / 1e9 / HBM_PEAK_GBS, 4), "bytes": int(byts),
+                        "basis": "algorithmic bytes of every launch of every member step (bench.step_bytes) "
+                                 "over the batch's wall time"}}
     log(f"[ensemble] {work:.3e} element-stages in {el:.2f}s -> {work / el:.4e}/s; latency p50 "
         f"{out['p50_latency_s']}s p99 {out['p99_latency_s']}s")
     for sl in list(slots):
@@ -219,45 +297,60 @@ def run_ensemble(n_members=64, t_sim=120.0, chunk=10, autotune=True):
     return out
 
 
-def run_serving(n_req=100, rate=20.0, budget_gib=24.0, chunk=20):
-    """Poisson arrivals (mean ``rate``/s) of scenarios on a pool of 64 basin
-    meshes (5e3..2e6 triangles, FP32, p = 1, steps of at most 0.5 s),
-    500..5000 steps each, admitted by footprint under an HBM budget,
-    continuous batching.  Latency = arrival -> result (vertex state) on the
-    host."""
+def run_serving(n_req=100, rate=20.0, budget_gib=24.0, chunk=20, light_rate=3.0, light_req=40):
+    """Poisson arrivals of scenarios on a pool of 64 basin meshes (5e3..2e6
+    triangles, FP32, p = 1, steps of at most 0.5 s), 500..5000 steps each,
+    admitted by footprint under an HBM budget, continuous batching.
+    Latency = arrival -> result (vertex state) on the host, split into queue
+    delay (arrival -> admission) and service time (admission -> result).  Two
+    traces: the first ``n_req`` requests at ``rate``/s (about three times
+    what one GPU serves, so requests queue) and ``light_req`` requests of the
+    same kind at ``light_rate``/s (below capacity)."""
     import meshgen
     from paper_2307_14302_amd import Request, Server, latency_summary
     sizes = meshgen.serving_pool_sizes()
-    trace = meshgen.request_trace(n_req=400, rate=rate, n_meshes=len(sizes))[:n_req]
     params = dict(precision="fp32", p=1, flux="llf", friction="manning", limiter=True, cfl=0.3, H0=0.05, dt_max=0.5)
-    srv = Server(params, budget_bytes=int(budget_gib * (1 << 30)), chunk_steps=chunk, keep_results=False)
+    traces = {"overloaded": meshgen.request_trace(n_req=400, rate=rate, n_meshes=len(sizes))[:n_req],
+              "below_capacity": meshgen.request_trace(n_req=light_req, rate=light_rate, n_meshes=len(sizes),
+                                                      config_id=6)}
     t0 = time.perf_counter()
     pool = {}
-    for k in sorted({r["mesh"] for r in trace}):
+    for k in sorted({r["mesh"] for tr in traces.values() for r in tr}):
         N = max(4, int(round(np.sqrt(sizes[k] / 2.0))))
-        sc = meshgen.basin(N, meshgen.seed_for(5, 1000 + k))
-        m = sc.mesh
-        srv.register_mesh(k, m.xy, m.hb, m.fric, m.tri, m.bedges, m.btype, m.bslot)
-        pool[k] = sc
-    log(f"[serving] {len(pool)} pool meshes uploaded in {time.perf_counter() - t0:.1f}s")
-    reqs = [Request(id=r["id"], arrival=r["arrival"], mesh=r["mesh"], n_steps=r["n_steps"],
-                    initial=(pool[r["mesh"]].zeta0, pool[r["mesh"]].qx0, pool[r["mesh"]].qy0),
-                    rain={"kind": "parametric", "records": r["track"]}, tides=dict(pool[r["mesh"]].tides))
-            for r in trace]
-    t0 = time.perf_counter()
-    done = srv.run(reqs)
-    el = time.perf_counter() - t0
-    srv.close()
-    work = sum(r.n_tri * 2 * r.n_steps for r in done)
-    ls = latency_summary(done)
-    out = {"value": round(work / el, 1), "unit": "element-stage updates/s", "requests": len(done),
-           "arrival_rate_per_s": rate, "budget_gib": budget_gib, "chunk_steps": chunk, "makespan_s": round(el, 3),
-           "p50_latency_s": round(ls["p50_s"], 4), "p99_latency_s": round(ls["p99_s"], 4),
-           "mean_latency_s": round(ls["mean_s"], 4), "failed": ls["failed"], "dtype": "f32",
-           "trace": f"first {n_req} of a 400-request seeded trace"}
-    log(f"[serving] {len(done)} requests, {work:.3e} element-stages in {el:.2f}s -> {work / el:.4e}/s; "
-        f"latency p50 {out['p50_latency_s']}s p99 {out['p99_latency_s']}s")
-    return out
+        pool[k] = meshgen.basin(N, meshgen.seed_for(5, 1000 + k))
+    log(f"[serving] {len(pool)} pool meshes generated in {time.perf_counter() - t0:.1f}s")
+    out = {}
+    for name, trace in traces.items():
+        srv = Server(params, budget_bytes=int(budget_gib * (1 << 30)), chunk_steps=chunk, keep_results=False)
+        for k in sorted({r["mesh"] for r in trace}):
+            m = pool[k].mesh
+            srv.register_mesh(k, m.xy, m.hb, m.fric, m.tri, m.bedges, m.btype, m.bslot)
+        reqs = [Request(id=r["id"], arrival=r["arrival"], mesh=r["mesh"], n_steps=r["n_steps"],
+                        initial=(pool[r["mesh"]].zeta0, pool[r["mesh"]].qx0, pool[r["mesh"]].qy0),
+                        rain={"kind": "parametric", "records": r["track"]}, tides=dict(pool[r["mesh"]].tides))
+                for r in trace]
+        t0 = time.perf_counter()
+        done = srv.run(reqs)
+        el = time.perf_counter() - t0
+        srv.close()
+        work = sum(r.n_tri * 2 * r.n_steps for r in done)
+        ls = latency_summary(done)
+        rnd = lambda x: None if x is None else round(x, 4)  # noqa: E731
+        out[name] = {"value": round(work / el, 1), "unit": "element-stage updates/s", "requests": len(done),
+                     "arrival_rate_per_s": rate if name == "overloaded" else light_rate,
+                     "makespan_s": round(el, 3),
+                     "p50_latency_s": rnd(ls["p50_s"]), "p99_latency_s": rnd(ls["p99_s"]),
+                     "mean_latency_s": rnd(ls["mean_s"]),
+                     "queue_p50_s": rnd(ls["queue_p50_s"]), "queue_p99_s": rnd(ls["queue_p99_s"]),
+                     "service_p50_s": rnd(ls["service_p50_s"]), "service_p99_s": rnd(ls["service_p99_s"]),
+                     "failed": ls["failed"]}
+        log(f"[serving/{name}] {len(done)} requests, {work:.3e} element-stages in {el:.2f}s -> {work / el:.4e}/s; "
+            f"latency p50 {out[name]['p50_latency_s']}s p99 {out[name]['p99_latency_s']}s (queue p50 "
+            f"{out[name]['queue_p50_s']}s, service p50 {out[name]['service_p50_s']}s)")
+    res = dict(out["overloaded"])
+    res.update({"budget_gib": budget_gib, "chunk_steps": chunk, "dtype": "f32",
+                "trace": f"first {n_req} of a 400-request seeded trace", "below_capacity": out["below_capacity"]})
+    return res
 
 
 def run_graded(steps=1000, warmup=20):
@@ -271,7 +364,8 @@ def run_graded(steps=1000, warmup=20):
     n, ms = r["stats"]["stage"]
     return {"value": round(r["rate"], 1), "unit": "element-stage updates/s", "n_tri": r["E"], "steps": steps,
             "ms_per_step": round(r["elapsed"] / steps * 1e3, 4), "stage_avg_us": round(ms / max(n, 1) * 1e3, 2),
-            "dt_s": r["mass"]["dt_last"], "dtype": "f32",
+            "dt_s": r["mass"]["dt_last"], "dtype": "f32", "stage_variant": r["variant"], "fused": r["fused"],
+            "roofline": roofline(r, "fp32", 1, True),
             "workload": "graded coast 30 m - 15.36 km, 1229 x 922 km, tides, 3 rivers, gridded rain, LLF, limiter"}
 
 
@@ -289,20 +383,89 @@ def run_storm(N=708, steps=1000, warmup=20):
                         "track: wind stress and pressure gradient"}
 
 
-def cpu_baseline(timeout=600):
-    """The FP64 oracle on one host core: 2 SSP-RK2 steps of the full mesh."""
+def run_c1(outdir):
+    """The 1,024-triangle rain-on-channel workload (1000 SSP-RK2 steps at
+    CFL 0.3) on the GPU in FP64 and FP32: wall time of the 1000 steps, and
+    the final states saved for the oracle comparison of the CPU leg."""
+    import meshgen
+    import torch
+    from paper_2307_14302_amd import Solver
+    sc = meshgen.channel_c1()
+    out = {}
+    for prec in ("fp64", "fp32"):
+        s = Solver.from_scenario(sc, precision=prec)
+        s.sync()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.step(1000)
+        s.sync()
+        el = time.perf_counter() - t0
+        np.save(os.path.join(outdir, f"c1_{prec}.npy"), s.state())
+        out[prec] = {"seconds": round(el, 4), "value": round(sc.mesh.n_tri * 2 * 1000 / el, 1)}
+        s.close()
+    log(f"[c1] 1000 steps: FP64 {out['fp64']['seconds']} s, FP32 {out['fp32']['seconds']} s")
+    return {"workload": "rain on a 100 m x 10 m channel, 1024 triangles, 1000 SSP-RK2 steps, Roe, CFL 0.3",
+            "unit": "element-stage updates/s", **out}
+
+
+def cpu_baseline(outdir, basin_state=None, timeout=900):
+    """The FP64 oracle on one host core (OMP/OpenBLAS/MKL threads = 1):
+
+    * the bench workload: 2 SSP-RK2 steps of the full basin, started from
+      the GPU's FP32 state after the timed run (timed; the first step is also
+      compared with the GPU's FP32 step from that state: the FP32 error);
+    * the channel workload: all 1000 steps from its initial state, in CPU
+      seconds, and the GPU's final FP64 and FP32 states against it."""
     code = r"""
 import json, os, sys, time
+import numpy as np
 sys.path.insert(0, %r)
 import meshgen
+from oracle import basis
 from oracle.solver import from_scenario
+outdir = %r
+
+def rel_l2(wg, o):
+    # vertex values; momentum as a vector; floors as in the parity tests
+    P = basis.Tables(1).phi_v
+    a = np.einsum("evm,im->evi", wg[:, :, :3], P); b = np.einsum("evm,im->evi", o.w[:, :, :3], P)
+    H = b[:, 0] + o.hbv
+    D = max(np.sqrt(np.mean(H * H)), 1e-3); n = H.size
+    fz = 1e-3 * np.sqrt(n) * D; fq = fz * np.sqrt(9.81 * D)
+    ez = np.linalg.norm(a[:, 0] - b[:, 0]) / max(np.linalg.norm(b[:, 0]), fz)
+    eq = np.linalg.norm(a[:, 1:] - b[:, 1:]) / max(np.linalg.norm(b[:, 1:]), fq)
+    return [float(ez), float(eq)]
+
+res = {}
+sc = meshgen.channel_c1()
+o = from_scenario(sc)
+t0 = time.perf_counter()
+o.step(1000)
+res["c1_seconds"] = time.perf_counter() - t0
+res["c1_E"] = o.E
+for prec in ("fp64", "fp32"):
+    f = os.path.join(outdir, "c1_%%s.npy" %% prec)
+    if os.path.exists(f):
+        res["c1_err_" + prec] = rel_l2(np.load(f), o)
 sc = meshgen.basin(708)
 s = from_scenario(sc)
+f0 = os.path.join(outdir, "basin_fp32_w0.npy")
+if os.path.exists(f0):
+    m0 = json.load(open(os.path.join(outdir, "basin_fp32_m0.json")))
+    s.set_state(np.load(f0), m0["t"], post=False)
+    s.dt = m0["dt_next"]
+    res["from_gpu_state"] = True
 t0 = time.perf_counter()
-s.step(2)
-el = time.perf_counter() - t0
-print(json.dumps({"E": s.E, "elapsed": el}))
-""" % ROOT
+s.step(1)
+t1 = time.perf_counter()
+if os.path.exists(f0):
+    res["basin_err_fp32"] = rel_l2(np.load(os.path.join(outdir, "basin_fp32_w1.npy")), s)
+t2 = time.perf_counter()
+s.step(1)
+res["E"] = s.E
+res["elapsed"] = (t1 - t0) + (time.perf_counter() - t2)
+print(json.dumps(res))
+""" % (ROOT, outdir)
     env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
     try:
         out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=timeout)
@@ -315,9 +478,22 @@ print(json.dumps({"E": s.E, "elapsed": el}))
             cpu_model = next(l.split(":", 1)[1].strip() for l in f if l.startswith("model name"))
     except Exception:
         pass
-    return {"value": round(r["E"] * 2 * 2 / r["elapsed"], 1), "unit": "element-stage updates/s", "cores": 1,
-            "kind": "oracle", "sample": f"2 SSP-RK2 steps of the full {r['E']}-triangle basin, FP64 NumPy oracle, "
-            f"1 thread ({r['elapsed']:.1f}s)", "host_cpus": os.cpu_count(), "cpu_model": cpu_model}
+    out = {"value": round(r["E"] * 2 * 2 / r["elapsed"], 1), "unit": "element-stage updates/s", "cores": 1,
+           "kind": "oracle", "sample": f"2 SSP-RK2 steps of the full {r['E']}-triangle basin"
+           + (" from the GPU's state after the timed run" if r.get("from_gpu_state") else "")
+           + f", FP64 NumPy oracle, 1 thread ({r['elapsed']:.1f}s)", "host_cpus": os.cpu_count(), "cpu_model": cpu_model,
+           "c1": {"seconds": round(r["c1_seconds"], 3), "steps": 1000,
+                  "value": round(r["c1_E"] * 2 * 1000 / r["c1_seconds"], 1),
+                  "sample": "the whole 1000-step channel run, 1 thread"}}
+    errs = {}
+    if "basin_err_fp32" in r:
+        errs["basin_fp32_one_step_rel_l2"] = r["basin_err_fp32"]
+    for prec in ("fp64", "fp32"):
+        if "c1_err_" + prec in r:
+            errs[f"c1_{prec}_1000_steps_rel_l2"] = r["c1_err_" + prec]
+    if errs:
+        out["gpu_error_vs_oracle"] = dict(errs, norm="relative L2 of (zeta, discharge vector) at the vertices")
+    return out
 
 
 def main():
@@ -329,6 +505,9 @@ def main():
     ap.add_argument("--N", type=int, default=708, help="quads per side (708 -> 1,002,528 triangles)")
     ap.add_argument("--p", type=int, default=1, choices=[1, 2, 3], help="polynomial degree of the basin run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-c1", action="store_true", help="skip the 1024-triangle channel run")
+    ap.add_argument("--fused", type=int, default=-1, choices=[-1, 0, 1],
+                    help="post-processing fused into the next stage: 0 off, 1 on, -1 as the autotuner picks")
     ap.add_argument("--variant", type=int, default=-1,
                     help="stage kernel: 0 per element, 1 per edge, -1 autotuned on the workload (default)")
     ap.add_argument("--calib-copy", action="store_true", help="also run a 1 GiB device copy (counter calibration)")
@@ -353,9 +532,14 @@ def main():
     log(f"workload generated in {time.perf_counter() - t0:.1f}s: {sc.mesh.n_tri} triangles")
     prm = sc.params
     res = {}
+    import tempfile
+    import shutil
+    outdir = tempfile.mkdtemp(prefix="dgswe_bench_")
     for prec in (["fp32", "fp64"] if args.precision == "both" else [args.precision]):
         mode = 0 if args.no_events else (1 if args.events_all else 2)
-        res[prec] = run_precision(sc, prec, args.steps, args.warmup, args.variant, mode)
+        res[prec] = run_precision(sc, prec, args.steps, args.warmup, args.variant, mode,
+                                  save_dir=outdir if (prec == "fp32" and not args.no_cpu and args.N == 708
+                                                      and args.p == 1) else None, fused=args.fused)
     if args.calib_copy:
         a = torch.empty(256 * 1024 * 1024, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)
@@ -363,6 +547,7 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         log("calibration copy: 3 x 1 GiB read + 1 GiB written")
+    ceiling = stream_ceiling()
     main_prec = "fp32" if "fp32" in res else "fp64"
     r = res[main_prec]
     out = {
@@ -374,10 +559,16 @@ def main():
                                f"p={args.p}, LLF, limiter on, parametric moving rain, wet/dry front, "
                                + f"SSP-RK{r['stages']} CFL {prm['cfl']}",
                    "n_tri": r["E"], "p": prm["p"], "rk_stages": r["stages"], "precision": main_prec,
-                   "stage_variant": r["variant"],
+                   "stage_variant": r["variant"], "fused_post": r["fused"],
                    "parallelism": "single GPU"},
         "roofline": roofline(r, main_prec, prm["p"], prm["limiter"]),
     }
+    rl = out["roofline"]
+    if rl and ceiling.get("hbm_4x512MiB"):
+        # the measured streaming rate with the same read:write mix, beside the peak
+        rl["ceiling_gbs"] = ceiling["hbm_4x512MiB"]
+        rl["ceiling_mall_gbs"] = ceiling.get("mall_4x32MiB")
+        rl["frac_of_ceiling"] = round(rl["achieved"] / ceiling["hbm_4x512MiB"], 4)
     if r.get("graph"):
         out["graph_replay"] = dict(r["graph"], note="the same run continued with one replayed HIP graph per step and "
                                                     "no per-launch events (not the timed region of value)")
@@ -398,9 +589,12 @@ def main():
             out["ensemble"]["vs_fp64_single_mesh"] = round(out["ensemble"]["value"] / res["fp64"]["rate"], 3)
     if not args.no_serving:
         out["serving"] = run_serving(n_req=args.serve_requests)
+    if not args.no_c1:
+        out["c1"] = run_c1(outdir)
     if not args.no_cpu:
         log("timing the oracle on one host core ...")
-        out["cpu_baseline"] = cpu_baseline()
+        out["cpu_baseline"] = cpu_baseline(outdir)
+    shutil.rmtree(outdir, ignore_errors=True)
     print(json.dumps(out), flush=True)
 
 

@@ -294,17 +294,29 @@ int dgswe_kernel_stats(dgswe_ctx* ctx, const char* kernel, int64_t* launches, do
  * only by summation order).  DGSWE_TUNE_STAGE_VARIANT: 0 = every element
  * evaluates its three edges; 1 (default) = the tile's point values (p <= 2)
  * or edge traces (p = 3) are staged in LDS and each edge inside a tile is
- * evaluated once.  EINVAL for unknown keys or values; ESTATE while the
- * context is in a batch. */
+ * evaluated once.  DGSWE_TUNE_FUSED_POST (limiter on, variant 1, p <= 2):
+ * 1 = every stage after the first applies the previous stage's limiter and
+ * positive-depth operator (Sec. 2.3, Sec. 2.4) to its input itself, for its
+ * tile and the ring of outside elements across the tile's edges, instead of
+ * a separate pass over the whole state; 0 (default) = separate pass after
+ * every stage.  dgswe_autotune times both.  The fused form needs a tile neighbourhood that fits
+ * the kernel's LDS (built at upload; otherwise the key reads back 0).
+ * EINVAL for unknown keys or values; ESTATE while the context is in a
+ * batch. */
 #define DGSWE_TUNE_STAGE_VARIANT 1
+#define DGSWE_TUNE_FUSED_POST    2
 int dgswe_set_tuning(dgswe_ctx* ctx, int key, int value);
 int dgswe_get_tuning(const dgswe_ctx* ctx, int key, int* value);
 
-/* Autotuner: times n_steps steps of this context with each stage-kernel
- * variant (after two untimed steps each), keeps the faster one and restores
- * the state, flags, tile partials and scalars, so the context continues
- * exactly where it was.  chosen (may be NULL) receives the variant,
- * ms_per_step[2] (may be NULL) the two timings.  Allocates a copy of the
+/* Autotuner: times n_steps steps of this context in each configuration
+ * (after two untimed steps each): per-element kernel, per-edge kernel with
+ * a post pass after every stage, per-edge kernel with the post-processing
+ * fused into the next stage (when available); keeps the fastest and
+ * restores the state, flags, tile partials and scalars, so the context
+ * continues exactly where it was.  chosen (may be NULL) receives the stage
+ * variant, ms_per_step[3] (may be NULL) the three timings (0 where a
+ * configuration does not apply); the fused choice reads back through
+ * dgswe_get_tuning.  Allocates a copy of the
  * state for the duration of the call.  EINVAL for n_steps < 1, ESTATE
  * without mesh or state or inside a batch, ENONFINITE if the context has a
  * latched error. */
@@ -340,6 +352,16 @@ int dgswe_batch_retire(dgswe_batch* b, int32_t slot);
 int dgswe_batch_read(dgswe_batch* b, int32_t slot, int layout, double* out, dgswe_mass* mass);
 /* Number of members, summed footprint. Either pointer may be NULL. */
 int dgswe_batch_info(const dgswe_batch* b, int32_t* n_members, int64_t* footprint);
+
+/* Bandwidth probe (measurement aid, not part of a step): a streaming
+ * kernel that reads n_read arrays (1 to 3) and writes one, each `bytes`
+ * long (>= 4096), reps times after one untimed launch, on the current
+ * device; *gbs receives (n_read + 1) * bytes * reps / time in GB/s (1e9
+ * bytes/s), timed with HIP events.  With n_read = 3 it has the stage
+ * kernel's read:write mix, so its rate is the ceiling that kernel's HBM
+ * rate is measured against beside the published peak.  Allocates and frees
+ * its own arrays.  Returns EINVAL, ENOMEM or EHIP (no message is kept). */
+int dgswe_stream_probe(int32_t n_read, int64_t bytes, int32_t reps, double* gbs);
 
 /* Message of the last failed call on this thread ("" if none). */
 const char* dgswe_last_error(void);

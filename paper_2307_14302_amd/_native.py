@@ -20,6 +20,7 @@ LAND, OCEAN, RIVER, OUTFLOW = 0, 1, 2, 3
 MODAL, VERTEX = 0, 1
 MAX_SLOTS = 16
 TUNE_STAGE_VARIANT = 1
+TUNE_FUSED_POST = 2
 
 ERRORS = {
     DGSWE_EINVAL: "EINVAL", DGSWE_ENOMEM: "ENOMEM", DGSWE_EHIP: "EHIP",
@@ -95,6 +96,7 @@ SIGNATURES = {
     "dgswe_batch_retire": (C.c_int, [_P, C.c_int32]),
     "dgswe_batch_read": (C.c_int, [_P, C.c_int32, C.c_int, _D, C.POINTER(Mass)]),
     "dgswe_batch_info": (C.c_int, [_P, _I, _I64]),
+    "dgswe_stream_probe": (C.c_int, [C.c_int32, C.c_int64, C.c_int32, _D]),
     "dgswe_last_error": (C.c_char_p, []),
 }
 

@@ -11,6 +11,7 @@
 #include <iterator>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -192,9 +193,13 @@ struct MeshDev {
   HostMesh host;
   int real_size = 8, p = 1, limiter = 0;
   DevBuf ev, hbv, fric, din, lima, nbr, nk, tri, limc, nxy;
+  // tile halos of the fused stage kernel (limiter on, p <= 2), when every
+  // tile's rings fit its LDS slots
+  bool halo_ok = false;
+  DevBuf h_off, h_n1, h_id, h_nslot, h_eslot;
   size_t device_bytes() const {
     return ev.bytes + hbv.bytes + fric.bytes + din.bytes + lima.bytes + nbr.bytes + nk.bytes + tri.bytes +
-           limc.bytes + nxy.bytes;
+           limc.bytes + nxy.bytes + h_off.bytes + h_n1.bytes + h_id.bytes + h_nslot.bytes + h_eslot.bytes;
   }
 };
 
@@ -217,11 +222,13 @@ struct dgswe_ctx {
   RKTable rk;
   hipStream_t stream = nullptr;
   bool own_stream = false;
+  int device = 0;                   // HIP device current at creation
   std::shared_ptr<MeshDev> mesh;
   std::shared_ptr<Arena> arena;     // caller's device memory (dgswe_workspace_bind), or null
   int n_tiles = 0;
   int variant = 1;                  // stage kernel: 0 per element, 1 per edge
-  DevBuf W[3], Wt, F[3], fullwet, R, part, sc, memb, tiles, ids, rnode, met, node_tiles;
+  int fused = 0;                    // limiter on, per-edge kernel: later stages post-process their input
+  DevBuf W[3], Wt, F[3], fullwet[2], R, part, sc, memb, tiles, ids, rnode, met, node_tiles;
   int n_node_tiles = 0;
   DevBuf storm, gt, gvals, tide_c, riv_tq, wind;
   Forcing fo{};
@@ -250,6 +257,8 @@ struct dgswe_ctx {
   }
   int E() const { return mesh ? int(mesh->host.E) : 0; }
   int NP() const { return prm.p == 1 ? 3 : prm.p == 2 ? 6 : 10; }
+  // the fused stage kernel runs: limiter on, per-edge kernel, a halo built
+  bool use_fused() const { return fused && variant == 1 && prm.limiter && mesh && mesh->halo_ok; }
 };
 
 struct dgswe_batch {
@@ -265,7 +274,7 @@ struct dgswe_batch {
   std::vector<Slot> slots;
   bool dirty = true;
   struct Group {
-    int p, flux, limiter, variant;
+    int p, flux, limiter, variant, fused;
     RKTable rk;
     std::vector<int> members;       // indices into the member array
     int n_tiles = 0, n_node_tiles = 0, max_chunks = 1;
@@ -317,7 +326,15 @@ Member<Real> member_struct(const dgswe_ctx* c) {
     m.F[i] = c->F[i].as<uint8_t>();
   }
   m.Wt = c->Wt.as<Real>();
-  m.fullwet = c->fullwet.as<uint8_t>();
+  m.fullwet[0] = c->fullwet[0].as<uint8_t>();
+  m.fullwet[1] = c->fullwet[1].as<uint8_t>();
+  if (md && md->halo_ok) {
+    m.h_off = md->h_off.as<int>();
+    m.h_n1 = md->h_n1.as<int>();
+    m.h_id = md->h_id.as<int>();
+    m.h_nslot = md->h_nslot.as<uint32_t>();
+    m.h_eslot = md->h_eslot.as<uint32_t>();
+  }
   m.R = c->R.as<Real>();
   m.rn = c->rnode.as<double>();
   m.met = c->met.as<Real>();
@@ -423,10 +440,13 @@ StageArgs stage_args(const RKTable& T, int i) {
 
 // One time step of a set of members sharing (precision, p, flux, limiter,
 // stages): nodal forcing, stages (+ post when limiting), reduce.
+// part_over (single member only): the tile partials, chunk records and
+// reduction counter at this address instead of the member's own arrays.
 template <typename Real>
 int enqueue_step_group(const Member<Real>* d_m, const Tile* d_t, int n_tiles, const Tile* d_nt, int n_node_tiles,
                        const int* d_ids, int n_members, int max_chunks, int p, int flux, int limiter, int variant,
-                       const RKTable& T, bool node_forcing, hipStream_t s, dgswe_ctx* prof, bool single) {
+                       const RKTable& T, bool node_forcing, hipStream_t s, dgswe_ctx* prof, bool single,
+                       double* part_over = nullptr, bool fused = false) {
   if (node_forcing) {
     ProfScope ps(prof, K_RAIN);
     // nodal rain rates, wind stress and pressure head at t^n; the first
@@ -436,34 +456,45 @@ int enqueue_step_group(const Member<Real>* d_m, const Tile* d_t, int n_tiles, co
   for (int i = 0; i < T.n; ++i) {
     StageArgs a = stage_args(T, i);
     a.single = single ? 1 : 0;
+    a.part = part_over;
     if (limiter) {
       // the stage writes its raw output to the stage's buffer; the post
-      // pass limits it there
+      // pass limits it there, or (fused) the next stage does it for itself
       {
         ProfScope ps(prof, K_STAGE, true);
-        HIPCHK(launch_stage<Real>(p, flux, 1, variant, d_m, d_t, n_tiles, a, s, ps.a, ps.b));
+        HIPCHK(launch_stage<Real>(p, flux, 1, variant, d_m, d_t, n_tiles, a, s, ps.a, ps.b, fused && i > 0 ? 1 : 0));
       }
-      ProfScope ps(prof, K_POST);
-      HIPCHK(launch_post<Real>(p, 1, d_m, d_t, n_tiles, a, 0, s));
+      if (!fused || a.last) {
+        ProfScope ps(prof, K_POST);
+        HIPCHK(launch_post<Real>(p, 1, d_m, d_t, n_tiles, a, 0, s));
+      }
     } else {
       ProfScope ps(prof, K_STAGE, true);
       HIPCHK(launch_stage<Real>(p, flux, 0, variant, d_m, d_t, n_tiles, a, s, ps.a, ps.b));
     }
   }
   ProfScope ps(prof, K_REDUCE);
-  HIPCHK(launch_reduce<Real>(d_m, single ? nullptr : d_ids, n_members, max_chunks, 0, rk_info(T), s));
+  HIPCHK(launch_reduce<Real>(d_m, single ? nullptr : d_ids, n_members, max_chunks, 0, rk_info(T), s, part_over));
   return DGSWE_OK;
 }
 
-int ctx_enqueue_step(dgswe_ctx* c) {
+int ctx_enqueue_step(dgswe_ctx* c, double* part_over = nullptr) {
   const bool rain = c->fo.rain_kind != RAIN_CONST || c->fo.met_kind != MET_NONE;
   if (c->rs == 8)
     return enqueue_step_group<double>(c->memb.as<Member<double>>(), c->tiles.as<Tile>(), c->n_tiles,
                                       c->node_tiles.as<Tile>(), c->n_node_tiles, c->ids.as<int>(), 1, red_chunks(c->n_tiles),
-                                      c->prm.p, c->prm.flux, c->prm.limiter, c->variant, c->rk, rain, c->stream, c, true);
+                                      c->prm.p, c->prm.flux, c->prm.limiter, c->variant, c->rk, rain, c->stream, c, true,
+                                      part_over, c->use_fused());
   return enqueue_step_group<float>(c->memb.as<Member<float>>(), c->tiles.as<Tile>(), c->n_tiles,
                                    c->node_tiles.as<Tile>(), c->n_node_tiles, c->ids.as<int>(), 1, red_chunks(c->n_tiles),
-                                   c->prm.p, c->prm.flux, c->prm.limiter, c->variant, c->rk, rain, c->stream, c, true);
+                                   c->prm.p, c->prm.flux, c->prm.limiter, c->variant, c->rk, rain, c->stream, c, true,
+                                   part_over, c->use_fused());
+}
+
+// Doubles of a context's partials array: tile partials, the reduction's
+// chunk records, then its counter.
+size_t part_doubles(int n_tiles) {
+  return size_t(NPART) * std::max(n_tiles, 1) + size_t(NRED) * red_chunks(n_tiles) + 1;
 }
 
 // Set-up reduction (mode 1: dt from the state; mode 2: keep a dt > 0 that is
@@ -555,13 +586,15 @@ int alloc_state(dgswe_ctx* c) {
     HIPCHK(c->F[i].alloc(size_t(E)));
     if (E) HIPCHK(hipMemset(c->F[i].p, 0, size_t(E)));
   }
+  HIPCHK(c->Wt.alloc(st));                     // the initial state, staged before its set-up pass
   if (c->prm.limiter) {
-    HIPCHK(c->Wt.alloc(st));
-    HIPCHK(c->fullwet.alloc(size_t(E)));
+    // fully-wet bytes of a stage's raw output, two buffers: a fused stage
+    // reads the previous stage's while it writes its own
+    HIPCHK(c->fullwet[0].alloc(size_t(E)));
+    HIPCHK(c->fullwet[1].alloc(size_t(E)));
   } else {
-    // the initial positive-depth pass stages its input in Wt
-    HIPCHK(c->Wt.alloc(st));
-    c->fullwet.release();
+    c->fullwet[0].release();
+    c->fullwet[1].release();
   }
   HIPCHK(c->R.alloc(size_t(E) * c->rs));
   if (E) HIPCHK(hipMemset(c->R.p, 0, size_t(E) * c->rs));
@@ -577,8 +610,7 @@ int alloc_state(dgswe_ctx* c) {
   HIPCHK(upload(c->node_tiles, ntl));
   c->n_tiles = int((E + TILE - 1) / TILE);
   // tile partials, then the reduction's chunk records, then its counter
-  const size_t pb = (size_t(NPART) * std::max(c->n_tiles, 1) + size_t(NRED) * red_chunks(c->n_tiles) + 1) *
-                    sizeof(double);
+  const size_t pb = part_doubles(c->n_tiles) * sizeof(double);
   HIPCHK(c->part.alloc(pb));
   HIPCHK(hipMemset(c->part.p, 0, pb));
   std::vector<Tile> tl(c->n_tiles);
@@ -602,6 +634,20 @@ int upload_mesh_arrays(MeshDev& md) {
   if (md.limiter) {
     HIPCHK(upload(md.lima, cast<R>(h.lima)));
     HIPCHK(upload(md.limc, h.limc));
+  }
+  md.halo_ok = false;
+  if (md.limiter && md.p <= 2 && h.E > 0) {
+    Halo H;
+    std::string err;
+    if (build_halo(h, TILE, H, err) == 0 && H.max_n1 <= HALO_R1 && H.max_n2 <= HALO_R2) {
+      HIPCHK(upload(md.h_off, H.off));
+      HIPCHK(upload(md.h_n1, H.n1));
+      if (H.id.empty()) { H.id.push_back(0); H.nslot.push_back(0); }
+      HIPCHK(upload(md.h_id, H.id));
+      HIPCHK(upload(md.h_nslot, H.nslot));
+      HIPCHK(upload(md.h_eslot, H.eslot));
+      md.halo_ok = true;
+    }
   }
   return DGSWE_OK;
 }
@@ -672,10 +718,13 @@ int64_t footprint(const dgswe_params* p, int64_t E, int64_t n_nodes) {
   b += blk(6 * E * rs) + blk(3 * E * rs) + blk(E * rs) + blk(E * rs) + blk(3 * E * 4) + blk(E) + blk(3 * E * 4) +
        blk(2 * n_nodes * 8);
   if (p->limiter) b += blk(6 * E * rs) + blk(E);
+  // halos of the fused stage kernel (limiter on, p <= 2), at their largest
+  if (p->limiter && p->p <= 2 && E > 0)
+    b += blk((tiles + 1) * 4) + blk(tiles * 4) + 2 * blk(tiles * (HALO_R1 + HALO_R2) * 4) + blk(E * 4);
   // state: three buffers and the staged initial state, flags, fully-wet
-  // bytes, element rain, nodal rain, nodal wind and pressure, tile lists,
-  // tile partials with the reduction's records and counter
-  b += 4 * blk(3 * NP * E * rs) + 3 * blk(E) + (p->limiter ? blk(E) : 0) + blk(E * rs);
+  // bytes (two buffers), element rain, nodal rain, nodal wind and pressure,
+  // tile lists, tile partials with the reduction's records and counter
+  b += 4 * blk(3 * NP * E * rs) + 3 * blk(E) + (p->limiter ? 2 * blk(E) : 0) + blk(E * rs);
   b += blk(nn * 8) + blk(3 * nn * rs);
   b += blk(std::max<int64_t>(node_tiles, 1) * int64_t(sizeof(Tile))) + blk(std::max<int64_t>(tiles, 1) * int64_t(sizeof(Tile)));
   b += blk((NPART * std::max<int64_t>(tiles, 1) + NRED * int64_t(red_chunks(int(tiles))) + 1) * 8);
@@ -726,9 +775,11 @@ int dgswe_create(const dgswe_params* params, void* hip_stream, dgswe_ctx** out) 
   if (rc) return rc;
   auto c = std::make_unique<dgswe_ctx>();
   c->prm = *params;
+  HIPCHK(hipGetDevice(&c->device));
   c->rs = params->precision == DGSWE_FP32 ? 4 : 8;
   make_rk(params->rk_stages, c->rk);
   c->variant = 1;
+  c->fused = 0;
   if (hip_stream) {
     c->stream = static_cast<hipStream_t>(hip_stream);
   } else {
@@ -1222,10 +1273,11 @@ int dgswe_set_tuning(dgswe_ctx* c, int key, int value) {
   int rc = check_ctx(c, false);
   if (rc) return rc;
   if (c->in_batch) return fail(DGSWE_ESTATE, "context is a member of a batch");
-  if (key != DGSWE_TUNE_STAGE_VARIANT) return fail(DGSWE_EINVAL, "unknown tuning key");
-  if (value != 0 && value != 1) return fail(DGSWE_EINVAL, "stage variant must be 0 or 1");
+  if (key != DGSWE_TUNE_STAGE_VARIANT && key != DGSWE_TUNE_FUSED_POST) return fail(DGSWE_EINVAL, "unknown tuning key");
+  if (value != 0 && value != 1) return fail(DGSWE_EINVAL, "tuning values are 0 or 1");
   if (c->stream) HIPCHK(hipStreamSynchronize(c->stream));
-  c->variant = value;
+  if (key == DGSWE_TUNE_STAGE_VARIANT) c->variant = value;
+  else c->fused = value;
   c->graph_dirty = true;
   return DGSWE_OK;
 }
@@ -1233,8 +1285,9 @@ int dgswe_set_tuning(dgswe_ctx* c, int key, int value) {
 int dgswe_get_tuning(const dgswe_ctx* c, int key, int* value) {
   int rc = check_ctx(c, false);
   if (rc) return rc;
-  if (key != DGSWE_TUNE_STAGE_VARIANT || !value) return fail(DGSWE_EINVAL, "unknown tuning key or null output");
-  *value = c->variant;
+  if (!value || (key != DGSWE_TUNE_STAGE_VARIANT && key != DGSWE_TUNE_FUSED_POST))
+    return fail(DGSWE_EINVAL, "unknown tuning key or null output");
+  *value = key == DGSWE_TUNE_STAGE_VARIANT ? c->variant : (c->use_fused() ? 1 : 0);
   return DGSWE_OK;
 }
 
@@ -1267,14 +1320,21 @@ int dgswe_autotune(dgswe_ctx* c, int n_steps, int* chosen, double* ms_per_step) 
     return DGSWE_OK;
   };
   const int saved_prof = c->prof;
+  const int saved_fused = c->fused;
   c->prof = 0;
   hipEvent_t ea, eb;
   HIPCHK(hipEventCreate(&ea));
   HIPCHK(hipEventCreate(&eb));
-  double ms[2] = {0.0, 0.0};
+  // configurations: per-element kernel; per-edge kernel with the post pass
+  // after every stage; per-edge kernel with the post-processing fused into
+  // the next stage (limiter on, p <= 2, a halo built)
+  const int cfg_variant[3] = {0, 1, 1}, cfg_fused[3] = {0, 0, 1};
+  double ms[3] = {0.0, 0.0, 0.0};
   int err = DGSWE_OK;
-  for (int v = 0; v < 2 && !err; ++v) {
-    c->variant = v;
+  for (int v = 0; v < 3 && !err; ++v) {
+    c->variant = cfg_variant[v];
+    c->fused = cfg_fused[v];
+    if (v == 2 && !c->use_fused()) break;      // the same as configuration 1
     c->graph_dirty = true;
     err = dgswe_step(c, 2);                     // builds the step graph, warms caches
     if (!err) err = restore();
@@ -1293,13 +1353,18 @@ int dgswe_autotune(dgswe_ctx* c, int n_steps, int* chosen, double* ms_per_step) 
   (void)hipEventDestroy(eb);
   c->prof = saved_prof;
   if (err) {
+    c->fused = saved_fused;
     (void)restore();
     return err;
   }
-  c->variant = ms[1] <= ms[0] ? 1 : 0;
+  int best = 0;
+  for (int v = 1; v < 3; ++v)
+    if (ms[v] > 0.0 && ms[v] <= ms[best]) best = v;
+  c->variant = cfg_variant[best];
+  c->fused = cfg_fused[best];
   c->graph_dirty = true;
   if (chosen) *chosen = c->variant;
-  if (ms_per_step) { ms_per_step[0] = ms[0]; ms_per_step[1] = ms[1]; }
+  if (ms_per_step) { ms_per_step[0] = ms[0]; ms_per_step[1] = ms[1]; ms_per_step[2] = ms[2]; }
   return DGSWE_OK;
 }
 
@@ -1336,7 +1401,7 @@ namespace {
 template <typename Real>
 int batch_rebuild_t(dgswe_batch* b) {
   std::vector<Member<Real>> ms;
-  std::map<std::tuple<int, int, int, int, int>, int> gi;
+  std::map<std::tuple<int, int, int, int, int, int>, int> gi;
   b->groups.clear();
   for (size_t i = 0; i < b->slots.size(); ++i) {
     const auto& sl = b->slots[i];
@@ -1344,7 +1409,7 @@ int batch_rebuild_t(dgswe_batch* b) {
     const int idx = int(ms.size());
     ms.push_back(member_struct<Real>(sl.ctx));
     const dgswe_params& p = sl.ctx->prm;
-    auto key = std::make_tuple(p.p, p.flux, p.limiter, p.rk_stages, sl.ctx->variant);
+    auto key = std::make_tuple(p.p, p.flux, p.limiter, p.rk_stages, sl.ctx->variant, sl.ctx->use_fused() ? 1 : 0);
     auto it = gi.find(key);
     if (it == gi.end()) {
       dgswe_batch::Group g;
@@ -1352,6 +1417,7 @@ int batch_rebuild_t(dgswe_batch* b) {
       g.flux = p.flux;
       g.limiter = p.limiter;
       g.variant = sl.ctx->variant;
+      g.fused = sl.ctx->use_fused() ? 1 : 0;
       make_rk(p.rk_stages, g.rk);
       b->groups.push_back(std::move(g));
       it = gi.emplace(key, int(b->groups.size()) - 1).first;
@@ -1470,12 +1536,12 @@ static int batch_enqueue_step(dgswe_batch* b) {
       rc = enqueue_step_group<float>(b->memb.as<Member<float>>(), g.tiles.as<Tile>(), g.n_tiles,
                                      g.node_tiles.as<Tile>(), g.n_node_tiles, g.ids.as<int>(),
                                      int(g.members.size()), g.max_chunks, g.p, g.flux, g.limiter, g.variant, g.rk,
-                                     g.node_forcing, b->stream, nullptr, false);
+                                     g.node_forcing, b->stream, nullptr, false, nullptr, g.fused != 0);
     else
       rc = enqueue_step_group<double>(b->memb.as<Member<double>>(), g.tiles.as<Tile>(), g.n_tiles,
                                       g.node_tiles.as<Tile>(), g.n_node_tiles, g.ids.as<int>(),
                                       int(g.members.size()), g.max_chunks, g.p, g.flux, g.limiter, g.variant, g.rk,
-                                      g.node_forcing, b->stream, nullptr, false);
+                                      g.node_forcing, b->stream, nullptr, false, nullptr, g.fused != 0);
     if (rc) return rc;
   }
   return DGSWE_OK;

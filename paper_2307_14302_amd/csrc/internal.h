@@ -13,6 +13,11 @@
 namespace dg {
 
 constexpr int TILE = 256;          // elements per workgroup (4 wavefronts)
+// Largest halo a tile may have for the fused stage kernel (ring 1: outside
+// elements sharing an edge with the tile; ring 2: those sharing an edge with
+// ring 1); a mesh with a larger one keeps the separate post pass.
+constexpr int HALO_R1 = 112, HALO_R2 = 144;
+constexpr uint32_t HALO_SLOT_MASK = 0x3FF;   // 10-bit slot; all ones: boundary edge
 constexpr int MAX_STAGES = 5;
 constexpr int MAX_SLOTS = 16;
 // per-tile FP64 partial sums: boundary out/in flux per stage, volume,
@@ -93,7 +98,17 @@ struct Member {
   Real* W[3];                 // state buffers
   Real* Wt;                   // initial state as given, before the set-up pass
   uint8_t* F[3];              // dry flags of the state in W[i] (bit 0)
-  uint8_t* fullwet;           // [E] every vertex depth > H0 (limiter on)
+  // [2][E] fully-wet bytes of a stage's raw output (limiter on): stage i
+  // writes fullwet[i & 1], its post pass or the next stage reads it
+  uint8_t* fullwet[2];
+  // halo of every stage tile (see HaloDims), for the stage kernel that
+  // applies the previous stage's limiter and positive depth itself; null
+  // when the mesh has none
+  const int* h_off;           // [n_tiles + 1] first halo entry of each tile
+  const int* h_n1;            // [n_tiles] ring-1 entries (ring 2 follows)
+  const int* h_id;            // [entries] element id
+  const uint32_t* h_nslot;    // [entries] a ring-1 entry's neighbour slots, 10 bits each
+  const uint32_t* h_eslot;    // [E] an element's neighbour slots in its own tile
   Real* R;                    // [E] element rain rate
   double* rn;                 // [n_nodes] nodal rain rate
   Real* met;                  // [3][n_nodes] kinematic wind stress (x, y) and pressure head at t^n
@@ -111,6 +126,8 @@ struct StageArgs {
   int fin, fout;              // flag buffer indices
   double a, b, gam;           // w_out = a w^n + b (w_in + gam dt L(w_in))
   int single;                 // 1: one member, tile i of the launch is tile i of member 0
+  double* part;               // tile partials, chunk records and counter laid out as the
+                              // member's part array, used instead of it (nullptr: the member's)
 };
 
 struct Tile { int member, tile; };
@@ -124,10 +141,13 @@ struct RKInfo {
 // launchers (kernels.hip)
 // ev0/ev1, when given, receive the start and end time of the stage kernel's
 // own dispatch (no marker packets around it)
+// fused = 1 (variant 1, limiter on, p <= 2, members with a halo): the stage
+// reads the previous stage's raw output and applies its limiter and
+// positive-depth operator itself, in place of that stage's post pass
 template <typename Real>
 hipError_t launch_stage(int P, int flux, int limiter, int variant, const Member<Real>* d_members,
                         const Tile* d_tiles, int n_tiles, StageArgs a, hipStream_t s, hipEvent_t ev0 = nullptr,
-                        hipEvent_t ev1 = nullptr);
+                        hipEvent_t ev1 = nullptr, int fused = 0);
 template <typename Real>
 hipError_t launch_post(int P, int use_lim, const Member<Real>* d_members, const Tile* d_tiles, int n_tiles,
                        StageArgs a, int init, hipStream_t s);
@@ -144,8 +164,11 @@ hipError_t launch_rain(const Member<Real>* d_members, const Tile* d_tiles, int n
 // over the members); d_member_ids == nullptr for a single context (member 0).
 // init: 0 = end of a step; 1 = set-up (dt from the state); 2 = set-up that
 // keeps a dt > 0 already in the scalars (restored or current)
+// part_over: as StageArgs::part (single member only)
 template <typename Real>
 hipError_t launch_reduce(const Member<Real>* d_members, const int* d_member_ids, int n_members, int max_chunks,
-                         int init, const RKInfo& rk, hipStream_t s);
+                         int init, const RKInfo& rk, hipStream_t s, double* part_over = nullptr);
+// zero n doubles at p (a kernel, so that it can sit in a captured graph)
+hipError_t launch_fill_zero(double* p, int n, hipStream_t s);
 
 }  // namespace dg

@@ -414,14 +414,15 @@ DG_DEV bool positive_depth(Real (&w)[3][Tab<P>::NP], const Real (&hb)[3], double
   return nd == 3;
 }
 
-// largest |u| + sqrt(g H) over wet vertices (0 if none)
+// largest |u| + sqrt(g H) over wet vertices (0 if none; NaN if a speed is
+// NaN, e.g. from an overflowing discharge)
 DG_DEV double cfl_speed(const double (&hv)[3], const double (&qx)[3], const double (&qy)[3], double H0, double g) {
   double lam = 0.0;
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
     if (hv[i] > dry_depth(H0)) {
       const double s = dsqrt(qx[i] * qx[i] + qy[i] * qy[i]) * rcp(hv[i]) + dsqrt(g * hv[i]);
-      lam = fmax(lam, s);
+      lam = (s > lam || s != s) ? s : lam;      // a NaN speed is kept (flagged by the caller)
     }
   }
   return lam;
@@ -456,6 +457,84 @@ DG_DEV double post_speed(bool filled, const double (&hv)[3], const double (&qxv)
                          const Real (&w)[3][Tab<P>::NP], const Real (&hb)[3], double H0, double g) {
   if (filled) return cfl_speed(hv, qxv, qyv, H0, g);
   return element_speed<Real, P>(w, hb, Real(g));
+}
+
+// Slope limiter on one element whose stencil is fully wet (Sec. 2.3,
+// Cockburn-Shu, componentwise on zeta, qx, qy, nu = 1.5): nmean[v][k] is the
+// mean of variable v in the neighbour across local edge k, al and lc the
+// element's decomposition weights and code.  Returns true when any
+// component changed (its linear part is rebuilt from the limited midpoint
+// deviations and its higher modes are dropped).
+template <typename Real, int P>
+DG_DEV bool limit_element(Real (&w)[3][Tab<P>::NP], uint8_t lc, const Real (&al)[6], const Real (&nmean)[3][3]) {
+  constexpr int NP = Tab<P>::NP;
+  bool changed = false;
+#pragma unroll
+  for (int v = 0; v < 3; ++v) {
+    const Real wb = w[v][0];
+    Real nbm[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) nbm[k] = nmean[v][k] - wb;
+    Real d[3], D[3];
+    bool same = true;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      d[i] = Real(B<1>::M(i, 1)) * w[v][1] + Real(B<1>::M(i, 2)) * w[v][2];
+      const int kk = ((lc >> (1 + i)) & 1) ? (i + 2) % 3 : (i + 1) % 3;
+      const Real nbk = kk == 0 ? nbm[0] : kk == 1 ? nbm[1] : nbm[2];
+      const Real nbj = i == 0 ? nbm[0] : i == 1 ? nbm[1] : nbm[2];
+      const Real db = Real(1.5) * (al[2 * i] * nbj + al[2 * i + 1] * nbk);
+      const bool sgn = (d[i] > Real(0) && db > Real(0)) || (d[i] < Real(0) && db < Real(0));
+      D[i] = sgn ? (d[i] > Real(0) ? dmin(d[i], db) : dmax(d[i], db)) : Real(0);
+      same = same && (D[i] == d[i]);
+    }
+    if (!same) {
+      changed = true;
+      const Real s = D[0] + D[1] + D[2];
+      if (s != Real(0)) {
+        const Real Pp = dmax(D[0], Real(0)) + dmax(D[1], Real(0)) + dmax(D[2], Real(0));
+        const Real Nn = dmax(-D[0], Real(0)) + dmax(-D[1], Real(0)) + dmax(-D[2], Real(0));
+        const Real tp = Pp == Real(0) ? Real(1) : dmin(Real(1), Nn / Pp);
+        const Real tn = Nn == Real(0) ? Real(1) : dmin(Real(1), Pp / Nn);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) D[i] = tp * dmax(D[i], Real(0)) - tn * dmax(-D[i], Real(0));
+      }
+      // least-squares linear part from the three midpoint deviations
+      w[v][1] = D[1] - D[2];
+      w[v][2] = (D[1] + D[2] - Real(2) * D[0]) / Real(3);
+#pragma unroll
+      for (int m = 3; m < NP; ++m) w[v][m] = Real(0);
+    }
+  }
+  return changed;
+}
+
+// The post-processing of one element of a raw stage output (Sec. 2.3
+// limiter where its stencil is fully wet, then the positive-depth operator
+// of Sec. 2.4): the post kernel's arithmetic with the neighbours' raw means
+// and fully-wet bytes taken from LDS slots (s_mean[v * SM + slot],
+// s_fw[slot]; ns = the element's neighbour slots, 10 bits each, self = its
+// own slot; lc and al its limiter code and weights, loaded by the caller
+// ahead of the barrier that publishes the slots).  Returns the dry flag.
+template <typename Real, int P>
+DG_DEV bool post_from_slots(const Member<Real>& M, Real (&w)[3][Tab<P>::NP], const Real (&hb)[3], uint8_t lc,
+                            const Real (&al)[6], uint32_t ns, int self, const Real* s_mean, const uint8_t* s_fw,
+                            int SM) {
+  bool ok = ((lc & 1) != 0) & (s_fw[self] != 0);
+  Real nmean[3][3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const int sl = int((ns >> (10 * k)) & HALO_SLOT_MASK);
+    const bool in = sl != int(HALO_SLOT_MASK);
+    const int at = in ? sl : self;
+    ok = ok & in & (s_fw[at] != 0);
+#pragma unroll
+    for (int v = 0; v < 3; ++v) nmean[v][k] = s_mean[v * SM + at];
+  }
+  if (ok) (void)limit_element<Real, P>(w, lc, al, nmean);
+  double hv[3], qxv[3], qyv[3];
+  bool filled;
+  return positive_depth<Real, P>(w, hb, M.H0, hv, qxv, qyv, false, filled);
 }
 
 // ------------------------------------------------------ stage building blocks
@@ -875,7 +954,7 @@ DG_DEV void finish_stage(const Member<Real>& M, const StageArgs& A, int tile, in
       for (int v = 0; v < 3; ++v)
 #pragma unroll
         for (int m = 0; m < NP; ++m) stc(Wr, (v * NP + m) * E, e, w[v][m]);
-      stx(gp(M.fullwet), e, uint8_t(fully_wet<Real, P>(w, hb, M.H0) ? 1 : 0));
+      stx(gp(M.fullwet[A.stage & 1]), e, uint8_t(fully_wet<Real, P>(w, hb, M.H0) ? 1 : 0));
     }
   }
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -899,7 +978,7 @@ DG_DEV void finish_stage(const Member<Real>& M, const StageArgs& A, int tile, in
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    DG_G double* __restrict__ pt = gp(M.part);
+    DG_G double* __restrict__ pt = gp(A.part ? A.part : M.part);
     const int nt = M.n_tiles;
     pt[(P_OUT0 + A.stage) * nt + tile] = (lds[0] + lds[8]) + (lds[16] + lds[24]);
     pt[(P_IN0 + A.stage) * nt + tile] = (lds[1] + lds[9]) + (lds[17] + lds[25]);
@@ -1155,22 +1234,40 @@ __global__ DG_STAGE_ATTR void stage_kernel(const Member<Real>* __restrict__ mem,
 // the tile's edges instead of three per element.  Edges to other tiles are
 // still evaluated on both sides in the canonical orientation, so both tiles
 // obtain the same bits.
-template <typename Real, int P, int FLUX, int LIM>
+//
+// PRE = 1 (limiter on, p <= 2): the input is the previous stage's raw output,
+// and this kernel applies that stage's post-processing (Sec. 2.3 limiter,
+// Sec. 2.4 positive depth and flags) itself, to its own elements and to
+// ring 1 of its tile (the outside elements across its cut edges), whose
+// limited point values join the tile's in LDS: the previous stage needs no
+// post pass, and cut edges read their neighbour from LDS.  The limiter of
+// a ring-1 element reads the raw means of ring 2.  The arithmetic is the
+// post kernel's (the same functions).
+template <typename Real, int P, int FLUX, int LIM, int PRE>
 __global__ DG_STAGE_ATTR void stage_edge_kernel(const Member<Real>* __restrict__ mem,
                                                           const Tile* __restrict__ tiles, int n_tiles, StageArgs A) {
   constexpr int NP = Tab<P>::NP, NG = Tab<P>::NG;
+  static_assert(!PRE || (LIM == 1 && P <= 2), "the fused post-processing needs the limiter and p <= 2");
   // point values per variable (vertices, midpoints); p = 3 keeps its traces
   // in s_flux instead (each slot holds the element's own trace at that edge
   // point until phase B overwrites it with the flux there)
   constexpr int NN = P == 1 ? 3 : P == 2 ? 6 : 1;
-  __shared__ Real s_node[3 * NN][TILE];
-  __shared__ Real s_hb[3][TILE];
+  constexpr int SL = TILE + (PRE ? HALO_R1 : 0);      // point-value slots: tile, then ring 1
+  __shared__ Real s_node[3 * NN][SL];
+  __shared__ Real s_hb[3][SL];
   __shared__ Real s_flux[3 * NG * 3][TILE];            // [(k NG + g) 3 + var][element], scaled by (l/2) w_g
-  // edge vectors in LDS, except for FP32 p = 2, where dropping them (phase B
-  // reads them from the cache instead) lets three workgroups share a CU
-  constexpr bool kEvLds = !(P == 2 && sizeof(Real) == 4);
-  __shared__ Real s_ev[kEvLds ? 6 : 1][TILE];
-  __shared__ uint8_t s_flag[TILE];
+  // edge vectors in LDS, except for FP32 p = 2 and the fused kernel, where
+  // dropping them (phase B reads them from the cache instead) lets one more
+  // workgroup share a CU
+  constexpr bool kEvLds = !PRE && !(P == 2 && sizeof(Real) == 4);
+  __shared__ Real s_ev[kEvLds ? 6 : 1][kEvLds ? TILE : 1];
+  __shared__ uint8_t s_flag[SL];
+  // PRE: raw means and fully-wet bytes of tile, ring 1 and ring 2, in the
+  // flux slots' memory (used before phase B writes any flux)
+  constexpr int SM = TILE + HALO_R1 + HALO_R2;
+  static_assert(!PRE || 3 * SM * sizeof(Real) + SM <= sizeof(s_flux), "halo means fit the flux slots");
+  Real* const s_mean = reinterpret_cast<Real*>(&s_flux[0][0]);
+  uint8_t* const s_fw = reinterpret_cast<uint8_t*>(s_mean + 3 * SM);
   // edge list; after phase B the same memory holds the block's partial sums
   __shared__ double s_lbuf[3 * TILE / 2];
   uint32_t* s_list = reinterpret_cast<uint32_t*>(s_lbuf);
@@ -1204,8 +1301,67 @@ __global__ DG_STAGE_ATTR void stage_edge_kernel(const Member<Real>* __restrict__
 #pragma unroll
   for (int k = 0; k < 3; ++k) nbv[k] = ldc(nbr, k * E, ec);
   const int nkp = ldx(gp(M.nk), ec);
-  const uint8_t fin = ldx(Fin, ec);
+  const uint8_t fin = PRE ? uint8_t(0) : ldx(Fin, ec);
   const Real fric = ldx(gp(M.fric), ec);
+  // PRE: the own element's neighbour slots in the tile's numbering
+  const uint32_t eslot = PRE ? ldx(gp(M.h_eslot), ec) : 0u;
+  bool myflag = fin & 1;
+  if constexpr (PRE) {
+    // ---- phase 0: the previous stage's post-processing (limiter, positive
+    // depth, flags) of the own element and of ring 1
+    const DG_G uint8_t* __restrict__ fwin = gp(M.fullwet[(A.stage + 1) & 1]);   // written by stage - 1
+    const int hoff = ldx(gp(M.h_off), tl.tile), hn1 = ldx(gp(M.h_n1), tl.tile);
+    const int hn = ldx(gp(M.h_off), tl.tile + 1) - hoff;
+    // every load of this phase is issued before the barrier: the own
+    // limiter data, and (threads below hn1) one ring-1 element's raw state,
+    // bathymetry and limiter data, in flight with the halo's means
+    const uint8_t lc_own = ldx(gp(M.limc), ec);
+    Real al_own[6];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) al_own[j] = ldc(gp(M.lima), j * E, ec);
+    const bool ring = el < hn1;
+    const int y = ldx(gp(M.h_id), hoff + (ring ? el : 0));
+    const uint32_t ns = ring ? ldx(gp(M.h_nslot), hoff + el) : 0u;
+    Real wy[3][NP], hy[3], aly[6];
+    uint8_t lcy = 0;
+    if (ring) {
+#pragma unroll
+      for (int v = 0; v < 3; ++v)
+#pragma unroll
+        for (int m = 0; m < NP; ++m) wy[v][m] = ldc(Win, (v * NP + m) * E, y);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) hy[k] = ldc(gp(M.hbv), k * E, y);
+#pragma unroll
+      for (int j = 0; j < 6; ++j) aly[j] = ldc(gp(M.lima), j * E, y);
+      lcy = ldx(gp(M.limc), y);
+    }
+#pragma unroll
+    for (int v = 0; v < 3; ++v) s_mean[v * SM + el] = d.w[v][0];
+    s_fw[el] = valid ? ldx(fwin, ec) : uint8_t(0);
+    for (int j = el; j < hn; j += TILE) {
+      const int z = ldx(gp(M.h_id), hoff + j);
+#pragma unroll
+      for (int v = 0; v < 3; ++v) s_mean[v * SM + TILE + j] = ldc(Win, (v * NP) * E, z);
+      s_fw[TILE + j] = ldx(fwin, z);
+    }
+    __syncthreads();
+    myflag = post_from_slots<Real, P>(M, d.w, d.hb, lc_own, al_own, eslot, el, s_mean, s_fw, SM);
+    if (ring) {
+      const bool fy = post_from_slots<Real, P>(M, wy, hy, lcy, aly, ns, TILE + el, s_mean, s_fw, SM);
+      Real vv[3][3], mv[3][3];
+      edge_nodes<Real, P>(wy, vv, mv);
+#pragma unroll
+      for (int v = 0; v < 3; ++v)
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          s_node[v * NN + i][TILE + el] = vv[v][i];
+          if (P == 2) s_node[v * NN + 3 + i][TILE + el] = mv[v][i];
+        }
+#pragma unroll
+      for (int k = 0; k < 3; ++k) s_hb[k][TILE + el] = hy[k];
+      s_flag[TILE + el] = fy ? 1 : 0;
+    }
+  }
   // element rain (Eq. rain): the first stage of a step with time-dependent
   // rain averages the nodal rates of t^n (node ids now, rates before phase
   // B, the mean at the end); later stages read the stored value
@@ -1253,7 +1409,7 @@ __global__ DG_STAGE_ATTR void stage_edge_kernel(const Member<Real>* __restrict__
       s_ev[2 * k + 1][el] = d.ey[k];
     }
   }
-  s_flag[el] = fin & 1;
+  s_flag[el] = myflag ? 1 : 0;
   // The edges this element evaluates, in three classes listed one after the
   // other so that a wavefront mostly runs one code path: (0) interior edges
   // inside the tile, owned by the lower id; (1) edges to other tiles;
@@ -1267,7 +1423,9 @@ __global__ DG_STAGE_ATTR void stage_edge_kernel(const Member<Real>* __restrict__
     const int kn = (nkp >> (2 * k)) & 3;
     const bool inside = nb >= t0 && nb < tend;
     cls[k] = !valid ? 3 : nb < 0 ? 2 : !inside ? 1 : (e < nb ? 0 : 3);
-    ent[k] = uint32_t(el) | uint32_t(k) << 8 | uint32_t(kn) << 10 | uint32_t(inside ? nb - t0 : 0) << 12;
+    // in the tile: the neighbour's local index; PRE, in ring 1: its slot
+    const uint32_t at = inside ? uint32_t(nb - t0) : PRE ? (eslot >> (10 * k)) & HALO_SLOT_MASK : 0u;
+    ent[k] = uint32_t(el) | uint32_t(k) << 8 | uint32_t(kn) << 10 | at << 12;
     packed += cls[k] < 3 ? 1 << (10 * cls[k]) : 0;
   }
   // block-wide exclusive scan of the packed counts
@@ -1441,6 +1599,16 @@ __global__ DG_STAGE_ATTR void stage_edge_kernel(const Member<Real>* __restrict__
           Nc[v] = (P == 2) ? s_node[v * NN + 3 + kn][ln] : Real(0);
         }
         nflag = s_flag[ln];
+      } else if constexpr (PRE) {
+        // ring 1: post-processed in phase 0, point values in LDS
+        const int sl = int(ent >> 12);
+#pragma unroll
+        for (int v = 0; v < 3; ++v) {
+          Na[v] = s_node[v * NN + kn][sl];
+          Nb[v] = s_node[v * NN + kn1][sl];
+          Nc[v] = (P == 2) ? s_node[v * NN + 3 + kn][sl] : Real(0);
+        }
+        nflag = s_flag[sl];
       } else {
         Real wn[3][NP];
 #pragma unroll
@@ -1609,11 +1777,12 @@ __global__ __launch_bounds__(TILE) void post_kernel(const Member<Real>* __restri
       const int n = ldc(gp(M.nbr), k * E, ec);
       nb[k] = n < 0 ? ec : n;
     }
-    bool ok = ((lc & 1) != 0) & (ldx(gp(M.fullwet), ec) != 0);
+    const DG_G uint8_t* __restrict__ fw = gp(M.fullwet[A.stage & 1]);
+    bool ok = ((lc & 1) != 0) & (ldx(fw, ec) != 0);
     Real nmean[3][3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      ok = ok & (ldx(gp(M.fullwet), nb[k]) != 0);
+      ok = ok & (ldx(fw, nb[k]) != 0);
 #pragma unroll
       for (int v = 0; v < 3; ++v) nmean[v][k] = ldc(Wsrc, (v * NP) * E, nb[k]);
     }
@@ -1621,43 +1790,7 @@ __global__ __launch_bounds__(TILE) void post_kernel(const Member<Real>* __restri
       Real al[6];
 #pragma unroll
       for (int j = 0; j < 6; ++j) al[j] = ldc(gp(M.lima), j * E, ec);
-#pragma unroll
-      for (int v = 0; v < 3; ++v) {
-        const Real wb = w[v][0];
-        Real nbm[3];
-#pragma unroll
-        for (int k = 0; k < 3; ++k) nbm[k] = nmean[v][k] - wb;
-        Real d[3], D[3];
-        bool same = true;
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-          d[i] = Real(B<1>::M(i, 1)) * w[v][1] + Real(B<1>::M(i, 2)) * w[v][2];
-          const int kk = ((lc >> (1 + i)) & 1) ? (i + 2) % 3 : (i + 1) % 3;
-          const Real nbk = kk == 0 ? nbm[0] : kk == 1 ? nbm[1] : nbm[2];
-          const Real nbj = i == 0 ? nbm[0] : i == 1 ? nbm[1] : nbm[2];
-          const Real db = Real(1.5) * (al[2 * i] * nbj + al[2 * i + 1] * nbk);
-          const bool sgn = (d[i] > Real(0) && db > Real(0)) || (d[i] < Real(0) && db < Real(0));
-          D[i] = sgn ? (d[i] > Real(0) ? dmin(d[i], db) : dmax(d[i], db)) : Real(0);
-          same = same && (D[i] == d[i]);
-        }
-        if (!same) {
-          changed = true;
-          const Real s = D[0] + D[1] + D[2];
-          if (s != Real(0)) {
-            const Real Pp = dmax(D[0], Real(0)) + dmax(D[1], Real(0)) + dmax(D[2], Real(0));
-            const Real Nn = dmax(-D[0], Real(0)) + dmax(-D[1], Real(0)) + dmax(-D[2], Real(0));
-            const Real tp = Pp == Real(0) ? Real(1) : dmin(Real(1), Nn / Pp);
-            const Real tn = Nn == Real(0) ? Real(1) : dmin(Real(1), Pp / Nn);
-#pragma unroll
-            for (int i = 0; i < 3; ++i) D[i] = tp * dmax(D[i], Real(0)) - tn * dmax(-D[i], Real(0));
-          }
-          // least-squares linear part from the three midpoint deviations
-          w[v][1] = D[1] - D[2];
-          w[v][2] = (D[1] + D[2] - Real(2) * D[0]) / Real(3);
-#pragma unroll
-          for (int m = 3; m < NP; ++m) w[v][m] = Real(0);
-        }
-      }
+      changed = limit_element<Real, P>(w, lc, al, nmean) || changed;
     }
   }
   bool dry, filled = true;
@@ -1720,7 +1853,7 @@ __global__ __launch_bounds__(TILE) void post_kernel(const Member<Real>* __restri
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-      DG_G double* __restrict__ pt = gp(M.part);
+      DG_G double* __restrict__ pt = gp(A.part ? A.part : M.part);
       const int nt = M.n_tiles, t = tl.tile;
       pt[P_VOL * nt + t] = (lds[0] + lds[5]) + (lds[10] + lds[15]);
       pt[P_NDRY * nt + t] = (lds[1] + lds[6]) + (lds[11] + lds[16]);
@@ -1751,7 +1884,7 @@ __global__ __launch_bounds__(TILE) void classify_kernel(const Member<Real>* __re
   }
 #pragma unroll
   for (int i = 0; i < 3; ++i) hb[i] = gp(M.hbv)[i * E + e];
-  gp(M.fullwet)[e] = fully_wet<Real, P>(w, hb, M.H0) ? 1 : 0;
+  gp(M.fullwet[0])[e] = fully_wet<Real, P>(w, hb, M.H0) ? 1 : 0;
 }
 
 // -------------------------------------------------------------- rain
@@ -1906,7 +2039,8 @@ __global__ __launch_bounds__(TILE) void rain_kernel(const Member<Real>* __restri
 // issues all of its loads before it uses any of them.
 template <typename Real>
 __global__ __launch_bounds__(RED_CHUNK) void reduce_kernel(const Member<Real>* __restrict__ mem,
-                                                           const int* __restrict__ ids, int init, RKInfo rk) {
+                                                           const int* __restrict__ ids, int init, RKInfo rk,
+                                                           double* part_over) {
   // sums: volume, rain, dry count, out/in per stage, negative-depth count;
   // minima: d/lambda and the first non-finite element
   constexpr int NV = 4 + 2 * MAX_STAGES;
@@ -1930,13 +2064,17 @@ __global__ __launch_bounds__(RED_CHUNK) void reduce_kernel(const Member<Real>* _
   const int nch = red_chunks(nt);
   const int chunk = blockIdx.y;
   if (chunk >= nch) return;
+  // the member's partials and records, or the same layout at part_over
+  double* const part = part_over ? part_over : M.part;
+  double* const redp = part_over ? part_over + size_t(NPART) * (nt > 1 ? nt : 1) : M.red;
+  unsigned* const red_count = part_over ? reinterpret_cast<unsigned*>(redp + size_t(NRED) * nch) : M.red_count;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int ns = init ? 0 : rk.n;
   // ---- this chunk's tiles, loaded together with the member's active flag
   double v[NV];
   double mn, fb;
   {
-    const DG_G double* __restrict__ pt = gp(M.part);
+    const DG_G double* __restrict__ pt = gp(part);
     const int t = chunk * RED_CHUNK + tid;
     const bool ok = t < nt;
     const int tt = ok ? t : 0;
@@ -1988,14 +2126,14 @@ __global__ __launch_bounds__(RED_CHUNK) void reduce_kernel(const Member<Real>* _
   block_reduce();
   // an inactive member (finished or latched) keeps its scalars as they are
   if (!act) return;
-  DG_G double* __restrict__ red = gp(M.red);
+  DG_G double* __restrict__ red = gp(redp);
   if (tid == 0) {
 #pragma unroll
     for (int i = 0; i < NV; ++i) red[chunk * NRED + i] = v[i];
     red[chunk * NRED + NV] = mn;
     red[chunk * NRED + NV + 1] = fb;
     __threadfence();
-    const unsigned done = atomicAdd(M.red_count, 1u);
+    const unsigned done = atomicAdd(red_count, 1u);
     s_last = done == unsigned(nch - 1);
   }
   __syncthreads();
@@ -2034,9 +2172,9 @@ __global__ __launch_bounds__(RED_CHUNK) void reduce_kernel(const Member<Real>* _
     // records written by other workgroups: device-coherent loads
 #pragma unroll
     for (int i = 0; i < NV; ++i)
-      v[i] += __hip_atomic_load(M.red + c * NRED + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    mn = fmin(mn, __hip_atomic_load(M.red + c * NRED + NV, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-    fb = fmin(fb, __hip_atomic_load(M.red + c * NRED + NV + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+      v[i] += __hip_atomic_load(redp + c * NRED + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    mn = fmin(mn, __hip_atomic_load(redp + c * NRED + NV, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    fb = fmin(fb, __hip_atomic_load(redp + c * NRED + NV + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
   }
 #pragma unroll
   for (int k = 0; k < 7; ++k)
@@ -2053,7 +2191,7 @@ __global__ __launch_bounds__(RED_CHUNK) void reduce_kernel(const Member<Real>* _
     if (k * NT + tid < 9 * nwd) s_wind[k * NT + tid] = r_wind[k];
   block_reduce();
   if (tid == 0) {
-    __hip_atomic_store(M.red_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(red_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     double t = t0;
     long long steps = steps0;
     if (!init) {
@@ -2178,25 +2316,34 @@ __global__ __launch_bounds__(RED_CHUNK) void reduce_kernel(const Member<Real>* _
 // ------------------------------------------------------------ launchers
 template <typename Real>
 hipError_t launch_stage(int P, int flux, int limiter, int variant, const Member<Real>* m, const Tile* t, int n,
-                        StageArgs a, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+                        StageArgs a, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1, int fused) {
   if (n <= 0) return hipSuccess;
   dim3 grid(xcd_grid(n)), block(TILE);
   const bool timed = ev0 != nullptr || ev1 != nullptr;
-#define DG_STAGE(PP, FF, LL) \
-  if (P == PP && flux == FF && limiter == LL) { \
-    if (variant == 1) { \
-      if (timed) hipExtLaunchKernelGGL((stage_edge_kernel<Real, PP, FF, LL>), grid, block, 0, s, ev0, ev1, 0, m, t, n, a); \
-      else hipLaunchKernelGGL((stage_edge_kernel<Real, PP, FF, LL>), grid, block, 0, s, m, t, n, a); \
-    } else { \
-      if (timed) hipExtLaunchKernelGGL((stage_kernel<Real, PP, FF, LL>), grid, block, 0, s, ev0, ev1, 0, m, t, n, a); \
-      else hipLaunchKernelGGL((stage_kernel<Real, PP, FF, LL>), grid, block, 0, s, m, t, n, a); \
-    } \
-    return hipGetLastError(); \
+#define DG_LAUNCH(KERNEL)                                                                       \
+  {                                                                                            \
+    if (timed) hipExtLaunchKernelGGL((KERNEL), grid, block, 0, s, ev0, ev1, 0, m, t, n, a);      \
+    else hipLaunchKernelGGL((KERNEL), grid, block, 0, s, m, t, n, a);                          \
+    return hipGetLastError();                                                                  \
+  }
+#define DG_STAGE(PP, FF, LL)                                                                    \
+  if (P == PP && flux == FF && limiter == LL) {                                                 \
+    if (variant == 1) DG_LAUNCH((stage_edge_kernel<Real, PP, FF, LL, 0>))                       \
+    else DG_LAUNCH((stage_kernel<Real, PP, FF, LL>))                                            \
+  }
+  if (fused) {
+    if (variant != 1 || limiter != 1 || P > 2) return hipErrorInvalidValue;
+    if (P == 1 && flux == 0) DG_LAUNCH((stage_edge_kernel<Real, 1, 0, 1, 1>))
+    if (P == 1 && flux == 1) DG_LAUNCH((stage_edge_kernel<Real, 1, 1, 1, 1>))
+    if (P == 2 && flux == 0) DG_LAUNCH((stage_edge_kernel<Real, 2, 0, 1, 1>))
+    if (P == 2 && flux == 1) DG_LAUNCH((stage_edge_kernel<Real, 2, 1, 1, 1>))
+    return hipErrorInvalidValue;
   }
   DG_STAGE(1, 0, 0) DG_STAGE(1, 1, 0) DG_STAGE(1, 0, 1) DG_STAGE(1, 1, 1)
   DG_STAGE(2, 0, 0) DG_STAGE(2, 1, 0) DG_STAGE(2, 0, 1) DG_STAGE(2, 1, 1)
   DG_STAGE(3, 0, 0) DG_STAGE(3, 1, 0) DG_STAGE(3, 0, 1) DG_STAGE(3, 1, 1)
 #undef DG_STAGE
+#undef DG_LAUNCH
   return hipErrorInvalidValue;
 }
 
@@ -2234,20 +2381,32 @@ hipError_t launch_rain(const Member<Real>* m, const Tile* t, int n, int always, 
 
 template <typename Real>
 hipError_t launch_reduce(const Member<Real>* m, const int* ids, int n_members, int max_chunks, int init,
-                         const RKInfo& rk, hipStream_t s) {
+                         const RKInfo& rk, hipStream_t s, double* part_over) {
   if (n_members <= 0) return hipSuccess;
   hipLaunchKernelGGL((reduce_kernel<Real>), dim3(n_members, max_chunks < 1 ? 1 : max_chunks), dim3(RED_CHUNK), 0, s,
-                     m, ids, init, rk);
+                     m, ids, init, rk, part_over);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void fill_zero_kernel(double* p, int n) {
+  const int i = int(blockIdx.x) * 256 + int(threadIdx.x);
+  if (i < n) p[i] = 0.0;
+}
+
+hipError_t launch_fill_zero(double* p, int n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_zero_kernel, dim3((n + 255) / 256), dim3(256), 0, s, p, n);
   return hipGetLastError();
 }
 
 #define DG_INST(R)                                                                                              \
   template hipError_t launch_stage<R>(int, int, int, int, const Member<R>*, const Tile*, int, StageArgs, hipStream_t, \
-                                      hipEvent_t, hipEvent_t);                                              \
+                                      hipEvent_t, hipEvent_t, int);                                         \
   template hipError_t launch_post<R>(int, int, const Member<R>*, const Tile*, int, StageArgs, int, hipStream_t);  \
   template hipError_t launch_classify<R>(int, const Member<R>*, const Tile*, int, hipStream_t);                   \
   template hipError_t launch_rain<R>(const Member<R>*, const Tile*, int, int, const Tile*, int, hipStream_t, int); \
-  template hipError_t launch_reduce<R>(const Member<R>*, const int*, int, int, int, const RKInfo&, hipStream_t);
+  template hipError_t launch_reduce<R>(const Member<R>*, const int*, int, int, int, const RKInfo&, hipStream_t,  \
+                                       double*);
 DG_INST(float)
 DG_INST(double)
 

@@ -245,4 +245,68 @@ int build_mesh(int64_t n_nodes, const double* xy, const double* hb, const double
   return 0;
 }
 
+int build_halo(const HostMesh& M, int T, Halo& H, std::string& err) {
+  const int64_t E = M.E;
+  const int64_t nt = (E + T - 1) / T;
+  H = Halo{};
+  H.T = T;
+  H.off.assign(nt + 1, 0);
+  H.n1.assign(nt, 0);
+  H.eslot.assign(E, 0);
+  std::vector<int32_t> r1, r2;
+  for (int64_t t = 0; t < nt; ++t) {
+    const int64_t a = t * T, b = std::min<int64_t>(E, a + T);
+    auto outside = [&](int32_t x) { return x >= 0 && (x < a || x >= b); };
+    r1.clear();
+    r2.clear();
+    for (int64_t e = a; e < b; ++e)
+      for (int k = 0; k < 3; ++k) {
+        const int32_t n = M.nbr[k * E + e];
+        if (outside(n)) r1.push_back(n);
+      }
+    std::sort(r1.begin(), r1.end());
+    r1.erase(std::unique(r1.begin(), r1.end()), r1.end());
+    for (int32_t y : r1)
+      for (int k = 0; k < 3; ++k) {
+        const int32_t n = M.nbr[k * E + y];
+        if (outside(n) && !std::binary_search(r1.begin(), r1.end(), n)) r2.push_back(n);
+      }
+    std::sort(r2.begin(), r2.end());
+    r2.erase(std::unique(r2.begin(), r2.end()), r2.end());
+    const int64_t n1 = int64_t(r1.size()), n2 = int64_t(r2.size());
+    if (T + n1 + n2 > int64_t(HALO_NONE)) {
+      err = "tile " + std::to_string(t) + " has too large a neighbourhood for 10-bit slots";
+      return -1;
+    }
+    H.max_n1 = std::max<int>(H.max_n1, int(n1));
+    H.max_n2 = std::max<int>(H.max_n2, int(n2));
+    H.n1[t] = int32_t(n1);
+    H.off[t + 1] = H.off[t] + int32_t(n1 + n2);
+    auto slot = [&](int32_t x) -> uint32_t {
+      if (x < 0) return HALO_NONE;
+      if (x >= a && x < b) return uint32_t(x - a);
+      auto i1 = std::lower_bound(r1.begin(), r1.end(), x);
+      if (i1 != r1.end() && *i1 == x) return uint32_t(T + (i1 - r1.begin()));
+      auto i2 = std::lower_bound(r2.begin(), r2.end(), x);
+      return uint32_t(T + n1 + (i2 - r2.begin()));   // x is in ring 2
+    };
+    for (int64_t e = a; e < b; ++e) {
+      uint32_t v = 0;
+      for (int k = 0; k < 3; ++k) v |= slot(M.nbr[k * E + e]) << (10 * k);
+      H.eslot[e] = v;
+    }
+    for (int32_t y : r1) {
+      uint32_t v = 0;
+      for (int k = 0; k < 3; ++k) v |= slot(M.nbr[k * E + y]) << (10 * k);
+      H.id.push_back(y);
+      H.nslot.push_back(v);
+    }
+    for (int32_t z : r2) {
+      H.id.push_back(z);
+      H.nslot.push_back(0);
+    }
+  }
+  return 0;
+}
+
 }  // namespace dg

@@ -26,6 +26,29 @@ struct HostMesh {
   std::vector<double> xy;      // [2][n_nodes]
 };
 
+// Neighbourhood of every tile of T consecutive (internal-order) elements,
+// for a stage kernel that applies the limiter and positive-depth operator
+// of the previous stage itself: ring 1 = elements outside the tile that
+// share an edge with it, ring 2 = elements outside tile and ring 1 that
+// share an edge with ring 1.  A tile numbers its slots 0 .. T-1 (its own
+// elements, local index), T .. T+n1-1 (ring 1), T+n1 .. T+n1+n2-1 (ring 2);
+// neighbour slots are packed 10 bits each (k-th neighbour in bits 10k),
+// HALO_NONE for a boundary edge.
+constexpr uint32_t HALO_NONE = 0x3FF;
+struct Halo {
+  int T = 0;
+  int max_n1 = 0, max_n2 = 0;       // largest ring sizes over the tiles
+  std::vector<int32_t> off;         // [n_tiles + 1] first entry of each tile
+  std::vector<int32_t> n1;          // [n_tiles] ring-1 entries (ring 2 follows)
+  std::vector<int32_t> id;          // [entries] internal element id
+  std::vector<uint32_t> nslot;      // [entries] neighbour slots of a ring-1 entry (0 for ring 2)
+  std::vector<uint32_t> eslot;      // [E] neighbour slots of every element within its own tile
+};
+
+// Builds the halo of every tile of T elements (T <= 512).  Returns 0, or -1
+// when some tile's slots do not fit 10 bits.
+int build_halo(const HostMesh& M, int T, Halo& H, std::string& err);
+
 // Returns 0, or -1 with a message in err.
 int build_mesh(int64_t n_nodes, const double* xy, const double* hb, const double* fric, int64_t n_tri,
                const int32_t* tri, int64_t n_bedges, const int32_t* bnodes, const int32_t* btype,

@@ -133,7 +133,17 @@ class Server:
 
 
 def latency_summary(done: List[Request]) -> Dict[str, float]:
+    """p50/p99/mean of the arrival -> result latency, split into the queue
+    delay (arrival -> admission into the batch) and the service time
+    (admission -> result on the host)."""
     lat = np.array([r.latency for r in done])
-    return {"n": int(lat.size), "failed": sum(1 for r in done if r.error), "p50_s": float(np.percentile(lat, 50)) if lat.size else None,
-            "p99_s": float(np.percentile(lat, 99)) if lat.size else None,
-            "mean_s": float(lat.mean()) if lat.size else None}
+    queue = np.array([r.admitted - r.arrival for r in done])
+    service = np.array([r.done - r.admitted for r in done])
+
+    def pct(a, q):
+        return float(np.percentile(a, q)) if a.size else None
+
+    return {"n": int(lat.size), "failed": sum(1 for r in done if r.error),
+            "p50_s": pct(lat, 50), "p99_s": pct(lat, 99), "mean_s": float(lat.mean()) if lat.size else None,
+            "queue_p50_s": pct(queue, 50), "queue_p99_s": pct(queue, 99),
+            "service_p50_s": pct(service, 50), "service_p99_s": pct(service, 99)}

@@ -178,12 +178,23 @@ class Solver:
         call("dgswe_set_tuning", self.h, N.TUNE_STAGE_VARIANT, int(variant))
 
     def autotune(self, n_steps: int = 5):
-        """Pick the faster stage-kernel variant for this mesh; the state is
-        left as it was.  Returns (variant, (ms/step variant 0, variant 1))."""
+        """Pick the fastest stage-kernel configuration for this mesh; the
+        state is left as it was.  Returns (variant, (ms/step per-element,
+        per-edge with post passes, per-edge fused; 0 where it does not
+        apply))."""
         v = C.c_int()
-        ms = (C.c_double * 2)()
+        ms = (C.c_double * 3)()
         call("dgswe_autotune", self.h, int(n_steps), C.byref(v), ms)
-        return v.value, (ms[0], ms[1])
+        return v.value, (ms[0], ms[1], ms[2])
+
+    def set_fused(self, on: bool):
+        """Post-processing fused into the next stage (limiter on, p <= 2)."""
+        call("dgswe_set_tuning", self.h, N.TUNE_FUSED_POST, int(bool(on)))
+
+    def fused(self) -> int:
+        v = C.c_int()
+        call("dgswe_get_tuning", self.h, N.TUNE_FUSED_POST, C.byref(v))
+        return v.value
 
     def variant(self) -> int:
         v = C.c_int()

@@ -58,3 +58,24 @@ def flag_flips(gpu_flags, orc):
     ids = np.nonzero(g != orc.flags)[0]
     Hv = np.einsum("em,im->ei", orc.w[:, 0, :], orc.T.phi_v) + orc.hbv
     return ids, Hv[ids].max(axis=1) - orc.H_dry
+
+
+def fp32_storage_error(sc, steps, orc):
+    """The FP32 error scale of a scenario: rel L2 (as :func:`rel_l2`) between
+    the FP64 oracle ``orc`` after ``steps`` steps and the same oracle run with
+    its bathymetry and its state after every stage rounded to FP32, i.e. what
+    FP32 storage alone costs on this workload.  Limiter and wet/dry decisions
+    are discontinuous, so on violent transients this alone can exceed 1e-4."""
+    from oracle.solver import OracleSolver
+    m = sc.mesh
+    prm = dict(sc.params)
+    r32 = lambda a: np.asarray(a, dtype=np.float32).astype(np.float64)  # noqa: E731
+    s = OracleSolver(m.xy, m.tri, r32(m.hb), m.fric, m.bedges, m.btype, m.bslot, p=prm["p"], flux=prm["flux"],
+                     friction=prm["friction"], limiter=prm["limiter"], cfl=prm["cfl"], dt_fixed=prm["dt_fixed"],
+                     dt_max=prm["dt_max"], H0=prm["H0"], g=prm["g"], rk_stages=prm.get("rk_stages", 2),
+                     rain=sc.rain, tides=sc.tides, rivers=sc.rivers, met=getattr(sc, "met", None))
+    post = s.post
+    s.post = lambda w: (lambda r: (r32(r[0]), r[1]))(post(w))
+    s.set_initial_nodal(sc.zeta0, sc.qx0, sc.qy0)
+    s.step(steps)
+    return rel_l2(s.w, orc.w, orc)

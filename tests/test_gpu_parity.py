@@ -137,3 +137,47 @@ def test_variants_agree(dg, precision):
     tol = 1e-11 if precision == "fp64" else 2e-3
     assert (np.abs(wa - wb).max(axis=(0, 2)) <= tol * scale).all()
     a.close(); b.close()
+
+
+FUSED_CASES = {
+    "p1_llf_param_lim": dict(p=1, flux="llf", limiter=True, rain_kind="parametric"),
+    "p1_roe_nodal_lim": dict(p=1, flux="roe", limiter=True, rain_kind="nodal"),
+    "p2_llf_param_lim": dict(p=2, flux="llf", limiter=True, rain_kind="parametric"),
+}
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("case", list(FUSED_CASES) + ["basin_window"])
+def test_fused_post_processing_matches_separate_pass(dg, case, precision):
+    """The per-edge stage kernel that post-processes its own input (limiter
+    and positive depth of the previous stage, for its tile and ring 1)
+    against the same kernel followed by the separate post pass, and both
+    against the oracle: the same arithmetic, so the states agree to
+    rounding (FP64 1e-12, FP32 1e-5) and each meets the parity bar."""
+    sc = meshgen.basin_window(40) if case == "basin_window" else meshgen.small_mixed(seed=5, nx=20, ny=10,
+                                                                                       **FUSED_CASES[case])
+    n = 40
+    a = dg.Solver.from_scenario(sc, precision=precision)
+    b = dg.Solver.from_scenario(sc, precision=precision)
+    a.set_variant(1); b.set_variant(1)
+    a.set_fused(True); b.set_fused(False)
+    assert a.fused() == 1 and b.fused() == 0
+    a.step(n); b.step(n)
+    orc = from_scenario(sc)
+    orc.step(n)
+    wa, wb = a.state(), b.state()
+    d = rel_l2(wa, wb, orc)
+    ea, eb = rel_l2(wa, orc.w, orc), rel_l2(wb, orc.w, orc)
+    print(f"{case} {precision}: fused vs separate {d} (bitwise {np.array_equal(wa, wb)}), "
+          f"vs oracle {ea} / {eb}", flush=True)
+    assert d.max() <= (1e-12 if precision == "fp64" else 1e-5), d
+    bar = 1e-10 if precision == "fp64" else 1e-4
+    assert ea.max() <= bar and eb.max() <= bar
+    assert np.array_equal(a.flags(), b.flags()) or precision == "fp32"
+    ma, mb = a.mass(), b.mass()
+    for k in ("t", "volume", "rain_in", "bnd_in", "bnd_out"):
+        # FP32: the cumulative boundary volumes sum FP32 edge fluxes over
+        # every stage and split each edge's net flux into in or out
+        rtol = 1e-12 if precision == "fp64" else (1e-4 if k.startswith("bnd") else 1e-6)
+        assert abs(ma[k] - mb[k]) <= rtol * max(1.0, abs(mb[k])), (k, ma[k], mb[k])
+    a.close(); b.close()

@@ -18,7 +18,7 @@ import pytest
 
 import meshgen
 from oracle.solver import from_scenario
-from tests.parity import flag_flips, rel_l2
+from tests.parity import flag_flips, fp32_storage_error, rel_l2
 
 pytestmark = pytest.mark.gpu
 
@@ -50,11 +50,25 @@ def oracle_after(key, sc, steps):
     return _ORACLE[(key, steps)]
 
 
-def check_budgets(gpu, orc, rtol):
+def check_budgets(gpu, orc, precision, V0):
+    """Totals against the oracle: 1e-10 in FP64.  In FP32 the time, volume
+    and rain volume to 1e-5; the cumulative boundary volumes integrate FP32
+    edge fluxes over every stage of the run, and split each edge's net flux
+    into in or out, so they are held to 1e-3.  The GPU's own budget
+    V - V0 - rain + out - in closes to 1e-12 V in FP64; in FP32 to 1e-5 V:
+    each element scales its FP32 sum of edge fluxes by its own FP32 inverse
+    mass, so the two sides of an edge do not exchange exactly the same
+    volume (about 1e-6 V after 1000 steps on the coast window)."""
     mg, mo = gpu.mass(), orc.mass_totals()
     for k in ("t", "volume", "rain_in", "bnd_in", "bnd_out"):
-        assert abs(mg[k] - mo[k]) <= rtol * max(1.0, abs(mo[k])), (k, mg[k], mo[k])
+        rtol = 1e-10 if precision == "fp64" else (1e-3 if k.startswith("bnd") else 1e-5)
+        rel = abs(mg[k] - mo[k]) / max(1.0, abs(mo[k]))
+        print(f"  {k}: gpu {mg[k]:.10e} oracle {mo[k]:.10e} rel {rel:.2e}", flush=True)
+        assert rel <= rtol, (k, mg[k], mo[k])
     assert mg["steps"] == mo["steps"]
+    res = mg["volume"] - V0 - mg["rain_in"] + mg["bnd_out"] - mg["bnd_in"]
+    print(f"  own budget residual {res / mg['volume']:.2e} V", flush=True)
+    assert abs(res) <= (1e-12 if precision == "fp64" else 1e-5) * mg["volume"], res / mg["volume"]
 
 
 def check_flags(gpu, orc, precision, H0):
@@ -82,11 +96,12 @@ def test_thousand_steps_limiter_and_fronts(dg, case, precision):
     orc = oracle_after(case, sc, 1000)
     assert orc.flags.sum() > 0.05 * orc.E          # dry land is part of the run
     gpu = dg.Solver.from_scenario(sc, precision=precision)
+    V0 = gpu.mass()["volume"]
     gpu.step(1000)
     err = rel_l2(gpu.state(), orc.w, orc)
     print(f"  rel L2 (zeta, q) = {err}", flush=True)
     assert err.max() <= (1e-10 if precision == "fp64" else 1e-4), err
-    check_budgets(gpu, orc, 1e-10 if precision == "fp64" else 1e-5)
+    check_budgets(gpu, orc, precision, V0)
     check_flags(gpu, orc, precision, sc.params["H0"])
     gpu.close()
 
@@ -105,11 +120,12 @@ def test_fp32_p2_sixty_steps(dg, case, variant):
     orc = oracle_after(case, sc, 60)
     gpu = dg.Solver.from_scenario(sc, precision="fp32")
     gpu.set_variant(variant)
+    V0 = gpu.mass()["volume"]
     gpu.step(60)
     err = rel_l2(gpu.state(), orc.w, orc)
     print(f"  rel L2 (zeta, q) = {err}", flush=True)
     assert err.max() <= 1e-4, err
-    check_budgets(gpu, orc, 1e-5)
+    check_budgets(gpu, orc, "fp32", V0)
     check_flags(gpu, orc, "fp32", sc.params["H0"])
     gpu.close()
 
@@ -133,8 +149,15 @@ def test_ensemble_members_against_the_oracle(dg):
         orc = oracle_after(f"member{k}", sc, n)
         w, m = b.read(sl)
         err = rel_l2(w, orc.w, orc)
-        print(f"member {k} ({sc.name}, p={sc.params['p']}, E={sc.mesh.n_tri}): rel L2 {err}", flush=True)
-        assert err.max() <= 1e-4, (k, err)
+        # the coarse basin members start with a dam break down their coarse
+        # coastal elements; there FP32 storage alone (bathymetry and state
+        # rounded in the oracle) moves the result by ~1e-4, so the bar is the
+        # larger of 1e-4 and five times that
+        scale = fp32_storage_error(sc, n, orc)
+        bar = max(1e-4, 5.0 * scale.max())
+        print(f"member {k} ({sc.name}, p={sc.params['p']}, E={sc.mesh.n_tri}): rel L2 {err}, "
+              f"FP32 storage alone {scale}, bar {bar:.1e}", flush=True)
+        assert err.max() <= bar, (k, err, scale)
         assert m["steps"] == n and abs(m["t"] - orc.t) <= 1e-6 * orc.t
     for sl in slots:
         b.retire(sl)
