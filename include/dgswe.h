@@ -256,6 +256,20 @@ int dgswe_set_river_flux(dgswe_ctx* ctx, int32_t slot, int32_t n, const double* 
 
 /* Advance n_steps time steps (asynchronous; see the conventions above). */
 int dgswe_step(dgswe_ctx* ctx, int64_t n_steps);
+/* The same steps as dgswe_step, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): nothing is allocated or freed, no graph is built and no
+ * event is created; the steps are enqueued one launch at a time on the
+ * context's stream.  The tile partials, reduction records and counter that
+ * dgswe_step keeps in the context are placed in one static array of 1 MiB
+ * per GPU instead, held until the process ends, which bounds the mesh:
+ * EINVAL (with the limit in the message) above 2,088,704 triangles.  The
+ * context's own arrays are updated at the end as after dgswe_step, so the
+ * two calls can be mixed.  Calls that overlap on one GPU share the array
+ * and race: keep them in one stream order.  ESTATE inside a batch or when
+ * the context's device is not the current one; results are bit for bit
+ * those of dgswe_step. */
+int dgswe_step_noalloc(dgswe_ctx* ctx, int64_t n_steps);
 /* Wait for queued work; returns the latched device error if any
  * (ENONFINITE, whose message names the first element whose state became
  * non-finite). */

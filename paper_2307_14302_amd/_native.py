@@ -77,6 +77,7 @@ SIGNATURES = {
     "dgswe_set_ocean_tide": (C.c_int, [_P, C.c_int32, C.c_double, C.c_int32, _D]),
     "dgswe_set_river_flux": (C.c_int, [_P, C.c_int32, C.c_int32, _D, _D]),
     "dgswe_step": (C.c_int, [_P, C.c_int64]),
+    "dgswe_step_noalloc": (C.c_int, [_P, C.c_int64]),
     "dgswe_sync": (C.c_int, [_P]),
     "dgswe_read_state": (C.c_int, [_P, C.c_int, _D]),
     "dgswe_read_flags": (C.c_int, [_P, _U8]),

@@ -733,6 +733,36 @@ int64_t footprint(const dgswe_params* p, int64_t E, int64_t n_nodes) {
 
 }  // namespace
 
+// ---------------------------------------------------- allocation-free step
+// The partials, chunk records and counter of dgswe_step_noalloc live in one
+// file-scope device array per GPU, held until the process ends.  In host
+// code `scratch` names a host-side stand-in, never the device array: its
+// device address is taken once per device with hipGetSymbolAddress (with
+// that device current) and only that address is used.
+constexpr size_t SCRATCH_BYTES = size_t(1) << 20;
+static __device__ __align__(256) double scratch[SCRATCH_BYTES / sizeof(double)];
+
+namespace {
+std::mutex g_scratch_mu;
+std::map<int, double*> g_scratch_ptr;      // device id -> device address of scratch
+
+// Device address of scratch on device dev (which must be current), taken on
+// the first call for that device.  nullptr and a message on failure.
+double* scratch_on(int dev, std::string& err) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  auto it = g_scratch_ptr.find(dev);
+  if (it != g_scratch_ptr.end()) return it->second;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr) {
+    err = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+    return nullptr;
+  }
+  g_scratch_ptr[dev] = static_cast<double*>(ptr);
+  return static_cast<double*>(ptr);
+}
+}  // namespace
+
 // ======================================================================= API
 extern "C" {
 
@@ -1146,6 +1176,44 @@ static int build_graph(dgswe_ctx* c) {
   (void)hipGraphDestroy(g);
   if (e != hipSuccess) return fail(DGSWE_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
   c->graph_dirty = false;
+  return DGSWE_OK;
+}
+
+int dgswe_step_noalloc(dgswe_ctx* c, int64_t n) {
+  int rc = check_ctx(c, true, true);
+  if (rc) return rc;
+  if (c->in_batch) return fail(DGSWE_ESTATE, "context is a member of a batch");
+  if (n < 0) return fail(DGSWE_EINVAL, "negative step count");
+  int dev = -1;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev != c->device) return fail(DGSWE_ESTATE, "the context's device is not the current device");
+  const size_t nd = part_doubles(c->n_tiles);
+  if (nd * sizeof(double) > SCRATCH_BYTES) {
+    int tmax = int(SCRATCH_BYTES / sizeof(double) / NPART);
+    while (tmax > 0 && part_doubles(tmax) * sizeof(double) > SCRATCH_BYTES) --tmax;
+    return fail(DGSWE_EINVAL, "mesh too large for the static scratch: its partials need " +
+                                  std::to_string(nd * sizeof(double)) + " bytes, the scratch holds " +
+                                  std::to_string(SCRATCH_BYTES) + " (" + std::to_string(int64_t(tmax) * TILE) +
+                                  " triangles at most)");
+  }
+  std::string err;
+  double* const ptr = scratch_on(dev, err);
+  if (!ptr) return fail(DGSWE_EHIP, err);
+  const int nt = std::max(c->n_tiles, 1);
+  // the array keeps the last call's contents: bring in what a step carries
+  // over (the rain partial, written once for constant rain) and clear the
+  // reduction counter, which must start at zero
+  HIPCHK(hipMemcpyAsync(ptr + size_t(P_RAIN) * nt, c->part.as<double>() + size_t(P_RAIN) * nt, sizeof(double) * nt,
+                        hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(launch_fill_zero(ptr + nd - 1, 1, c->stream));
+  const int prof = c->prof;
+  c->prof = 0;                             // no events: nothing is created
+  for (int64_t i = 0; i < n && !rc; ++i) rc = ctx_enqueue_step(c, ptr);
+  c->prof = prof;
+  if (rc) return rc;
+  // leave the context's own arrays as dgswe_step would (later set-up calls
+  // read the last step's partials from them)
+  HIPCHK(hipMemcpyAsync(c->part.p, ptr, nd * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
   return DGSWE_OK;
 }
 
