@@ -519,6 +519,8 @@ def main():
     ap.add_argument("--no-serving", action="store_true", help="skip the request-loop run")
     ap.add_argument("--no-storm", action="store_true", help="skip the basin run with storm wind and pressure")
     ap.add_argument("--serve-requests", type=int, default=100, help="requests of the 400-request trace to serve")
+    ap.add_argument("--graded-only", action="store_true",
+                    help="run only the 3.6M-triangle graded leg (--steps steps) and print its JSON (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the library drives one GPU per process and has no multi-GPU "
@@ -527,6 +529,9 @@ def main():
     import torch
     import meshgen
     torch.cuda.set_device(0)
+    if args.graded_only:
+        print(json.dumps(run_graded(steps=args.steps, warmup=args.warmup)), flush=True)
+        return
     t0 = time.perf_counter()
     sc = meshgen.basin(args.N, p=args.p)
     log(f"workload generated in {time.perf_counter() - t0:.1f}s: {sc.mesh.n_tri} triangles")
