@@ -89,7 +89,7 @@ def step_bytes(E, n_nodes, rs, p, stages, limiter, fused, node_forcing=True):
     return b
 
 
-def run_precision(sc, precision, steps, warmup, variant=1, events=2, save_dir=None, fused=-1):
+def run_precision(sc, precision, steps, warmup, variant=1, events=2, save_dir=None, fused=-1, tile=-1):
     from paper_2307_14302_amd import Solver
     import torch
 
@@ -104,10 +104,13 @@ def run_precision(sc, precision, steps, warmup, variant=1, events=2, save_dir=No
         s.set_variant(variant)
     if fused >= 0:
         s.set_fused(fused)
-    fused = s.fused()
-    log(f"[{precision}] setup {time.perf_counter() - t0:.1f}s  E={s.n_tri}  stage variant {variant} fused {fused}"
-        + (f" (autotuned ms/step: per-element {tuned[0]:.3f}, per-edge {tuned[1]:.3f}, fused {tuned[2]:.3f})"
-           if tuned else ""))
+    if tile > 0:
+        s.set_tile(tile)
+    fused, tile = s.fused(), s.tile()
+    log(f"[{precision}] setup {time.perf_counter() - t0:.1f}s  E={s.n_tri}  stage variant {variant} fused {fused} "
+        f"tile {tile}"
+        + (f" (autotuned ms/step: per-element {tuned[0]:.3f}, per-edge {tuned[1]:.3f}, fused {tuned[2]:.3f}, "
+           f"tile 512 {tuned[3]:.3f})" if tuned else ""))
     s.step(warmup)
     s.sync()
     # events on the stage kernel's own dispatches only: the dominant
@@ -157,7 +160,7 @@ def run_precision(sc, precision, steps, warmup, variant=1, events=2, save_dir=No
     n_nodes = s.n_nodes
     s.close()
     return dict(rate=rate, elapsed=el, stats=stats, mass=m, E=E, stages=stages, variant=variant, graph=graph,
-                fused=fused, tuned=tuned, steps=steps, n_nodes=n_nodes)
+                fused=fused, tile=tile, tuned=tuned, steps=steps, n_nodes=n_nodes)
 
 
 def kernel_sources_hash():
@@ -365,6 +368,7 @@ def run_graded(steps=1000, warmup=20):
     return {"value": round(r["rate"], 1), "unit": "element-stage updates/s", "n_tri": r["E"], "steps": steps,
             "ms_per_step": round(r["elapsed"] / steps * 1e3, 4), "stage_avg_us": round(ms / max(n, 1) * 1e3, 2),
             "dt_s": r["mass"]["dt_last"], "dtype": "f32", "stage_variant": r["variant"], "fused": r["fused"],
+            "stage_tile": r["tile"],
             "roofline": roofline(r, "fp32", 1, True),
             "workload": "graded coast 30 m - 15.36 km, 1229 x 922 km, tides, 3 rivers, gridded rain, LLF, limiter"}
 
@@ -508,6 +512,8 @@ def main():
     ap.add_argument("--no-c1", action="store_true", help="skip the 1024-triangle channel run")
     ap.add_argument("--fused", type=int, default=-1, choices=[-1, 0, 1],
                     help="post-processing fused into the next stage: 0 off, 1 on, -1 as the autotuner picks")
+    ap.add_argument("--tile", type=int, default=-1, choices=[-1, 256, 512],
+                    help="elements per workgroup of the per-edge stage kernel (p = 1): -1 as the autotuner picks")
     ap.add_argument("--variant", type=int, default=-1,
                     help="stage kernel: 0 per element, 1 per edge, -1 autotuned on the workload (default)")
     ap.add_argument("--calib-copy", action="store_true", help="also run a 1 GiB device copy (counter calibration)")
@@ -544,7 +550,8 @@ def main():
         mode = 0 if args.no_events else (1 if args.events_all else 2)
         res[prec] = run_precision(sc, prec, args.steps, args.warmup, args.variant, mode,
                                   save_dir=outdir if (prec == "fp32" and not args.no_cpu and args.N == 708
-                                                      and args.p == 1) else None, fused=args.fused)
+                                                      and args.p == 1) else None, fused=args.fused,
+                                  tile=args.tile)
     if args.calib_copy:
         a = torch.empty(256 * 1024 * 1024, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)
@@ -564,7 +571,7 @@ def main():
                                f"p={args.p}, LLF, limiter on, parametric moving rain, wet/dry front, "
                                + f"SSP-RK{r['stages']} CFL {prm['cfl']}",
                    "n_tri": r["E"], "p": prm["p"], "rk_stages": r["stages"], "precision": main_prec,
-                   "stage_variant": r["variant"], "fused_post": r["fused"],
+                   "stage_variant": r["variant"], "fused_post": r["fused"], "stage_tile": r["tile"],
                    "parallelism": "single GPU"},
         "roofline": roofline(r, main_prec, prm["p"], prm["limiter"]),
     }

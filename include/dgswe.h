@@ -313,23 +313,29 @@ int dgswe_kernel_stats(dgswe_ctx* ctx, const char* kernel, int64_t* launches, do
  * positive-depth operator (Sec. 2.3, Sec. 2.4) to its input itself, for its
  * tile and the ring of outside elements across the tile's edges, instead of
  * a separate pass over the whole state; 0 (default) = separate pass after
- * every stage.  dgswe_autotune times both.  The fused form needs a tile neighbourhood that fits
- * the kernel's LDS (built at upload; otherwise the key reads back 0).
- * EINVAL for unknown keys or values; ESTATE while the context is in a
- * batch. */
+ * every stage.  The fused form needs a tile neighbourhood that fits the
+ * kernel's LDS (built at upload; otherwise the key reads back 0).
+ * DGSWE_TUNE_STAGE_TILE (variant 1, p = 1, not fused): elements per
+ * workgroup of the per-edge stage kernel, 256 (default) or 512; a larger
+ * tile evaluates fewer cut edges twice and stages more point values per
+ * workgroup (otherwise the key reads back 256).  dgswe_autotune times
+ * every applicable choice.  EINVAL for unknown keys or values; ESTATE
+ * while the context is in a batch. */
 #define DGSWE_TUNE_STAGE_VARIANT 1
 #define DGSWE_TUNE_FUSED_POST    2
+#define DGSWE_TUNE_STAGE_TILE    3
 int dgswe_set_tuning(dgswe_ctx* ctx, int key, int value);
 int dgswe_get_tuning(const dgswe_ctx* ctx, int key, int* value);
 
 /* Autotuner: times n_steps steps of this context in each configuration
  * (after two untimed steps each): per-element kernel, per-edge kernel with
  * a post pass after every stage, per-edge kernel with the post-processing
- * fused into the next stage (when available); keeps the fastest and
- * restores the state, flags, tile partials and scalars, so the context
- * continues exactly where it was.  chosen (may be NULL) receives the stage
- * variant, ms_per_step[3] (may be NULL) the three timings (0 where a
- * configuration does not apply); the fused choice reads back through
+ * fused into the next stage (when available), per-edge kernel on
+ * 512-element tiles (p = 1); keeps the fastest and restores the state,
+ * flags, tile partials and scalars, so the context continues exactly where
+ * it was.  chosen (may be NULL) receives the stage variant, ms_per_step[4]
+ * (may be NULL) the four timings in that order (0 where a configuration
+ * does not apply); the fused and tile choices read back through
  * dgswe_get_tuning.  Allocates a copy of the
  * state for the duration of the call.  EINVAL for n_steps < 1, ESTATE
  * without mesh or state or inside a batch, ENONFINITE if the context has a

@@ -21,6 +21,7 @@ MODAL, VERTEX = 0, 1
 MAX_SLOTS = 16
 TUNE_STAGE_VARIANT = 1
 TUNE_FUSED_POST = 2
+TUNE_STAGE_TILE = 3
 
 ERRORS = {
     DGSWE_EINVAL: "EINVAL", DGSWE_ENOMEM: "ENOMEM", DGSWE_EHIP: "EHIP",

@@ -228,7 +228,9 @@ struct dgswe_ctx {
   int n_tiles = 0;
   int variant = 1;                  // stage kernel: 0 per element, 1 per edge
   int fused = 0;                    // limiter on, per-edge kernel: later stages post-process their input
-  DevBuf W[3], Wt, F[3], fullwet[2], R, part, sc, memb, tiles, ids, rnode, met, node_tiles;
+  int tile = TILE;                  // elements per workgroup of the per-edge stage kernel (256, or 512 at p = 1)
+  int n_tiles512 = 0;
+  DevBuf W[3], Wt, F[3], fullwet[2], R, part, sc, memb, tiles, tiles512, ids, rnode, met, node_tiles;
   int n_node_tiles = 0;
   DevBuf storm, gt, gvals, tide_c, riv_tq, wind;
   Forcing fo{};
@@ -257,8 +259,11 @@ struct dgswe_ctx {
   }
   int E() const { return mesh ? int(mesh->host.E) : 0; }
   int NP() const { return prm.p == 1 ? 3 : prm.p == 2 ? 6 : 10; }
-  // the fused stage kernel runs: limiter on, per-edge kernel, a halo built
-  bool use_fused() const { return fused && variant == 1 && prm.limiter && mesh && mesh->halo_ok; }
+  // stage workgroups of 512 elements: per-edge kernel at p = 1
+  bool use_tile512() const { return tile == 512 && variant == 1 && prm.p == 1; }
+  // the fused stage kernel runs: limiter on, per-edge kernel, a halo built,
+  // 256-element tiles
+  bool use_fused() const { return fused && variant == 1 && prm.limiter && mesh && mesh->halo_ok && !use_tile512(); }
 };
 
 struct dgswe_batch {
@@ -274,11 +279,11 @@ struct dgswe_batch {
   std::vector<Slot> slots;
   bool dirty = true;
   struct Group {
-    int p, flux, limiter, variant, fused;
+    int p, flux, limiter, variant, fused, tile;
     RKTable rk;
     std::vector<int> members;       // indices into the member array
-    int n_tiles = 0, n_node_tiles = 0, max_chunks = 1;
-    DevBuf tiles, node_tiles, ids;
+    int n_tiles = 0, n_node_tiles = 0, max_chunks = 1, n_tiles512 = 0;
+    DevBuf tiles, node_tiles, ids, tiles512;
     bool node_forcing = false;    // some member needs the per-step node kernel
   };
   std::vector<Group> groups;
@@ -446,7 +451,13 @@ template <typename Real>
 int enqueue_step_group(const Member<Real>* d_m, const Tile* d_t, int n_tiles, const Tile* d_nt, int n_node_tiles,
                        const int* d_ids, int n_members, int max_chunks, int p, int flux, int limiter, int variant,
                        const RKTable& T, bool node_forcing, hipStream_t s, dgswe_ctx* prof, bool single,
-                       double* part_over = nullptr, bool fused = false) {
+                       double* part_over = nullptr, bool fused = false, const Tile* d_t512 = nullptr,
+                       int n_tiles512 = 0) {
+  // stage launches over 512-element tiles when a list of them is given
+  const bool t512 = d_t512 != nullptr;
+  const Tile* st_tiles = t512 ? d_t512 : d_t;
+  const int st_n = t512 ? n_tiles512 : n_tiles;
+  const int st_tile = t512 ? 512 : TILE;
   if (node_forcing) {
     ProfScope ps(prof, K_RAIN);
     // nodal rain rates, wind stress and pressure head at t^n; the first
@@ -462,7 +473,8 @@ int enqueue_step_group(const Member<Real>* d_m, const Tile* d_t, int n_tiles, co
       // pass limits it there, or (fused) the next stage does it for itself
       {
         ProfScope ps(prof, K_STAGE, true);
-        HIPCHK(launch_stage<Real>(p, flux, 1, variant, d_m, d_t, n_tiles, a, s, ps.a, ps.b, fused && i > 0 ? 1 : 0));
+        HIPCHK(launch_stage<Real>(p, flux, 1, variant, d_m, st_tiles, st_n, a, s, ps.a, ps.b, fused && i > 0 ? 1 : 0,
+                                  st_tile));
       }
       if (!fused || a.last) {
         ProfScope ps(prof, K_POST);
@@ -470,7 +482,7 @@ int enqueue_step_group(const Member<Real>* d_m, const Tile* d_t, int n_tiles, co
       }
     } else {
       ProfScope ps(prof, K_STAGE, true);
-      HIPCHK(launch_stage<Real>(p, flux, 0, variant, d_m, d_t, n_tiles, a, s, ps.a, ps.b));
+      HIPCHK(launch_stage<Real>(p, flux, 0, variant, d_m, st_tiles, st_n, a, s, ps.a, ps.b, 0, st_tile));
     }
   }
   ProfScope ps(prof, K_REDUCE);
@@ -484,11 +496,13 @@ int ctx_enqueue_step(dgswe_ctx* c, double* part_over = nullptr) {
     return enqueue_step_group<double>(c->memb.as<Member<double>>(), c->tiles.as<Tile>(), c->n_tiles,
                                       c->node_tiles.as<Tile>(), c->n_node_tiles, c->ids.as<int>(), 1, red_chunks(c->n_tiles),
                                       c->prm.p, c->prm.flux, c->prm.limiter, c->variant, c->rk, rain, c->stream, c, true,
-                                      part_over, c->use_fused());
+                                      part_over, c->use_fused(), c->use_tile512() ? c->tiles512.as<Tile>() : nullptr,
+                                      c->n_tiles512);
   return enqueue_step_group<float>(c->memb.as<Member<float>>(), c->tiles.as<Tile>(), c->n_tiles,
                                    c->node_tiles.as<Tile>(), c->n_node_tiles, c->ids.as<int>(), 1, red_chunks(c->n_tiles),
                                    c->prm.p, c->prm.flux, c->prm.limiter, c->variant, c->rk, rain, c->stream, c, true,
-                                   part_over, c->use_fused());
+                                   part_over, c->use_fused(), c->use_tile512() ? c->tiles512.as<Tile>() : nullptr,
+                                   c->n_tiles512);
 }
 
 // Doubles of a context's partials array: tile partials, the reduction's
@@ -617,6 +631,13 @@ int alloc_state(dgswe_ctx* c) {
   for (int t = 0; t < c->n_tiles; ++t) tl[t] = {0, t};
   if (tl.empty()) tl.push_back({0, 0});
   HIPCHK(upload(c->tiles, tl));
+  // 512-element tiles of the per-edge stage kernel (p = 1)
+  c->n_tiles512 = int((E + 511) / 512);
+  if (c->prm.p == 1) {
+    std::vector<Tile> t2(std::max(c->n_tiles512, 1), Tile{0, 0});
+    for (int t = 0; t < c->n_tiles512; ++t) t2[t] = {0, t};
+    HIPCHK(upload(c->tiles512, t2));
+  }
   return push_member(c);
 }
 
@@ -727,6 +748,7 @@ int64_t footprint(const dgswe_params* p, int64_t E, int64_t n_nodes) {
   b += 4 * blk(3 * NP * E * rs) + 3 * blk(E) + (p->limiter ? 2 * blk(E) : 0) + blk(E * rs);
   b += blk(nn * 8) + blk(3 * nn * rs);
   b += blk(std::max<int64_t>(node_tiles, 1) * int64_t(sizeof(Tile))) + blk(std::max<int64_t>(tiles, 1) * int64_t(sizeof(Tile)));
+  if (p->p == 1) b += blk(std::max<int64_t>((E + 511) / 512, 1) * int64_t(sizeof(Tile)));   // 512-element tiles
   b += blk((NPART * std::max<int64_t>(tiles, 1) + NRED * int64_t(red_chunks(int(tiles))) + 1) * 8);
   return b;
 }
@@ -1341,11 +1363,14 @@ int dgswe_set_tuning(dgswe_ctx* c, int key, int value) {
   int rc = check_ctx(c, false);
   if (rc) return rc;
   if (c->in_batch) return fail(DGSWE_ESTATE, "context is a member of a batch");
-  if (key != DGSWE_TUNE_STAGE_VARIANT && key != DGSWE_TUNE_FUSED_POST) return fail(DGSWE_EINVAL, "unknown tuning key");
-  if (value != 0 && value != 1) return fail(DGSWE_EINVAL, "tuning values are 0 or 1");
+  if (key != DGSWE_TUNE_STAGE_VARIANT && key != DGSWE_TUNE_FUSED_POST && key != DGSWE_TUNE_STAGE_TILE)
+    return fail(DGSWE_EINVAL, "unknown tuning key");
+  if (key == DGSWE_TUNE_STAGE_TILE ? (value != TILE && value != 512) : (value != 0 && value != 1))
+    return fail(DGSWE_EINVAL, "tuning values are 0 or 1 (stage tile: 256 or 512)");
   if (c->stream) HIPCHK(hipStreamSynchronize(c->stream));
   if (key == DGSWE_TUNE_STAGE_VARIANT) c->variant = value;
-  else c->fused = value;
+  else if (key == DGSWE_TUNE_FUSED_POST) c->fused = value;
+  else c->tile = value;
   c->graph_dirty = true;
   return DGSWE_OK;
 }
@@ -1353,13 +1378,16 @@ int dgswe_set_tuning(dgswe_ctx* c, int key, int value) {
 int dgswe_get_tuning(const dgswe_ctx* c, int key, int* value) {
   int rc = check_ctx(c, false);
   if (rc) return rc;
-  if (!value || (key != DGSWE_TUNE_STAGE_VARIANT && key != DGSWE_TUNE_FUSED_POST))
+  if (!value || (key != DGSWE_TUNE_STAGE_VARIANT && key != DGSWE_TUNE_FUSED_POST && key != DGSWE_TUNE_STAGE_TILE))
     return fail(DGSWE_EINVAL, "unknown tuning key or null output");
-  *value = key == DGSWE_TUNE_STAGE_VARIANT ? c->variant : (c->use_fused() ? 1 : 0);
+  *value = key == DGSWE_TUNE_STAGE_VARIANT ? c->variant
+           : key == DGSWE_TUNE_FUSED_POST  ? (c->use_fused() ? 1 : 0)
+                                           : (c->use_tile512() ? 512 : TILE);
   return DGSWE_OK;
 }
 
 int dgswe_autotune(dgswe_ctx* c, int n_steps, int* chosen, double* ms_per_step) {
+  constexpr int NCFG = 4;
   int rc = check_ctx(c, true, true);
   if (rc) return rc;
   ArenaScope arena_scope(c->arena);
@@ -1388,21 +1416,24 @@ int dgswe_autotune(dgswe_ctx* c, int n_steps, int* chosen, double* ms_per_step) 
     return DGSWE_OK;
   };
   const int saved_prof = c->prof;
-  const int saved_fused = c->fused;
+  const int saved_fused = c->fused, saved_tile = c->tile;
   c->prof = 0;
   hipEvent_t ea, eb;
   HIPCHK(hipEventCreate(&ea));
   HIPCHK(hipEventCreate(&eb));
   // configurations: per-element kernel; per-edge kernel with the post pass
   // after every stage; per-edge kernel with the post-processing fused into
-  // the next stage (limiter on, p <= 2, a halo built)
-  const int cfg_variant[3] = {0, 1, 1}, cfg_fused[3] = {0, 0, 1};
-  double ms[3] = {0.0, 0.0, 0.0};
+  // the next stage (limiter on, p <= 2, a halo built); per-edge kernel on
+  // 512-element tiles (p = 1)
+  const int cfg_variant[NCFG] = {0, 1, 1, 1}, cfg_fused[NCFG] = {0, 0, 1, 0}, cfg_tile[NCFG] = {TILE, TILE, TILE, 512};
+  double ms[NCFG] = {0.0, 0.0, 0.0, 0.0};
   int err = DGSWE_OK;
-  for (int v = 0; v < 3 && !err; ++v) {
+  for (int v = 0; v < NCFG && !err; ++v) {
     c->variant = cfg_variant[v];
     c->fused = cfg_fused[v];
-    if (v == 2 && !c->use_fused()) break;      // the same as configuration 1
+    c->tile = cfg_tile[v];
+    if (v == 2 && !c->use_fused()) continue;    // the same as configuration 1
+    if (v == 3 && !c->use_tile512()) continue;
     c->graph_dirty = true;
     err = dgswe_step(c, 2);                     // builds the step graph, warms caches
     if (!err) err = restore();
@@ -1422,17 +1453,20 @@ int dgswe_autotune(dgswe_ctx* c, int n_steps, int* chosen, double* ms_per_step) 
   c->prof = saved_prof;
   if (err) {
     c->fused = saved_fused;
+    c->tile = saved_tile;
     (void)restore();
     return err;
   }
   int best = 0;
-  for (int v = 1; v < 3; ++v)
+  for (int v = 1; v < NCFG; ++v)
     if (ms[v] > 0.0 && ms[v] <= ms[best]) best = v;
   c->variant = cfg_variant[best];
   c->fused = cfg_fused[best];
+  c->tile = cfg_tile[best];
   c->graph_dirty = true;
   if (chosen) *chosen = c->variant;
-  if (ms_per_step) { ms_per_step[0] = ms[0]; ms_per_step[1] = ms[1]; ms_per_step[2] = ms[2]; }
+  if (ms_per_step)
+    for (int v = 0; v < NCFG; ++v) ms_per_step[v] = ms[v];
   return DGSWE_OK;
 }
 
@@ -1469,7 +1503,7 @@ namespace {
 template <typename Real>
 int batch_rebuild_t(dgswe_batch* b) {
   std::vector<Member<Real>> ms;
-  std::map<std::tuple<int, int, int, int, int, int>, int> gi;
+  std::map<std::tuple<int, int, int, int, int, int, int>, int> gi;
   b->groups.clear();
   for (size_t i = 0; i < b->slots.size(); ++i) {
     const auto& sl = b->slots[i];
@@ -1477,7 +1511,8 @@ int batch_rebuild_t(dgswe_batch* b) {
     const int idx = int(ms.size());
     ms.push_back(member_struct<Real>(sl.ctx));
     const dgswe_params& p = sl.ctx->prm;
-    auto key = std::make_tuple(p.p, p.flux, p.limiter, p.rk_stages, sl.ctx->variant, sl.ctx->use_fused() ? 1 : 0);
+    auto key = std::make_tuple(p.p, p.flux, p.limiter, p.rk_stages, sl.ctx->variant, sl.ctx->use_fused() ? 1 : 0,
+                               sl.ctx->use_tile512() ? 512 : TILE);
     auto it = gi.find(key);
     if (it == gi.end()) {
       dgswe_batch::Group g;
@@ -1486,6 +1521,7 @@ int batch_rebuild_t(dgswe_batch* b) {
       g.limiter = p.limiter;
       g.variant = sl.ctx->variant;
       g.fused = sl.ctx->use_fused() ? 1 : 0;
+      g.tile = sl.ctx->use_tile512() ? 512 : TILE;
       make_rk(p.rk_stages, g.rk);
       b->groups.push_back(std::move(g));
       it = gi.emplace(key, int(b->groups.size()) - 1).first;
@@ -1497,12 +1533,14 @@ int batch_rebuild_t(dgswe_batch* b) {
   if (ms.empty()) ms.push_back(Member<Real>{});
   HIPCHK(upload(b->memb, ms));
   for (auto& g : b->groups) {
-    std::vector<Tile> tl, ntl;
+    std::vector<Tile> tl, ntl, t2;
     g.max_chunks = 1;
     for (int m : g.members) {
       const int nt = ms[m].n_tiles;
       g.max_chunks = std::max(g.max_chunks, red_chunks(nt));
       for (int t = 0; t < nt; ++t) tl.push_back({m, t});
+      if (g.tile == 512)
+        for (int t = 0; t < (ms[m].E + 511) / 512; ++t) t2.push_back({m, t});
       const int nnt = (ms[m].n_nodes + TILE - 1) / TILE;
       for (int t = 0; t < nnt; ++t) ntl.push_back({m, t});
     }
@@ -1513,6 +1551,11 @@ int batch_rebuild_t(dgswe_batch* b) {
     HIPCHK(upload(g.tiles, tl));
     HIPCHK(upload(g.node_tiles, ntl));
     HIPCHK(upload(g.ids, g.members));
+    g.n_tiles512 = int(t2.size());
+    if (g.tile == 512) {
+      if (t2.empty()) t2.push_back({0, 0});
+      HIPCHK(upload(g.tiles512, t2));
+    }
   }
   b->dirty = false;
   return DGSWE_OK;
@@ -1604,12 +1647,14 @@ static int batch_enqueue_step(dgswe_batch* b) {
       rc = enqueue_step_group<float>(b->memb.as<Member<float>>(), g.tiles.as<Tile>(), g.n_tiles,
                                      g.node_tiles.as<Tile>(), g.n_node_tiles, g.ids.as<int>(),
                                      int(g.members.size()), g.max_chunks, g.p, g.flux, g.limiter, g.variant, g.rk,
-                                     g.node_forcing, b->stream, nullptr, false, nullptr, g.fused != 0);
+                                     g.node_forcing, b->stream, nullptr, false, nullptr, g.fused != 0,
+                                     g.tile == 512 ? g.tiles512.as<Tile>() : nullptr, g.n_tiles512);
     else
       rc = enqueue_step_group<double>(b->memb.as<Member<double>>(), g.tiles.as<Tile>(), g.n_tiles,
                                       g.node_tiles.as<Tile>(), g.n_node_tiles, g.ids.as<int>(),
                                       int(g.members.size()), g.max_chunks, g.p, g.flux, g.limiter, g.variant, g.rk,
-                                      g.node_forcing, b->stream, nullptr, false, nullptr, g.fused != 0);
+                                      g.node_forcing, b->stream, nullptr, false, nullptr, g.fused != 0,
+                                     g.tile == 512 ? g.tiles512.as<Tile>() : nullptr, g.n_tiles512);
     if (rc) return rc;
   }
   return DGSWE_OK;

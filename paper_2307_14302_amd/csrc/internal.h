@@ -144,10 +144,12 @@ struct RKInfo {
 // fused = 1 (variant 1, limiter on, p <= 2, members with a halo): the stage
 // reads the previous stage's raw output and applies its limiter and
 // positive-depth operator itself, in place of that stage's post pass
+// tile = 512 (variant 1, p = 1, not fused): workgroups of 512 elements; the
+// tile list and count are then those of 512-element tiles
 template <typename Real>
 hipError_t launch_stage(int P, int flux, int limiter, int variant, const Member<Real>* d_members,
                         const Tile* d_tiles, int n_tiles, StageArgs a, hipStream_t s, hipEvent_t ev0 = nullptr,
-                        hipEvent_t ev1 = nullptr, int fused = 0);
+                        hipEvent_t ev1 = nullptr, int fused = 0, int tile = TILE);
 template <typename Real>
 hipError_t launch_post(int P, int use_lim, const Member<Real>* d_members, const Tile* d_tiles, int n_tiles,
                        StageArgs a, int init, hipStream_t s);

@@ -28,6 +28,7 @@ namespace dg {
 #define DG_STAGE_WAVES 1
 #endif
 #define DG_STAGE_ATTR __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(DG_STAGE_WAVES)))
+#define DG_STAGE_ATTR_T(T) __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(DG_STAGE_WAVES)))
 
 // f(std::integral_constant<int, i>) for i = 0 .. N-1, expanded at compile time
 template <typename F, int... I>
@@ -902,7 +903,7 @@ DG_DEV void load_blend(const Member<Real>& M, const StageArgs& A, int E, int ec,
 // Inverse mass, SSP combination, positive-depth operator (LIM = 0) or the
 // fully-wet byte (LIM = 1), stores, and the tile partials (lds: 4 x 8
 // doubles of the caller's shared memory).
-template <typename Real, int P, int LIM>
+template <typename Real, int P, int LIM, int T = TILE>
 DG_DEV void finish_stage(const Member<Real>& M, const StageArgs& A, int tile, int e, int ec, bool valid, int E,
                          Real (&w)[3][Tab<P>::NP], Real (&acc)[3][Tab<P>::NP], const Real (&hb)[3], const Real (&ex)[3],
                          const Real (&ey)[3], Real detJ, Real idet, double dt, double bout, double bin, Real Rv,
@@ -969,7 +970,7 @@ DG_DEV void finish_stage(const Member<Real>& M, const StageArgs& A, int tile, in
     s4 = double(__popcll(__ballot(part[4] != 0.0)));
     mn = wave_min(part[3]);
     s6 = double(__popcll(__ballot(neg)));
-    fb = first_lane_id(__ballot(bad), tile * TILE + wv * 64);
+    fb = first_lane_id(__ballot(bad), tile * T + wv * 64);
   }
   if (rain_here) s5 = wave_sum(rain_part);
   if (lane == 0) {
@@ -977,19 +978,23 @@ DG_DEV void finish_stage(const Member<Real>& M, const StageArgs& A, int tile, in
     l[0] = s0; l[1] = s1; l[2] = s2; l[3] = mn; l[4] = s4; l[5] = s5; l[6] = s6; l[7] = fb;
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
+  // one partial per 256 elements (four wavefronts), whatever the workgroup's
+  // tile size, so the sums and their order do not depend on it
+  const int sub = tile * (T / TILE) + int(threadIdx.x) / TILE;
+  if (threadIdx.x % TILE == 0 && sub < M.n_tiles) {
     DG_G double* __restrict__ pt = gp(A.part ? A.part : M.part);
     const int nt = M.n_tiles;
-    pt[(P_OUT0 + A.stage) * nt + tile] = (lds[0] + lds[8]) + (lds[16] + lds[24]);
-    pt[(P_IN0 + A.stage) * nt + tile] = (lds[1] + lds[9]) + (lds[17] + lds[25]);
+    const double* q = lds + (int(threadIdx.x) / TILE) * 32;
+    pt[(P_OUT0 + A.stage) * nt + sub] = (q[0] + q[8]) + (q[16] + q[24]);
+    pt[(P_IN0 + A.stage) * nt + sub] = (q[1] + q[9]) + (q[17] + q[25]);
     if (LIM == 0 && A.last) {
-      pt[P_VOL * nt + tile] = (lds[2] + lds[10]) + (lds[18] + lds[26]);
-      pt[P_MINR * nt + tile] = fmin(fmin(lds[3], lds[11]), fmin(lds[19], lds[27]));
-      pt[P_NDRY * nt + tile] = (lds[4] + lds[12]) + (lds[20] + lds[28]);
-      pt[P_NNEG * nt + tile] = (lds[6] + lds[14]) + (lds[22] + lds[30]);
-      pt[P_BAD * nt + tile] = fmin(fmin(lds[7], lds[15]), fmin(lds[23], lds[31]));
+      pt[P_VOL * nt + sub] = (q[2] + q[10]) + (q[18] + q[26]);
+      pt[P_MINR * nt + sub] = fmin(fmin(q[3], q[11]), fmin(q[19], q[27]));
+      pt[P_NDRY * nt + sub] = (q[4] + q[12]) + (q[20] + q[28]);
+      pt[P_NNEG * nt + sub] = (q[6] + q[14]) + (q[22] + q[30]);
+      pt[P_BAD * nt + sub] = fmin(fmin(q[7], q[15]), fmin(q[23], q[31]));
     }
-    if (rain_here) pt[P_RAIN * nt + tile] = (lds[5] + lds[13]) + (lds[21] + lds[29]);
+    if (rain_here) pt[P_RAIN * nt + sub] = (q[5] + q[13]) + (q[21] + q[29]);
   }
 }
 
@@ -1243,35 +1248,38 @@ __global__ DG_STAGE_ATTR void stage_kernel(const Member<Real>* __restrict__ mem,
 // post pass, and cut edges read their neighbour from LDS.  The limiter of
 // a ring-1 element reads the raw means of ring 2.  The arithmetic is the
 // post kernel's (the same functions).
-template <typename Real, int P, int FLUX, int LIM, int PRE>
-__global__ DG_STAGE_ATTR void stage_edge_kernel(const Member<Real>* __restrict__ mem,
+template <typename Real, int P, int FLUX, int LIM, int PRE, int T>
+__global__ DG_STAGE_ATTR_T(T) void stage_edge_kernel(const Member<Real>* __restrict__ mem,
                                                           const Tile* __restrict__ tiles, int n_tiles, StageArgs A) {
   constexpr int NP = Tab<P>::NP, NG = Tab<P>::NG;
   static_assert(!PRE || (LIM == 1 && P <= 2), "the fused post-processing needs the limiter and p <= 2");
+  static_assert(T == 256 || (T == 512 && !PRE), "tiles of 256, or 512 without the fused post-processing");
+  constexpr int NW = T / 64;                            // wavefronts per workgroup
+  constexpr int LB = T == 512 ? 9 : 8;                  // bits of a local element index in an edge entry
   // point values per variable (vertices, midpoints); p = 3 keeps its traces
   // in s_flux instead (each slot holds the element's own trace at that edge
   // point until phase B overwrites it with the flux there)
   constexpr int NN = P == 1 ? 3 : P == 2 ? 6 : 1;
-  constexpr int SL = TILE + (PRE ? HALO_R1 : 0);      // point-value slots: tile, then ring 1
+  constexpr int SL = T + (PRE ? HALO_R1 : 0);      // point-value slots: tile, then ring 1
   __shared__ Real s_node[3 * NN][SL];
   __shared__ Real s_hb[3][SL];
-  __shared__ Real s_flux[3 * NG * 3][TILE];            // [(k NG + g) 3 + var][element], scaled by (l/2) w_g
+  __shared__ Real s_flux[3 * NG * 3][T];            // [(k NG + g) 3 + var][element], scaled by (l/2) w_g
   // edge vectors in LDS, except for FP32 p = 2 and the fused kernel, where
   // dropping them (phase B reads them from the cache instead) lets one more
   // workgroup share a CU
   constexpr bool kEvLds = !PRE && !(P == 2 && sizeof(Real) == 4);
-  __shared__ Real s_ev[kEvLds ? 6 : 1][kEvLds ? TILE : 1];
+  __shared__ Real s_ev[kEvLds ? 6 : 1][kEvLds ? T : 1];
   __shared__ uint8_t s_flag[SL];
   // PRE: raw means and fully-wet bytes of tile, ring 1 and ring 2, in the
   // flux slots' memory (used before phase B writes any flux)
-  constexpr int SM = TILE + HALO_R1 + HALO_R2;
+  constexpr int SM = T + HALO_R1 + HALO_R2;
   static_assert(!PRE || 3 * SM * sizeof(Real) + SM <= sizeof(s_flux), "halo means fit the flux slots");
   Real* const s_mean = reinterpret_cast<Real*>(&s_flux[0][0]);
   uint8_t* const s_fw = reinterpret_cast<uint8_t*>(s_mean + 3 * SM);
   // edge list; after phase B the same memory holds the block's partial sums
-  __shared__ double s_lbuf[3 * TILE / 2];
+  __shared__ double s_lbuf[3 * T / 2];
   uint32_t* s_list = reinterpret_cast<uint32_t*>(s_lbuf);
-  __shared__ int s_wsum[4];
+  __shared__ int s_wsum[2][NW];
   const int ti = xcd_tile();
   if (ti >= n_tiles) return;
   const Tile tl = A.single ? Tile{0, ti} : tiles[ti];
@@ -1279,8 +1287,8 @@ __global__ DG_STAGE_ATTR void stage_edge_kernel(const Member<Real>* __restrict__
   const DG_G Scalars* __restrict__ sc = gp((const Scalars*)M.sc);
   if (!sc->active) return;
   const int E = M.E;
-  const int t0 = tl.tile * TILE;
-  const int tend = t0 + TILE < E ? t0 + TILE : E;
+  const int t0 = tl.tile * T;
+  const int tend = t0 + T < E ? t0 + T : E;
   const int el = threadIdx.x;
   const int e = t0 + el;
   const bool valid = e < E;
@@ -1338,28 +1346,28 @@ __global__ DG_STAGE_ATTR void stage_edge_kernel(const Member<Real>* __restrict__
 #pragma unroll
     for (int v = 0; v < 3; ++v) s_mean[v * SM + el] = d.w[v][0];
     s_fw[el] = valid ? ldx(fwin, ec) : uint8_t(0);
-    for (int j = el; j < hn; j += TILE) {
+    for (int j = el; j < hn; j += T) {
       const int z = ldx(gp(M.h_id), hoff + j);
 #pragma unroll
-      for (int v = 0; v < 3; ++v) s_mean[v * SM + TILE + j] = ldc(Win, (v * NP) * E, z);
-      s_fw[TILE + j] = ldx(fwin, z);
+      for (int v = 0; v < 3; ++v) s_mean[v * SM + T + j] = ldc(Win, (v * NP) * E, z);
+      s_fw[T + j] = ldx(fwin, z);
     }
     __syncthreads();
     myflag = post_from_slots<Real, P>(M, d.w, d.hb, lc_own, al_own, eslot, el, s_mean, s_fw, SM);
     if (ring) {
-      const bool fy = post_from_slots<Real, P>(M, wy, hy, lcy, aly, ns, TILE + el, s_mean, s_fw, SM);
+      const bool fy = post_from_slots<Real, P>(M, wy, hy, lcy, aly, ns, T + el, s_mean, s_fw, SM);
       Real vv[3][3], mv[3][3];
       edge_nodes<Real, P>(wy, vv, mv);
 #pragma unroll
       for (int v = 0; v < 3; ++v)
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
-          s_node[v * NN + i][TILE + el] = vv[v][i];
-          if (P == 2) s_node[v * NN + 3 + i][TILE + el] = mv[v][i];
+          s_node[v * NN + i][T + el] = vv[v][i];
+          if (P == 2) s_node[v * NN + 3 + i][T + el] = mv[v][i];
         }
 #pragma unroll
-      for (int k = 0; k < 3; ++k) s_hb[k][TILE + el] = hy[k];
-      s_flag[TILE + el] = fy ? 1 : 0;
+      for (int k = 0; k < 3; ++k) s_hb[k][T + el] = hy[k];
+      s_flag[T + el] = fy ? 1 : 0;
     }
   }
   // element rain (Eq. rain): the first stage of a step with time-dependent
@@ -1413,10 +1421,12 @@ __global__ DG_STAGE_ATTR void stage_edge_kernel(const Member<Real>* __restrict__
   // The edges this element evaluates, in three classes listed one after the
   // other so that a wavefront mostly runs one code path: (0) interior edges
   // inside the tile, owned by the lower id; (1) edges to other tiles;
-  // (2) boundary edges.  Entry: l | k << 8 | kn << 10 | ln << 12.
+  // (2) boundary edges.  Entry: l | k << LB | kn << (LB + 2) | ln << (LB + 4).
   uint32_t ent[3];
   int cls[3];
-  int packed = 0;                                    // 10-bit count per class
+  // counts per class: classes 0 and 1 in 16-bit fields, class 2 apart (a
+  // class holds at most 3 T entries)
+  int packed = 0, packed2 = 0;
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     const int nb = nbv[k];
@@ -1425,13 +1435,17 @@ __global__ DG_STAGE_ATTR void stage_edge_kernel(const Member<Real>* __restrict__
     cls[k] = !valid ? 3 : nb < 0 ? 2 : !inside ? 1 : (e < nb ? 0 : 3);
     // in the tile: the neighbour's local index; PRE, in ring 1: its slot
     const uint32_t at = inside ? uint32_t(nb - t0) : PRE ? (eslot >> (10 * k)) & HALO_SLOT_MASK : 0u;
-    ent[k] = uint32_t(el) | uint32_t(k) << 8 | uint32_t(kn) << 10 | at << 12;
-    packed += cls[k] < 3 ? 1 << (10 * cls[k]) : 0;
+    ent[k] = uint32_t(el) | uint32_t(k) << LB | uint32_t(kn) << (LB + 2) | at << (LB + 4);
+    packed += cls[k] == 0 ? 1 : cls[k] == 1 ? 1 << 16 : 0;
+    packed2 += cls[k] == 2 ? 1 : 0;
   }
-  // block-wide exclusive scan of the packed counts
+  // block-wide exclusive scan of the counts
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int incl = wave_incl_scan(packed);
-  if (lane == 63) s_wsum[wv] = incl;
+  const int incl = wave_incl_scan(packed), incl2 = wave_incl_scan(packed2);
+  if (lane == 63) {
+    s_wsum[0][wv] = incl;
+    s_wsum[1][wv] = incl2;
+  }
   Real acc[3][NP];
 #pragma unroll
   for (int v = 0; v < 3; ++v)
@@ -1448,15 +1462,19 @@ __global__ DG_STAGE_ATTR void stage_edge_kernel(const Member<Real>* __restrict__
     met_terms<Real, P>(mtx, mty, mps, d.w, d.hb, d.cx0, d.cx1, d.cy0, d.cy1, d.detJ, d.idet, g, acc);
   }
   __syncthreads();
-  int base = 0;
+  int base = 0, base2 = 0, tot = 0, tot2 = 0;
 #pragma unroll
-  for (int i = 0; i < 4; ++i) base += (i < wv) ? s_wsum[i] : 0;
-  const int tot = s_wsum[0] + s_wsum[1] + s_wsum[2] + s_wsum[3];
-  const int n0 = tot & 1023, n1 = (tot >> 10) & 1023, n2 = tot >> 20;
+  for (int i = 0; i < NW; ++i) {
+    base += (i < wv) ? s_wsum[0][i] : 0;
+    base2 += (i < wv) ? s_wsum[1][i] : 0;
+    tot += s_wsum[0][i];
+    tot2 += s_wsum[1][i];
+  }
+  const int n0 = tot & 0xFFFF, n1 = tot >> 16, n2 = tot2;
   const int n_list = n0 + n1 + n2;
   {
-    const int ex_ = base + incl - packed;
-    int pos[3] = {ex_ & 1023, n0 + ((ex_ >> 10) & 1023), n0 + n1 + (ex_ >> 20)};
+    const int ex_ = base + incl - packed, ex2 = base2 + incl2 - packed2;
+    int pos[3] = {ex_ & 0xFFFF, n0 + (ex_ >> 16), n0 + n1 + ex2};
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       const int c = cls[k];
@@ -1481,13 +1499,13 @@ __global__ DG_STAGE_ATTR void stage_edge_kernel(const Member<Real>* __restrict__
     // traces come from s_flux (own side, and the neighbour's when it is in
     // the tile) or from the neighbour's modes; only the thread of an edge
     // touches that edge's slots, so it reads them all before writing fluxes
-    for (int it = threadIdx.x; it < n_list; it += TILE) {
+    for (int it = threadIdx.x; it < n_list; it += T) {
       const uint32_t ent = s_list[it];
-      const int l = ent & 255, k = (ent >> 8) & 3, kn = (ent >> 10) & 3;
+      const int l = ent & (T - 1), k = (ent >> LB) & 3, kn = (ent >> (LB + 2)) & 3;
       const int k1 = k == 2 ? 0 : k + 1;
       const int eg = t0 + l;
       const bool in_tile = it < n0;
-      const int nb = in_tile ? t0 + int(ent >> 12) : ldc(nbr, k * E, eg);
+      const int nb = in_tile ? t0 + int(ent >> (LB + 4)) : ldc(nbr, k * E, eg);
       const Real exk = s_ev[2 * k][l], eyk = s_ev[2 * k + 1][l];
       Real ell, il;
       edge_length<Real>(exk, eyk, ell, il);
@@ -1564,14 +1582,14 @@ __global__ DG_STAGE_ATTR void stage_edge_kernel(const Member<Real>* __restrict__
       }
     }
   } else
-  for (int it = threadIdx.x; it < n_list; it += TILE) {
+  for (int it = threadIdx.x; it < n_list; it += T) {
     const uint32_t ent = s_list[it];
-    const int l = ent & 255, k = (ent >> 8) & 3, kn = (ent >> 10) & 3;
+    const int l = ent & (T - 1), k = (ent >> LB) & 3, kn = (ent >> (LB + 2)) & 3;
     const int k1 = k == 2 ? 0 : k + 1;
     const int eg = t0 + l;
     const bool in_tile = it < n0;
     // class 0: the neighbour's id is in the entry; otherwise re-read (cached)
-    const int nb = in_tile ? t0 + int(ent >> 12) : ldc(nbr, k * E, eg);
+    const int nb = in_tile ? t0 + int(ent >> (LB + 4)) : ldc(nbr, k * E, eg);
     const Real exk = kEvLds ? s_ev[2 * k][l] : ldc(gp(M.ev), (2 * k) * E, eg);
     const Real eyk = kEvLds ? s_ev[2 * k + 1][l] : ldc(gp(M.ev), (2 * k + 1) * E, eg);
     Real ell, il;
@@ -1601,7 +1619,7 @@ __global__ DG_STAGE_ATTR void stage_edge_kernel(const Member<Real>* __restrict__
         nflag = s_flag[ln];
       } else if constexpr (PRE) {
         // ring 1: post-processed in phase 0, point values in LDS
-        const int sl = int(ent >> 12);
+        const int sl = int(ent >> (LB + 4));
 #pragma unroll
         for (int v = 0; v < 3; ++v) {
           Na[v] = s_node[v * NN + kn][sl];
@@ -1721,7 +1739,7 @@ __global__ DG_STAGE_ATTR void stage_edge_kernel(const Member<Real>* __restrict__
     const double area = 0.5 * (double(d.ex[2]) * double(d.ey[0]) - double(d.ex[0]) * double(d.ey[2]));
     rain_part = valid ? area * double(Rv) : 0.0;
   }
-  finish_stage<Real, P, LIM>(M, A, tl.tile, e, ec, valid, E, d.w, acc, d.hb, d.ex, d.ey, d.detJ, d.idet, dt, bout,
+  finish_stage<Real, P, LIM, T>(M, A, tl.tile, e, ec, valid, E, d.w, acc, d.hb, d.ex, d.ey, d.detJ, d.idet, dt, bout,
                              bin, Rv, rain_part, s_lbuf, w0v);
 }
 
@@ -2316,9 +2334,9 @@ __global__ __launch_bounds__(RED_CHUNK) void reduce_kernel(const Member<Real>* _
 // ------------------------------------------------------------ launchers
 template <typename Real>
 hipError_t launch_stage(int P, int flux, int limiter, int variant, const Member<Real>* m, const Tile* t, int n,
-                        StageArgs a, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1, int fused) {
+                        StageArgs a, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1, int fused, int tile) {
   if (n <= 0) return hipSuccess;
-  dim3 grid(xcd_grid(n)), block(TILE);
+  dim3 grid(xcd_grid(n)), block(tile == 512 ? 512 : TILE);
   const bool timed = ev0 != nullptr || ev1 != nullptr;
 #define DG_LAUNCH(KERNEL)                                                                       \
   {                                                                                            \
@@ -2328,15 +2346,24 @@ hipError_t launch_stage(int P, int flux, int limiter, int variant, const Member<
   }
 #define DG_STAGE(PP, FF, LL)                                                                    \
   if (P == PP && flux == FF && limiter == LL) {                                                 \
-    if (variant == 1) DG_LAUNCH((stage_edge_kernel<Real, PP, FF, LL, 0>))                       \
+    if (variant == 1) DG_LAUNCH((stage_edge_kernel<Real, PP, FF, LL, 0, TILE>))                 \
     else DG_LAUNCH((stage_kernel<Real, PP, FF, LL>))                                            \
+  }
+  if (tile != TILE) {
+    // tiles of 512 elements: per-edge kernel, p = 1, no fused post-processing
+    if (tile != 512 || variant != 1 || fused || P != 1) return hipErrorInvalidValue;
+    if (flux == 0 && limiter == 0) DG_LAUNCH((stage_edge_kernel<Real, 1, 0, 0, 0, 512>))
+    if (flux == 1 && limiter == 0) DG_LAUNCH((stage_edge_kernel<Real, 1, 1, 0, 0, 512>))
+    if (flux == 0 && limiter == 1) DG_LAUNCH((stage_edge_kernel<Real, 1, 0, 1, 0, 512>))
+    if (flux == 1 && limiter == 1) DG_LAUNCH((stage_edge_kernel<Real, 1, 1, 1, 0, 512>))
+    return hipErrorInvalidValue;
   }
   if (fused) {
     if (variant != 1 || limiter != 1 || P > 2) return hipErrorInvalidValue;
-    if (P == 1 && flux == 0) DG_LAUNCH((stage_edge_kernel<Real, 1, 0, 1, 1>))
-    if (P == 1 && flux == 1) DG_LAUNCH((stage_edge_kernel<Real, 1, 1, 1, 1>))
-    if (P == 2 && flux == 0) DG_LAUNCH((stage_edge_kernel<Real, 2, 0, 1, 1>))
-    if (P == 2 && flux == 1) DG_LAUNCH((stage_edge_kernel<Real, 2, 1, 1, 1>))
+    if (P == 1 && flux == 0) DG_LAUNCH((stage_edge_kernel<Real, 1, 0, 1, 1, TILE>))
+    if (P == 1 && flux == 1) DG_LAUNCH((stage_edge_kernel<Real, 1, 1, 1, 1, TILE>))
+    if (P == 2 && flux == 0) DG_LAUNCH((stage_edge_kernel<Real, 2, 0, 1, 1, TILE>))
+    if (P == 2 && flux == 1) DG_LAUNCH((stage_edge_kernel<Real, 2, 1, 1, 1, TILE>))
     return hipErrorInvalidValue;
   }
   DG_STAGE(1, 0, 0) DG_STAGE(1, 1, 0) DG_STAGE(1, 0, 1) DG_STAGE(1, 1, 1)
@@ -2401,7 +2428,7 @@ hipError_t launch_fill_zero(double* p, int n, hipStream_t s) {
 
 #define DG_INST(R)                                                                                              \
   template hipError_t launch_stage<R>(int, int, int, int, const Member<R>*, const Tile*, int, StageArgs, hipStream_t, \
-                                      hipEvent_t, hipEvent_t, int);                                         \
+                                      hipEvent_t, hipEvent_t, int, int);                                    \
   template hipError_t launch_post<R>(int, int, const Member<R>*, const Tile*, int, StageArgs, int, hipStream_t);  \
   template hipError_t launch_classify<R>(int, const Member<R>*, const Tile*, int, hipStream_t);                   \
   template hipError_t launch_rain<R>(const Member<R>*, const Tile*, int, int, const Tile*, int, hipStream_t, int); \

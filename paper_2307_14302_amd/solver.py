@@ -180,12 +180,12 @@ class Solver:
     def autotune(self, n_steps: int = 5):
         """Pick the fastest stage-kernel configuration for this mesh; the
         state is left as it was.  Returns (variant, (ms/step per-element,
-        per-edge with post passes, per-edge fused; 0 where it does not
-        apply))."""
+        per-edge with post passes, per-edge fused, per-edge on 512-element
+        tiles; 0 where it does not apply))."""
         v = C.c_int()
-        ms = (C.c_double * 3)()
+        ms = (C.c_double * 4)()
         call("dgswe_autotune", self.h, int(n_steps), C.byref(v), ms)
-        return v.value, (ms[0], ms[1], ms[2])
+        return v.value, tuple(ms)
 
     def set_fused(self, on: bool):
         """Post-processing fused into the next stage (limiter on, p <= 2)."""
@@ -194,6 +194,16 @@ class Solver:
     def fused(self) -> int:
         v = C.c_int()
         call("dgswe_get_tuning", self.h, N.TUNE_FUSED_POST, C.byref(v))
+        return v.value
+
+    def set_tile(self, tile: int):
+        """Elements per workgroup of the per-edge stage kernel (256 or 512;
+        512 applies at p = 1 without fused post-processing)."""
+        call("dgswe_set_tuning", self.h, N.TUNE_STAGE_TILE, int(tile))
+
+    def tile(self) -> int:
+        v = C.c_int()
+        call("dgswe_get_tuning", self.h, N.TUNE_STAGE_TILE, C.byref(v))
         return v.value
 
     def variant(self) -> int:

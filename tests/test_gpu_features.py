@@ -455,14 +455,16 @@ def test_autotune_keeps_the_state(dg):
     a = dg.Solver.from_scenario(sc)
     a.step(7)
     v, ms = a.autotune(3)
-    # three configurations timed: per element, per edge, per edge fused
-    assert v in (0, 1) and ms[0] > 0.0 and ms[1] > 0.0 and ms[2] > 0.0
+    # four configurations timed: per element, per edge, per edge fused,
+    # per edge on 512-element tiles
+    assert v in (0, 1) and len(ms) == 4 and min(ms) > 0.0
     assert a.variant() == v and a.mass()["steps"] == 7
     a.step(10)
     b = dg.Solver.from_scenario(sc)
     b.step(7)
     b.set_variant(v)
     b.set_fused(a.fused())
+    b.set_tile(a.tile())
     b.step(10)
     assert np.array_equal(a.state(), b.state())
     assert a.mass() == b.mass()
@@ -532,6 +534,7 @@ def test_workspace_bind_places_the_context_in_caller_memory(dg):
         # timing noise may pick different kernels: run both on a's choice
         b.set_variant(a.variant())
         b.set_fused(a.fused())
+        b.set_tile(a.tile())
         a.step(5); b.step(5)
         assert np.array_equal(a.state(), b.state())
         a.sync()

@@ -181,3 +181,70 @@ def test_fused_post_processing_matches_separate_pass(dg, case, precision):
         rtol = 1e-12 if precision == "fp64" else (1e-4 if k.startswith("bnd") else 1e-6)
         assert abs(ma[k] - mb[k]) <= rtol * max(1.0, abs(mb[k])), (k, ma[k], mb[k])
     a.close(); b.close()
+
+
+TILE_CASES = {
+    "p1_roe_gridded": dict(p=1, flux="roe", limiter=False, rain_kind="gridded"),
+    "p1_llf_param_lim": dict(p=1, flux="llf", limiter=True, rain_kind="parametric"),
+    "p1_roe_nodal_lim": dict(p=1, flux="roe", limiter=True, rain_kind="nodal"),
+}
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("case", list(TILE_CASES) + ["basin_window"])
+def test_stage_tile_512_matches_256(dg, case, precision):
+    """The per-edge stage kernel on 512-element workgroups against 256: the
+    same arithmetic per edge and per element, and partial sums still taken
+    per 256 elements, so only which edges count as cut (evaluated from both
+    sides) changes; the states agree to rounding, each meets the oracle bar,
+    and the mass totals agree.  The meshes span several 512-element tiles
+    with a ragged last one."""
+    sc = meshgen.basin_window(40) if case == "basin_window" else meshgen.small_mixed(seed=6, nx=36, ny=18,
+                                                                                       **TILE_CASES[case])
+    E = sc.mesh.n_tri
+    assert E > 1024 and E % 512 != 0, E
+    n = 40
+    a = dg.Solver.from_scenario(sc, precision=precision)
+    b = dg.Solver.from_scenario(sc, precision=precision)
+    a.set_variant(1); b.set_variant(1)
+    a.set_tile(512)
+    assert a.tile() == 512 and b.tile() == 256
+    a.step(n); b.step(n)
+    orc = from_scenario(sc)
+    orc.step(n)
+    wa, wb = a.state(), b.state()
+    d = rel_l2(wa, wb, orc)
+    ea, eb = rel_l2(wa, orc.w, orc), rel_l2(wb, orc.w, orc)
+    print(f"{case} {precision} E={E}: tile 512 vs 256 {d} (bitwise {np.array_equal(wa, wb)}), "
+          f"vs oracle {ea} / {eb}", flush=True)
+    assert d.max() <= (1e-12 if precision == "fp64" else 1e-5), d
+    bar = 1e-10 if precision == "fp64" else 1e-4
+    assert ea.max() <= bar and eb.max() <= bar
+    assert np.array_equal(a.flags(), b.flags()) or precision == "fp32"
+    ma, mb = a.mass(), b.mass()
+    for k in ("t", "volume", "rain_in", "bnd_in", "bnd_out"):
+        rtol = 1e-12 if precision == "fp64" else (1e-4 if k.startswith("bnd") else 1e-6)
+        assert abs(ma[k] - mb[k]) <= rtol * max(1.0, abs(mb[k])), (k, ma[k], mb[k])
+    a.close(); b.close()
+
+
+def test_stage_tile_key(dg):
+    """512 applies to the per-edge kernel at p = 1 without fused
+    post-processing; elsewhere the key reads back 256.  Other values are
+    refused."""
+    import paper_2307_14302_amd._native as N
+    sc1 = meshgen.small_mixed(seed=6, nx=12, ny=6, p=1, flux="llf", limiter=True)
+    sc2 = meshgen.small_mixed(seed=6, nx=12, ny=6, p=2, flux="llf", limiter=True)
+    a, b = dg.Solver.from_scenario(sc1), dg.Solver.from_scenario(sc2)
+    a.set_variant(1); a.set_tile(512)
+    assert a.tile() == 512
+    a.set_variant(0)
+    assert a.tile() == 256
+    a.set_variant(1); a.set_fused(True)
+    assert a.tile() == 512 and a.fused() == 0          # the larger tile has no fused form
+    b.set_variant(1); b.set_tile(512)
+    assert b.tile() == 256
+    for bad in (0, 128, 300, 1024):
+        with pytest.raises(N.DgsweError, match="EINVAL"):
+            a.set_tile(bad)
+    a.close(); b.close()
