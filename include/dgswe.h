@@ -260,10 +260,10 @@ int dgswe_step(dgswe_ctx* ctx, int64_t n_steps);
  * memory (code under HIP graph capture, tight serving loops, harnesses that
  * forbid hipMalloc): nothing is allocated or freed, no graph is built and no
  * event is created; the steps are enqueued one launch at a time on the
- * context's stream.  The tile partials, reduction records and counter that
- * dgswe_step keeps in the context are placed in one static array of 1 MiB
- * per GPU instead, held until the process ends, which bounds the mesh:
- * EINVAL (with the limit in the message) above 2,088,704 triangles.  The
+ * context's stream.  The wavefront partials, reduction records and counter
+ * that dgswe_step keeps in the context are placed in one static array of
+ * 4 MiB per GPU instead, held until the process ends, which bounds the
+ * mesh: EINVAL (with the limit in the message) above 2,094,848 triangles.  The
  * context's own arrays are updated at the end as after dgswe_step, so the
  * two calls can be mixed.  Calls that overlap on one GPU share the array
  * and race: keep them in one stream order.  ESTATE inside a batch or when
@@ -315,10 +315,13 @@ int dgswe_kernel_stats(dgswe_ctx* ctx, const char* kernel, int64_t* launches, do
  * a separate pass over the whole state; 0 (default) = separate pass after
  * every stage.  The fused form needs a tile neighbourhood that fits the
  * kernel's LDS (built at upload; otherwise the key reads back 0).
- * DGSWE_TUNE_STAGE_TILE (variant 1, p = 1, not fused): elements per
- * workgroup of the per-edge stage kernel, 256 (default) or 512; a larger
- * tile evaluates fewer cut edges twice and stages more point values per
- * workgroup (otherwise the key reads back 256).  dgswe_autotune times
+ * DGSWE_TUNE_STAGE_TILE (variant 1): elements per workgroup of the
+ * per-edge stage kernel, 64, 128, 256 (default) or, at p = 1, 512.  A
+ * larger tile evaluates fewer cut edges twice; a smaller one lets more
+ * independent workgroups share a CU, with fewer wavefronts waiting at each
+ * barrier.  Results do not depend on it (partials are kept per wavefront).
+ * It reads back 256 where it does not apply (variant 0, 512 at p > 1); a
+ * tile other than 256 turns the fused form off.  dgswe_autotune times
  * every applicable choice.  EINVAL for unknown keys or values; ESTATE
  * while the context is in a batch. */
 #define DGSWE_TUNE_STAGE_VARIANT 1
@@ -330,13 +333,13 @@ int dgswe_get_tuning(const dgswe_ctx* ctx, int key, int* value);
 /* Autotuner: times n_steps steps of this context in each configuration
  * (after two untimed steps each): per-element kernel, per-edge kernel with
  * a post pass after every stage, per-edge kernel with the post-processing
- * fused into the next stage (when available), per-edge kernel on
- * 512-element tiles (p = 1); keeps the fastest and restores the state,
- * flags, tile partials and scalars, so the context continues exactly where
- * it was.  chosen (may be NULL) receives the stage variant, ms_per_step[4]
- * (may be NULL) the four timings in that order (0 where a configuration
- * does not apply); the fused and tile choices read back through
- * dgswe_get_tuning.  Allocates a copy of the
+ * fused into the next stage (when available), per-edge kernel on tiles of
+ * 512 (p = 1), 128 and 64 elements; keeps the fastest and restores the
+ * state, flags, partials and scalars, so the context continues exactly
+ * where it was.  chosen (may be NULL) receives the stage variant,
+ * ms_per_step[6] (may be NULL) the six timings in that order (0 where a
+ * configuration does not apply); the fused and tile choices read back
+ * through dgswe_get_tuning.  Allocates a copy of the
  * state for the duration of the call.  EINVAL for n_steps < 1, ESTATE
  * without mesh or state or inside a batch, ENONFINITE if the context has a
  * latched error. */

@@ -228,9 +228,11 @@ struct dgswe_ctx {
   int n_tiles = 0;
   int variant = 1;                  // stage kernel: 0 per element, 1 per edge
   int fused = 0;                    // limiter on, per-edge kernel: later stages post-process their input
-  int tile = TILE;                  // elements per workgroup of the per-edge stage kernel (256, or 512 at p = 1)
-  int n_tiles512 = 0;
-  DevBuf W[3], Wt, F[3], fullwet[2], R, part, sc, memb, tiles, tiles512, ids, rnode, met, node_tiles;
+  int tile = TILE;                  // elements per workgroup of the per-edge stage kernel (64, 128, 256, 512)
+  int n_tiles64 = 0;
+  // tiles of 64 elements {0, t}: its first ceil(E / T) entries list the
+  // stage tiles of any size T
+  DevBuf W[3], Wt, F[3], fullwet[2], R, part, sc, memb, tiles, tiles64, ids, rnode, met, node_tiles;
   int n_node_tiles = 0;
   DevBuf storm, gt, gvals, tide_c, riv_tq, wind;
   Forcing fo{};
@@ -259,11 +261,17 @@ struct dgswe_ctx {
   }
   int E() const { return mesh ? int(mesh->host.E) : 0; }
   int NP() const { return prm.p == 1 ? 3 : prm.p == 2 ? 6 : 10; }
-  // stage workgroups of 512 elements: per-edge kernel at p = 1
-  bool use_tile512() const { return tile == 512 && variant == 1 && prm.p == 1; }
+  // elements per workgroup of the stage kernel as launched: the chosen
+  // tile for the per-edge kernel (512 only at p = 1), else 256
+  int stage_tile() const {
+    if (variant != 1 || (tile == 512 && prm.p != 1)) return TILE;
+    return tile;
+  }
   // the fused stage kernel runs: limiter on, per-edge kernel, a halo built,
   // 256-element tiles
-  bool use_fused() const { return fused && variant == 1 && prm.limiter && mesh && mesh->halo_ok && !use_tile512(); }
+  bool use_fused() const {
+    return fused && variant == 1 && prm.limiter && mesh && mesh->halo_ok && stage_tile() == TILE;
+  }
 };
 
 struct dgswe_batch {
@@ -282,8 +290,8 @@ struct dgswe_batch {
     int p, flux, limiter, variant, fused, tile;
     RKTable rk;
     std::vector<int> members;       // indices into the member array
-    int n_tiles = 0, n_node_tiles = 0, max_chunks = 1, n_tiles512 = 0;
-    DevBuf tiles, node_tiles, ids, tiles512;
+    int n_tiles = 0, n_node_tiles = 0, max_chunks = 1, n_stage_tiles = 0;
+    DevBuf tiles, node_tiles, ids, stage_tiles;   // stage_tiles: tiles of `tile` elements when not 256
     bool node_forcing = false;    // some member needs the per-step node kernel
   };
   std::vector<Group> groups;
@@ -344,7 +352,7 @@ Member<Real> member_struct(const dgswe_ctx* c) {
   m.rn = c->rnode.as<double>();
   m.met = c->met.as<Real>();
   m.part = c->part.as<double>();
-  m.red = m.part ? m.part + size_t(NPART) * std::max(c->n_tiles, 1) : nullptr;
+  m.red = m.part ? m.part + size_t(NPART) * part_row(c->n_tiles) : nullptr;
   m.red_count = m.red ? reinterpret_cast<unsigned*>(m.red + size_t(NRED) * red_chunks(c->n_tiles)) : nullptr;
   m.sc = c->sc.as<Scalars>();
   m.fo = c->fo;
@@ -451,13 +459,12 @@ template <typename Real>
 int enqueue_step_group(const Member<Real>* d_m, const Tile* d_t, int n_tiles, const Tile* d_nt, int n_node_tiles,
                        const int* d_ids, int n_members, int max_chunks, int p, int flux, int limiter, int variant,
                        const RKTable& T, bool node_forcing, hipStream_t s, dgswe_ctx* prof, bool single,
-                       double* part_over = nullptr, bool fused = false, const Tile* d_t512 = nullptr,
-                       int n_tiles512 = 0) {
-  // stage launches over 512-element tiles when a list of them is given
-  const bool t512 = d_t512 != nullptr;
-  const Tile* st_tiles = t512 ? d_t512 : d_t;
-  const int st_n = t512 ? n_tiles512 : n_tiles;
-  const int st_tile = t512 ? 512 : TILE;
+                       double* part_over = nullptr, bool fused = false, const Tile* d_ts = nullptr, int n_ts = 0,
+                       int st_tile = TILE) {
+  // stage launches over tiles of st_tile elements (list d_ts, n_ts of them)
+  // when it is not 256
+  const Tile* st_tiles = st_tile != TILE ? d_ts : d_t;
+  const int st_n = st_tile != TILE ? n_ts : n_tiles;
   if (node_forcing) {
     ProfScope ps(prof, K_RAIN);
     // nodal rain rates, wind stress and pressure head at t^n; the first
@@ -496,19 +503,19 @@ int ctx_enqueue_step(dgswe_ctx* c, double* part_over = nullptr) {
     return enqueue_step_group<double>(c->memb.as<Member<double>>(), c->tiles.as<Tile>(), c->n_tiles,
                                       c->node_tiles.as<Tile>(), c->n_node_tiles, c->ids.as<int>(), 1, red_chunks(c->n_tiles),
                                       c->prm.p, c->prm.flux, c->prm.limiter, c->variant, c->rk, rain, c->stream, c, true,
-                                      part_over, c->use_fused(), c->use_tile512() ? c->tiles512.as<Tile>() : nullptr,
-                                      c->n_tiles512);
+                                      part_over, c->use_fused(), c->tiles64.as<Tile>(),
+                                      (c->E() + c->stage_tile() - 1) / c->stage_tile(), c->stage_tile());
   return enqueue_step_group<float>(c->memb.as<Member<float>>(), c->tiles.as<Tile>(), c->n_tiles,
                                    c->node_tiles.as<Tile>(), c->n_node_tiles, c->ids.as<int>(), 1, red_chunks(c->n_tiles),
                                    c->prm.p, c->prm.flux, c->prm.limiter, c->variant, c->rk, rain, c->stream, c, true,
-                                   part_over, c->use_fused(), c->use_tile512() ? c->tiles512.as<Tile>() : nullptr,
-                                   c->n_tiles512);
+                                   part_over, c->use_fused(), c->tiles64.as<Tile>(),
+                                   (c->E() + c->stage_tile() - 1) / c->stage_tile(), c->stage_tile());
 }
 
-// Doubles of a context's partials array: tile partials, the reduction's
-// chunk records, then its counter.
+// Doubles of a context's partials array: wavefront partials, the
+// reduction's chunk records, then its counter.
 size_t part_doubles(int n_tiles) {
-  return size_t(NPART) * std::max(n_tiles, 1) + size_t(NRED) * red_chunks(n_tiles) + 1;
+  return size_t(NPART) * part_row(n_tiles) + size_t(NRED) * red_chunks(n_tiles) + 1;
 }
 
 // Set-up reduction (mode 1: dt from the state; mode 2: keep a dt > 0 that is
@@ -631,13 +638,11 @@ int alloc_state(dgswe_ctx* c) {
   for (int t = 0; t < c->n_tiles; ++t) tl[t] = {0, t};
   if (tl.empty()) tl.push_back({0, 0});
   HIPCHK(upload(c->tiles, tl));
-  // 512-element tiles of the per-edge stage kernel (p = 1)
-  c->n_tiles512 = int((E + 511) / 512);
-  if (c->prm.p == 1) {
-    std::vector<Tile> t2(std::max(c->n_tiles512, 1), Tile{0, 0});
-    for (int t = 0; t < c->n_tiles512; ++t) t2[t] = {0, t};
-    HIPCHK(upload(c->tiles512, t2));
-  }
+  // stage tiles of other sizes: prefixes of the 64-element list
+  c->n_tiles64 = int((E + 63) / 64);
+  std::vector<Tile> t64(std::max(c->n_tiles64, 1), Tile{0, 0});
+  for (int t = 0; t < c->n_tiles64; ++t) t64[t] = {0, t};
+  HIPCHK(upload(c->tiles64, t64));
   return push_member(c);
 }
 
@@ -748,8 +753,8 @@ int64_t footprint(const dgswe_params* p, int64_t E, int64_t n_nodes) {
   b += 4 * blk(3 * NP * E * rs) + 3 * blk(E) + (p->limiter ? 2 * blk(E) : 0) + blk(E * rs);
   b += blk(nn * 8) + blk(3 * nn * rs);
   b += blk(std::max<int64_t>(node_tiles, 1) * int64_t(sizeof(Tile))) + blk(std::max<int64_t>(tiles, 1) * int64_t(sizeof(Tile)));
-  if (p->p == 1) b += blk(std::max<int64_t>((E + 511) / 512, 1) * int64_t(sizeof(Tile)));   // 512-element tiles
-  b += blk((NPART * std::max<int64_t>(tiles, 1) + NRED * int64_t(red_chunks(int(tiles))) + 1) * 8);
+  b += blk(std::max<int64_t>((E + 63) / 64, 1) * int64_t(sizeof(Tile)));        // 64-element tiles
+  b += blk(int64_t(part_doubles(int(tiles))) * 8);
   return b;
 }
 
@@ -761,7 +766,7 @@ int64_t footprint(const dgswe_params* p, int64_t E, int64_t n_nodes) {
 // code `scratch` names a host-side stand-in, never the device array: its
 // device address is taken once per device with hipGetSymbolAddress (with
 // that device current) and only that address is used.
-constexpr size_t SCRATCH_BYTES = size_t(1) << 20;
+constexpr size_t SCRATCH_BYTES = size_t(4) << 20;
 static __device__ __align__(256) double scratch[SCRATCH_BYTES / sizeof(double)];
 
 namespace {
@@ -1053,8 +1058,8 @@ int dgswe_clear_rain(dgswe_ctx* c) {
   if (c->in_batch) return fail(DGSWE_ESTATE, "context is a member of a batch; retire it first");
   HIPCHK(hipStreamSynchronize(c->stream));
   if (c->R.bytes) HIPCHK(hipMemset(c->R.p, 0, c->R.bytes));
-  HIPCHK(hipMemset(c->part.as<double>() + size_t(P_RAIN) * std::max(c->n_tiles, 1), 0,
-                   sizeof(double) * std::max(c->n_tiles, 1)));
+  HIPCHK(hipMemset(c->part.as<double>() + size_t(P_RAIN) * part_row(c->n_tiles), 0,
+                   sizeof(double) * part_row(c->n_tiles)));
   c->fo.rain_kind = RAIN_CONST;
   return refresh_forcing(c);
 }
@@ -1211,7 +1216,7 @@ int dgswe_step_noalloc(dgswe_ctx* c, int64_t n) {
   if (dev != c->device) return fail(DGSWE_ESTATE, "the context's device is not the current device");
   const size_t nd = part_doubles(c->n_tiles);
   if (nd * sizeof(double) > SCRATCH_BYTES) {
-    int tmax = int(SCRATCH_BYTES / sizeof(double) / NPART);
+    int tmax = int(SCRATCH_BYTES / sizeof(double) / (NPART * PSLOT));
     while (tmax > 0 && part_doubles(tmax) * sizeof(double) > SCRATCH_BYTES) --tmax;
     return fail(DGSWE_EINVAL, "mesh too large for the static scratch: its partials need " +
                                   std::to_string(nd * sizeof(double)) + " bytes, the scratch holds " +
@@ -1221,12 +1226,12 @@ int dgswe_step_noalloc(dgswe_ctx* c, int64_t n) {
   std::string err;
   double* const ptr = scratch_on(dev, err);
   if (!ptr) return fail(DGSWE_EHIP, err);
-  const int nt = std::max(c->n_tiles, 1);
+  const size_t row = part_row(c->n_tiles);
   // the array keeps the last call's contents: bring in what a step carries
   // over (the rain partial, written once for constant rain) and clear the
   // reduction counter, which must start at zero
-  HIPCHK(hipMemcpyAsync(ptr + size_t(P_RAIN) * nt, c->part.as<double>() + size_t(P_RAIN) * nt, sizeof(double) * nt,
-                        hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(hipMemcpyAsync(ptr + size_t(P_RAIN) * row, c->part.as<double>() + size_t(P_RAIN) * row,
+                        sizeof(double) * row, hipMemcpyDeviceToDevice, c->stream));
   HIPCHK(launch_fill_zero(ptr + nd - 1, 1, c->stream));
   const int prof = c->prof;
   c->prof = 0;                             // no events: nothing is created
@@ -1365,8 +1370,9 @@ int dgswe_set_tuning(dgswe_ctx* c, int key, int value) {
   if (c->in_batch) return fail(DGSWE_ESTATE, "context is a member of a batch");
   if (key != DGSWE_TUNE_STAGE_VARIANT && key != DGSWE_TUNE_FUSED_POST && key != DGSWE_TUNE_STAGE_TILE)
     return fail(DGSWE_EINVAL, "unknown tuning key");
-  if (key == DGSWE_TUNE_STAGE_TILE ? (value != TILE && value != 512) : (value != 0 && value != 1))
-    return fail(DGSWE_EINVAL, "tuning values are 0 or 1 (stage tile: 256 or 512)");
+  if (key == DGSWE_TUNE_STAGE_TILE ? (value != 64 && value != 128 && value != TILE && value != 512)
+                                   : (value != 0 && value != 1))
+    return fail(DGSWE_EINVAL, "tuning values are 0 or 1 (stage tile: 64, 128, 256 or 512)");
   if (c->stream) HIPCHK(hipStreamSynchronize(c->stream));
   if (key == DGSWE_TUNE_STAGE_VARIANT) c->variant = value;
   else if (key == DGSWE_TUNE_FUSED_POST) c->fused = value;
@@ -1382,12 +1388,12 @@ int dgswe_get_tuning(const dgswe_ctx* c, int key, int* value) {
     return fail(DGSWE_EINVAL, "unknown tuning key or null output");
   *value = key == DGSWE_TUNE_STAGE_VARIANT ? c->variant
            : key == DGSWE_TUNE_FUSED_POST  ? (c->use_fused() ? 1 : 0)
-                                           : (c->use_tile512() ? 512 : TILE);
+                                           : c->stage_tile();
   return DGSWE_OK;
 }
 
 int dgswe_autotune(dgswe_ctx* c, int n_steps, int* chosen, double* ms_per_step) {
-  constexpr int NCFG = 4;
+  constexpr int NCFG = 6;
   int rc = check_ctx(c, true, true);
   if (rc) return rc;
   ArenaScope arena_scope(c->arena);
@@ -1424,16 +1430,17 @@ int dgswe_autotune(dgswe_ctx* c, int n_steps, int* chosen, double* ms_per_step) 
   // configurations: per-element kernel; per-edge kernel with the post pass
   // after every stage; per-edge kernel with the post-processing fused into
   // the next stage (limiter on, p <= 2, a halo built); per-edge kernel on
-  // 512-element tiles (p = 1)
-  const int cfg_variant[NCFG] = {0, 1, 1, 1}, cfg_fused[NCFG] = {0, 0, 1, 0}, cfg_tile[NCFG] = {TILE, TILE, TILE, 512};
-  double ms[NCFG] = {0.0, 0.0, 0.0, 0.0};
+  // tiles of 512 (p = 1), 128 and 64 elements
+  const int cfg_variant[NCFG] = {0, 1, 1, 1, 1, 1}, cfg_fused[NCFG] = {0, 0, 1, 0, 0, 0},
+            cfg_tile[NCFG] = {TILE, TILE, TILE, 512, 128, 64};
+  double ms[NCFG] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   int err = DGSWE_OK;
   for (int v = 0; v < NCFG && !err; ++v) {
     c->variant = cfg_variant[v];
     c->fused = cfg_fused[v];
     c->tile = cfg_tile[v];
     if (v == 2 && !c->use_fused()) continue;    // the same as configuration 1
-    if (v == 3 && !c->use_tile512()) continue;
+    if (c->stage_tile() != cfg_tile[v]) continue;   // 512 at p > 1
     c->graph_dirty = true;
     err = dgswe_step(c, 2);                     // builds the step graph, warms caches
     if (!err) err = restore();
@@ -1512,7 +1519,7 @@ int batch_rebuild_t(dgswe_batch* b) {
     ms.push_back(member_struct<Real>(sl.ctx));
     const dgswe_params& p = sl.ctx->prm;
     auto key = std::make_tuple(p.p, p.flux, p.limiter, p.rk_stages, sl.ctx->variant, sl.ctx->use_fused() ? 1 : 0,
-                               sl.ctx->use_tile512() ? 512 : TILE);
+                               sl.ctx->stage_tile());
     auto it = gi.find(key);
     if (it == gi.end()) {
       dgswe_batch::Group g;
@@ -1521,7 +1528,7 @@ int batch_rebuild_t(dgswe_batch* b) {
       g.limiter = p.limiter;
       g.variant = sl.ctx->variant;
       g.fused = sl.ctx->use_fused() ? 1 : 0;
-      g.tile = sl.ctx->use_tile512() ? 512 : TILE;
+      g.tile = sl.ctx->stage_tile();
       make_rk(p.rk_stages, g.rk);
       b->groups.push_back(std::move(g));
       it = gi.emplace(key, int(b->groups.size()) - 1).first;
@@ -1533,14 +1540,14 @@ int batch_rebuild_t(dgswe_batch* b) {
   if (ms.empty()) ms.push_back(Member<Real>{});
   HIPCHK(upload(b->memb, ms));
   for (auto& g : b->groups) {
-    std::vector<Tile> tl, ntl, t2;
+    std::vector<Tile> tl, ntl, ts;
     g.max_chunks = 1;
     for (int m : g.members) {
       const int nt = ms[m].n_tiles;
       g.max_chunks = std::max(g.max_chunks, red_chunks(nt));
       for (int t = 0; t < nt; ++t) tl.push_back({m, t});
-      if (g.tile == 512)
-        for (int t = 0; t < (ms[m].E + 511) / 512; ++t) t2.push_back({m, t});
+      if (g.tile != TILE)
+        for (int t = 0; t < (ms[m].E + g.tile - 1) / g.tile; ++t) ts.push_back({m, t});
       const int nnt = (ms[m].n_nodes + TILE - 1) / TILE;
       for (int t = 0; t < nnt; ++t) ntl.push_back({m, t});
     }
@@ -1551,10 +1558,10 @@ int batch_rebuild_t(dgswe_batch* b) {
     HIPCHK(upload(g.tiles, tl));
     HIPCHK(upload(g.node_tiles, ntl));
     HIPCHK(upload(g.ids, g.members));
-    g.n_tiles512 = int(t2.size());
-    if (g.tile == 512) {
-      if (t2.empty()) t2.push_back({0, 0});
-      HIPCHK(upload(g.tiles512, t2));
+    g.n_stage_tiles = int(ts.size());
+    if (g.tile != TILE) {
+      if (ts.empty()) ts.push_back({0, 0});
+      HIPCHK(upload(g.stage_tiles, ts));
     }
   }
   b->dirty = false;
@@ -1648,13 +1655,13 @@ static int batch_enqueue_step(dgswe_batch* b) {
                                      g.node_tiles.as<Tile>(), g.n_node_tiles, g.ids.as<int>(),
                                      int(g.members.size()), g.max_chunks, g.p, g.flux, g.limiter, g.variant, g.rk,
                                      g.node_forcing, b->stream, nullptr, false, nullptr, g.fused != 0,
-                                     g.tile == 512 ? g.tiles512.as<Tile>() : nullptr, g.n_tiles512);
+                                     g.stage_tiles.as<Tile>(), g.n_stage_tiles, g.tile);
     else
       rc = enqueue_step_group<double>(b->memb.as<Member<double>>(), g.tiles.as<Tile>(), g.n_tiles,
                                       g.node_tiles.as<Tile>(), g.n_node_tiles, g.ids.as<int>(),
                                       int(g.members.size()), g.max_chunks, g.p, g.flux, g.limiter, g.variant, g.rk,
                                       g.node_forcing, b->stream, nullptr, false, nullptr, g.fused != 0,
-                                     g.tile == 512 ? g.tiles512.as<Tile>() : nullptr, g.n_tiles512);
+                                     g.stage_tiles.as<Tile>(), g.n_stage_tiles, g.tile);
     if (rc) return rc;
   }
   return DGSWE_OK;

@@ -27,6 +27,13 @@ constexpr int MAX_SLOTS = 16;
 enum PartKind {
   P_OUT0 = 0, P_IN0 = MAX_STAGES, P_VOL = 2 * MAX_STAGES, P_MINR, P_RAIN, P_NDRY, P_NNEG, P_BAD, NPART
 };
+// Partials are kept per wavefront: PSLOT slots per 256-element tile, slot s
+// of tile t covering elements 256 t + 64 s .. 256 t + 64 s + 63, so kernels
+// of any workgroup size write them alike and nothing is combined across
+// workgroups; the reduction combines a tile's slots as (s0 + s1) + (s2 + s3)
+// (minima alike) and takes a slot that starts at or beyond E as empty.
+constexpr int PSLOT = TILE / 64;
+__host__ __device__ inline size_t part_row(int n_tiles) { return size_t(PSLOT) * (n_tiles > 0 ? n_tiles : 1); }
 enum RainKind { RAIN_CONST = 0, RAIN_PARAM = 1, RAIN_GRID = 2 };
 enum MetKind { MET_NONE = 0, MET_VORTEX = 1 };
 // wind stress and pressure forcing: air and water densities (kg/m^3), cap
@@ -112,7 +119,7 @@ struct Member {
   Real* R;                    // [E] element rain rate
   double* rn;                 // [n_nodes] nodal rain rate
   Real* met;                  // [3][n_nodes] kinematic wind stress (x, y) and pressure head at t^n
-  double* part;               // [NPART][n_tiles]
+  double* part;               // [NPART][PSLOT * n_tiles], see part_row
   double* red;                // [red_chunks(n_tiles)][NRED] chunk records
   unsigned* red_count;        // chunks finished in the current reduction (0 between launches)
   Scalars* sc;
@@ -144,8 +151,8 @@ struct RKInfo {
 // fused = 1 (variant 1, limiter on, p <= 2, members with a halo): the stage
 // reads the previous stage's raw output and applies its limiter and
 // positive-depth operator itself, in place of that stage's post pass
-// tile = 512 (variant 1, p = 1, not fused): workgroups of 512 elements; the
-// tile list and count are then those of 512-element tiles
+// tile = 64, 128 or (p = 1) 512 (variant 1, not fused): workgroups of that
+// many elements; the tile list and count are then those of such tiles
 template <typename Real>
 hipError_t launch_stage(int P, int flux, int limiter, int variant, const Member<Real>* d_members,
                         const Tile* d_tiles, int n_tiles, StageArgs a, hipStream_t s, hipEvent_t ev0 = nullptr,

@@ -137,21 +137,6 @@ DG_DEV double first_lane_id(unsigned long long mask, int base) {
   return mask ? double(base + __builtin_ctzll(mask)) : __builtin_inf();
 }
 
-// Sums a per-thread value over the workgroup in a fixed order.
-template <int NV>
-DG_DEV void block_sums(double (&v)[NV], double* lds) {
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-#pragma unroll
-  for (int i = 0; i < NV; ++i) {
-    double s = wave_sum(v[i]);
-    if (lane == 0) lds[wv * NV + i] = s;
-  }
-  __syncthreads();
-#pragma unroll
-  for (int i = 0; i < NV; ++i) v[i] = (lds[i] + lds[NV + i]) + (lds[2 * NV + i] + lds[3 * NV + i]);
-  __syncthreads();
-}
-
 // Decision margins: the positive-depth operator puts vertices at exactly H0,
 // so the tests that follow use H0 (1 + 1e-3) for "dry", and a wet-dry edge
 // exchanges water only above a mass flux of 1e-3 H0 sqrt(g H0) (Member::feps,
@@ -901,13 +886,13 @@ DG_DEV void load_blend(const Member<Real>& M, const StageArgs& A, int E, int ec,
 }
 
 // Inverse mass, SSP combination, positive-depth operator (LIM = 0) or the
-// fully-wet byte (LIM = 1), stores, and the tile partials (lds: 4 x 8
-// doubles of the caller's shared memory).
+// fully-wet byte (LIM = 1), stores, and the wavefront's partials.  tile
+// counts workgroups of T elements.
 template <typename Real, int P, int LIM, int T = TILE>
 DG_DEV void finish_stage(const Member<Real>& M, const StageArgs& A, int tile, int e, int ec, bool valid, int E,
                          Real (&w)[3][Tab<P>::NP], Real (&acc)[3][Tab<P>::NP], const Real (&hb)[3], const Real (&ex)[3],
                          const Real (&ey)[3], Real detJ, Real idet, double dt, double bout, double bin, Real Rv,
-                         double rain_part, double* lds, const Real (&w0v)[3][Tab<P>::NP]) {
+                         double rain_part, const Real (&w0v)[3][Tab<P>::NP]) {
   constexpr int NP = Tab<P>::NP;
   acc[0][0] += Real(2) * detJ * Rv;
   const Real cdt = Real(A.gam * dt);
@@ -959,7 +944,7 @@ DG_DEV void finish_stage(const Member<Real>& M, const StageArgs& A, int tile, in
     }
   }
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  // bout/bin arrive already restricted to the edges this lane evaluated
+  // bout/bin: volume out of and into this lane's element through its boundary edges
   const bool rain_here = A.stage == 0 && M.fo.rain_kind != RAIN_CONST;
   // most tiles have no boundary edge: skip those sums when the wavefront holds only zeros
   const bool any_b = __any(part[0] != 0.0 || part[1] != 0.0);
@@ -973,28 +958,22 @@ DG_DEV void finish_stage(const Member<Real>& M, const StageArgs& A, int tile, in
     fb = first_lane_id(__ballot(bad), tile * T + wv * 64);
   }
   if (rain_here) s5 = wave_sum(rain_part);
-  if (lane == 0) {
-    double* l = lds + wv * 8;
-    l[0] = s0; l[1] = s1; l[2] = s2; l[3] = mn; l[4] = s4; l[5] = s5; l[6] = s6; l[7] = fb;
-  }
-  __syncthreads();
-  // one partial per 256 elements (four wavefronts), whatever the workgroup's
-  // tile size, so the sums and their order do not depend on it
-  const int sub = tile * (T / TILE) + int(threadIdx.x) / TILE;
-  if (threadIdx.x % TILE == 0 && sub < M.n_tiles) {
+  // this wavefront's slot of the partials (a 512-element tile's second
+  // half can lie past the last 256-element tile)
+  const size_t row = part_row(M.n_tiles);
+  const size_t slot = size_t(tile) * (T / 64) + wv;
+  if (lane == 0 && slot < row) {
     DG_G double* __restrict__ pt = gp(A.part ? A.part : M.part);
-    const int nt = M.n_tiles;
-    const double* q = lds + (int(threadIdx.x) / TILE) * 32;
-    pt[(P_OUT0 + A.stage) * nt + sub] = (q[0] + q[8]) + (q[16] + q[24]);
-    pt[(P_IN0 + A.stage) * nt + sub] = (q[1] + q[9]) + (q[17] + q[25]);
+    pt[(P_OUT0 + A.stage) * row + slot] = s0;
+    pt[(P_IN0 + A.stage) * row + slot] = s1;
     if (LIM == 0 && A.last) {
-      pt[P_VOL * nt + sub] = (q[2] + q[10]) + (q[18] + q[26]);
-      pt[P_MINR * nt + sub] = fmin(fmin(q[3], q[11]), fmin(q[19], q[27]));
-      pt[P_NDRY * nt + sub] = (q[4] + q[12]) + (q[20] + q[28]);
-      pt[P_NNEG * nt + sub] = (q[6] + q[14]) + (q[22] + q[30]);
-      pt[P_BAD * nt + sub] = fmin(fmin(q[7], q[15]), fmin(q[23], q[31]));
+      pt[P_VOL * row + slot] = s2;
+      pt[P_MINR * row + slot] = mn;
+      pt[P_NDRY * row + slot] = s4;
+      pt[P_NNEG * row + slot] = s6;
+      pt[P_BAD * row + slot] = fb;
     }
-    if (rain_here) pt[P_RAIN * nt + sub] = (q[5] + q[13]) + (q[21] + q[29]);
+    if (rain_here) pt[P_RAIN * row + slot] = s5;
   }
 }
 
@@ -1037,7 +1016,6 @@ template <typename Real, int P, int FLUX, int LIM>
 __global__ DG_STAGE_ATTR void stage_kernel(const Member<Real>* __restrict__ mem,
                                                      const Tile* __restrict__ tiles, int n_tiles, StageArgs A) {
   constexpr int NP = Tab<P>::NP, NG = Tab<P>::NG;
-  __shared__ double lds[4 * 8];                        // finish_stage: eight values per wavefront
   const int ti = xcd_tile();
   if (ti >= n_tiles) return;
   const Tile tl = A.single ? Tile{0, ti} : tiles[ti];
@@ -1229,7 +1207,7 @@ __global__ DG_STAGE_ATTR void stage_kernel(const Member<Real>* __restrict__ mem,
   const Real Rv = element_rain<Real>(M, A, E, e, ec, valid, d.ex, d.ey, rain_part);
   // lanes past the end of the mesh evaluated a copy of the last element
   finish_stage<Real, P, LIM>(M, A, tl.tile, e, ec, valid, E, d.w, acc, d.hb, d.ex, d.ey, d.detJ, d.idet, dt,
-                             valid ? bout : 0.0, valid ? bin : 0.0, Rv, rain_part, lds, w0v);
+                             valid ? bout : 0.0, valid ? bin : 0.0, Rv, rain_part, w0v);
 }
 
 // ---------------------------------------------------- stage kernel, per edge
@@ -1253,9 +1231,10 @@ __global__ DG_STAGE_ATTR_T(T) void stage_edge_kernel(const Member<Real>* __restr
                                                           const Tile* __restrict__ tiles, int n_tiles, StageArgs A) {
   constexpr int NP = Tab<P>::NP, NG = Tab<P>::NG;
   static_assert(!PRE || (LIM == 1 && P <= 2), "the fused post-processing needs the limiter and p <= 2");
-  static_assert(T == 256 || (T == 512 && !PRE), "tiles of 256, or 512 without the fused post-processing");
+  static_assert(T == 256 || ((T == 64 || T == 128 || (T == 512 && P == 1)) && !PRE),
+                "tiles of 256; 64, 128 or (p = 1) 512 without the fused post-processing");
   constexpr int NW = T / 64;                            // wavefronts per workgroup
-  constexpr int LB = T == 512 ? 9 : 8;                  // bits of a local element index in an edge entry
+  constexpr int LB = T == 512 ? 9 : T == 256 ? 8 : T == 128 ? 7 : 6;   // bits of a local element index in an edge entry
   // point values per variable (vertices, midpoints); p = 3 keeps its traces
   // in s_flux instead (each slot holds the element's own trace at that edge
   // point until phase B overwrites it with the flux there)
@@ -1276,7 +1255,7 @@ __global__ DG_STAGE_ATTR_T(T) void stage_edge_kernel(const Member<Real>* __restr
   static_assert(!PRE || 3 * SM * sizeof(Real) + SM <= sizeof(s_flux), "halo means fit the flux slots");
   Real* const s_mean = reinterpret_cast<Real*>(&s_flux[0][0]);
   uint8_t* const s_fw = reinterpret_cast<uint8_t*>(s_mean + 3 * SM);
-  // edge list; after phase B the same memory holds the block's partial sums
+  // edge list
   __shared__ double s_lbuf[3 * T / 2];
   uint32_t* s_list = reinterpret_cast<uint32_t*>(s_lbuf);
   __shared__ int s_wsum[2][NW];
@@ -1494,7 +1473,6 @@ __global__ DG_STAGE_ATTR_T(T) void stage_edge_kernel(const Member<Real>* __restr
   }
 
   // ---- phase B: edge fluxes, scaled by (l/2) w_g, into s_flux
-  double bout = 0.0, bin = 0.0;
   if constexpr (P >= 3) {
     // traces come from s_flux (own side, and the neighbour's when it is in
     // the tile) or from the neighbour's modes; only the thread of an edge
@@ -1566,7 +1544,6 @@ __global__ DG_STAGE_ATTR_T(T) void stage_edge_kernel(const Member<Real>* __restr
         const int code = -1 - nb;
         const int type = code & 3, slot = code >> 2;
         const Real tide = Real(sc->tide[A.stage][slot]), qr = Real(sc->river[A.stage][slot]);
-        double fm = 0.0;
         static_for<NG>([&](auto gc) {
           constexpr int gi = decltype(gc)::value;
           const W3<Real> a{tO[0][gi], tO[1][gi], tO[2][gi]};
@@ -1574,11 +1551,9 @@ __global__ DG_STAGE_ATTR_T(T) void stage_edge_kernel(const Member<Real>* __restr
           Real F[3];
           boundary_point<FLUX>(a, hg, nx, ny, g, H0, type, tide, qr, F);
           const Real wg = half * Real(gl_w(P, gi));
-          fm += double(wg * F[0]);
 #pragma unroll
           for (int v = 0; v < 3; ++v) s_flux[(k * NG + gi) * 3 + v][l] = wg * F[v];
         });
-        if (fm > 0.0) bout += fm; else bin -= fm;
       }
     }
   } else
@@ -1678,7 +1653,6 @@ __global__ DG_STAGE_ATTR_T(T) void stage_edge_kernel(const Member<Real>* __restr
       const int code = -1 - nb;
       const int type = code & 3, slot = code >> 2;
       const Real tide = Real(sc->tide[A.stage][slot]), qr = Real(sc->river[A.stage][slot]);
-      double fm = 0.0;
 #pragma unroll
       for (int gi = 0; gi < NG; ++gi) {
         W3<Real> a{trace<Real, P>(Oa[0], Oc[0], Ob[0], gi), trace<Real, P>(Oa[1], Oc[1], Ob[1], gi),
@@ -1687,14 +1661,24 @@ __global__ DG_STAGE_ATTR_T(T) void stage_edge_kernel(const Member<Real>* __restr
         Real F[3];
         boundary_point<FLUX>(a, hg, nx, ny, g, H0, type, tide, qr, F);
         const Real wg = half * Real(gl_w(P, gi));
-        fm += double(wg * F[0]);
 #pragma unroll
         for (int v = 0; v < 3; ++v) s_flux[(k * NG + gi) * 3 + v][l] = wg * F[v];
       }
-      if (fm > 0.0) bout += fm; else bin -= fm;
     }
   }
   __syncthreads();
+  // volume through this element's own boundary edges, from the mass
+  // components of their fluxes (so that a wavefront's partials depend only
+  // on its own elements, not on which thread evaluated an edge)
+  double bout = 0.0, bin = 0.0;
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+    if (valid && nbv[k] < 0) {
+      double fm = 0.0;
+#pragma unroll
+      for (int gi = 0; gi < NG; ++gi) fm += double(s_flux[(k * NG + gi) * 3][el]);
+      if (fm > 0.0) bout += fm; else bin -= fm;
+    }
 
   // ---- phase C: edge contributions, inverse mass, stage combination, post
   Real w0v[3][NP];
@@ -1740,7 +1724,7 @@ __global__ DG_STAGE_ATTR_T(T) void stage_edge_kernel(const Member<Real>* __restr
     rain_part = valid ? area * double(Rv) : 0.0;
   }
   finish_stage<Real, P, LIM, T>(M, A, tl.tile, e, ec, valid, E, d.w, acc, d.hb, d.ex, d.ey, d.detJ, d.idet, dt, bout,
-                             bin, Rv, rain_part, s_lbuf, w0v);
+                             bin, Rv, rain_part, w0v);
 }
 
 // ------------------------------------------------------------ post kernel
@@ -1761,7 +1745,6 @@ __global__ __launch_bounds__(TILE) void post_kernel(const Member<Real>* __restri
                                                     const Tile* __restrict__ tiles, int n_tiles, StageArgs A,
                                                     int init, int use_lim) {
   constexpr int NP = Tab<P>::NP;
-  __shared__ double lds[4 * 5];
   const int ti = xcd_tile();
   if (ti >= n_tiles) return;
   const Tile tl = A.single ? Tile{0, ti} : tiles[ti];
@@ -1866,18 +1849,13 @@ __global__ __launch_bounds__(TILE) void post_kernel(const Member<Real>* __restri
     const double fb = first_lane_id(__ballot(valid && !(__builtin_isfinite(md) && __builtin_isfinite(lam))),
                                     tl.tile * TILE + wv * 64);
     if (lane == 0) {
-      double* l = lds + wv * 5;
-      l[0] = s0; l[1] = s1; l[2] = mn; l[3] = s2; l[4] = fb;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
       DG_G double* __restrict__ pt = gp(A.part ? A.part : M.part);
-      const int nt = M.n_tiles, t = tl.tile;
-      pt[P_VOL * nt + t] = (lds[0] + lds[5]) + (lds[10] + lds[15]);
-      pt[P_NDRY * nt + t] = (lds[1] + lds[6]) + (lds[11] + lds[16]);
-      pt[P_MINR * nt + t] = fmin(fmin(lds[2], lds[7]), fmin(lds[12], lds[17]));
-      pt[P_NNEG * nt + t] = (lds[3] + lds[8]) + (lds[13] + lds[18]);
-      pt[P_BAD * nt + t] = fmin(fmin(lds[4], lds[9]), fmin(lds[14], lds[19]));
+      const size_t row = part_row(M.n_tiles), slot = size_t(tl.tile) * PSLOT + wv;
+      pt[P_VOL * row + slot] = s0;
+      pt[P_NDRY * row + slot] = s1;
+      pt[P_MINR * row + slot] = mn;
+      pt[P_NNEG * row + slot] = s2;
+      pt[P_BAD * row + slot] = fb;
     }
   }
 }
@@ -2015,7 +1993,6 @@ __global__ __launch_bounds__(TILE) void node_forcing_kernel(const Member<Real>* 
 template <typename Real>
 __global__ __launch_bounds__(TILE) void rain_kernel(const Member<Real>* __restrict__ mem,
                                                     const Tile* __restrict__ tiles, int n_tiles, int always) {
-  __shared__ double lds[4];
   const int ti = xcd_tile();
   if (ti >= n_tiles) return;
   const Tile tl = tiles[ti];
@@ -2036,9 +2013,7 @@ __global__ __launch_bounds__(TILE) void rain_kernel(const Member<Real>* __restri
   double v = valid ? area * double(Re) : 0.0;
   v = wave_sum(v);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  if (lane == 0) lds[wv] = v;
-  __syncthreads();
-  if (threadIdx.x == 0) gp(M.part)[P_RAIN * M.n_tiles + tl.tile] = (lds[0] + lds[1]) + (lds[2] + lds[3]);
+  if (lane == 0) gp(M.part)[P_RAIN * part_row(M.n_tiles) + size_t(tl.tile) * PSLOT + wv] = v;
 }
 
 // ------------------------------------------------------------ reduce
@@ -2084,7 +2059,7 @@ __global__ __launch_bounds__(RED_CHUNK) void reduce_kernel(const Member<Real>* _
   if (chunk >= nch) return;
   // the member's partials and records, or the same layout at part_over
   double* const part = part_over ? part_over : M.part;
-  double* const redp = part_over ? part_over + size_t(NPART) * (nt > 1 ? nt : 1) : M.red;
+  double* const redp = part_over ? part_over + size_t(NPART) * part_row(nt) : M.red;
   unsigned* const red_count = part_over ? reinterpret_cast<unsigned*>(redp + size_t(NRED) * nch) : M.red_count;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int ns = init ? 0 : rk.n;
@@ -2092,21 +2067,39 @@ __global__ __launch_bounds__(RED_CHUNK) void reduce_kernel(const Member<Real>* _
   double v[NV];
   double mn, fb;
   {
+    // the tile's four wavefront slots, combined as (s0 + s1) + (s2 + s3);
+    // a slot that starts at or beyond E holds no element
     const DG_G double* __restrict__ pt = gp(part);
+    const size_t row = part_row(nt);
     const int t = chunk * RED_CHUNK + tid;
     const bool ok = t < nt;
-    const int tt = ok ? t : 0;
-    v[0] = ok ? pt[P_VOL * nt + tt] : 0.0;
-    v[1] = ok ? pt[P_RAIN * nt + tt] : 0.0;
-    v[2] = ok ? pt[P_NDRY * nt + tt] : 0.0;
-    mn = ok ? pt[P_MINR * nt + tt] : __builtin_inf();
+    const size_t s0 = size_t(ok ? t : 0) * PSLOT;
+    static_assert(PSLOT == 4, "four slots per tile");
+    const int nslot = ok ? (M.E - t * TILE + 63) / 64 : 0;       // slots holding elements
+    auto sum4 = [&](int r, bool on) -> double {
+      if (!on) return 0.0;
+      double x[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) x[k] = k < nslot ? pt[r * row + s0 + k] : 0.0;
+      return (x[0] + x[1]) + (x[2] + x[3]);
+    };
+    auto min4 = [&](int r) -> double {
+      double x[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) x[k] = k < nslot ? pt[r * row + s0 + k] : __builtin_inf();
+      return fmin(fmin(x[0], x[1]), fmin(x[2], x[3]));
+    };
+    v[0] = sum4(P_VOL, ok);
+    v[1] = sum4(P_RAIN, ok);
+    v[2] = sum4(P_NDRY, ok);
+    mn = min4(P_MINR);
 #pragma unroll
     for (int s = 0; s < MAX_STAGES; ++s) {
-      v[3 + s] = (ok && s < ns) ? pt[(P_OUT0 + s) * nt + tt] : 0.0;
-      v[3 + MAX_STAGES + s] = (ok && s < ns) ? pt[(P_IN0 + s) * nt + tt] : 0.0;
+      v[3 + s] = sum4(P_OUT0 + s, ok && s < ns);
+      v[3 + MAX_STAGES + s] = sum4(P_IN0 + s, ok && s < ns);
     }
-    v[INEG] = ok ? pt[P_NNEG * nt + tt] : 0.0;
-    fb = ok ? pt[P_BAD * nt + tt] : __builtin_inf();
+    v[INEG] = sum4(P_NNEG, ok);
+    fb = min4(P_BAD);
   }
   const bool act = init || sc->active;
   // fixed-order block sums: within each wavefront, then wavefronts 0..NW-1
@@ -2336,7 +2329,7 @@ template <typename Real>
 hipError_t launch_stage(int P, int flux, int limiter, int variant, const Member<Real>* m, const Tile* t, int n,
                         StageArgs a, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1, int fused, int tile) {
   if (n <= 0) return hipSuccess;
-  dim3 grid(xcd_grid(n)), block(tile == 512 ? 512 : TILE);
+  dim3 grid(xcd_grid(n)), block(tile);
   const bool timed = ev0 != nullptr || ev1 != nullptr;
 #define DG_LAUNCH(KERNEL)                                                                       \
   {                                                                                            \
@@ -2350,12 +2343,26 @@ hipError_t launch_stage(int P, int flux, int limiter, int variant, const Member<
     else DG_LAUNCH((stage_kernel<Real, PP, FF, LL>))                                            \
   }
   if (tile != TILE) {
-    // tiles of 512 elements: per-edge kernel, p = 1, no fused post-processing
-    if (tile != 512 || variant != 1 || fused || P != 1) return hipErrorInvalidValue;
-    if (flux == 0 && limiter == 0) DG_LAUNCH((stage_edge_kernel<Real, 1, 0, 0, 0, 512>))
-    if (flux == 1 && limiter == 0) DG_LAUNCH((stage_edge_kernel<Real, 1, 1, 0, 0, 512>))
-    if (flux == 0 && limiter == 1) DG_LAUNCH((stage_edge_kernel<Real, 1, 0, 1, 0, 512>))
-    if (flux == 1 && limiter == 1) DG_LAUNCH((stage_edge_kernel<Real, 1, 1, 1, 0, 512>))
+    // per-edge kernel on tiles of 64 or 128 elements (any p) or 512 (p = 1),
+    // without the fused post-processing
+    if (variant != 1 || fused || !(tile == 64 || tile == 128 || (tile == 512 && P == 1)))
+      return hipErrorInvalidValue;
+#define DG_TILED(PP, FF, LL)                                                                    \
+  if (P == PP && flux == FF && limiter == LL) {                                                 \
+    if (tile == 64) DG_LAUNCH((stage_edge_kernel<Real, PP, FF, LL, 0, 64>))                     \
+    DG_LAUNCH((stage_edge_kernel<Real, PP, FF, LL, 0, 128>))                                    \
+  }
+    if (tile == 512) {
+      if (flux == 0 && limiter == 0) DG_LAUNCH((stage_edge_kernel<Real, 1, 0, 0, 0, 512>))
+      if (flux == 1 && limiter == 0) DG_LAUNCH((stage_edge_kernel<Real, 1, 1, 0, 0, 512>))
+      if (flux == 0 && limiter == 1) DG_LAUNCH((stage_edge_kernel<Real, 1, 0, 1, 0, 512>))
+      if (flux == 1 && limiter == 1) DG_LAUNCH((stage_edge_kernel<Real, 1, 1, 1, 0, 512>))
+      return hipErrorInvalidValue;
+    }
+    DG_TILED(1, 0, 0) DG_TILED(1, 1, 0) DG_TILED(1, 0, 1) DG_TILED(1, 1, 1)
+    DG_TILED(2, 0, 0) DG_TILED(2, 1, 0) DG_TILED(2, 0, 1) DG_TILED(2, 1, 1)
+    DG_TILED(3, 0, 0) DG_TILED(3, 1, 0) DG_TILED(3, 0, 1) DG_TILED(3, 1, 1)
+#undef DG_TILED
     return hipErrorInvalidValue;
   }
   if (fused) {

@@ -180,10 +180,10 @@ class Solver:
     def autotune(self, n_steps: int = 5):
         """Pick the fastest stage-kernel configuration for this mesh; the
         state is left as it was.  Returns (variant, (ms/step per-element,
-        per-edge with post passes, per-edge fused, per-edge on 512-element
-        tiles; 0 where it does not apply))."""
+        per-edge with post passes, per-edge fused, per-edge on tiles of 512,
+        128 and 64 elements; 0 where it does not apply))."""
         v = C.c_int()
-        ms = (C.c_double * 4)()
+        ms = (C.c_double * 6)()
         call("dgswe_autotune", self.h, int(n_steps), C.byref(v), ms)
         return v.value, tuple(ms)
 
@@ -197,8 +197,9 @@ class Solver:
         return v.value
 
     def set_tile(self, tile: int):
-        """Elements per workgroup of the per-edge stage kernel (256 or 512;
-        512 applies at p = 1 without fused post-processing)."""
+        """Elements per workgroup of the per-edge stage kernel: 64, 128, 256
+        or (p = 1) 512; a tile other than 256 turns fused post-processing
+        off."""
         call("dgswe_set_tuning", self.h, N.TUNE_STAGE_TILE, int(tile))
 
     def tile(self) -> int:

@@ -52,7 +52,7 @@ def test_noalloc_refuses_meshes_beyond_its_scratch(dg):
     s = dg.Solver(dict(precision="fp32", dt_fixed=1.0))
     s.upload_mesh(xy, np.full(len(xy), 5.0), np.full(len(xy), 0.02), tri)
     s.set_initial_nodal(np.zeros(len(xy)), np.zeros(len(xy)), np.zeros(len(xy)))
-    with pytest.raises(N.DgsweError, match="2088704 triangles at most") as ei:
+    with pytest.raises(N.DgsweError, match="2094848 triangles at most") as ei:
         N.call("dgswe_step_noalloc", s.h, 1)
     assert ei.value.code == N.DGSWE_EINVAL
     assert s.mass()["steps"] == 0
