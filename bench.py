@@ -172,10 +172,14 @@ def kernel_sources_hash():
     return h.hexdigest()[:16]
 
 
-def counted_traffic(kernel, precision, variant=1):
+def counted_traffic(kernel, precision, variant=1, tile=256, workload=None):
     """HBM bytes per launch of ``kernel`` from the committed rocprofv3 counter
     summary (FETCH_SIZE and WRITE_SIZE scaled by the copy calibration), or
-    None when the kernel sources changed since the counters were taken."""
+    None when the summary does not cover this workload and kernel
+    configuration or the kernel sources changed since it was taken.  The
+    summary covers the 1M-triangle p = 1 basin ("basin1M_p1")."""
+    if workload != "basin1M_p1":
+        return None
     path = os.path.join(ROOT, "profiles", "stage_edge_kernel_basin1M_counters.md")
     try:
         with open(path) as f:
@@ -185,7 +189,10 @@ def counted_traffic(kernel, precision, variant=1):
         return None
     if d.get("sources") != kernel_sources_hash():
         return None
-    name = ("stage_edge_kernel" if variant == 1 else "stage_kernel") if kernel == "stage" else "post_kernel"
+    if kernel == "stage":
+        name = f"stage_edge_kernel/t{tile}" if variant == 1 else "stage_kernel"
+    else:
+        name = "post_kernel"
     return d["bytes"].get(f"{name}/{precision}")
 
 
@@ -204,7 +211,7 @@ def stream_ceiling():
     return out
 
 
-def roofline(res, precision, p, limiter):
+def roofline(res, precision, p, limiter, workload=None):
     rs = 4 if precision == "fp32" else 8
     stats = res["stats"]
     dom = max(("stage", "post"), key=lambda k: stats[k][1])
@@ -220,13 +227,15 @@ def roofline(res, precision, p, limiter):
     byts = sum(per_launch) / len(per_launch)
     avg_s = ms / n * 1e-3
     ach = byts / avg_s / 1e9
-    traffic = counted_traffic(dom, precision, res.get("variant", 1))
+    traffic = counted_traffic(dom, precision, res.get("variant", 1), res.get("tile", 256), workload)
     out = {"kernel": dom, "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
            "traffic_source": ("FETCH_SIZE and WRITE_SIZE per launch from the committed rocprofv3 summary "
                               "profiles/stage_edge_kernel_basin1M_counters.md (same kernel sources), scaled by "
                               "its copy calibration; not counted in this run") if traffic else
-                             "null: the committed counter summary is for other kernel sources",
+                             ("null: the committed counter summary is for other kernel sources or another "
+                              "stage tile" if workload == "basin1M_p1" else
+                              "null: no committed counter summary for this workload"),
            "bytes_per_launch": int(byts),
            "avg_us": round(avg_s * 1e6, 2), "launches": n}
     # the whole step against the same peak: every launch's algorithmic bytes
@@ -561,6 +570,7 @@ def main():
         log("calibration copy: 3 x 1 GiB read + 1 GiB written")
     ceiling = stream_ceiling()
     main_prec = "fp32" if "fp32" in res else "fp64"
+    basin_key = "basin1M_p1" if args.N == 708 and args.p == 1 else None
     r = res[main_prec]
     out = {
         "metric": METRIC, "value": round(r["rate"], 1), "unit": "element-stage updates/s", "n_gpus": 1,
@@ -573,7 +583,7 @@ def main():
                    "n_tri": r["E"], "p": prm["p"], "rk_stages": r["stages"], "precision": main_prec,
                    "stage_variant": r["variant"], "fused_post": r["fused"], "stage_tile": r["tile"],
                    "parallelism": "single GPU"},
-        "roofline": roofline(r, main_prec, prm["p"], prm["limiter"]),
+        "roofline": roofline(r, main_prec, prm["p"], prm["limiter"], basin_key),
     }
     rl = out["roofline"]
     if rl and ceiling.get("hbm_4x512MiB"):
@@ -588,7 +598,7 @@ def main():
         f = res["fp64"]
         out["fp64"] = {"value": round(f["rate"], 1), "ms_per_step": round(f["elapsed"] / args.steps * 1e3, 4),
                        "stage_variant": f["variant"],
-                       "dtype": "f64", "roofline": roofline(f, "fp64", prm["p"], prm["limiter"]),
+                       "dtype": "f64", "roofline": roofline(f, "fp64", prm["p"], prm["limiter"], basin_key),
                        "fp32_over_fp64": round(r["rate"] / f["rate"], 3)}
     if not args.no_storm:
         out["storm"] = run_storm(args.N)

@@ -28,7 +28,11 @@ namespace dg {
 #define DG_STAGE_WAVES 1
 #endif
 #define DG_STAGE_ATTR __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(DG_STAGE_WAVES)))
-#define DG_STAGE_ATTR_T(T) __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(DG_STAGE_WAVES)))
+// the FP64 p = 3 per-edge kernel on 64-element tiles is built for two
+// wavefronts per SIMD (its LDS allows six workgroups per CU), the others for
+// one (their occupancy is set by LDS or by registers the compiler keeps)
+#define DG_STAGE_ATTR_T(T) \
+  __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu((P == 3 && sizeof(Real) == 8 && T == 64) ? 2 : DG_STAGE_WAVES)))
 
 // f(std::integral_constant<int, i>) for i = 0 .. N-1, expanded at compile time
 template <typename F, int... I>
@@ -1425,21 +1429,33 @@ __global__ DG_STAGE_ATTR_T(T) void stage_edge_kernel(const Member<Real>* __restr
     s_wsum[0][wv] = incl;
     s_wsum[1][wv] = incl2;
   }
+  // area integrals and storm terms: in phase A, or (kAreaLate) after the
+  // edge loop, so that their accumulators are not live across it
   Real acc[3][NP];
 #pragma unroll
   for (int v = 0; v < 3; ++v)
 #pragma unroll
     for (int m = 0; m < NP; ++m) acc[v][m] = Real(0);
-  area_terms<Real, P>(d.w, d.hb, d.cx0, d.cx1, d.cy0, d.cy1, d.detJ, d.idet, fric, M.friction, g, H0, acc);
-  if (met_on) {
-    if constexpr (!kMetEarly) {
-      int tm[3];
+  auto volume = [&](const Real (&w)[3][NP]) {
+    area_terms<Real, P>(w, d.hb, d.cx0, d.cx1, d.cy0, d.cy1, d.detJ, d.idet, fric, M.friction, g, H0, acc);
+    if (met_on) {
+      if constexpr (!kMetEarly) {
+        int tm[3];
 #pragma unroll
-      for (int i = 0; i < 3; ++i) tm[i] = ldc(gp(M.tri), i * E, ec);
-      met_nodes<Real>(M, tm, mtx, mty, mps);
+        for (int i = 0; i < 3; ++i) tm[i] = ldc(gp(M.tri), i * E, ec);
+        met_nodes<Real>(M, tm, mtx, mty, mps);
+      }
+      met_terms<Real, P>(mtx, mty, mps, w, d.hb, d.cx0, d.cx1, d.cy0, d.cy1, d.detJ, d.idet, g, acc);
     }
-    met_terms<Real, P>(mtx, mty, mps, d.w, d.hb, d.cx0, d.cx1, d.cy0, d.cy1, d.detJ, d.idet, g, acc);
-  }
+  };
+  // FP64 p = 3 on 64-element tiles computes them after the edge loop and
+  // reads its modes again there (they stay in the cache) rather than keeping
+  // 60 registers of modes and 60 of accumulators live across the loop: with
+  // the two-wavefront register budget this spills less.  (The fused kernel,
+  // p <= 2, changes the modes in phase 0 and never reloads them.)
+  constexpr bool kAreaLate = P == 3 && sizeof(Real) == 8 && T == 64;
+  constexpr bool kReloadW = kAreaLate && !PRE;
+  if constexpr (!kAreaLate) volume(d.w);
   __syncthreads();
   int base = 0, base2 = 0, tot = 0, tot2 = 0;
 #pragma unroll
@@ -1539,6 +1555,8 @@ __global__ DG_STAGE_ATTR_T(T) void stage_edge_kernel(const Member<Real>* __restr
 #pragma unroll
             for (int v = 0; v < 3; ++v) s_flux[(kn * NG + gR) * 3 + v][nb - t0] = wg * FR[v];
           }
+          // one Gauss point at a time (interleaving them raises the register peak)
+          if constexpr (kAreaLate) __builtin_amdgcn_sched_barrier(0);
         });
       } else {
         const int code = -1 - nb;
@@ -1681,6 +1699,17 @@ __global__ DG_STAGE_ATTR_T(T) void stage_edge_kernel(const Member<Real>* __restr
     }
 
   // ---- phase C: edge contributions, inverse mass, stage combination, post
+  Real wr[3][NP];
+  if constexpr (kReloadW) {
+#pragma unroll
+    for (int v = 0; v < 3; ++v)
+#pragma unroll
+      for (int m = 0; m < NP; ++m) wr[v][m] = ldc(Win, (v * NP + m) * E, ec);
+    volume(wr);
+  } else if constexpr (kAreaLate) {
+    volume(d.w);
+  }
+  Real (&wf)[3][NP] = kReloadW ? wr : d.w;
   Real w0v[3][NP];
   load_blend<Real, P>(M, A, E, ec, w0v);
   if constexpr (P >= 3) {
@@ -1723,7 +1752,7 @@ __global__ DG_STAGE_ATTR_T(T) void stage_edge_kernel(const Member<Real>* __restr
     const double area = 0.5 * (double(d.ex[2]) * double(d.ey[0]) - double(d.ex[0]) * double(d.ey[2]));
     rain_part = valid ? area * double(Rv) : 0.0;
   }
-  finish_stage<Real, P, LIM, T>(M, A, tl.tile, e, ec, valid, E, d.w, acc, d.hb, d.ex, d.ey, d.detJ, d.idet, dt, bout,
+  finish_stage<Real, P, LIM, T>(M, A, tl.tile, e, ec, valid, E, wf, acc, d.hb, d.ex, d.ey, d.detJ, d.idet, dt, bout,
                              bin, Rv, rain_part, w0v);
 }
 
@@ -2067,39 +2096,45 @@ __global__ __launch_bounds__(RED_CHUNK) void reduce_kernel(const Member<Real>* _
   double v[NV];
   double mn, fb;
   {
-    // the tile's four wavefront slots, combined as (s0 + s1) + (s2 + s3);
-    // a slot that starts at or beyond E holds no element
+    // the tile's four wavefront slots (one 32-byte load per row), combined
+    // as (s0 + s1) + (s2 + s3); a slot that starts at or beyond E holds no
+    // element and reads as empty
     const DG_G double* __restrict__ pt = gp(part);
     const size_t row = part_row(nt);
     const int t = chunk * RED_CHUNK + tid;
     const bool ok = t < nt;
     const size_t s0 = size_t(ok ? t : 0) * PSLOT;
     static_assert(PSLOT == 4, "four slots per tile");
-    const int nslot = ok ? (M.E - t * TILE + 63) / 64 : 0;       // slots holding elements
-    auto sum4 = [&](int r, bool on) -> double {
-      if (!on) return 0.0;
-      double x[4];
-#pragma unroll
-      for (int k = 0; k < 4; ++k) x[k] = k < nslot ? pt[r * row + s0 + k] : 0.0;
-      return (x[0] + x[1]) + (x[2] + x[3]);
+    const int nslot = ok ? (M.E - t * TILE + 63) / 64 : 0;
+    typedef double d4 __attribute__((ext_vector_type(4)));
+    auto ld4 = [&](int r) -> d4 { return *reinterpret_cast<const DG_G d4*>(pt + r * row + s0); };
+    auto sum4 = [&](const d4 q) -> double {
+      return ((nslot > 0 ? q.x : 0.0) + (nslot > 1 ? q.y : 0.0)) + ((nslot > 2 ? q.z : 0.0) + (nslot > 3 ? q.w : 0.0));
     };
-    auto min4 = [&](int r) -> double {
-      double x[4];
-#pragma unroll
-      for (int k = 0; k < 4; ++k) x[k] = k < nslot ? pt[r * row + s0 + k] : __builtin_inf();
-      return fmin(fmin(x[0], x[1]), fmin(x[2], x[3]));
+    auto min4 = [&](const d4 q) -> double {
+      constexpr double inf = __builtin_inf();
+      return fmin(fmin(nslot > 0 ? q.x : inf, nslot > 1 ? q.y : inf), fmin(nslot > 2 ? q.z : inf, nslot > 3 ? q.w : inf));
     };
-    v[0] = sum4(P_VOL, ok);
-    v[1] = sum4(P_RAIN, ok);
-    v[2] = sum4(P_NDRY, ok);
-    mn = min4(P_MINR);
+    const d4 qv = ld4(P_VOL), qr = ld4(P_RAIN), qd = ld4(P_NDRY), qm = ld4(P_MINR), qn = ld4(P_NNEG),
+             qb = ld4(P_BAD);
+    d4 qo[MAX_STAGES], qi[MAX_STAGES];
+#pragma unroll
+    for (int s = 0; s < MAX_STAGES; ++s)
+      if (s < ns) {
+        qo[s] = ld4(P_OUT0 + s);
+        qi[s] = ld4(P_IN0 + s);
+      }
+    v[0] = sum4(qv);
+    v[1] = sum4(qr);
+    v[2] = sum4(qd);
+    mn = min4(qm);
 #pragma unroll
     for (int s = 0; s < MAX_STAGES; ++s) {
-      v[3 + s] = sum4(P_OUT0 + s, ok && s < ns);
-      v[3 + MAX_STAGES + s] = sum4(P_IN0 + s, ok && s < ns);
+      v[3 + s] = s < ns ? sum4(qo[s]) : 0.0;
+      v[3 + MAX_STAGES + s] = s < ns ? sum4(qi[s]) : 0.0;
     }
-    v[INEG] = sum4(P_NNEG, ok);
-    fb = min4(P_BAD);
+    v[INEG] = sum4(qn);
+    fb = min4(qb);
   }
   const bool act = init || sc->active;
   // fixed-order block sums: within each wavefront, then wavefronts 0..NW-1
