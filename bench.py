@@ -110,7 +110,8 @@ def run_precision(sc, precision, steps, warmup, variant=1, events=2, save_dir=No
     log(f"[{precision}] setup {time.perf_counter() - t0:.1f}s  E={s.n_tri}  stage variant {variant} fused {fused} "
         f"tile {tile}"
         + (f" (autotuned ms/step: per-element {tuned[0]:.3f}, per-edge {tuned[1]:.3f}, fused {tuned[2]:.3f}, "
-           f"tiles 512/128/64 {tuned[3]:.3f}/{tuned[4]:.3f}/{tuned[5]:.3f})" if tuned else ""))
+           f"tiles 512/128/64 {tuned[3]:.3f}/{tuned[4]:.3f}/{tuned[5]:.3f}, matrix-core area {tuned[6]:.3f})"
+           if tuned else ""))
     s.step(warmup)
     s.sync()
     # events on the stage kernel's own dispatches only: the dominant
@@ -524,7 +525,8 @@ def main():
     ap.add_argument("--tile", type=int, default=-1, choices=[-1, 64, 128, 256, 512],
                     help="elements per workgroup of the per-edge stage kernel: -1 as the autotuner picks")
     ap.add_argument("--variant", type=int, default=-1,
-                    help="stage kernel: 0 per element, 1 per edge, -1 autotuned on the workload (default)")
+                    help="stage kernel: 0 per element, 1 per edge, 2 per edge with matrix-core area integrals (p = 3, "
+                         "FP32), -1 autotuned on the workload (default)")
     ap.add_argument("--calib-copy", action="store_true", help="also run a 1 GiB device copy (counter calibration)")
     ap.add_argument("--no-events", action="store_true",
                     help="no HIP events in the timed region (steps replay a HIP graph; no roofline)")

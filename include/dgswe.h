@@ -308,7 +308,10 @@ int dgswe_kernel_stats(dgswe_ctx* ctx, const char* kernel, int64_t* launches, do
  * only by summation order).  DGSWE_TUNE_STAGE_VARIANT: 0 = every element
  * evaluates its three edges; 1 (default) = the tile's point values (p <= 2)
  * or edge traces (p = 3) are staged in LDS and each edge inside a tile is
- * evaluated once.  DGSWE_TUNE_FUSED_POST (limiter on, variant 1, p <= 2):
+ * evaluated once; 2 (p = 3, FP32 only, else EINVAL) = variant 1 on
+ * 64-element tiles with the area integrals of Eq. elem_weak_form (modes to
+ * the 16 area points, fluxes and sources back onto the 10 modes) computed
+ * as 16x16x4 matrix products on the matrix cores.  DGSWE_TUNE_FUSED_POST (limiter on, variant 1, p <= 2):
  * 1 = every stage after the first applies the previous stage's limiter and
  * positive-depth operator (Sec. 2.3, Sec. 2.4) to its input itself, for its
  * tile and the ring of outside elements across the tile's edges, instead of
@@ -334,12 +337,12 @@ int dgswe_get_tuning(const dgswe_ctx* ctx, int key, int* value);
  * (after two untimed steps each): per-element kernel, per-edge kernel with
  * a post pass after every stage, per-edge kernel with the post-processing
  * fused into the next stage (when available), per-edge kernel on tiles of
- * 512 (p = 1), 128 and 64 elements; keeps the fastest and restores the
- * state, flags, partials and scalars, so the context continues exactly
- * where it was.  chosen (may be NULL) receives the stage variant,
- * ms_per_step[6] (may be NULL) the six timings in that order (0 where a
- * configuration does not apply); the fused and tile choices read back
- * through dgswe_get_tuning.  Allocates a copy of the
+ * 512 (p = 1), 128 and 64 elements, stage variant 2 (p = 3, FP32); keeps
+ * the fastest and restores the state, flags, partials and scalars, so the
+ * context continues exactly where it was.  chosen (may be NULL) receives
+ * the stage variant, ms_per_step[7] (may be NULL) the seven timings in that
+ * order (0 where a configuration does not apply); the fused and tile
+ * choices read back through dgswe_get_tuning.  Allocates a copy of the
  * state for the duration of the call.  EINVAL for n_steps < 1, ESTATE
  * without mesh or state or inside a batch, ENONFINITE if the context has a
  * latched error. */

@@ -226,7 +226,7 @@ struct dgswe_ctx {
   std::shared_ptr<MeshDev> mesh;
   std::shared_ptr<Arena> arena;     // caller's device memory (dgswe_workspace_bind), or null
   int n_tiles = 0;
-  int variant = 1;                  // stage kernel: 0 per element, 1 per edge
+  int variant = 1;                  // stage kernel: 0 per element, 1 per edge, 2 per edge with matrix-core area terms
   int fused = 0;                    // limiter on, per-edge kernel: later stages post-process their input
   int tile = TILE;                  // elements per workgroup of the per-edge stage kernel (64, 128, 256, 512)
   int n_tiles64 = 0;
@@ -264,6 +264,7 @@ struct dgswe_ctx {
   // elements per workgroup of the stage kernel as launched: the chosen
   // tile for the per-edge kernel (512 only at p = 1), else 256
   int stage_tile() const {
+    if (variant == 2) return 64;
     if (variant != 1 || (tile == 512 && prm.p != 1)) return TILE;
     return tile;
   }
@@ -1371,8 +1372,10 @@ int dgswe_set_tuning(dgswe_ctx* c, int key, int value) {
   if (key != DGSWE_TUNE_STAGE_VARIANT && key != DGSWE_TUNE_FUSED_POST && key != DGSWE_TUNE_STAGE_TILE)
     return fail(DGSWE_EINVAL, "unknown tuning key");
   if (key == DGSWE_TUNE_STAGE_TILE ? (value != 64 && value != 128 && value != TILE && value != 512)
-                                   : (value != 0 && value != 1))
-    return fail(DGSWE_EINVAL, "tuning values are 0 or 1 (stage tile: 64, 128, 256 or 512)");
+      : key == DGSWE_TUNE_STAGE_VARIANT ? (value < 0 || value > 2) : (value != 0 && value != 1))
+    return fail(DGSWE_EINVAL, "tuning values are 0 or 1 (stage variant: 0, 1, 2; stage tile: 64, 128, 256 or 512)");
+  if (key == DGSWE_TUNE_STAGE_VARIANT && value == 2 && !(c->prm.p == 3 && c->prm.precision == DGSWE_FP32))
+    return fail(DGSWE_EINVAL, "stage variant 2 (matrix-core area integrals) is built for p = 3 in FP32");
   if (c->stream) HIPCHK(hipStreamSynchronize(c->stream));
   if (key == DGSWE_TUNE_STAGE_VARIANT) c->variant = value;
   else if (key == DGSWE_TUNE_FUSED_POST) c->fused = value;
@@ -1393,7 +1396,7 @@ int dgswe_get_tuning(const dgswe_ctx* c, int key, int* value) {
 }
 
 int dgswe_autotune(dgswe_ctx* c, int n_steps, int* chosen, double* ms_per_step) {
-  constexpr int NCFG = 6;
+  constexpr int NCFG = 7;
   int rc = check_ctx(c, true, true);
   if (rc) return rc;
   ArenaScope arena_scope(c->arena);
@@ -1422,7 +1425,7 @@ int dgswe_autotune(dgswe_ctx* c, int n_steps, int* chosen, double* ms_per_step) 
     return DGSWE_OK;
   };
   const int saved_prof = c->prof;
-  const int saved_fused = c->fused, saved_tile = c->tile;
+  const int saved_fused = c->fused, saved_tile = c->tile, saved_variant = c->variant;
   c->prof = 0;
   hipEvent_t ea, eb;
   HIPCHK(hipEventCreate(&ea));
@@ -1430,16 +1433,19 @@ int dgswe_autotune(dgswe_ctx* c, int n_steps, int* chosen, double* ms_per_step) 
   // configurations: per-element kernel; per-edge kernel with the post pass
   // after every stage; per-edge kernel with the post-processing fused into
   // the next stage (limiter on, p <= 2, a halo built); per-edge kernel on
-  // tiles of 512 (p = 1), 128 and 64 elements
-  const int cfg_variant[NCFG] = {0, 1, 1, 1, 1, 1}, cfg_fused[NCFG] = {0, 0, 1, 0, 0, 0},
-            cfg_tile[NCFG] = {TILE, TILE, TILE, 512, 128, 64};
-  double ms[NCFG] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  // tiles of 512 (p = 1), 128 and 64 elements; per-edge kernel with the
+  // area integrals on the matrix cores (p = 3, FP32)
+  const int cfg_variant[NCFG] = {0, 1, 1, 1, 1, 1, 2}, cfg_fused[NCFG] = {0, 0, 1, 0, 0, 0, 0},
+            cfg_tile[NCFG] = {TILE, TILE, TILE, 512, 128, 64, 64};
+  double ms[NCFG] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  const bool mf_ok = c->prm.p == 3 && c->prm.precision == DGSWE_FP32;
   int err = DGSWE_OK;
   for (int v = 0; v < NCFG && !err; ++v) {
     c->variant = cfg_variant[v];
     c->fused = cfg_fused[v];
     c->tile = cfg_tile[v];
     if (v == 2 && !c->use_fused()) continue;    // the same as configuration 1
+    if (v == 6 && !mf_ok) continue;
     if (c->stage_tile() != cfg_tile[v]) continue;   // 512 at p > 1
     c->graph_dirty = true;
     err = dgswe_step(c, 2);                     // builds the step graph, warms caches
@@ -1459,6 +1465,7 @@ int dgswe_autotune(dgswe_ctx* c, int n_steps, int* chosen, double* ms_per_step) 
   (void)hipEventDestroy(eb);
   c->prof = saved_prof;
   if (err) {
+    c->variant = saved_variant;
     c->fused = saved_fused;
     c->tile = saved_tile;
     (void)restore();

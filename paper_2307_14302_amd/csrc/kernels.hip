@@ -29,10 +29,12 @@ namespace dg {
 #endif
 #define DG_STAGE_ATTR __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(DG_STAGE_WAVES)))
 // the FP64 p = 3 per-edge kernel on 64-element tiles is built for two
-// wavefronts per SIMD (its LDS allows six workgroups per CU), the others for
-// one (their occupancy is set by LDS or by registers the compiler keeps)
-#define DG_STAGE_ATTR_T(T) \
-  __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu((P == 3 && sizeof(Real) == 8 && T == 64) ? 2 : DG_STAGE_WAVES)))
+// wavefronts per SIMD (its LDS allows six workgroups per CU) and the FP32
+// one with matrix-core area integrals (MF) for three, the others for one
+// (their occupancy is set by LDS or by registers the compiler keeps)
+#define DG_STAGE_ATTR_T(T)                                                                        \
+  __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(                                        \
+      MF ? 3 : (P == 3 && sizeof(Real) == 8 && T == 64) ? 2 : DG_STAGE_WAVES)))
 
 // f(std::integral_constant<int, i>) for i = 0 .. N-1, expanded at compile time
 template <typename F, int... I>
@@ -712,11 +714,46 @@ DG_DEV const AreaTable<Real, P>& area_table() {
         sizeof(Real) == 4 ? static_cast<const void*>(&c_area3f) : static_cast<const void*>(&c_area3d));
 }
 
+// Fluxes and sources at one area point (Eq. SWE: advective flux, pressure,
+// bed slope, friction), from the point's state wq, bathymetry hq, bed
+// gradient (dhx, dhy), the element's det J J^{-T} entries and quadrature
+// weight Wq: the fluxes mapped to the reference directions, Gr = Wq (cx0 Fx
+// + cy0 Fy), Gs = Wq (cx1 Fx + cy1 Fy), and the momentum sources s1, s2.
+template <typename Real>
+DG_DEV void area_point(const Real (&wq)[3], Real hq, Real dhx, Real dhy, Real cx0, Real cx1, Real cy0, Real cy1,
+                       Real fc, Real gn2, int friction, Real g, Real H0, Real Wq, Real (&Gr)[3], Real (&Gs)[3],
+                       Real& s1, Real& s2) {
+  const Real Hs = dmax(wq[0] + hq, H0);
+  Real iH, Hm43;
+  if constexpr (sizeof(Real) == 4) {
+    const float r = __builtin_amdgcn_rsqf(Hs);
+    iH = r * r;
+    Hm43 = friction == 0 ? __builtin_amdgcn_exp2f(-1.3333333333333333f * __builtin_amdgcn_logf(Hs)) : 0.0f;
+  } else {
+    const Real r = rsq(Hs);
+    iH = r * r;
+    Hm43 = friction == 0 ? rpow43(Hs) : Real(0);
+  }
+  const Real u = wq[1] * iH, vv_ = wq[2] * iH;
+  const Real Pq = Real(0.5) * g * wq[0] * (wq[0] + Real(2) * hq);
+  const Real spd = dsqrt(wq[1] * wq[1] + wq[2] * wq[2]) * iH;
+  const Real tau = (friction == 0) ? gn2 * spd * Hm43 : fc * spd * iH;
+  const Real Fx[3] = {wq[1], wq[1] * u + Pq, wq[2] * u};
+  const Real Fy[3] = {wq[2], wq[1] * vv_, wq[2] * vv_ + Pq};
+  s1 = g * wq[0] * dhx - tau * wq[1];
+  s2 = g * wq[0] * dhy - tau * wq[2];
+#pragma unroll
+  for (int v = 0; v < 3; ++v) {
+    Gr[v] = Wq * (cx0 * Fx[v] + cy0 * Fy[v]);
+    Gs[v] = Wq * (cx1 * Fx[v] + cy1 * Fy[v]);
+  }
+}
+
 // p >= 2 area integrals: one quadrature point per loop trip with the table
 // above (the unrolled form keeps far more registers live than the 3 Np
 // accumulators need).  Per point the fluxes are mapped once to the
-// reference directions, Gr = w (cx0 Fx + cy0 Fy), Gs = w (cx1 Fx + cy1 Fy),
-// then every mode takes dphi/dr Gr + dphi/ds Gs.
+// reference directions (area_point), then every mode takes dphi/dr Gr +
+// dphi/ds Gs.
 template <typename Real, int P>
 DG_DEV void area_terms_table(const Real (&w)[3][Tab<P>::NP], const Real (&hb)[3], Real cx0, Real cx1, Real cy0,
                              Real cy1, Real detJ, Real idet, Real fc, int friction, Real g, Real H0,
@@ -737,33 +774,10 @@ DG_DEV void area_terms_table(const Real (&w)[3][Tab<P>::NP], const Real (&hb)[3]
       wq[v] = s;
     }
     const Real hq = T.L[q][0] * hb[0] + T.L[q][1] * hb[1] + T.L[q][2] * hb[2];
-    const Real Hs = dmax(wq[0] + hq, H0);
-    Real iH, Hm43;
-    if constexpr (sizeof(Real) == 4) {
-      const float r = __builtin_amdgcn_rsqf(Hs);
-      iH = r * r;
-      Hm43 = friction == 0 ? __builtin_amdgcn_exp2f(-1.3333333333333333f * __builtin_amdgcn_logf(Hs)) : 0.0f;
-    } else {
-      const Real r = rsq(Hs);
-      iH = r * r;
-      Hm43 = friction == 0 ? rpow43(Hs) : Real(0);
-    }
-    const Real u = wq[1] * iH, vv_ = wq[2] * iH;
-    const Real Pq = Real(0.5) * g * wq[0] * (wq[0] + Real(2) * hq);
-    const Real spd = dsqrt(wq[1] * wq[1] + wq[2] * wq[2]) * iH;
-    const Real tau = (friction == 0) ? gn2 * spd * Hm43 : fc * spd * iH;
-    const Real Fx[3] = {wq[1], wq[1] * u + Pq, wq[2] * u};
-    const Real Fy[3] = {wq[2], wq[1] * vv_, wq[2] * vv_ + Pq};
-    const Real s1 = g * wq[0] * dhx - tau * wq[1];
-    const Real s2 = g * wq[0] * dhy - tau * wq[2];
     const Real Wq = T.W[q];
     const Real wdet = Wq * detJ;
-    Real Gr[3], Gs[3];
-#pragma unroll
-    for (int v = 0; v < 3; ++v) {
-      Gr[v] = Wq * (cx0 * Fx[v] + cy0 * Fy[v]);
-      Gs[v] = Wq * (cx1 * Fx[v] + cy1 * Fy[v]);
-    }
+    Real Gr[3], Gs[3], s1, s2;
+    area_point<Real>(wq, hq, dhx, dhy, cx0, cx1, cy0, cy1, fc, gn2, friction, g, H0, Wq, Gr, Gs, s1, s2);
 #pragma unroll
     for (int m = 0; m < NP; ++m) {
       if (m > 0) {
@@ -774,6 +788,111 @@ DG_DEV void area_terms_table(const Real (&w)[3][Tab<P>::NP], const Real (&hb)[3]
       const Real ps = wdet * T.Q[q][m];
       acc[1][m] += ps * s1;
       acc[2][m] += ps * s2;
+    }
+  }
+}
+
+// p = 3 area integrals on the matrix cores, FP32, for one wavefront of 64
+// elements (lane l holds element l of the tile).  Per block of 16 elements:
+// the state at the 16 area points is the product Q (16 points x 10 modes)
+// times U (10 modes x 16 elements), three 16x16x4 products per variable with
+// the modes padded to 12; each lane forms the fluxes and sources of the four
+// points it holds (area_point); the projections back onto the modes are
+// four products per operand (Gr against dphi/dr, Gs against dphi/ds, the
+// momentum sources against phi), the points split over the four K-slices
+// so that a lane's four point values are its B operands as they stand; the
+// rows of the result return to the element's lane by cross-lane reads.
+// v_mfma_f32_16x16x4f32 (one block): lane l supplies A[l % 16][l / 16] and
+// B[l / 16][l % 16] and holds D[4 (l / 16) + r][l % 16] in register r.
+// s_w: row v * 10 + m holds mode m of variable v for the 64 elements;
+// s_hb, s_ev, s_fc: their vertex bathymetry, edge vectors and friction.
+DG_DEV void area_terms_mfma_p3(const float (*s_w)[64], const float (*s_hb)[64], const float (*s_ev)[64],
+                               const float* s_fc, int friction, float g, float H0, float (&acc)[3][10]) {
+  typedef float f4 __attribute__((ext_vector_type(4)));
+  constexpr int NP = 10;
+  const AreaTable<float, 3>& AT = area_table<float, 3>();
+  const int lane = threadIdx.x & 63, hi = lane >> 4, lo = lane & 15;
+  // A of the point evaluation: Q[q = lo][m = 4 s + hi]
+  float aQ[3];
+#pragma unroll
+  for (int s = 0; s < 3; ++s) {
+    const int m = 4 * s + hi;
+    aQ[s] = m < NP ? AT.Q[lo][m < NP ? m : 0] : 0.0f;
+  }
+  // A of the projections at q = 4 hi + s, m = lo (dphi/dr, dphi/ds vanish for m = 0)
+  float aR[4], aS[4], aP[4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const int q = 4 * hi + s, m = lo < NP ? lo : 0;
+    aR[s] = (lo >= 1 && lo < NP) ? AT.QR[q][m] : 0.0f;
+    aS[s] = (lo >= 1 && lo < NP) ? AT.QS[q][m] : 0.0f;
+    aP[s] = lo < NP ? AT.Q[q][m] : 0.0f;
+  }
+#pragma unroll 1
+  for (int b = 0; b < 4; ++b) {
+    const int ee = 16 * b + lo;                     // the element whose points this lane holds
+    f4 D[3];
+#pragma unroll
+    for (int v = 0; v < 3; ++v) {
+      D[v] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+      for (int s = 0; s < 3; ++s) {
+        const int m = 4 * s + hi;
+        const float u = s_w[v * NP + (m < NP ? m : NP - 1)][ee];
+        D[v] = __builtin_amdgcn_mfma_f32_16x16x4f32(aQ[s], m < NP ? u : 0.0f, D[v], 0, 0, 0);
+      }
+    }
+    // element ee's geometry (as load_elem forms it) and bed gradient
+    const float ex0 = s_ev[0][ee], ey0 = s_ev[1][ee], ex2 = s_ev[4][ee], ey2 = s_ev[5][ee];
+    const float hb0 = s_hb[0][ee], hb1 = s_hb[1][ee], hb2 = s_hb[2][ee], fc = s_fc[ee];
+    const float detJ = 0.25f * (ex2 * ey0 - ex0 * ey2);
+    const float idet = rcp(detJ);
+    const float cx0 = -0.5f * ey2, cx1 = -0.5f * ey0, cy0 = 0.5f * ex2, cy1 = 0.5f * ex0;
+    const float dhr = 0.5f * (hb1 - hb0), dhs = 0.5f * (hb2 - hb0);
+    const float dhx = (cx0 * dhr + cx1 * dhs) * idet, dhy = (cy0 * dhr + cy1 * dhs) * idet;
+    const float gn2 = g * fc * fc;
+    f4 X[3], Y[3], Z1, Z2;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int q = 4 * hi + r;
+      const float wq[3] = {D[0][r], D[1][r], D[2][r]};
+      const float hq = AT.L[q][0] * hb0 + AT.L[q][1] * hb1 + AT.L[q][2] * hb2;
+      const float Wq = AT.W[q];
+      float Gr[3], Gs[3], s1, s2;
+      area_point<float>(wq, hq, dhx, dhy, cx0, cx1, cy0, cy1, fc, gn2, friction, g, H0, Wq, Gr, Gs, s1, s2);
+#pragma unroll
+      for (int v = 0; v < 3; ++v) {
+        X[v][r] = Gr[v];
+        Y[v][r] = Gs[v];
+      }
+      const float wdet = Wq * detJ;
+      Z1[r] = wdet * s1;
+      Z2[r] = wdet * s2;
+    }
+    f4 Dp[3];
+#pragma unroll
+    for (int v = 0; v < 3; ++v) {
+      Dp[v] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        Dp[v] = __builtin_amdgcn_mfma_f32_16x16x4f32(aR[s], X[v][s], Dp[v], 0, 0, 0);
+        Dp[v] = __builtin_amdgcn_mfma_f32_16x16x4f32(aS[s], Y[v][s], Dp[v], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      Dp[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(aP[s], Z1[s], Dp[1], 0, 0, 0);
+      Dp[2] = __builtin_amdgcn_mfma_f32_16x16x4f32(aP[s], Z2[s], Dp[2], 0, 0, 0);
+    }
+    // mode m of element 16 b + lo sits in lane 16 (m / 4) + lo, register m % 4
+#pragma unroll
+    for (int m = 0; m < NP; ++m) {
+      const int src = (16 * (m >> 2) + lo) << 2;
+#pragma unroll
+      for (int v = 0; v < 3; ++v) {
+        const float x = __int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(Dp[v][m & 3])));
+        if (hi == b) acc[v][m] += x;
+      }
     }
   }
 }
@@ -1230,13 +1349,15 @@ __global__ DG_STAGE_ATTR void stage_kernel(const Member<Real>* __restrict__ mem,
 // post pass, and cut edges read their neighbour from LDS.  The limiter of
 // a ring-1 element reads the raw means of ring 2.  The arithmetic is the
 // post kernel's (the same functions).
-template <typename Real, int P, int FLUX, int LIM, int PRE, int T>
+template <typename Real, int P, int FLUX, int LIM, int PRE, int T, int MF = 0>
 __global__ DG_STAGE_ATTR_T(T) void stage_edge_kernel(const Member<Real>* __restrict__ mem,
                                                           const Tile* __restrict__ tiles, int n_tiles, StageArgs A) {
   constexpr int NP = Tab<P>::NP, NG = Tab<P>::NG;
   static_assert(!PRE || (LIM == 1 && P <= 2), "the fused post-processing needs the limiter and p <= 2");
   static_assert(T == 256 || ((T == 64 || T == 128 || (T == 512 && P == 1)) && !PRE),
                 "tiles of 256; 64, 128 or (p = 1) 512 without the fused post-processing");
+  // MF: the area integrals on the matrix cores (p = 3, FP32, one wavefront per tile)
+  static_assert(!MF || (P == 3 && sizeof(Real) == 4 && T == 64 && !PRE), "matrix-core area integrals: p = 3, FP32, T = 64");
   constexpr int NW = T / 64;                            // wavefronts per workgroup
   constexpr int LB = T == 512 ? 9 : T == 256 ? 8 : T == 128 ? 7 : 6;   // bits of a local element index in an edge entry
   // point values per variable (vertices, midpoints); p = 3 keeps its traces
@@ -1401,6 +1522,7 @@ __global__ DG_STAGE_ATTR_T(T) void stage_edge_kernel(const Member<Real>* __restr
     }
   }
   s_flag[el] = myflag ? 1 : 0;
+  if constexpr (MF) s_node[0][el] = fric;           // p = 3 keeps no point values here
   // The edges this element evaluates, in three classes listed one after the
   // other so that a wavefront mostly runs one code path: (0) interior edges
   // inside the tile, owned by the lower id; (1) edges to other tiles;
@@ -1437,7 +1559,8 @@ __global__ DG_STAGE_ATTR_T(T) void stage_edge_kernel(const Member<Real>* __restr
 #pragma unroll
     for (int m = 0; m < NP; ++m) acc[v][m] = Real(0);
   auto volume = [&](const Real (&w)[3][NP]) {
-    area_terms<Real, P>(w, d.hb, d.cx0, d.cx1, d.cy0, d.cy1, d.detJ, d.idet, fric, M.friction, g, H0, acc);
+    if constexpr (!MF)
+      area_terms<Real, P>(w, d.hb, d.cx0, d.cx1, d.cy0, d.cy1, d.detJ, d.idet, fric, M.friction, g, H0, acc);
     if (met_on) {
       if constexpr (!kMetEarly) {
         int tm[3];
@@ -1711,7 +1834,7 @@ __global__ DG_STAGE_ATTR_T(T) void stage_edge_kernel(const Member<Real>* __restr
   }
   Real (&wf)[3][NP] = kReloadW ? wr : d.w;
   Real w0v[3][NP];
-  load_blend<Real, P>(M, A, E, ec, w0v);
+  if constexpr (!MF) load_blend<Real, P>(M, A, E, ec, w0v);
   if constexpr (P >= 3) {
     // expanded at compile time so that every basis value is a constant
     static_for<3>([&](auto kc) {
@@ -1729,6 +1852,25 @@ __global__ DG_STAGE_ATTR_T(T) void stage_edge_kernel(const Member<Real>* __restr
         }
       });
     });
+    if constexpr (MF) {
+      // the flux slots are read: they take the tile's modes for the
+      // matrix-core area integrals, and hold them for the combine (read
+      // back afterwards instead of keeping 30 registers live across it);
+      // w^n is read after it for the same reason
+      __syncthreads();
+#pragma unroll
+      for (int v = 0; v < 3; ++v)
+#pragma unroll
+        for (int m = 0; m < NP; ++m) s_flux[v * NP + m][el] = wf[v][m];
+      __syncthreads();
+      area_terms_mfma_p3(s_flux, s_hb, s_ev, s_node[0], M.friction, Real(g), Real(H0), acc);
+      asm volatile("" ::: "memory");
+#pragma unroll
+      for (int v = 0; v < 3; ++v)
+#pragma unroll
+        for (int m = 0; m < NP; ++m) wf[v][m] = s_flux[v * NP + m][el];
+      load_blend<Real, P>(M, A, E, ec, w0v);
+    }
   } else {
 #pragma unroll
   for (int k = 0; k < 3; ++k)
@@ -2376,6 +2518,18 @@ hipError_t launch_stage(int P, int flux, int limiter, int variant, const Member<
   if (P == PP && flux == FF && limiter == LL) {                                                 \
     if (variant == 1) DG_LAUNCH((stage_edge_kernel<Real, PP, FF, LL, 0, TILE>))                 \
     else DG_LAUNCH((stage_kernel<Real, PP, FF, LL>))                                            \
+  }
+  if (variant == 2) {
+    // per-edge kernel with the area integrals on the matrix cores: p = 3,
+    // FP32, 64-element tiles
+    if constexpr (sizeof(Real) == 4) {
+      if (P != 3 || tile != 64 || fused) return hipErrorInvalidValue;
+      if (flux == 0 && limiter == 0) DG_LAUNCH((stage_edge_kernel<Real, 3, 0, 0, 0, 64, 1>))
+      if (flux == 1 && limiter == 0) DG_LAUNCH((stage_edge_kernel<Real, 3, 1, 0, 0, 64, 1>))
+      if (flux == 0 && limiter == 1) DG_LAUNCH((stage_edge_kernel<Real, 3, 0, 1, 0, 64, 1>))
+      if (flux == 1 && limiter == 1) DG_LAUNCH((stage_edge_kernel<Real, 3, 1, 1, 0, 64, 1>))
+    }
+    return hipErrorInvalidValue;
   }
   if (tile != TILE) {
     // per-edge kernel on tiles of 64 or 128 elements (any p) or 512 (p = 1),

@@ -181,9 +181,10 @@ class Solver:
         """Pick the fastest stage-kernel configuration for this mesh; the
         state is left as it was.  Returns (variant, (ms/step per-element,
         per-edge with post passes, per-edge fused, per-edge on tiles of 512,
-        128 and 64 elements; 0 where it does not apply))."""
+        128 and 64 elements, per-edge with matrix-core area integrals; 0
+        where it does not apply))."""
         v = C.c_int()
-        ms = (C.c_double * 6)()
+        ms = (C.c_double * 7)()
         call("dgswe_autotune", self.h, int(n_steps), C.byref(v), ms)
         return v.value, tuple(ms)
 

@@ -68,7 +68,7 @@ def test_p3_parity_fp64(dg, case, variant):
     gpu.close()
 
 
-@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("variant", [0, 1, 2])
 def test_p3_closed_basin_storm_fp32(dg, variant):
     rec = [[0.0, 20e3, 40e3, 5000.0, 15e3, 1.4, 1.0, 2.0, 1.0],
            [4.0e3, 60e3, 40e3, 5000.0, 15e3, 1.4, 1.0, 2.0, 1.0]]
@@ -90,8 +90,8 @@ def test_p3_closed_basin_storm_fp32(dg, variant):
     gpu.close()
 
 
-@pytest.mark.parametrize("variant", [0, 1])
-@pytest.mark.parametrize("precision,tol", [("fp64", 1e-11), ("fp32", 1e-4)])
+@pytest.mark.parametrize("precision,tol,variant", [("fp64", 1e-11, 0), ("fp64", 1e-11, 1), ("fp32", 1e-4, 0),
+                                                   ("fp32", 1e-4, 1), ("fp32", 1e-4, 2)])
 def test_p3_lake_at_rest(dg, precision, tol, variant):
     sc = meshgen.lake_at_rest(p=3)
     gpu = dg.Solver.from_scenario(sc, precision=precision)
@@ -120,8 +120,8 @@ def test_p3_kernels_agree_and_autotune(dg):
     a.close(); b.close()
 
 
-@pytest.mark.parametrize("variant", [0, 1])
-@pytest.mark.parametrize("precision,tol", [("fp64", 1e-11), ("fp32", 5e-5)])
+@pytest.mark.parametrize("precision,tol,variant", [("fp64", 1e-11, 0), ("fp64", 1e-11, 1), ("fp32", 5e-5, 0),
+                                                   ("fp32", 5e-5, 1), ("fp32", 5e-5, 2)])
 def test_p3_basin_window_one_step(dg, precision, tol, variant):
     sc = meshgen.basin_window(100, p=3)
     gpu = dg.Solver.from_scenario(sc, precision=precision)
@@ -138,3 +138,56 @@ def test_p3_basin_window_one_step(dg, precision, tol, variant):
     print(precision, "p=3 basin window one-step rel L2", err, flush=True)
     assert err.max() < tol, err
     gpu.close()
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_p3_matrix_core_area_integrals_fp32(dg, case):
+    """Stage variant 2: the area integrals as 16x16x4 matrix products on the
+    matrix cores (FP32).  Against the oracle to the FP32 bar after one and
+    after 30 steps, and against the vector kernel on the same 64-element
+    tiles (variant 1), from which it differs only in the order of the area
+    sums: to 1e-5 of the state scale after 30 steps."""
+    sc = _mixed(case)
+    a = dg.Solver.from_scenario(sc, precision="fp32")
+    b = dg.Solver.from_scenario(sc, precision="fp32")
+    a.set_variant(2)
+    b.set_variant(1); b.set_tile(64)
+    assert a.variant() == 2 and a.tile() == 64 and b.tile() == 64
+    orc = from_scenario(sc)
+    a.step(1); b.step(1); orc.step(1)
+    e1 = rel_l2(a.state(), orc.w, orc)
+    d1 = rel_l2(a.state(), b.state(), orc)
+    a.step(29); b.step(29); orc.step(29)
+    ea = rel_l2(a.state(), orc.w, orc)
+    eb = rel_l2(b.state(), orc.w, orc)
+    d = rel_l2(a.state(), b.state(), orc)
+    print(f"p=3 {case} FP32 matrix-core area: one step {e1} (vs vector {d1}); 30 steps {ea} "
+          f"(vector kernel {eb}, between them {d})", flush=True)
+    assert e1.max() < 5e-6, e1
+    assert ea.max() < 1e-4 and eb.max() < 1e-4, (ea, eb)
+    assert d.max() < 1e-5, d
+    ma, mb = a.mass(), b.mass()
+    for k in ("t", "volume", "rain_in"):
+        assert abs(ma[k] - mb[k]) <= 1e-6 * max(1.0, abs(mb[k])), (k, ma[k], mb[k])
+    a.close(); b.close()
+
+
+def test_p3_matrix_core_variant_scope_and_autotune(dg):
+    """Variant 2 is refused where it is not built (FP64, p < 3); on a p = 3
+    FP32 context the autotuner times it as its seventh configuration and
+    leaves the state as it was."""
+    import paper_2307_14302_amd._native as N
+    sc = _mixed("llf_param_lim")
+    c64 = dg.Solver.from_scenario(sc, precision="fp64")
+    with pytest.raises(N.DgsweError, match="EINVAL"):
+        c64.set_variant(2)
+    p1 = dg.Solver.from_scenario(meshgen.small_mixed(seed=5, nx=12, ny=6, p=1), precision="fp32")
+    with pytest.raises(N.DgsweError, match="EINVAL"):
+        p1.set_variant(2)
+    b = dg.Solver.from_scenario(sc, precision="fp32")
+    b.step(5)
+    w = b.state()
+    v, ms = b.autotune(2)
+    assert v in (0, 1, 2) and ms[6] > 0.0 and ms[0] > 0.0 and ms[5] > 0.0
+    assert np.array_equal(b.state(), w)
+    c64.close(); p1.close(); b.close()
