@@ -251,25 +251,42 @@ def roofline(res, precision, p, limiter, workload=None):
     return out
 
 
-def run_ensemble(n_members=64, t_sim=120.0, chunk=10, autotune=True):
-    """64 members (sizes log-uniform in [1e4, 5e5] triangles, even members
-    p = 1, odd members p = 2, FP32), each simulating t_sim seconds, stepped
-    together by one batch: every launch covers all active members of a
-    scheme.  Latency = completion time of a member from the batch start."""
+def _ensemble_members(n_members, t_sim, policy):
+    """The ensemble's members, FP32, with their stage-kernel configuration
+    chosen by ``policy``: "member" autotunes every member on its own mesh;
+    "degree" autotunes the largest member of each degree and gives its
+    choice to the others, so that each degree is one launch group."""
     import math
     import meshgen
-    from paper_2307_14302_amd import Batch, Solver
-    t0 = time.perf_counter()
+    from paper_2307_14302_amd import Solver
     members = []
     for i, n_tri, p in meshgen.ensemble_plan(n_members):
         sc = meshgen.basin_member(4, i, n_tri, p=p)
         s = Solver.from_scenario(sc, precision="fp32")
-        if autotune:
+        if policy == "member":
             s.autotune(3)
         dt0 = s.mass()["dt_next"]
         members.append((s, int(math.ceil(t_sim / dt0)), int(sc.params["rk_stages"]), p))
-    log(f"[ensemble] {len(members)} members, {sum(m[0].n_tri for m in members)} triangles, set-up "
-        f"{time.perf_counter() - t0:.1f}s")
+    if policy == "degree":
+        for p in sorted({m[3] for m in members}):
+            group = [m[0] for m in members if m[3] == p]
+            ref = max(group, key=lambda s: s.n_tri)
+            ref.autotune(3)
+            for s in group:
+                s.set_variant(ref.variant())
+                s.set_fused(ref.fused())
+                s.set_tile(ref.tile())
+    return members
+
+
+def _launch_groups(members):
+    """Launch groups of a batch: members that share degree, scheme and kernel
+    configuration run in the same launches."""
+    return len({(p, st, s.variant(), s.fused(), s.tile()) for s, _, st, p in members})
+
+
+def _run_batch(members, chunk):
+    from paper_2307_14302_amd import Batch
     b = Batch({"precision": "fp32"})
     slots = {b.add(s, n): k for k, (s, n, _, _) in enumerate(members)}
     b.step(0)                                   # builds the member tables
@@ -282,29 +299,62 @@ def run_ensemble(n_members=64, t_sim=120.0, chunk=10, autotune=True):
         for sl in b.poll():
             done_at.setdefault(sl, now)
     el = time.perf_counter() - t0
+    lat = np.array([done_at[sl] for sl in slots])
+    for sl in list(slots):
+        b.retire(sl)
+    b.close()
+    return el, lat
+
+
+def run_ensemble(n_members=64, t_sim=120.0, chunk=10):
+    """64 members (sizes log-uniform in [1e4, 5e5] triangles, even members
+    p = 1, odd members p = 2, FP32), each simulating t_sim seconds, stepped
+    together by one batch: every launch covers all active members of one
+    launch group (degree, scheme, kernel configuration).  Latency =
+    completion time of a member from the batch start.  Run twice: kernel
+    configuration autotuned per degree (one launch group per degree: the
+    reported value), and per member, which prices the extra launch groups."""
+    t0 = time.perf_counter()
+    members = _ensemble_members(n_members, t_sim, "degree")
+    log(f"[ensemble] {len(members)} members, {sum(m[0].n_tri for m in members)} triangles, set-up "
+        f"{time.perf_counter() - t0:.1f}s (one kernel configuration per degree)")
+    groups = _launch_groups(members)
+    el, lat = _run_batch(members, chunk)
     work = sum(s.n_tri * st * n for s, n, st, _ in members)
     # algorithmic bytes of every member's steps (each array streamed once
     # per launch, as for the single-mesh roofline), over the batch's time
     byts = sum(step_bytes(s.n_tri, s.n_nodes, 4, p, st, True, bool(s.fused())) * n for s, n, st, p in members)
-    lat = np.array([done_at[sl] for sl in slots])
     out = {"value": round(work / el, 1), "unit": "element-stage updates/s", "members": len(members),
            "n_tri_total": int(sum(s.n_tri for s, _, _, _ in members)),
            "p_mix": {"p1": sum(1 for m in members if m[3] == 1), "p2": sum(1 for m in members if m[3] == 2)},
            "t_sim_s": t_sim, "steps_min": int(min(m[1] for m in members)), "steps_max": int(max(m[1] for m in members)),
            "stage_variants": {"per_element": sum(1 for m in members if m[0].variant() == 0),
                               "per_edge": sum(1 for m in members if m[0].variant() == 1)},
+           "stage_tiles": {str(t): sum(1 for m in members if m[0].tile() == t) for t in (64, 128, 256, 512)},
            "fused_members": sum(1 for m in members if m[0].fused()),
+           "launch_groups": groups,
            "wall_s": round(el, 3), "p50_latency_s": round(float(np.percentile(lat, 50)), 4),
            "p99_latency_s": round(float(np.percentile(lat, 99)), 4), "dtype": "f32",
            "roofline": {"bound": "hbm", "achieved": round(byts / el / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": round(byts / el / 1e9 / HBM_PEAK_GBS, 4), "bytes": int(byts),
                         "basis": "algorithmic bytes of every launch of every member step (bench.step_bytes) "
                                  "over the batch's wall time"}}
-    log(f"[ensemble] {work:.3e} element-stages in {el:.2f}s -> {work / el:.4e}/s; latency p50 "
-        f"{out['p50_latency_s']}s p99 {out['p99_latency_s']}s")
-    for sl in list(slots):
-        b.retire(sl)
-    b.close()
+    log(f"[ensemble] {work:.3e} element-stages in {el:.2f}s -> {work / el:.4e}/s with {groups} launch groups; "
+        f"latency p50 {out['p50_latency_s']}s p99 {out['p99_latency_s']}s")
+    for s, _, _, _ in members:
+        s.close()
+    # the same ensemble with the kernel configuration autotuned per member
+    members = _ensemble_members(n_members, t_sim, "member")
+    g2 = _launch_groups(members)
+    el2, lat2 = _run_batch(members, chunk)
+    work2 = sum(s.n_tri * st * n for s, n, st, _ in members)
+    out["per_member_config"] = {"value": round(work2 / el2, 1), "launch_groups": g2, "wall_s": round(el2, 3),
+                                "p50_latency_s": round(float(np.percentile(lat2, 50)), 4),
+                                "p99_latency_s": round(float(np.percentile(lat2, 99)), 4),
+                                "note": "every member autotuned on its own mesh; members whose choices differ "
+                                        "run in separate launches"}
+    log(f"[ensemble/per-member] {work2 / el2:.4e}/s with {g2} launch groups; latency p50 "
+        f"{out['per_member_config']['p50_latency_s']}s p99 {out['per_member_config']['p99_latency_s']}s")
     for s, _, _, _ in members:
         s.close()
     return out
