@@ -297,11 +297,16 @@ struct dgswe_batch {
   };
   std::vector<Group> groups;
   DevBuf memb;
+  std::vector<int> member_slot;     // member index (as in memb) -> slot
+  DevBuf flags;                     // [members] active flags gathered by dgswe_batch_poll
+  int* flags_host = nullptr;        // pinned copy of flags
+  size_t flags_cap = 0;
   hipGraphExec_t graph = nullptr;   // one step of every group, replayed
   bool graph_dirty = true;
   ~dgswe_batch() {
     if (stream) (void)hipStreamSynchronize(stream);
     if (graph) (void)hipGraphExecDestroy(graph);
+    if (flags_host) (void)hipHostFree(flags_host);
     if (own_stream && stream) (void)hipStreamDestroy(stream);
   }
 };
@@ -1519,11 +1524,13 @@ int batch_rebuild_t(dgswe_batch* b) {
   std::vector<Member<Real>> ms;
   std::map<std::tuple<int, int, int, int, int, int, int>, int> gi;
   b->groups.clear();
+  b->member_slot.clear();
   for (size_t i = 0; i < b->slots.size(); ++i) {
     const auto& sl = b->slots[i];
     if (!sl.live) continue;
     const int idx = int(ms.size());
     ms.push_back(member_struct<Real>(sl.ctx));
+    b->member_slot.push_back(int(i));
     const dgswe_params& p = sl.ctx->prm;
     auto key = std::make_tuple(p.p, p.flux, p.limiter, p.rk_stages, sl.ctx->variant, sl.ctx->use_fused() ? 1 : 0,
                                sl.ctx->stage_tile());
@@ -1575,9 +1582,12 @@ int batch_rebuild_t(dgswe_batch* b) {
   return DGSWE_OK;
 }
 
+// New member tables (and so a new step graph) for the live slots.
 int batch_rebuild(dgswe_batch* b) {
   HIPCHK(hipStreamSynchronize(b->stream));
-  return b->prm.precision == DGSWE_FP32 ? batch_rebuild_t<float>(b) : batch_rebuild_t<double>(b);
+  const int rc = b->prm.precision == DGSWE_FP32 ? batch_rebuild_t<float>(b) : batch_rebuild_t<double>(b);
+  if (!rc) b->graph_dirty = true;
+  return rc;
 }
 
 int64_t batch_footprint(const dgswe_batch* b) {
@@ -1702,7 +1712,6 @@ int dgswe_batch_step(dgswe_batch* b, int64_t max_steps) {
   if (b->dirty) {
     int rc = batch_rebuild(b);
     if (rc) return rc;
-    b->graph_dirty = true;
   }
   if (b->groups.empty()) return DGSWE_OK;
   const bool use_graph = max_steps >= 2;
@@ -1723,18 +1732,35 @@ int dgswe_batch_step(dgswe_batch* b, int64_t max_steps) {
 
 int dgswe_batch_poll(dgswe_batch* b, int32_t* done_slots, int32_t cap, int32_t* n_done) {
   if (!b || !n_done) return fail(DGSWE_EINVAL, "null argument");
-  HIPCHK(hipStreamSynchronize(b->stream));
+  // the member table must list the live slots: rebuild it after a change
+  if (b->dirty) {
+    int rc = batch_rebuild(b);
+    if (rc) return rc;
+  }
+  const size_t nm = b->member_slot.size();
   int32_t n = 0;
-  for (size_t i = 0; i < b->slots.size(); ++i) {
-    const auto& sl = b->slots[i];
-    if (!sl.live) continue;
-    Scalars s;
-    HIPCHK(hipMemcpy(&s, sl.ctx->sc.p, sizeof s, hipMemcpyDeviceToHost));
-    if (!s.active) {
-      if (done_slots && n < cap) done_slots[n] = int32_t(i);
+  if (nm > 0) {
+    // every member's active flag in one small kernel and one copy
+    if (nm > b->flags_cap) {
+      if (b->flags_host) HIPCHK(hipHostFree(b->flags_host));
+      b->flags_host = nullptr;
+      b->flags_cap = 0;
+      HIPCHK(b->flags.alloc(nm * sizeof(int)));
+      HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&b->flags_host), nm * sizeof(int), hipHostMallocDefault));
+      b->flags_cap = nm;
+    }
+    if (b->prm.precision == DGSWE_FP32)
+      HIPCHK(launch_active_flags<float>(b->memb.as<Member<float>>(), int(nm), b->flags.as<int>(), b->stream));
+    else
+      HIPCHK(launch_active_flags<double>(b->memb.as<Member<double>>(), int(nm), b->flags.as<int>(), b->stream));
+    HIPCHK(hipMemcpyAsync(b->flags_host, b->flags.p, nm * sizeof(int), hipMemcpyDeviceToHost, b->stream));
+  }
+  HIPCHK(hipStreamSynchronize(b->stream));
+  for (size_t m = 0; m < nm; ++m)
+    if (!b->flags_host[m]) {
+      if (done_slots && n < cap) done_slots[n] = int32_t(b->member_slot[m]);
       ++n;
     }
-  }
   *n_done = n;
   return DGSWE_OK;
 }

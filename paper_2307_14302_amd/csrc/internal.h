@@ -179,5 +179,8 @@ hipError_t launch_reduce(const Member<Real>* d_members, const int* d_member_ids,
                          int init, const RKInfo& rk, hipStream_t s, double* part_over = nullptr);
 // zero n doubles at p (a kernel, so that it can sit in a captured graph)
 hipError_t launch_fill_zero(double* p, int n, hipStream_t s);
+// out[i] = active flag of member i, i < n
+template <typename Real>
+hipError_t launch_active_flags(const Member<Real>* d_members, int n, int* out, hipStream_t s);
 
 }  // namespace dg

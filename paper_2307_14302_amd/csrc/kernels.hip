@@ -2622,6 +2622,22 @@ hipError_t launch_fill_zero(double* p, int n, hipStream_t s) {
   return hipGetLastError();
 }
 
+// Active flags of the members of a batch, gathered into one array so the
+// host reads them in one copy.
+template <typename Real>
+__global__ __launch_bounds__(256) void active_flags_kernel(const Member<Real>* __restrict__ mem, int n,
+                                                           int* __restrict__ out) {
+  const int i = int(blockIdx.x) * 256 + int(threadIdx.x);
+  if (i < n) out[i] = gp((const Scalars*)mem[i].sc)->active;
+}
+
+template <typename Real>
+hipError_t launch_active_flags(const Member<Real>* m, int n, int* out, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL((active_flags_kernel<Real>), dim3((n + 255) / 256), dim3(256), 0, s, m, n, out);
+  return hipGetLastError();
+}
+
 #define DG_INST(R)                                                                                              \
   template hipError_t launch_stage<R>(int, int, int, int, const Member<R>*, const Tile*, int, StageArgs, hipStream_t, \
                                       hipEvent_t, hipEvent_t, int, int);                                    \
@@ -2629,7 +2645,8 @@ hipError_t launch_fill_zero(double* p, int n, hipStream_t s) {
   template hipError_t launch_classify<R>(int, const Member<R>*, const Tile*, int, hipStream_t);                   \
   template hipError_t launch_rain<R>(const Member<R>*, const Tile*, int, int, const Tile*, int, hipStream_t, int); \
   template hipError_t launch_reduce<R>(const Member<R>*, const int*, int, int, int, const RKInfo&, hipStream_t,  \
-                                       double*);
+                                       double*);                                                              \
+  template hipError_t launch_active_flags<R>(const Member<R>*, int, int*, hipStream_t);
 DG_INST(float)
 DG_INST(double)
 

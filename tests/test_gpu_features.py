@@ -292,6 +292,49 @@ def test_batch_members_match_alone_bitwise(dg):
         m.close()
 
 
+def test_batch_poll_across_membership_changes_with_graph_steps(dg):
+    """Poll right after members join (the member tables are rebuilt by the
+    poll), graph-replayed steps after each change, a member joining while
+    others run: every member still ends bit for bit as it does alone, and
+    poll reports finished members by slot."""
+    scs = [meshgen.small_mixed(seed=41, nx=16, ny=8, rain_kind="gridded"),
+           meshgen.small_mixed(seed=42, nx=14, ny=8, p=2, flux="llf", limiter=True, rain_kind="parametric"),
+           meshgen.basin_window(30, seed=meshgen.seed_for(3, 5))]
+    steps = [12, 20, 28]
+    alone = []
+    for sc, n in zip(scs, steps):
+        s = _member(dg, sc)
+        s.step(n)
+        alone.append((s.state(), s.mass()))
+        s.close()
+    members = [_member(dg, sc) for sc in scs]
+    b = dg.Batch({"precision": "fp32"})
+    s0 = b.add(members[0], steps[0])
+    s1 = b.add(members[1], steps[1])
+    assert b.poll() == []
+    b.step(8)
+    s2 = b.add(members[2], steps[2])
+    assert b.poll() == []
+    b.step(8)
+    assert b.poll() == [s0]                     # 16 steps offered, its target is 12
+    finished = []
+    for _ in range(20):
+        b.step(4)
+        finished = b.poll()
+        if len(finished) == 3:
+            break
+    assert finished == sorted([s0, s1, s2])
+    for m, (w, mass) in zip(members, alone):
+        assert np.array_equal(m.state(), w)
+        assert m.mass() == mass
+    for sl in (s0, s1, s2):
+        b.retire(sl)
+    assert b.poll() == []
+    b.close()
+    for m in members:
+        m.close()
+
+
 def test_batch_admission_budget(dg):
     from paper_2307_14302_amd import _native as N
     sc = meshgen.basin_window(40)
