@@ -47,7 +47,10 @@ int build_mesh(int64_t n_nodes, const double* xy, const double* hb, const double
   char buf[256];
   if (n_nodes < 0 || n_tri < 0 || n_bedges < 0) { err = "negative size"; return -1; }
   if (n_tri > (int64_t(1) << 30)) { err = "too many triangles"; return -1; }
-  if (n_tri > 0 && (!xy || !hb || !fric || !tri_in)) { err = "null array"; return -1; }
+  if ((n_nodes > 0 && (!xy || !hb || !fric)) || (n_tri > 0 && !tri_in) || (n_bedges > 0 && !bnodes)) {
+    err = "null array";
+    return -1;
+  }
   for (int64_t i = 0; i < n_nodes; ++i) {
     if (!std::isfinite(xy[2 * i]) || !std::isfinite(xy[2 * i + 1]) || !std::isfinite(hb[i]) ||
         !std::isfinite(fric[i]) || fric[i] < 0.0) {
