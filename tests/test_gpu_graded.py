@@ -69,3 +69,29 @@ def test_graded_full_size_properties(dg, full_size):
     print("graded full fp32 vs fp64", err, flush=True)
     assert err.max() < 1e-4
     assert abs(res["fp32"][1]["t"] - res["fp64"][1]["t"]) < 1e-5 * res["fp64"][1]["t"]
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-11), ("fp32", 5e-5)])
+def test_graded_full_size_one_step_against_oracle(dg, full_size, precision, tol):
+    """The full 3,596,698-triangle graded coast in the launch configuration
+    the bench times (autotuned stage kernel): 30 GPU steps, then one more
+    step on the GPU and in the oracle from the GPU's state, every element
+    compared."""
+    sc = full_size
+    gpu = dg.Solver.from_scenario(sc, precision=precision)
+    variant, _ = gpu.autotune(2)
+    gpu.step(30)
+    w = gpu.state()
+    m0 = gpu.mass()
+    orc = from_scenario(sc)
+    orc.set_state(w, m0["t"], post=False)
+    orc.dt = m0["dt_next"]
+    gpu.step(1)
+    orc.step(1)
+    err = rel_l2(gpu.state(), orc.w, orc)
+    print(precision, f"graded full one step from the GPU state (variant {variant}, tile {gpu.tile()}): rel L2",
+          err, flush=True)
+    assert err.max() < tol, err
+    m1 = gpu.mass()
+    assert abs(m1["t"] - (m0["t"] + m0["dt_next"])) <= 1e-12 * m1["t"]
+    gpu.close()
