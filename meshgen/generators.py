@@ -396,14 +396,14 @@ def lake_at_rest(seed: int = 3, nx: int = 16, ny: int = 10, level: float = 0.7,
 # textbook checks: dam breaks on a strip, rain on an inclined plane
 # ---------------------------------------------------------------------------
 def dam_break(nx: int = 200, *, h_left: float = 2.0, h_right: float = 1.0, L: float = 200.0,
-              W: float = 2.0, H0: float = 1e-3, limiter: bool = True) -> Scenario:
-    """Quasi-1D strip x in (-L/2, L/2), nx x 1 quads, flat bed at the datum
+              W: float = 2.0, H0: float = 1e-3, limiter: bool = True, ny: int = 1) -> Scenario:
+    """Quasi-1D strip x in (-L/2, L/2), nx x ny quads, flat bed at the datum
     (hb = 0), walls all round, fluid at rest with depth h_left for x < 0 and
     h_right for x > 0 (h_right = 0 is a dry bed).  No friction, no rain.
     The nodal zeta0 puts the nodes on x = 0 on the right; a piecewise
     constant start (element means h_left / h_right, the dam on the quad
     boundary at x = 0 for even nx) is set from the element centroids."""
-    xy, tri, sides = rect_grid(nx, 1, L, W, x0=-L / 2)
+    xy, tri, sides = rect_grid(nx, ny, L, W, x0=-L / 2)
     be, bt, bs = _bnd(sides, {})
     hb = np.zeros(len(xy))
     mesh = Mesh(xy, tri, hb, np.zeros(len(hb)), be, bt, bs)
