@@ -335,6 +335,55 @@ def test_batch_poll_across_membership_changes_with_graph_steps(dg):
         m.close()
 
 
+def test_batch_members_with_mixed_stage_kernels_match_alone(dg):
+    """Members whose stage kernels differ (tiles of 64, 128, 256 and 512
+    elements, and a p = 3 member with the matrix-core area integrals) run in
+    separate launch groups of one batch step, and each ends bit for bit as
+    it does alone."""
+    scs = [meshgen.small_mixed(seed=51, nx=20, ny=10, rain_kind="gridded"),
+           meshgen.basin_window(34, seed=meshgen.seed_for(3, 7)),
+           meshgen.small_mixed(seed=52, nx=16, ny=8, p=2, flux="llf", limiter=True, rain_kind="parametric"),
+           meshgen.small_mixed(seed=53, nx=18, ny=9, rain_kind="nodal"),
+           meshgen.small_mixed(seed=54, nx=12, ny=6, p=3, flux="llf", limiter=True, rain_kind="parametric")]
+    kernels = [(1, 64), (1, 128), (1, 64), (1, 512), (2, 64)]
+    steps = [15, 20, 12, 18, 10]
+
+    def configure(s, k):
+        variant, tile = k
+        s.set_variant(variant)
+        if variant == 1:
+            s.set_tile(tile)
+        assert s.variant() == variant and s.tile() == tile
+
+    alone = []
+    for sc, k, n in zip(scs, kernels, steps):
+        s = _member(dg, sc)
+        configure(s, k)
+        s.step(n)
+        alone.append((s.state(), s.mass()))
+        s.close()
+    members = [_member(dg, sc) for sc in scs]
+    for s, k in zip(members, kernels):
+        configure(s, k)
+    b = dg.Batch({"precision": "fp32"})
+    slots = [b.add(m, n) for m, n in zip(members, steps)]
+    done = []
+    for _ in range(30):
+        b.step(2)
+        done = b.poll()
+        if len(done) == len(slots):
+            break
+    assert sorted(done) == sorted(slots)
+    for m, (w, mass) in zip(members, alone):
+        assert np.array_equal(m.state(), w)
+        assert m.mass() == mass
+    for sl in slots:
+        b.retire(sl)
+    b.close()
+    for m in members:
+        m.close()
+
+
 def test_batch_admission_budget(dg):
     from paper_2307_14302_amd import _native as N
     sc = meshgen.basin_window(40)

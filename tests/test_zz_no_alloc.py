@@ -21,8 +21,9 @@ def dg():
     return pkg
 
 
+@pytest.mark.parametrize("tile", [256, 64])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-def test_noalloc_step_equals_step(dg, precision):
+def test_noalloc_step_equals_step(dg, precision, tile):
     from paper_2307_14302_amd import _native as N
     cases = [(meshgen.basin_window(40), 30),                                              # limiter on
              (meshgen.small_mixed(seed=9, nx=12, ny=6, rain_kind="gridded"), 20)]          # smaller, no limiter
@@ -30,6 +31,9 @@ def test_noalloc_step_equals_step(dg, precision):
         print(f"{precision} {sc.name} E={sc.mesh.n_tri} limiter={sc.params['limiter']} {n} steps", flush=True)
         a = dg.Solver.from_scenario(sc, precision=precision)
         b = dg.Solver.from_scenario(sc, precision=precision)
+        for s in (a, b):
+            s.set_variant(1)
+            s.set_tile(tile)
         a.step(n)
         N.call("dgswe_step_noalloc", b.h, n)
         assert np.array_equal(a.state(), b.state())
