@@ -588,6 +588,8 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=100, help="requests of the 400-request trace to serve")
     ap.add_argument("--graded-only", action="store_true",
                     help="run only the 3.6M-triangle graded leg (--steps steps) and print its JSON (for profiling)")
+    ap.add_argument("--ensemble-only", action="store_true",
+                    help="run only the 64-member ensemble leg and print its JSON (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the library drives one GPU per process and has no multi-GPU "
@@ -598,6 +600,9 @@ def main():
     torch.cuda.set_device(0)
     if args.graded_only:
         print(json.dumps(run_graded(steps=args.steps, warmup=args.warmup)), flush=True)
+        return
+    if args.ensemble_only:
+        print(json.dumps(run_ensemble()), flush=True)
         return
     t0 = time.perf_counter()
     sc = meshgen.basin(args.N, p=args.p)
