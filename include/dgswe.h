@@ -323,8 +323,8 @@ int dgswe_kernel_stats(dgswe_ctx* ctx, const char* kernel, int64_t* launches, do
  * larger tile evaluates fewer cut edges twice; a smaller one lets more
  * independent workgroups share a CU, with fewer wavefronts waiting at each
  * barrier.  Results do not depend on it (partials are kept per wavefront).
- * It reads back 256 where it does not apply (variant 0, 512 at p > 1); a
- * tile other than 256 turns the fused form off.  dgswe_autotune times
+ * It reads back 256 where it does not apply (variant 0, 512 at p > 1) and
+ * 64 under variant 2; a tile other than 256 turns the fused form off.  dgswe_autotune times
  * every applicable choice.  EINVAL for unknown keys or values; ESTATE
  * while the context is in a batch. */
 #define DGSWE_TUNE_STAGE_VARIANT 1
