@@ -171,7 +171,15 @@ template <int P> struct B {
   DG_HD static double EG(int k, int g, int m) { return phi_(m, er_(k, gl_t(P, g)), es_(k, gl_t(P, g))); }
 };
 
+// a b + c rounded once
+template <typename Real>
+DG_DEV Real fmac(Real a, Real b, Real c) {
+  if constexpr (sizeof(Real) == 4) return __builtin_fmaf(a, b, c);
+  else return __builtin_fma(a, b, c);
+}
+
 // point values at the three vertices and (p = 2) the three edge midpoints
+// (fused multiply-adds written out, so that every call site rounds alike)
 template <typename Real, int P>
 DG_DEV void edge_nodes(const Real (&w)[3][Tab<P>::NP], Real (&vv)[3][3], Real (&mv)[3][3]) {
   constexpr int NP = Tab<P>::NP;
@@ -179,14 +187,14 @@ DG_DEV void edge_nodes(const Real (&w)[3][Tab<P>::NP], Real (&vv)[3][3], Real (&
   for (int v = 0; v < 3; ++v)
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-      Real s = Real(0), t = Real(0);
+      Real s = Real(B<P>::V(i, 0)) * w[v][0], t = Real(B<P>::M(i, 0)) * w[v][0];
 #pragma unroll
-      for (int m = 0; m < NP; ++m) {
-        s += Real(B<P>::V(i, m)) * w[v][m];
-        if (P >= 2) t += Real(B<P>::M(i, m)) * w[v][m];
+      for (int m = 1; m < NP; ++m) {
+        s = fmac(Real(B<P>::V(i, m)), w[v][m], s);
+        if (P >= 2) t = fmac(Real(B<P>::M(i, m)), w[v][m], t);
       }
       vv[v][i] = s;
-      mv[v][i] = t;
+      mv[v][i] = P >= 2 ? t : Real(0);
     }
 }
 
@@ -223,13 +231,16 @@ DG_DEV Real trace_modal(const Real (&w)[Tab<P>::NP], int k) {
 
 // trace along an edge from its start-vertex value a, midpoint value c
 // (p = 2) and end-vertex value b, at the edge's Gauss point g (p <= 2: the
-// trace is the 1-D interpolant of those point values)
+// trace is the 1-D interpolant of those point values).  The fused
+// multiply-adds are written out so that every call site rounds alike: the
+// traces of an element's own edges and those of a neighbour in another
+// tile are formed in different places, and must agree to the bit.
 template <typename Real, int P>
 DG_DEV Real trace(Real a, Real c, Real b, int g) {
   static_assert(P <= 2, "point-value traces are exact for p <= 2 only");
   const double t = gl_t(P, g);
-  if (P == 1) return Real(lag_(1, 0, t)) * a + Real(lag_(1, 1, t)) * b;
-  return Real(lag_(2, 0, t)) * a + Real(lag_(2, 1, t)) * c + Real(lag_(2, 2, t)) * b;
+  if (P == 1) return fmac(Real(lag_(1, 1, t)), b, Real(lag_(1, 0, t)) * a);
+  return fmac(Real(lag_(2, 2, t)), b, fmac(Real(lag_(2, 1, t)), c, Real(lag_(2, 0, t)) * a));
 }
 
 // Positive-depth operator (Sec. 2.4) on one element, FP64 decisions.
@@ -1360,18 +1371,22 @@ __global__ DG_STAGE_ATTR_T(T) void stage_edge_kernel(const Member<Real>* __restr
   static_assert(!MF || (P == 3 && sizeof(Real) == 4 && T == 64 && !PRE), "matrix-core area integrals: p = 3, FP32, T = 64");
   constexpr int NW = T / 64;                            // wavefronts per workgroup
   constexpr int LB = T == 512 ? 9 : T == 256 ? 8 : T == 128 ? 7 : 6;   // bits of a local element index in an edge entry
-  // point values per variable (vertices, midpoints); p = 3 keeps its traces
-  // in s_flux instead (each slot holds the element's own trace at that edge
-  // point until phase B overwrites it with the flux there)
+  // point values per variable (vertices, midpoints); p = 3, and p = 2 but
+  // in the fused kernel, keep their traces in s_flux instead (each slot holds
+  // the element's own trace at that edge point until phase B overwrites it
+  // with the flux there), which leaves the flux slots as the only per-point
+  // LDS array
+  constexpr bool kTr = P == 3 || (P == 2 && !PRE);
   constexpr int NN = P == 1 ? 3 : P == 2 ? 6 : 1;
   constexpr int SL = T + (PRE ? HALO_R1 : 0);      // point-value slots: tile, then ring 1
-  __shared__ Real s_node[3 * NN][SL];
+  __shared__ Real s_node[kTr ? 1 : 3 * NN][SL];
   __shared__ Real s_hb[3][SL];
   __shared__ Real s_flux[3 * NG * 3][T];            // [(k NG + g) 3 + var][element], scaled by (l/2) w_g
-  // edge vectors in LDS, except for FP32 p = 2 and the fused kernel, where
-  // dropping them (phase B reads them from the cache instead) lets one more
-  // workgroup share a CU
-  constexpr bool kEvLds = !PRE && !(P == 2 && sizeof(Real) == 4);
+  // edge vectors in LDS, except for FP32 p = 2, FP64 p = 3 on 64-element
+  // tiles and the fused kernel, where dropping them (phase B reads them from
+  // the cache instead) lets more workgroups share a CU (FP64 p = 3: eight
+  // instead of six, with the 16-bit edge list below)
+  constexpr bool kEvLds = !PRE && !(P == 2 && sizeof(Real) == 4) && !(P == 3 && sizeof(Real) == 8 && T == 64);
   __shared__ Real s_ev[kEvLds ? 6 : 1][kEvLds ? T : 1];
   __shared__ uint8_t s_flag[SL];
   // PRE: raw means and fully-wet bytes of tile, ring 1 and ring 2, in the
@@ -1381,8 +1396,10 @@ __global__ DG_STAGE_ATTR_T(T) void stage_edge_kernel(const Member<Real>* __restr
   Real* const s_mean = reinterpret_cast<Real*>(&s_flux[0][0]);
   uint8_t* const s_fw = reinterpret_cast<uint8_t*>(s_mean + 3 * SM);
   // edge list
-  __shared__ double s_lbuf[3 * T / 2];
-  uint32_t* s_list = reinterpret_cast<uint32_t*>(s_lbuf);
+  // (16-bit entries on 64-element tiles: 6 + 2 + 2 + 6 bits)
+  using ListT = std::conditional_t<T == 64, uint16_t, uint32_t>;
+  __shared__ double s_lbuf[3 * T * sizeof(ListT) / 8];
+  ListT* s_list = reinterpret_cast<ListT*>(s_lbuf);
   __shared__ int s_wsum[2][NW];
   const int ti = xcd_tile();
   if (ti >= n_tiles) return;
@@ -1493,7 +1510,19 @@ __global__ DG_STAGE_ATTR_T(T) void stage_edge_kernel(const Member<Real>* __restr
   }
   Real mtx[3] = {Real(0), Real(0), Real(0)}, mty[3] = {Real(0), Real(0), Real(0)}, mps[3] = {Real(0), Real(0), Real(0)};
   if (kMetEarly && met_on) met_nodes<Real>(M, tn, mtx, mty, mps);
-  if constexpr (P <= 2) {
+  if constexpr (P == 2 && kTr) {
+    // the same point-value interpolant as the fused kernel's phase B, so
+    // both give the same bits
+    Real vv[3][3], mv[3][3];
+    edge_nodes<Real, P>(d.w, vv, mv);
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+      for (int gg = 0; gg < NG; ++gg)
+#pragma unroll
+        for (int v = 0; v < 3; ++v)
+          s_flux[(k * NG + gg) * 3 + v][el] = trace<Real, P>(vv[v][k], mv[v][k], vv[v][k == 2 ? 0 : k + 1], gg);
+  } else if constexpr (P <= 2) {
     Real vv[3][3], mv[3][3];
     edge_nodes<Real, P>(d.w, vv, mv);
 #pragma unroll
@@ -1598,7 +1627,7 @@ __global__ DG_STAGE_ATTR_T(T) void stage_edge_kernel(const Member<Real>* __restr
       const int c = cls[k];
       if (c < 3) {
         const int at = c == 0 ? pos[0]++ : c == 1 ? pos[1]++ : pos[2]++;
-        s_list[at] = ent[k];
+        s_list[at] = ListT(ent[k]);
       }
     }
   }
@@ -1612,7 +1641,7 @@ __global__ DG_STAGE_ATTR_T(T) void stage_edge_kernel(const Member<Real>* __restr
   }
 
   // ---- phase B: edge fluxes, scaled by (l/2) w_g, into s_flux
-  if constexpr (P >= 3) {
+  if constexpr (kTr) {
     // traces come from s_flux (own side, and the neighbour's when it is in
     // the tile) or from the neighbour's modes; only the thread of an edge
     // touches that edge's slots, so it reads them all before writing fluxes
@@ -1623,7 +1652,8 @@ __global__ DG_STAGE_ATTR_T(T) void stage_edge_kernel(const Member<Real>* __restr
       const int eg = t0 + l;
       const bool in_tile = it < n0;
       const int nb = in_tile ? t0 + int(ent >> (LB + 4)) : ldc(nbr, k * E, eg);
-      const Real exk = s_ev[2 * k][l], eyk = s_ev[2 * k + 1][l];
+      const Real exk = kEvLds ? s_ev[2 * k][l] : ldc(gp(M.ev), (2 * k) * E, eg);
+      const Real eyk = kEvLds ? s_ev[2 * k + 1][l] : ldc(gp(M.ev), (2 * k + 1) * E, eg);
       Real ell, il;
       edge_length<Real>(exk, eyk, ell, il);
       const Real nx = eyk * il, ny = -exk * il;
@@ -1644,6 +1674,24 @@ __global__ DG_STAGE_ATTR_T(T) void stage_edge_kernel(const Member<Real>* __restr
 #pragma unroll
             for (int v = 0; v < 3; ++v) tN[v][gg] = s_flux[(kn * NG + gg) * 3 + v][ln];
           nflag = s_flag[ln];
+        } else if constexpr (P == 2) {
+          Real wn[3][NP];
+#pragma unroll
+          for (int v = 0; v < 3; ++v)
+#pragma unroll
+            for (int m = 0; m < NP; ++m) wn[v][m] = ldc(Win, (v * NP + m) * E, nb);
+          Real nvv[3][3], nmv[3][3];
+          edge_nodes<Real, P>(wn, nvv, nmv);
+          const int kn1 = kn == 2 ? 0 : kn + 1;
+#pragma unroll
+          for (int v = 0; v < 3; ++v) {
+            const Real Na = kn == 0 ? nvv[v][0] : kn == 1 ? nvv[v][1] : nvv[v][2];
+            const Real Nb = kn1 == 0 ? nvv[v][0] : kn1 == 1 ? nvv[v][1] : nvv[v][2];
+            const Real Nc = kn == 0 ? nmv[v][0] : kn == 1 ? nmv[v][1] : nmv[v][2];
+#pragma unroll
+            for (int gg = 0; gg < NG; ++gg) tN[v][gg] = trace<Real, P>(Na, Nc, Nb, gg);
+          }
+          nflag = ldx(Fin, nb) & 1;
         } else {
 #pragma unroll
           for (int v = 0; v < 3; ++v) {
