@@ -1371,22 +1371,24 @@ __global__ DG_STAGE_ATTR_T(T) void stage_edge_kernel(const Member<Real>* __restr
   static_assert(!MF || (P == 3 && sizeof(Real) == 4 && T == 64 && !PRE), "matrix-core area integrals: p = 3, FP32, T = 64");
   constexpr int NW = T / 64;                            // wavefronts per workgroup
   constexpr int LB = T == 512 ? 9 : T == 256 ? 8 : T == 128 ? 7 : 6;   // bits of a local element index in an edge entry
-  // point values per variable (vertices, midpoints); p = 3, and p = 2 but
-  // in the fused kernel, keep their traces in s_flux instead (each slot holds
-  // the element's own trace at that edge point until phase B overwrites it
-  // with the flux there), which leaves the flux slots as the only per-point
-  // LDS array
-  constexpr bool kTr = P == 3 || (P == 2 && !PRE);
+  // point values per variable (vertices, midpoints); p = 3, p = 2 and FP64
+  // p = 1 (but the fused kernel) keep their traces in s_flux instead (each
+  // slot holds the element's own trace at that edge point until phase B
+  // overwrites it with the flux there), which leaves the flux slots as the
+  // only per-point LDS array (FP32 p = 1 measured faster with the vertex
+  // values, three per variable against six traces)
+  constexpr bool kTr = P == 3 || (P == 2 && !PRE) || (P == 1 && sizeof(Real) == 8 && !PRE);
   constexpr int NN = P == 1 ? 3 : P == 2 ? 6 : 1;
   constexpr int SL = T + (PRE ? HALO_R1 : 0);      // point-value slots: tile, then ring 1
   __shared__ Real s_node[kTr ? 1 : 3 * NN][SL];
   __shared__ Real s_hb[3][SL];
   __shared__ Real s_flux[3 * NG * 3][T];            // [(k NG + g) 3 + var][element], scaled by (l/2) w_g
-  // edge vectors in LDS, except for FP32 p = 2, FP64 p = 3 on 64-element
-  // tiles and the fused kernel, where dropping them (phase B reads them from
-  // the cache instead) lets more workgroups share a CU (FP64 p = 3: eight
-  // instead of six, with the 16-bit edge list below)
-  constexpr bool kEvLds = !PRE && !(P == 2 && sizeof(Real) == 4) && !(P == 3 && sizeof(Real) == 8 && T == 64);
+  // edge vectors in LDS, except for FP32 p = 2, FP64 p = 1 and p = 3 on
+  // 64-element tiles and the fused kernel, where dropping them (phase B
+  // reads them from the cache instead) lets more workgroups share a CU
+  // (FP64 p = 3: eight instead of six, with the 16-bit edge list below;
+  // FP64 p = 1: fourteen, for three wavefronts per SIMD at 164 VGPRs)
+  constexpr bool kEvLds = !PRE && !(P == 2 && sizeof(Real) == 4) && !(P != 2 && sizeof(Real) == 8 && T == 64);
   __shared__ Real s_ev[kEvLds ? 6 : 1][kEvLds ? T : 1];
   __shared__ uint8_t s_flag[SL];
   // PRE: raw means and fully-wet bytes of tile, ring 1 and ring 2, in the
@@ -1510,7 +1512,7 @@ __global__ DG_STAGE_ATTR_T(T) void stage_edge_kernel(const Member<Real>* __restr
   }
   Real mtx[3] = {Real(0), Real(0), Real(0)}, mty[3] = {Real(0), Real(0), Real(0)}, mps[3] = {Real(0), Real(0), Real(0)};
   if (kMetEarly && met_on) met_nodes<Real>(M, tn, mtx, mty, mps);
-  if constexpr (P == 2 && kTr) {
+  if constexpr (P <= 2 && kTr) {
     // the same point-value interpolant as the fused kernel's phase B, so
     // both give the same bits
     Real vv[3][3], mv[3][3];
@@ -1674,7 +1676,7 @@ __global__ DG_STAGE_ATTR_T(T) void stage_edge_kernel(const Member<Real>* __restr
 #pragma unroll
             for (int v = 0; v < 3; ++v) tN[v][gg] = s_flux[(kn * NG + gg) * 3 + v][ln];
           nflag = s_flag[ln];
-        } else if constexpr (P == 2) {
+        } else if constexpr (P <= 2) {
           Real wn[3][NP];
 #pragma unroll
           for (int v = 0; v < 3; ++v)
