@@ -173,15 +173,20 @@ def kernel_sources_hash():
     return h.hexdigest()[:16]
 
 
+COUNTER_SUMMARIES = {"basin1M_p1": "stage_edge_kernel_basin1M_counters.md",
+                     "graded3.6M_p1": "graded_coast3.6M_counters.md"}
+
+
 def counted_traffic(kernel, precision, variant=1, tile=256, workload=None):
     """HBM bytes per launch of ``kernel`` from the committed rocprofv3 counter
-    summary (FETCH_SIZE and WRITE_SIZE scaled by the copy calibration), or
-    None when the summary does not cover this workload and kernel
-    configuration or the kernel sources changed since it was taken.  The
-    summary covers the 1M-triangle p = 1 basin ("basin1M_p1")."""
-    if workload != "basin1M_p1":
+    summary of ``workload`` (FETCH_SIZE and WRITE_SIZE scaled by the copy
+    calibration), or None when no summary covers this workload and kernel
+    configuration or the kernel sources changed since it was taken.
+    Summaries: the 1M-triangle p = 1 basin ("basin1M_p1") and the
+    3.6M-triangle graded coast ("graded3.6M_p1")."""
+    if workload not in COUNTER_SUMMARIES:
         return None
-    path = os.path.join(ROOT, "profiles", "stage_edge_kernel_basin1M_counters.md")
+    path = os.path.join(ROOT, "profiles", COUNTER_SUMMARIES[workload])
     try:
         with open(path) as f:
             line = next(l for l in f if l.startswith("traffic-json:"))
@@ -195,6 +200,18 @@ def counted_traffic(kernel, precision, variant=1, tile=256, workload=None):
     else:
         name = "post_kernel"
     return d["bytes"].get(f"{name}/{precision}")
+
+
+def calib_copy():
+    """A plain 1 GiB device copy, three times: the known byte count that the
+    FETCH_SIZE and WRITE_SIZE counters are scaled by."""
+    import torch
+    a = torch.empty(256 * 1024 * 1024, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    log("calibration copy: 3 x 1 GiB read + 1 GiB written")
 
 
 def stream_ceiling():
@@ -232,10 +249,10 @@ def roofline(res, precision, p, limiter, workload=None):
     out = {"kernel": dom, "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
            "traffic_source": ("FETCH_SIZE and WRITE_SIZE per launch from the committed rocprofv3 summary "
-                              "profiles/stage_edge_kernel_basin1M_counters.md (same kernel sources), scaled by "
+                              f"profiles/{COUNTER_SUMMARIES[workload]} (same kernel sources), scaled by "
                               "its copy calibration; not counted in this run") if traffic else
                              ("null: the committed counter summary is for other kernel sources or another "
-                              "stage tile" if workload == "basin1M_p1" else
+                              "stage tile" if workload in COUNTER_SUMMARIES else
                               "null: no committed counter summary for this workload"),
            "bytes_per_launch": int(byts),
            "avg_us": round(avg_s * 1e6, 2), "launches": n}
@@ -420,20 +437,21 @@ def run_serving(n_req=100, rate=20.0, budget_gib=24.0, chunk=20, light_rate=3.0,
     return res
 
 
-def run_graded(steps=1000, warmup=20):
+def run_graded(steps=1000, warmup=20, variant=-1, fused=-1, tile=-1):
     """The graded coastal workload at full size (3,596,698 triangles, FP32
-    state, FP64 reductions, tidal boundary, river inflow, gridded rain)."""
+    state, FP64 reductions, tidal boundary, river inflow, gridded rain);
+    the stage kernel autotuned unless ``variant`` is given."""
     import meshgen
     t0 = time.perf_counter()
     sc = meshgen.graded_coast()
     log(f"[graded] {sc.mesh.n_tri} triangles generated in {time.perf_counter() - t0:.1f}s")
-    r = run_precision(sc, "fp32", steps, warmup, -1, 2)
+    r = run_precision(sc, "fp32", steps, warmup, variant, 2, fused=fused, tile=tile)
     n, ms = r["stats"]["stage"]
     return {"value": round(r["rate"], 1), "unit": "element-stage updates/s", "n_tri": r["E"], "steps": steps,
             "ms_per_step": round(r["elapsed"] / steps * 1e3, 4), "stage_avg_us": round(ms / max(n, 1) * 1e3, 2),
             "dt_s": r["mass"]["dt_last"], "dtype": "f32", "stage_variant": r["variant"], "fused": r["fused"],
             "stage_tile": r["tile"],
-            "roofline": roofline(r, "fp32", 1, True),
+            "roofline": roofline(r, "fp32", 1, True, "graded3.6M_p1"),
             "workload": "graded coast 30 m - 15.36 km, 1229 x 922 km, tides, 3 rivers, gridded rain, LLF, limiter"}
 
 
@@ -603,7 +621,11 @@ def main():
     import meshgen
     torch.cuda.set_device(0)
     if args.graded_only:
-        print(json.dumps(run_graded(steps=args.steps, warmup=args.warmup)), flush=True)
+        out = run_graded(steps=args.steps, warmup=args.warmup, variant=args.variant, fused=args.fused,
+                         tile=args.tile)
+        if args.calib_copy:
+            calib_copy()
+        print(json.dumps(out), flush=True)
         return
     if args.ensemble_only:
         print(json.dumps(run_ensemble()), flush=True)
@@ -623,12 +645,7 @@ def main():
                                                       and args.p == 1) else None, fused=args.fused,
                                   tile=args.tile)
     if args.calib_copy:
-        a = torch.empty(256 * 1024 * 1024, dtype=torch.float32, device="cuda")
-        b = torch.empty_like(a)
-        for _ in range(3):
-            b.copy_(a)
-        torch.cuda.synchronize()
-        log("calibration copy: 3 x 1 GiB read + 1 GiB written")
+        calib_copy()
     ceiling = stream_ceiling()
     main_prec = "fp32" if "fp32" in res else "fp64"
     basin_key = "basin1M_p1" if args.N == 708 and args.p == 1 else None
