@@ -753,10 +753,12 @@ DG_DEV void area_point(const Real (&wq)[3], Real hq, Real dhx, Real dhy, Real cx
   const Real Fy[3] = {wq[2], wq[1] * vv_, wq[2] * vv_ + Pq};
   s1 = g * wq[0] * dhx - tau * wq[1];
   s2 = g * wq[0] * dhy - tau * wq[2];
+  // the weight goes into the four mapping coefficients once
+  const Real ax = Wq * cx0, ay = Wq * cy0, bx = Wq * cx1, by = Wq * cy1;
 #pragma unroll
   for (int v = 0; v < 3; ++v) {
-    Gr[v] = Wq * (cx0 * Fx[v] + cy0 * Fy[v]);
-    Gs[v] = Wq * (cx1 * Fx[v] + cy1 * Fy[v]);
+    Gr[v] = ax * Fx[v] + ay * Fy[v];
+    Gs[v] = bx * Fx[v] + by * Fy[v];
   }
 }
 
@@ -789,16 +791,18 @@ DG_DEV void area_terms_table(const Real (&w)[3][Tab<P>::NP], const Real (&hb)[3]
     const Real wdet = Wq * detJ;
     Real Gr[3], Gs[3], s1, s2;
     area_point<Real>(wq, hq, dhx, dhy, cx0, cx1, cy0, cy1, fc, gn2, friction, g, H0, Wq, Gr, Gs, s1, s2);
+    const Real s1w = wdet * s1, s2w = wdet * s2;
 #pragma unroll
     for (int m = 0; m < NP; ++m) {
       if (m > 0) {
         const Real dr = T.QR[q][m], ds = T.QS[q][m];
+        // two fused multiply-adds into the accumulator (written as
+        // acc + (dr Gr + ds Gs) the sum would take a third instruction)
 #pragma unroll
-        for (int v = 0; v < 3; ++v) acc[v][m] += dr * Gr[v] + ds * Gs[v];
+        for (int v = 0; v < 3; ++v) acc[v][m] = fmac(ds, Gs[v], fmac(dr, Gr[v], acc[v][m]));
       }
-      const Real ps = wdet * T.Q[q][m];
-      acc[1][m] += ps * s1;
-      acc[2][m] += ps * s2;
+      acc[1][m] = fmac(T.Q[q][m], s1w, acc[1][m]);
+      acc[2][m] = fmac(T.Q[q][m], s2w, acc[2][m]);
     }
   }
 }
