@@ -517,11 +517,14 @@ def test_rain_switching_and_mesh_sharing(dg):
 
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-11), ("fp32", 2e-5)])
 def test_full_size_basin_one_step(dg, precision, tol):
-    """The benchmark workload at full size (1,002,528 triangles): 20 GPU
+    """The benchmark workload at full size (1,002,528 triangles) in the
+    launch configuration the bench times (autotuned stage kernel): 20 GPU
     steps, then one more step on the GPU and in the oracle from the same
     state; every element is compared."""
     sc = meshgen.basin(708)
     gpu = dg.Solver.from_scenario(sc, precision=precision)
+    variant, _ = gpu.autotune(2)
+    print(precision, f"autotuned: variant {variant}, tile {gpu.tile()}, fused {gpu.fused()}", flush=True)
     gpu.step(20)
     w = gpu.state()
     m0 = gpu.mass()

@@ -2,15 +2,16 @@
 
 * small mixed basins (every boundary type, wet/dry fronts, limiter or p = 2)
   crossed by a storm vortex over a background wind: one step to 1e-12 and
-  fifty steps to 1e-10 (FP64), both stage-kernel variants; a closed wet
-  basin in FP32 to 1e-4;
+  fifty steps to 1e-10 (FP64), both stage-kernel variants, the per-edge one
+  on 256- and 64-element tiles; a closed wet basin in FP32 to 1e-4;
 * the two discrete equilibria of the oracle pins (inverse barometer under a
   stationary low, wind set-up over a bed of the same slope) stay at rest on
   the GPU;
 * clearing the wind gives back the run without it, bit for bit; bad records
   are refused;
-* the full-size 1M-triangle basin with the storm's wind and pressure: one
-  step from a GPU state, every element against the oracle.
+* the full-size 1M-triangle basin with the storm's wind and pressure, in
+  the autotuned configuration the bench times: one step from a GPU state,
+  every element against the oracle.
 """
 import numpy as np
 import pytest
@@ -38,13 +39,15 @@ CASES = {
 }
 
 
-@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("variant,tile", [(0, 256), (1, 256), (1, 64)])
 @pytest.mark.parametrize("case", list(CASES))
-def test_storm_parity_fp64(dg, case, variant):
+def test_storm_parity_fp64(dg, case, variant, tile):
     sc = meshgen.small_mixed(seed=5, nx=20, ny=10, **CASES[case])
-    print(f"case {case} variant {variant}: E={sc.mesh.n_tri}", flush=True)
+    print(f"case {case} variant {variant} tile {tile}: E={sc.mesh.n_tri}", flush=True)
     gpu = dg.Solver.from_scenario(sc, precision="fp64")
     gpu.set_variant(variant)
+    if variant == 1:
+        gpu.set_tile(tile)
     orc = from_scenario(sc)
     gpu.step(1)
     orc.step(1)
@@ -147,9 +150,13 @@ def test_bad_wind_records_are_refused(dg):
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-11), ("fp32", 2e-5)])
 def test_full_size_basin_with_storm_one_step(dg, precision, tol):
     """1,002,528 triangles with the storm's wind and pressure on the rain
-    track: 20 GPU steps, then one step on both sides from the same state."""
+    track, in the launch configuration the bench times (autotuned stage
+    kernel): 20 GPU steps, then one step on both sides from the same
+    state."""
     sc = meshgen.basin(708, wind=True)
     gpu = dg.Solver.from_scenario(sc, precision=precision)
+    variant, _ = gpu.autotune(2)
+    print(precision, f"autotuned: variant {variant}, tile {gpu.tile()}, fused {gpu.fused()}", flush=True)
     gpu.step(20)
     w = gpu.state()
     m0 = gpu.mass()
