@@ -89,7 +89,8 @@ def step_bytes(E, n_nodes, rs, p, stages, limiter, fused, node_forcing=True):
     return b
 
 
-def run_precision(sc, precision, steps, warmup, variant=1, events=2, save_dir=None, fused=-1, tile=-1):
+def run_precision(sc, precision, steps, warmup, variant=1, events=2, save_dir=None, fused=-1, tile=-1,
+                  save_name="basin"):
     from paper_2307_14302_amd import Solver
     import torch
 
@@ -152,16 +153,23 @@ def run_precision(sc, precision, steps, warmup, variant=1, events=2, save_dir=No
     if save_dir:
         # the state after the run and after one more step, for the oracle's
         # one-step comparison in the CPU leg
-        m0 = s.mass()
-        np.save(os.path.join(save_dir, f"basin_{precision}_w0.npy"), s.state())
-        with open(os.path.join(save_dir, f"basin_{precision}_m0.json"), "w") as f:
-            json.dump({"t": m0["t"], "dt_next": m0["dt_next"]}, f)
-        s.step(1)
-        np.save(os.path.join(save_dir, f"basin_{precision}_w1.npy"), s.state())
+        save_one_step(s, save_dir, f"{save_name}_{precision}")
     n_nodes = s.n_nodes
     s.close()
     return dict(rate=rate, elapsed=el, stats=stats, mass=m, E=E, stages=stages, variant=variant, graph=graph,
                 fused=fused, tile=tile, tuned=tuned, steps=steps, n_nodes=n_nodes)
+
+
+def save_one_step(s, save_dir, name):
+    """A solver's state, time and next dt, then its state after one more
+    step: the oracle's one-step comparison in the CPU leg starts from the
+    first and is compared with the second."""
+    m0 = s.mass()
+    np.save(os.path.join(save_dir, f"{name}_w0.npy"), s.state())
+    with open(os.path.join(save_dir, f"{name}_m0.json"), "w") as f:
+        json.dump({"t": m0["t"], "dt_next": m0["dt_next"]}, f)
+    s.step(1)
+    np.save(os.path.join(save_dir, f"{name}_w1.npy"), s.state())
 
 
 def kernel_sources_hash():
@@ -327,7 +335,7 @@ def _run_batch(members, chunk):
     return el, lat
 
 
-def run_ensemble(n_members=64, t_sim=120.0, chunk=10):
+def run_ensemble(n_members=64, t_sim=120.0, chunk=10, save_dir=None):
     """64 members (sizes log-uniform in [1e4, 5e5] triangles, even members
     p = 1, odd members p = 2, FP32), each simulating t_sim seconds, stepped
     together by one batch: every launch covers all active members of one
@@ -362,6 +370,15 @@ def run_ensemble(n_members=64, t_sim=120.0, chunk=10):
                                  "over the batch's wall time"}}
     log(f"[ensemble] {work:.3e} element-stages in {el:.2f}s -> {work / el:.4e}/s with {groups} launch groups; "
         f"latency p50 {out['p50_latency_s']}s p99 {out['p99_latency_s']}s")
+    if save_dir:
+        # the p = 2 member of median size, as the batch left it, for the
+        # oracle's one-step comparison in the CPU leg
+        p2 = sorted((m[0].n_tri, k) for k, m in enumerate(members) if m[3] == 2)
+        k = p2[len(p2) // 2][1]
+        save_one_step(members[k][0], save_dir, "ensemble_fp32")
+        with open(os.path.join(save_dir, "ensemble_member.json"), "w") as f:
+            json.dump({"index": k, "n_members": n_members}, f)
+        out["oracle_member"] = {"index": k, "n_tri": members[k][0].n_tri, "p": 2}
     for s, _, _, _ in members:
         s.close()
     # the same ensemble with the kernel configuration autotuned per member
@@ -437,7 +454,7 @@ def run_serving(n_req=100, rate=20.0, budget_gib=24.0, chunk=20, light_rate=3.0,
     return res
 
 
-def run_graded(steps=1000, warmup=20, variant=-1, fused=-1, tile=-1):
+def run_graded(steps=1000, warmup=20, variant=-1, fused=-1, tile=-1, save_dir=None):
     """The graded coastal workload at full size (3,596,698 triangles, FP32
     state, FP64 reductions, tidal boundary, river inflow, gridded rain);
     the stage kernel autotuned unless ``variant`` is given."""
@@ -445,7 +462,8 @@ def run_graded(steps=1000, warmup=20, variant=-1, fused=-1, tile=-1):
     t0 = time.perf_counter()
     sc = meshgen.graded_coast()
     log(f"[graded] {sc.mesh.n_tri} triangles generated in {time.perf_counter() - t0:.1f}s")
-    r = run_precision(sc, "fp32", steps, warmup, variant, 2, fused=fused, tile=tile)
+    r = run_precision(sc, "fp32", steps, warmup, variant, 2, fused=fused, tile=tile, save_dir=save_dir,
+                      save_name="graded")
     n, ms = r["stats"]["stage"]
     return {"value": round(r["rate"], 1), "unit": "element-stage updates/s", "n_tri": r["E"], "steps": steps,
             "ms_per_step": round(r["elapsed"] / steps * 1e3, 4), "stage_avg_us": round(ms / max(n, 1) * 1e3, 2),
@@ -455,12 +473,12 @@ def run_graded(steps=1000, warmup=20, variant=-1, fused=-1, tile=-1):
             "workload": "graded coast 30 m - 15.36 km, 1229 x 922 km, tides, 3 rivers, gridded rain, LLF, limiter"}
 
 
-def run_storm(N=708, steps=1000, warmup=20):
+def run_storm(N=708, steps=1000, warmup=20, save_dir=None):
     """The basin with the storm's wind stress and pressure on the rain track
     (FP32): the cost of the meteorological forcing."""
     import meshgen
     sc = meshgen.basin(N, wind=True)
-    r = run_precision(sc, "fp32", steps, warmup, -1, 2)
+    r = run_precision(sc, "fp32", steps, warmup, -1, 2, save_dir=save_dir, save_name="storm")
     n, ms = r["stats"]["stage"]
     return {"value": round(r["rate"], 1), "unit": "element-stage updates/s", "n_tri": r["E"], "steps": steps,
             "ms_per_step": round(r["elapsed"] / steps * 1e3, 4), "stage_avg_us": round(ms / max(n, 1) * 1e3, 2),
@@ -501,7 +519,10 @@ def cpu_baseline(outdir, basin_state=None, timeout=900):
       the GPU's FP32 state after the timed run (timed; the first step is also
       compared with the GPU's FP32 step from that state: the FP32 error);
     * the channel workload: all 1000 steps from its initial state, in CPU
-      seconds, and the GPU's final FP64 and FP32 states against it."""
+      seconds, and the GPU's final FP64 and FP32 states against it;
+    * the other FP32 legs (the storm basin, the graded coast and the median
+      p = 2 ensemble member): one oracle step from the GPU's state after the
+      leg, against the GPU's step (untimed: their FP32 error)."""
     code = r"""
 import json, os, sys, time
 import numpy as np
@@ -512,10 +533,19 @@ from oracle.solver import from_scenario
 outdir = %r
 
 def rel_l2(wg, o):
-    # vertex values; momentum as a vector; floors as in the parity tests
-    P = basis.Tables(1).phi_v
-    a = np.einsum("evm,im->evi", wg[:, :, :3], P); b = np.einsum("evm,im->evi", o.w[:, :, :3], P)
-    H = b[:, 0] + o.hbv
+    # vertex values (p = 1) or values at the collapsed (p+1) x (p+1) Gauss
+    # points (p >= 2); momentum as a vector; floors as in the parity tests
+    if o.p >= 2:
+        t, _ = np.polynomial.legendre.leggauss(o.p + 1)
+        A, B = np.meshgrid(t, t)
+        r, s_ = (0.5 * (1.0 + A) * (1.0 - B) - 1.0).ravel(), B.ravel()
+        P = basis.eval_basis(o.p, r, s_)[0]
+        a = np.einsum("evm,mq->evq", wg, P); b = np.einsum("evm,mq->evq", o.w, P)
+        H = b[:, 0] + o.hbv @ np.array(basis.barycentric(r, s_))
+    else:
+        P = basis.Tables(1).phi_v
+        a = np.einsum("evm,im->evi", wg[:, :, :3], P); b = np.einsum("evm,im->evi", o.w[:, :, :3], P)
+        H = b[:, 0] + o.hbv
     D = max(np.sqrt(np.mean(H * H)), 1e-3); n = H.size
     fz = 1e-3 * np.sqrt(n) * D; fq = fz * np.sqrt(9.81 * D)
     ez = np.linalg.norm(a[:, 0] - b[:, 0]) / max(np.linalg.norm(b[:, 0]), fz)
@@ -550,6 +580,27 @@ t2 = time.perf_counter()
 s.step(1)
 res["E"] = s.E
 res["elapsed"] = (t1 - t0) + (time.perf_counter() - t2)
+del s
+
+def one_step(name, scenario):
+    # the oracle's step from the GPU's saved state, against the GPU's step
+    f0 = os.path.join(outdir, name + "_w0.npy")
+    if not os.path.exists(f0):
+        return
+    m0 = json.load(open(os.path.join(outdir, name + "_m0.json")))
+    o = from_scenario(scenario())
+    o.set_state(np.load(f0), m0["t"], post=False)
+    o.dt = m0["dt_next"]
+    o.step(1)
+    res[name + "_err"] = rel_l2(np.load(os.path.join(outdir, name + "_w1.npy")), o)
+
+one_step("storm_fp32", lambda: meshgen.basin(708, wind=True))
+one_step("graded_fp32", meshgen.graded_coast)
+fm = os.path.join(outdir, "ensemble_member.json")
+if os.path.exists(fm):
+    em = json.load(open(fm))
+    i, n_tri, p = list(meshgen.ensemble_plan(em["n_members"]))[em["index"]]
+    one_step("ensemble_fp32", lambda: meshgen.basin_member(4, i, n_tri, p=p))
 print(json.dumps(res))
 """ % (ROOT, outdir)
     env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
@@ -574,11 +625,15 @@ print(json.dumps(res))
     errs = {}
     if "basin_err_fp32" in r:
         errs["basin_fp32_one_step_rel_l2"] = r["basin_err_fp32"]
+    for leg in ("storm", "graded", "ensemble"):
+        if f"{leg}_fp32_err" in r:
+            errs[f"{leg}_fp32_one_step_rel_l2"] = r[f"{leg}_fp32_err"]
     for prec in ("fp64", "fp32"):
         if "c1_err_" + prec in r:
             errs[f"c1_{prec}_1000_steps_rel_l2"] = r["c1_err_" + prec]
     if errs:
-        out["gpu_error_vs_oracle"] = dict(errs, norm="relative L2 of (zeta, discharge vector) at the vertices")
+        out["gpu_error_vs_oracle"] = dict(errs, norm="relative L2 of (zeta, discharge vector) at the vertices "
+                                                    "(p = 1) or the collapsed Gauss points (p = 2)")
     return out
 
 
@@ -678,13 +733,15 @@ def main():
                        "stage_variant": f["variant"],
                        "dtype": "f64", "roofline": roofline(f, "fp64", prm["p"], prm["limiter"], basin_key),
                        "fp32_over_fp64": round(r["rate"] / f["rate"], 3)}
+    # the FP32 legs also leave one step for the oracle to check in the CPU leg
+    keep = outdir if (not args.no_cpu and args.N == 708 and args.p == 1) else None
     if not args.no_storm:
-        out["storm"] = run_storm(args.N)
+        out["storm"] = run_storm(args.N, save_dir=keep)
         out["storm"]["vs_no_wind"] = round(out["storm"]["value"] / r["rate"], 3)
     if not args.no_graded:
-        out["graded"] = run_graded()
+        out["graded"] = run_graded(save_dir=keep)
     if not args.no_ensemble:
-        out["ensemble"] = run_ensemble()
+        out["ensemble"] = run_ensemble(save_dir=keep)
         if "fp64" in res:
             out["ensemble"]["vs_fp64_single_mesh"] = round(out["ensemble"]["value"] / res["fp64"]["rate"], 3)
     if not args.no_serving:
