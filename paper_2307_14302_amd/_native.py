@@ -109,7 +109,7 @@ def _load():
     except Exception:  # pragma: no cover
         pass
     if not os.path.exists(LIB_PATH):
-        raise ImportError(f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'`")
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2307_14302_amd.build`")
     lib = C.CDLL(LIB_PATH)
     for name, (res, args) in SIGNATURES.items():
         f = getattr(lib, name)
