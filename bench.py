@@ -259,8 +259,9 @@ def roofline(res, precision, p, limiter, workload=None):
            "traffic_source": ("FETCH_SIZE and WRITE_SIZE per launch from the committed rocprofv3 summary "
                               f"profiles/{COUNTER_SUMMARIES[workload]} (same kernel sources), scaled by "
                               "its copy calibration; not counted in this run") if traffic else
-                             ("null: the committed counter summary is for other kernel sources or another "
-                              "stage tile" if workload in COUNTER_SUMMARIES else
+                             ("null: the committed counter summary has no figure for this kernel, stage tile and "
+                              "precision, or the kernel sources changed since it was taken"
+                              if workload in COUNTER_SUMMARIES else
                               "null: no committed counter summary for this workload"),
            "bytes_per_launch": int(byts),
            "avg_us": round(avg_s * 1e6, 2), "launches": n}
@@ -454,10 +455,11 @@ def run_serving(n_req=100, rate=20.0, budget_gib=24.0, chunk=20, light_rate=3.0,
     return res
 
 
-def run_graded(steps=1000, warmup=20, variant=-1, fused=-1, tile=-1, save_dir=None):
+def run_graded(steps=1000, warmup=20, variant=-1, fused=-1, tile=-1, save_dir=None, fp64=True):
     """The graded coastal workload at full size (3,596,698 triangles, FP32
     state, FP64 reductions, tidal boundary, river inflow, gridded rain);
-    the stage kernel autotuned unless ``variant`` is given."""
+    the stage kernel autotuned unless ``variant`` is given.  With ``fp64``
+    the same steps also run on the plain FP64 path, its rate beside."""
     import meshgen
     t0 = time.perf_counter()
     sc = meshgen.graded_coast()
@@ -465,12 +467,19 @@ def run_graded(steps=1000, warmup=20, variant=-1, fused=-1, tile=-1, save_dir=No
     r = run_precision(sc, "fp32", steps, warmup, variant, 2, fused=fused, tile=tile, save_dir=save_dir,
                       save_name="graded")
     n, ms = r["stats"]["stage"]
-    return {"value": round(r["rate"], 1), "unit": "element-stage updates/s", "n_tri": r["E"], "steps": steps,
-            "ms_per_step": round(r["elapsed"] / steps * 1e3, 4), "stage_avg_us": round(ms / max(n, 1) * 1e3, 2),
-            "dt_s": r["mass"]["dt_last"], "dtype": "f32", "stage_variant": r["variant"], "fused": r["fused"],
-            "stage_tile": r["tile"],
-            "roofline": roofline(r, "fp32", 1, True, "graded3.6M_p1"),
-            "workload": "graded coast 30 m - 15.36 km, 1229 x 922 km, tides, 3 rivers, gridded rain, LLF, limiter"}
+    out = {"value": round(r["rate"], 1), "unit": "element-stage updates/s", "n_tri": r["E"], "steps": steps,
+           "ms_per_step": round(r["elapsed"] / steps * 1e3, 4), "stage_avg_us": round(ms / max(n, 1) * 1e3, 2),
+           "dt_s": r["mass"]["dt_last"], "dtype": "f32", "stage_variant": r["variant"], "fused": r["fused"],
+           "stage_tile": r["tile"],
+           "roofline": roofline(r, "fp32", 1, True, "graded3.6M_p1"),
+           "workload": "graded coast 30 m - 15.36 km, 1229 x 922 km, tides, 3 rivers, gridded rain, LLF, limiter"}
+    if fp64:
+        f = run_precision(sc, "fp64", steps, warmup, variant, 2, fused=fused, tile=tile)
+        out["fp64"] = {"value": round(f["rate"], 1), "ms_per_step": round(f["elapsed"] / steps * 1e3, 4),
+                       "stage_variant": f["variant"], "stage_tile": f["tile"], "dtype": "f64",
+                       "roofline": roofline(f, "fp64", 1, True, "graded3.6M_p1"),
+                       "fp32_over_fp64": round(r["rate"] / f["rate"], 3)}
+    return out
 
 
 def run_storm(N=708, steps=1000, warmup=20, save_dir=None):
@@ -664,7 +673,8 @@ def main():
     ap.add_argument("--no-storm", action="store_true", help="skip the basin run with storm wind and pressure")
     ap.add_argument("--serve-requests", type=int, default=100, help="requests of the 400-request trace to serve")
     ap.add_argument("--graded-only", action="store_true",
-                    help="run only the 3.6M-triangle graded leg (--steps steps) and print its JSON (for profiling)")
+                    help="run only the FP32 part of the 3.6M-triangle graded leg (--steps steps) and print its JSON "
+                         "(for profiling)")
     ap.add_argument("--ensemble-only", action="store_true",
                     help="run only the 64-member ensemble leg and print its JSON (for profiling)")
     args = ap.parse_args()
@@ -677,7 +687,7 @@ def main():
     torch.cuda.set_device(0)
     if args.graded_only:
         out = run_graded(steps=args.steps, warmup=args.warmup, variant=args.variant, fused=args.fused,
-                         tile=args.tile)
+                         tile=args.tile, fp64=False)
         if args.calib_copy:
             calib_copy()
         print(json.dumps(out), flush=True)
