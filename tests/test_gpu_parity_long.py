@@ -3,8 +3,9 @@ parity cases leave out:
 
 * 1000 steps with the slope limiter on and wet/dry fronts (Sec. 2.3
   limiter, Sec. 2.4 wetting and drying): a window of the basin across its
-  coast with dry land, and the small instance of the graded coastal mesh
-  (tides, rivers, gridded rain); FP64 to 1e-10, FP32 to 1e-4, budgets, and
+  coast with dry land, the same window under the storm's wind stress and
+  pressure, and the small instance of the graded coastal mesh (tides,
+  rivers, gridded rain); FP64 to 1e-10, FP32 to 1e-4, budgets, and
   the dry flags (equal in FP64; in FP32 every flip is reported with the
   margin of the oracle's decision and must sit at the threshold);
 * p = 2 (400 steps) and p = 3 (250 steps) on coast windows with the limiter
@@ -34,12 +35,13 @@ def dg():
     return pkg
 
 
-def coast_window(N=36, x0=168e3):
+def coast_window(N=36, x0=168e3, wind=False):
     """N x N piece of the 200 km basin at its own element size across the
     coast (x from 168 km): ocean, shelf, beach and dry land (about a quarter
-    of the elements dry)."""
+    of the elements dry); with ``wind`` the storm's wind stress and pressure
+    (its vortex and the background wind) act on it too."""
     size = N * 200e3 / 708
-    return meshgen.basin(N, meshgen.seed_for(1), window=(x0, 100e3 - 0.5 * size, size))
+    return meshgen.basin(N, meshgen.seed_for(1), window=(x0, 100e3 - 0.5 * size, size), wind=wind)
 
 
 _ORACLE = {}
@@ -87,7 +89,8 @@ def check_flags(gpu, orc, precision, H0):
         assert np.all(np.abs(margins) <= 1e-2 * H0), margins
 
 
-LONG = {"coast_window": coast_window, "graded_small": meshgen.graded_small}
+LONG = {"coast_window": coast_window, "graded_small": meshgen.graded_small,
+        "coast_window_storm": lambda: coast_window(wind=True)}
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
