@@ -4,8 +4,8 @@ parity cases leave out:
 * 1000 steps with the slope limiter on and wet/dry fronts (Sec. 2.3
   limiter, Sec. 2.4 wetting and drying): a window of the basin across its
   coast with dry land, the same window under the storm's wind stress and
-  pressure, and the small instance of the graded coastal mesh (tides,
-  rivers, gridded rain); FP64 to 1e-10, FP32 to 1e-4, budgets, and
+  pressure and advanced by the 5-stage scheme, and the small instance of
+  the graded coastal mesh (tides, rivers, gridded rain); FP64 to 1e-10, FP32 to 1e-4, budgets, and
   the dry flags (equal in FP64; in FP32 every flip is reported with the
   margin of the oracle's decision and must sit at the threshold);
 * p = 2 (400 steps) and p = 3 (250 steps) on coast windows with the limiter
@@ -89,8 +89,16 @@ def check_flags(gpu, orc, precision, H0):
         assert np.all(np.abs(margins) <= 1e-2 * H0), margins
 
 
+def coast_window_ssp5():
+    """The coast window advanced by the 5-stage order-2 scheme (the stand-in
+    for the 5-stage scheme of Sec. 3.3) at CFL 0.5."""
+    sc = coast_window()
+    sc.params.update(rk_stages=5, cfl=0.5)
+    return sc
+
+
 LONG = {"coast_window": coast_window, "graded_small": meshgen.graded_small,
-        "coast_window_storm": lambda: coast_window(wind=True)}
+        "coast_window_storm": lambda: coast_window(wind=True), "coast_window_ssp5": coast_window_ssp5}
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
